@@ -1,0 +1,285 @@
+"""Pins of the CPU oracle: checks against what mathematics, the paper's
+definitions, independent libraries (numpy, torch CPU casts, math.fsum) and
+brute force fix.  Each pin takes an ``Oracle`` instance and raises
+AssertionError on a mismatch, so the same pins can be run against the real
+oracle and against deliberately broken builds of it (mutation tests)."""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+import workloads as W
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+SD = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+
+
+def _gold(name):
+    with open(os.path.join(GOLD, name)) as f:
+        return json.load(f)
+
+
+# ------------------------------------------------------------------ transpose
+
+def pin_tpose_golden(o):
+    """Hand-worked examples of out[x][y] = in[y][x] (Listing 3.5)."""
+    for case in _gold("tpose_small.json")["cases"]:
+        a = np.array(case["in"], dtype=np.int32)
+        want = np.array(case["out"], dtype=np.int32)
+        got = o.tpose(a)
+        assert got.shape == want.shape and np.array_equal(got, want), (case, got)
+
+
+def pin_tpose_iota(o):
+    """Closed form: src[r][c] = r*cols + c gives dst[c][r] = r*cols + c."""
+    for eb in (1, 2, 4, 8):
+        for rows, cols in ((1, 1), (3, 5), (17, 9), (64, 65), (70, 33)):
+            iota = (np.arange(rows * cols, dtype=np.uint64)).astype(SD[eb]).reshape(rows, cols)
+            got = o.tpose(iota)
+            r = np.arange(rows)[None, :]
+            c = np.arange(cols)[:, None]
+            want = (r * cols + c).astype(np.uint64).astype(SD[eb])
+            assert np.array_equal(got, want), (eb, rows, cols)
+
+
+def pin_tpose_library(o):
+    """Special case that reduces to a library routine: numpy's ``.T.copy()``
+    (bitwise, so NaN payloads and -0.0 must survive)."""
+    for eb in (1, 2, 4, 8):
+        a = W.random_bits(37 * 91, 101 + eb, eb).reshape(37, 91)
+        assert np.array_equal(o.tpose(a), a.T.copy())
+    f = np.array([[np.nan, -0.0], [np.inf, 1.5]], dtype=np.float32)
+    f.view(np.uint32)[0, 0] = 0x7fc12345                   # NaN with a payload
+    got = o.tpose(f).view(np.uint32)
+    assert np.array_equal(got, f.view(np.uint32).T.copy())
+
+
+def pin_tpose_involution_and_ld(o):
+    """tpose(tpose(A)) == A through padded leading dimensions; padding and
+    canary bytes around dst are never written."""
+    rng = np.random.Generator(np.random.PCG64(7))
+    for eb in (1, 2, 4, 8):
+        for rows, cols, pad_s, pad_d in ((5, 7, 0, 3), (33, 2, 17, 1), (1, 40, 1, 0), (16, 16, 5, 5)):
+            ld_s, ld_d = cols + pad_s, rows + pad_d
+            src = rng.integers(0, 255, (rows * ld_s) * eb, dtype=np.uint8).view(SD[eb])
+            canary = np.array(0xA5, dtype=np.uint8).repeat(eb).view(SD[eb])[0]
+            dst = np.full((cols - 1) * ld_d + rows + 13, canary, dtype=SD[eb])
+            o.tpose(src, rows, cols, ld_s, ld_d, dst=dst)
+            for c in range(cols - 1):             # padding after each dst row untouched
+                assert np.all(dst[c * ld_d + rows:(c + 1) * ld_d] == canary)
+            assert np.all(dst[(cols - 1) * ld_d + rows:] == canary)   # canary after the end
+            back = np.full(rows * ld_s, canary, dtype=SD[eb])
+            o.tpose(dst, cols, rows, ld_d, ld_s, dst=back)
+            for r in range(rows):
+                assert np.array_equal(back[r * ld_s:r * ld_s + cols], src[r * ld_s:r * ld_s + cols])
+
+
+def pin_tpose_permutation(o):
+    """The output is a permutation of the input: equal sorted multisets."""
+    a = W.random_bits(61 * 47, 5, 2).reshape(61, 47)
+    got = o.tpose(a)
+    assert np.array_equal(np.sort(got, axis=None), np.sort(a, axis=None))
+
+
+def pin_tpose_bruteforce(o):
+    """Tiny exhaustive enumeration against a pure-Python double loop."""
+    for eb in (1, 4):
+        for rows in range(1, 9):
+            for cols in range(1, 9):
+                a = W.random_bits(rows * cols, rows * 31 + cols, eb)
+                want = [a[r * cols + c] for c in range(cols) for r in range(rows)]
+                got = o.tpose(a.reshape(rows, cols)).ravel()
+                assert list(got) == want, (eb, rows, cols)
+
+
+# ------------------------------------------------------------------ integer sums
+
+def pin_int_golden(o):
+    g = _gold("sum_small.json")
+    for case in g["int_cases"]:
+        for dt in ("i32", "i64"):
+            a = np.array(case["A"], dtype=np.int32 if dt == "i32" else np.int64)
+            assert o.sum_int(a, dt) == (case["sum"], False), (case, dt)
+
+
+def pin_int_closed_forms(o):
+    """Gauss: sum_{i<n} i = n(n-1)/2; alternating sum_{i<n} (-1)^i i."""
+    for n in (0, 1, 2, 3, 1000, 65537, 1 << 20):
+        a = np.arange(n, dtype=np.int64)
+        assert o.sum_int(a, "i64")[0] == n * (n - 1) // 2
+        assert o.sum_int(a.astype(np.int32), "i32")[0] == n * (n - 1) // 2
+        alt = np.where(a % 2 == 0, a, -a)
+        want = -(n // 2) if n % 2 == 0 else (n - 1) // 2     # pairs (2k, -(2k+1)) give -1
+        assert o.sum_int(alt, "i64")[0] == want, n
+
+
+def pin_int_bruteforce_shuffle(o):
+    """Brute force with Python integers; invariance under random shuffles;
+    numpy's int64 sum (same modulo-2^64 semantics) where it applies."""
+    rng = np.random.Generator(np.random.PCG64(11))
+    for n in (0, 1, 5, 127, 4099):
+        a32 = W.integers(n, 40 + n, -1000, 1000, "i32")
+        want = sum(int(v) for v in a32)
+        assert o.sum_int(a32, "i32") == (want, False)
+        assert o.sum_int(rng.permutation(a32), "i32")[0] == want
+        a64 = W.integers(n, 50 + n, -(1 << 40), 1 << 40, "i64")
+        want = sum(int(v) for v in a64)
+        assert o.sum_int(a64, "i64") == (want, False)
+        assert o.sum_int(rng.permutation(a64), "i64")[0] == int(np.sum(a64, dtype=np.int64))
+
+
+def pin_int_wrap(o):
+    """int64 sums wrap modulo 2^64, and the overflow flag says so."""
+    big = np.array([2 ** 63 - 1, 2 ** 63 - 1], dtype=np.int64)
+    assert o.sum_int(big, "i64") == (-2, True)
+    lo = np.array([-2 ** 63, -1], dtype=np.int64)
+    assert o.sum_int(lo, "i64") == (2 ** 63 - 1, True)
+    back = np.array([2 ** 63 - 1, 1, -1], dtype=np.int64)   # leaves the range, comes back
+    assert o.sum_int(back, "i64") == (2 ** 63 - 1, False)
+    mx = np.full(1 << 16, np.iinfo(np.int32).max, dtype=np.int32)   # int32 never wraps in int64
+    assert o.sum_int(mx, "i32") == ((1 << 16) * (2 ** 31 - 1), False)
+
+
+# ------------------------------------------------------------------ decoders
+
+def pin_decode_golden(o):
+    g = _gold("decode_codes.json")
+    for dt in ("f8e4m3", "bf16", "f16"):
+        sd = np.uint8 if dt == "f8e4m3" else np.uint16
+        for code, val in g[dt]:
+            got = o.decode(np.array([int(code, 16)], dtype=sd), dt)[0]
+            if val == "nan":
+                assert math.isnan(got), (dt, code)
+                continue
+            want = float.fromhex(val) if "0x" in val else float(val)
+            assert got == want and math.copysign(1, got) == math.copysign(1, want), (dt, code, got)
+
+
+def pin_decode_all_codes(o):
+    """Every code of the 8- and 16-bit formats against torch's CPU casts
+    (independent library), NaN positions included."""
+    import torch
+    u8 = np.arange(256, dtype=np.uint8)
+    want = torch.from_numpy(u8).view(torch.float8_e4m3fn).to(torch.float64).numpy()
+    got = o.decode(u8, "f8e4m3")
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    m = ~np.isnan(want)
+    assert np.array_equal(got[m].view(np.uint64), want[m].view(np.uint64))
+    u16 = np.arange(65536, dtype=np.uint16)
+    want = torch.from_numpy(u16.view(np.int16)).view(torch.bfloat16).to(torch.float64).numpy()
+    got = o.decode(u16, "bf16")
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    m = ~np.isnan(want)
+    assert np.array_equal(got[m].view(np.uint64), want[m].view(np.uint64))
+    want = u16.view(np.float16).astype(np.float64)
+    got = o.decode(u16, "f16")
+    assert np.array_equal(np.isnan(got), np.isnan(want))
+    m = ~np.isnan(want)
+    assert np.array_equal(got[m].view(np.uint64), want[m].view(np.uint64))
+    f = W.random_bits(4096, 3, 4).view(np.float32)
+    got = o.decode(f, "f32")
+    with np.errstate(invalid="ignore"):
+        want = f.astype(np.float64)
+    m = ~np.isnan(want)
+    assert np.array_equal(np.isnan(got), ~m) and np.array_equal(got[m], want[m])
+
+
+# ------------------------------------------------------------------ float sums
+
+def pin_float_golden(o):
+    g = _gold("sum_small.json")
+    for case in g["float_cases_exact"]:
+        a = np.array(case["A"], dtype=np.float32)
+        assert o.sum_float(a, "f32") == case["sum"], case
+    for case in g["plain_f32_cases"]:
+        a = np.array(case["A"], dtype=np.float32)
+        assert o.sum_plain_f32(a, "f32") == case["sum"], case
+
+
+def pin_float_fsum(o):
+    """Against math.fsum (correctly rounded): the fp64 Neumaier oracle is
+    within a couple of ulps of the exactly rounded sum, per input format."""
+    cases = [("f32", W.normal(1 << 16, 21, "f32")),
+             ("f32", W.uniform(12345, 22, "f32")),
+             ("bf16", W.signed_lognormal(1 << 15, 23, "bf16")[0]),
+             ("f16", W.signed_lognormal(1 << 15, 24, "f16")[0]),
+             ("f8e4m3", W.signed_lognormal(1 << 15, 25, "f8e4m3")[0])]
+    for dt, bits in cases:
+        vals = o.decode(bits, dt)
+        exact = math.fsum(vals.tolist())
+        got = o.sum_float(bits, dt)
+        tol = 4 * math.ulp(abs(exact)) + 1e-300
+        assert abs(got - exact) <= tol, (dt, got, exact)
+
+
+def pin_float_closed_forms(o):
+    """Sums fixed by arithmetic: 2^k copies of 1.0, x/-x pairs, a geometric
+    series of powers of two; n = 0 and n = 1."""
+    one_bf16 = np.full((1 << 20) + 3, 0x3F80, dtype=np.uint16)
+    assert o.sum_float(one_bf16, "bf16") == float((1 << 20) + 3)
+    one_f8 = np.full(1000, 0x38, dtype=np.uint8)
+    assert o.sum_float(one_f8, "f8e4m3") == 1000.0
+    x = W.normal(5000, 31, "f32")
+    pairs = np.empty(10000, dtype=np.float32)
+    pairs[0::2], pairs[1::2] = x, -x
+    assert o.sum_float(pairs, "f32") == 0.0
+    geo = np.array([2.0 ** -k for k in range(0, 41)], dtype=np.float32)
+    assert o.sum_float(geo, "f32") == 2.0 - 2.0 ** -40
+    assert o.sum_float(geo[::-1].copy(), "f32") == 2.0 - 2.0 ** -40
+    assert o.sum_float(np.zeros(0, np.float32), "f32") == 0.0
+    v = np.array([-3.25], dtype=np.float32)
+    assert o.sum_float(v, "f32") == -3.25
+    # cancellation a plain fp64 left-to-right sum gets wrong
+    c = np.array([1.0, 1e30, 1.0, -1e30], dtype=np.float32)
+    assert o.sum_float(c, "f32") == 2.0
+
+
+def pin_float_nonfinite(o):
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    assert o.sum_float(np.array([1, inf, 2], np.float32), "f32") == math.inf
+    assert o.sum_float(np.array([1, -inf, -inf], np.float32), "f32") == -math.inf
+    assert math.isnan(o.sum_float(np.array([inf, 1, -inf], np.float32), "f32"))
+    assert math.isnan(o.sum_float(np.array([1, nan, 1], np.float32), "f32"))
+    assert math.isnan(o.sum_float(np.array([0x38, 0x7F], np.uint8), "f8e4m3"))
+
+
+def pin_plain_f32(o):
+    """Listing 2.1 as written: a sequential float accumulator.  numpy's
+    float32 cumsum is the same left-to-right recurrence; at 2^24 + k ones the
+    accumulator stagnates at 2^24 while the exact sum keeps counting."""
+    for dt, bits in (("f32", W.normal(9999, 41, "f32")), ("f32", W.uniform(777, 42, "f32"))):
+        want = float(np.cumsum(bits.astype(np.float32), dtype=np.float32)[-1])
+        assert o.sum_plain_f32(bits, dt) == want
+    ones = np.full((1 << 24) + 100, 0x3F80, dtype=np.uint16)
+    assert o.sum_plain_f32(ones, "bf16") == float(1 << 24)
+    assert o.sum_float(ones, "bf16") == float((1 << 24) + 100)
+
+
+def pin_segmented(o):
+    """Per-segment sums equal the single-range oracle on each segment; empty
+    segments give 0."""
+    off = W.segment_offsets(20000, 300, 61)
+    bits = W.normal(20000, 62, "f32")
+    got = o.sum_segmented(bits, off, "f32")
+    for i in range(300):
+        seg = bits[off[i]:off[i + 1]]
+        assert got[i] == (o.sum_float(seg, "f32") if seg.size else 0.0)
+        assert abs(got[i] - math.fsum(seg.astype(np.float64).tolist())) <= \
+            4 * math.ulp(max(abs(got[i]), 1e-300))
+    ints = W.integers(20000, 63, -1000, 1000, "i32")
+    goti = o.sum_segmented(ints, off, "i32")
+    for i in range(300):
+        assert goti[i] == int(ints[off[i]:off[i + 1]].astype(np.int64).sum())
+    off2 = np.array([0, 0, 3, 3, 5], dtype=np.int64)
+    assert list(o.sum_segmented(np.arange(5, dtype=np.int32), off2, "i32")) == [0, 3, 0, 7]
+
+
+PINS_TPOSE = [pin_tpose_golden, pin_tpose_iota, pin_tpose_library, pin_tpose_involution_and_ld,
+              pin_tpose_permutation, pin_tpose_bruteforce]
+PINS_INT = [pin_int_golden, pin_int_closed_forms, pin_int_bruteforce_shuffle, pin_int_wrap]
+PINS_FLOAT = [pin_decode_golden, pin_decode_all_codes, pin_float_golden, pin_float_fsum,
+              pin_float_closed_forms, pin_float_nonfinite, pin_plain_f32, pin_segmented]
+ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT
