@@ -1,0 +1,247 @@
+#!/usr/bin/env python3
+"""Throughput of the transpose and sum-reduction hot path on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--suite step|full] [--no-cpu]
+
+One step = one pass over the large single-job workload: an fp32 16384 x 16384
+transpose, a bf16 12288 x 20000 transpose, an fp32 sum of 2^28 N(0,1) values
+and an int64 sum of 2^28 values uniform in [-2^40, 2^40].  `value` is the
+step's algorithmic bytes (transpose: read + write once; sum: read once) over
+the step's device time, in GB/s, with inputs already resident in HBM.
+Each kernel is also timed alone with HIP events on the stream it runs on, and
+the dominant one is reported against the HBM roofline.  The CPU oracle is
+timed on a bounded 1/16 sample of the same workload.
+
+`--suite full` adds the batched (one launch per batch vs one per job),
+segmented, precision and serving measurements under "suite".
+
+Prints ONE JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0    # MI355X HBM3E, public spec
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2605_13864_amd", "csrc"))):
+        with open(os.path.join(ROOT, "paper_2605_13864_amd", "csrc", f), "rb") as fh:
+            h.update(f.encode() + fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 counters (FETCH_SIZE,
+    WRITE_SIZE, scaled by a plain-copy calibration) when the committed counter
+    summary was taken on the current kernel sources; else None."""
+    p = os.path.join(ROOT, "profiles", "counters.json")
+    if not os.path.exists(p):
+        return None
+    with open(p) as f:
+        d = json.load(f)
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel_key)
+    return None if k is None else k.get("hbm_bytes_per_launch")
+
+
+class Step:
+    """The four kernels of one step, with their inputs resident on the GPU."""
+
+    def __init__(self, xtr, torch):
+        import numpy as np
+        import workloads as W
+        dev = torch.device("cuda")
+        self.xtr, self.torch = xtr, torch
+        log("bench: generating inputs ...")
+        t0 = time.time()
+        a = W.matrix(16384, 16384, 2, "f32")
+        self.t32_in = torch.from_numpy(a).to(dev)
+        del a
+        self.t32_out = torch.empty((16384, 16384), dtype=torch.float32, device=dev)
+        b = W.matrix(12288, 20000, 3, "bf16")
+        self.t16_in = torch.from_numpy(b.view(np.int16)).to(dev)
+        del b
+        self.t16_out = torch.empty((20000, 12288), dtype=torch.int16, device=dev)
+        self.s32 = torch.from_numpy(W.normal(1 << 28, 4, "f32")).to(dev)
+        self.s64 = torch.from_numpy(W.integers(1 << 28, 5, -(1 << 40), 1 << 40, "i64")).to(dev)
+        self.o32 = torch.empty((), dtype=torch.float64, device=dev)
+        self.o64 = torch.empty((), dtype=torch.int64, device=dev)
+        torch.cuda.synchronize()
+        log(f"bench: inputs ready in {time.time() - t0:.1f}s")
+        self.kernels = [
+            ("tpose_f32_16384x16384", 2 * 16384 * 16384 * 4,
+             lambda: xtr.tpose(self.t32_in, self.t32_out, dtype="f32")),
+            ("tpose_bf16_12288x20000", 2 * 12288 * 20000 * 2,
+             lambda: xtr.tpose(self.t16_in, self.t16_out, dtype="bf16")),
+            ("sum_f32_2^28", (1 << 28) * 4,
+             lambda: xtr.reduce_sum(self.s32, self.o32, dtype="f32")),
+            ("sum_i64_2^28", (1 << 28) * 8,
+             lambda: xtr.reduce_sum(self.s64, self.o64, dtype="i64")),
+        ]
+        self.bytes = sum(k[1] for k in self.kernels)
+
+    def run(self, events=None):
+        for i, (_, _, fn) in enumerate(self.kernels):
+            if events is not None:
+                events[i][0].record()
+            fn()
+            if events is not None:
+                events[i][1].record()
+
+
+def copy_ceiling(torch, nbytes=1 << 30, reps=20):
+    """Plain device-to-device copy bandwidth (read + write) for context."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e.record()
+    torch.cuda.synchronize()
+    ms = s.elapsed_time(e) / reps
+    del a, b
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline():
+    """The oracle, as it stands, on a 1/16 sample of the step's workload
+    (single thread)."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    o = oracle.get()
+    parts = []
+    a = W.matrix(4096, 4096, 2, "f32")
+    parts.append(("tpose f32 4096x4096", 2 * a.nbytes, lambda: o.tpose(a)))
+    b = W.matrix(3072, 5000, 3, "bf16")
+    parts.append(("tpose bf16 3072x5000", 2 * b.nbytes, lambda: o.tpose(b)))
+    c = W.normal(1 << 24, 4, "f32")
+    parts.append(("sum f32 2^24", c.nbytes, lambda: o.sum_float(c, "f32")))
+    d = W.integers(1 << 24, 5, -(1 << 40), 1 << 40, "i64")
+    parts.append(("sum i64 2^24", d.nbytes, lambda: o.sum_int(d, "i64")))
+    total_b, total_t = 0, 0.0
+    reps = 0
+    t_start = time.time()
+    while reps < 1 or (time.time() - t_start < 8.0 and reps < 20):
+        for _, nb, fn in parts:
+            t0 = time.perf_counter()
+            fn()
+            total_t += time.perf_counter() - t0
+            total_b += nb
+        reps += 1
+    _ = np
+    return {"value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"1/16 of the step ({', '.join(p[0] for p in parts)}), "
+                      f"{reps} repetition(s), {total_t:.1f}s of CPU time, single thread"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--suite", choices=["step", "full"], default="step")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+              f"--gpus {args.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2605_13864_amd as xtr
+    xtr.load()
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    log(f"bench: device {torch.cuda.get_device_name(0)}")
+
+    step = Step(xtr, torch)
+    for _ in range(args.warmup):
+        step.run()
+    torch.cuda.synchronize()
+
+    # whole-step timing
+    t0 = time.perf_counter()
+    s_ev, e_ev = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s_ev.record()
+    for _ in range(args.steps):
+        step.run()
+    e_ev.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = s_ev.elapsed_time(e_ev) / args.steps
+    log(f"bench: {args.steps} steps, {ms_per_step:.3f} ms/step (wall {wall:.2f}s)")
+
+    # per-kernel timing (events on the current stream, which the kernels run on)
+    n = len(step.kernels)
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in range(n)] for _ in range(args.steps)]
+    for k in range(args.steps):
+        step.run(evs[k])
+    torch.cuda.synchronize()
+    per = []
+    for i, (name, nbytes, _) in enumerate(step.kernels):
+        us = sum(evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)) / args.steps * 1e3
+        gbs = nbytes / (us * 1e-6) / 1e9
+        per.append({"kernel": name, "bytes": nbytes, "avg_us": round(us, 2), "gbs": round(gbs, 1),
+                    "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        log(f"bench: {name:28s} {us:9.2f} us  {gbs:8.1f} GB/s  {gbs / HBM_PEAK_GBS:6.1%} of peak")
+    dom = max(per, key=lambda p: p["avg_us"])
+    value = step.bytes / (ms_per_step * 1e-3) / 1e9
+    copy = copy_ceiling(torch)
+    log(f"bench: step {value:.1f} GB/s; plain copy ceiling {copy:.1f} GB/s")
+
+    tr = traffic_from_profile(dom["kernel"])
+    out = {
+        "metric": "HBM GB/s & % of peak: transpose, sum-reduce; batched vs per-job; p99 latency",
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+bf16 (transpose bit copies); f32-pair compensated / int64 (sums)",
+        "data": "synthetic",
+        "config": {"workload": "large single jobs: tpose f32 16384x16384 + tpose bf16 "
+                               "12288x20000 + sum f32 2^28 N(0,1) + sum i64 2^28 U[-2^40,2^40]",
+                   "bytes_per_step": step.bytes, "frac_of_peak": round(value / HBM_PEAK_GBS, 4),
+                   "parallelism": "single GPU"},
+        "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"],
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac"],
+                     "traffic": tr},
+        "kernels": per,
+        "copy_ceiling_gbs": round(copy, 1),
+    }
+    if not args.no_cpu:
+        log("bench: timing the CPU oracle on a bounded sample ...")
+        out["cpu_baseline"] = cpu_baseline()
+    if args.suite == "full":
+        import bench_suite
+        out["suite"] = bench_suite.run_all(xtr, torch, log)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

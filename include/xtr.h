@@ -1,0 +1,186 @@
+/*
+ * xtr — out-of-place matrix transpose and tree-based sum reduction on
+ * AMD Instinct MI355X (gfx950).  C ABI of libxtr.so.
+ *
+ * The two operations are the case studies of "Source-to-Source
+ * Transformations for GPU Code Generation" (de Castelnau, 2026):
+ *   - transpose: the sequential specification of Listing 3.5
+ *     (out[x][y] = in[y][x], in is H x W, out is W x H, both row-major),
+ *     computed with LDS-staged tiles and a block barrier at the point where
+ *     tile ownership moves from the loading threads to the storing threads
+ *     (Listings 3.8 and 3.10, Section 3.3);
+ *   - sum: the sequential reduce of Listing 2.1 (specification reduce_sum,
+ *     Section 2.1), computed as per-thread register accumulators, a
+ *     cross-lane wavefront reduction, an LDS tree across the waves of a
+ *     workgroup (the tree reduction of Section 7.2, with the register
+ *     accumulator of Listing 7.22) and a grid-level combine of per-workgroup
+ *     partials (the partial-sums-then-combine split of Listing 2.2).
+ *
+ * Conventions for every entry point:
+ *   - Data pointers are DEVICE pointers unless the comment says "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *     Calls only enqueue work; results are valid once the stream has
+ *     reached that point (hipStreamSynchronize or an event).
+ *   - The caller owns every data buffer; the library never frees them.
+ *     The library owns its internal workspace (per device and stream, grown
+ *     on demand and kept until xtr_release or process exit) and its pinned
+ *     host staging for descriptor tables.
+ *   - Return value: XTR_OK (0) or a negative XTR_E* code.  On a validation
+ *     error (EINVAL, EDTYPE, EOVERLAP, EALIGN) nothing has been enqueued.
+ *     EHIP means a HIP call failed (message in xtr_last_error()).  No C++
+ *     exception crosses this interface.
+ *   - Sizes and leading dimensions are in ELEMENTS, never bytes.
+ */
+#ifndef XTR_H
+#define XTR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Element formats.  Transpose accepts all of them (it copies element bits);
+ * the sums accept F32, F16, BF16, F8E4M3 (OCP E4M3 "FN": bias 7, no inf,
+ * S.1111.111 = NaN) and I32, I64. */
+typedef enum {
+    XTR_F32 = 0, XTR_F16 = 1, XTR_BF16 = 2, XTR_F8E4M3 = 3,
+    XTR_I32 = 4, XTR_I64 = 5, XTR_F64 = 6, XTR_U8 = 7, XTR_U16 = 8
+} xtr_dtype;
+
+enum {
+    XTR_OK = 0,
+    XTR_EINVAL = -1,    /* null pointer, negative size, ld too small, bad offsets table */
+    XTR_EDTYPE = -2,    /* unknown dtype, or a dtype the operation does not take   */
+    XTR_EOVERLAP = -3,  /* src and dst byte ranges overlap (transpose is out-of-place) */
+    XTR_EALIGN = -4,    /* a pointer is not aligned to its element size             */
+    XTR_EHIP = -5,      /* a HIP runtime call failed                               */
+    XTR_ENOMEM = -6,    /* workspace allocation failed                             */
+    XTR_EBUDGET = -7    /* caller workspace too small                              */
+};
+
+/* ------------------------------------------------------------------------
+ * tpose — out-of-place transpose (Listing 3.5; tiled form Listings 3.8/3.10).
+ *
+ *   dst[c*ld_dst + r] = src[r*ld_src + c]   for 0 <= r < rows, 0 <= c < cols
+ *
+ * src: rows x cols, row-major, leading dimension ld_src >= max(cols, 1).
+ * dst: cols x rows, row-major, leading dimension ld_dst >= max(rows, 1).
+ * The copy is of element bits (NaN payloads, -0.0 survive).  Elements of dst
+ * in columns [rows, ld_dst) of each dst row are not written.
+ * rows == 0 or cols == 0 is a no-op returning XTR_OK.
+ * Any alignment of src/dst (to the element size) and any ld is accepted; the
+ * 16-byte vector path is used when src, dst, ld_src*elem and ld_dst*elem are
+ * 16-byte aligned, and an element-wise path (same result) otherwise.
+ * Errors: EINVAL (null, negative, small ld), EDTYPE, EOVERLAP, EALIGN.
+ */
+int tpose(const void *src, void *dst, int64_t rows, int64_t cols,
+          int64_t ld_src, int64_t ld_dst, int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * reduce_sum — sum of n elements (Listing 2.1; reduce_sum of Section 2.1).
+ *
+ * out: for F32/F16/BF16/F8E4M3 a device double*, for I32/I64 a device int64_t*.
+ *   - Integers: exact int64 sum for I32; sum modulo 2^64 for I64.  Bit-exact
+ *     and independent of order.
+ *   - Floats: elements are decoded exactly to fp32 and accumulated in fp32
+ *     pairs (s, c) with an error-free two-sum per element (compensated,
+ *     Neumaier style); pairs are combined with the same pair arithmetic
+ *     across lanes and waves; the per-workgroup pairs are combined in fp64
+ *     in a fixed order.  The result is a deterministic function of
+ *     (data, n, dtype, src alignment).  NaN in -> NaN out; +inf and -inf ->
+ *     NaN; a single-signed inf -> that inf.  The domain is |partial sums| <
+ *     FLT_MAX (the fp32 accumulators overflow to inf beyond it).
+ * n == 0 writes 0.  Uses library workspace (per device/stream); see
+ * reduce_sum_ws for a caller-provided one.
+ * Errors: EINVAL, EDTYPE, EALIGN, ENOMEM, EHIP.
+ */
+int reduce_sum(const void *src, int64_t n, void *out, int dtype, void *stream);
+
+/* Same reduction structure with plain (uncompensated) fp32 adds at every
+ * level and an fp32 grid combine; writes one float.  Float dtypes only.  It
+ * is the comparator that shows what the compensation buys. */
+int reduce_sum_plain_f32(const void *src, int64_t n, float *out, int dtype, void *stream);
+
+/* Workspace bytes reduce_sum_ws needs for (n, dtype). */
+size_t xtr_reduce_workspace_bytes(int64_t n, int dtype);
+
+/* reduce_sum with caller-owned device workspace `ws` of `ws_bytes` bytes
+ * (>= xtr_reduce_workspace_bytes(n, dtype)).  The workspace must be zeroed
+ * before its first use; every call leaves its ticket counters at zero again,
+ * so the workspace can be reused by later calls on the same stream without
+ * clearing.  Calls that share one workspace must not overlap in time.  Errors
+ * as reduce_sum, plus EBUDGET when ws_bytes is too small. */
+int reduce_sum_ws(const void *src, int64_t n, void *out, int dtype,
+                  void *ws, size_t ws_bytes, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batched and segmented forms (one persistent launch per batch).
+ */
+typedef struct {
+    const void *src;   /* device */
+    void *dst;         /* device */
+    int64_t rows, cols, ld_src, ld_dst;
+    int32_t dtype, _pad;
+} xtr_tpose_desc;
+
+/* Transposes descs[0..count) (host array), each as tpose().  Jobs are grouped
+ * by element size; each group runs as one persistent launch whose workgroups
+ * stride over the concatenated tile space of its jobs.  count == 0 is a no-op.
+ * Every descriptor is validated before anything is enqueued.  dst ranges of
+ * different jobs must not overlap each other or any src. */
+int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream);
+
+/* Sum of each CSR segment: segment i is src[offsets[i] .. offsets[i+1]).
+ * offsets: device int64_t[nseg + 1], non-decreasing, offsets[0] >= 0.
+ * out: device double[nseg] (float dtypes) or int64_t[nseg] (integer dtypes).
+ * Empty segments give 0.  Each segment is reduced with exactly the chunking
+ * and combine order of reduce_sum on that segment alone, so the result equals
+ * reduce_sum(src + offsets[i], len_i) bit for bit.
+ * This entry point reads offsets[nseg] back to the host (a blocking 8-byte
+ * copy) to size its chunk space; reduce_sum_segmented_ws takes the total from
+ * the caller and stays fully asynchronous.
+ * Invalid tables (a decreasing pair, or lengths summing to more than
+ * offsets[nseg]) are detected on the device: every output of the call is then
+ * NaN (float dtypes) or 0 (integer dtypes); nothing is read out of the ranges
+ * the table names. */
+int reduce_sum_segmented(const void *src, const int64_t *offsets, int64_t nseg,
+                         void *out, int dtype, void *stream);
+
+/* Workspace bytes reduce_sum_segmented_ws needs for nseg segments holding
+ * total_elems elements in all (total_elems = offsets[nseg] - offsets[0]). */
+size_t xtr_segmented_workspace_bytes(int64_t nseg, int64_t total_elems, int dtype);
+
+/* reduce_sum_segmented with the element total given by the caller and a
+ * caller-owned workspace (zeroed before first use; left reusable, as for
+ * reduce_sum_ws). */
+int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg,
+                            int64_t total_elems, void *out, int dtype, void *ws,
+                            size_t ws_bytes, void *stream);
+
+/* Sums of `count` independent arrays: srcs (host array of device pointers),
+ * ns (host array of lengths), out device double[count] / int64_t[count]. */
+int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count,
+                       void *out, int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Misc.
+ */
+/* Thread-local message describing the last nonzero return on this thread. */
+const char *xtr_last_error(void);
+
+/* Element size of a dtype in bytes, 0 if unknown. */
+int xtr_elem_bytes(int dtype);
+
+/* Library version, (major << 16) | minor. */
+int xtr_version(void);
+
+/* Frees the library's workspaces and staging buffers (the caller must have
+ * synchronized every stream that used them). */
+int xtr_release(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* XTR_H */

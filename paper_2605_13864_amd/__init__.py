@@ -1,0 +1,284 @@
+"""xtr: out-of-place transpose and compensated sum reduction for MI355X (gfx950).
+
+Thin Python binding over the C ABI of ``libxtr.so`` (declared in
+``include/xtr.h``).  Every function here only marshals arguments -- tensor
+data pointers, sizes, the current HIP stream -- and calls the library; all
+work runs in the library's HIP kernels.  There is no fallback: if the library
+is missing or fails to load, ``load()`` raises.
+
+Tensors are torch tensors on the GPU.  Element formats are given by name
+("f32", "f16", "bf16", "f8e4m3", "i32", "i64", "f64", "u8", "u16") or taken
+from the tensor's dtype; raw-bit tensors (e.g. uint16 holding bf16 bits) pass
+``dtype=`` explicitly.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libxtr.so")
+
+CODES = {"f32": 0, "f16": 1, "bf16": 2, "f8e4m3": 3, "i32": 4, "i64": 5, "f64": 6,
+         "u8": 7, "u16": 8}
+ELEM_BYTES = {"f32": 4, "f16": 2, "bf16": 2, "f8e4m3": 1, "i32": 4, "i64": 8, "f64": 8,
+              "u8": 1, "u16": 2}
+FLOAT_SUM = ("f32", "f16", "bf16", "f8e4m3")
+INT_SUM = ("i32", "i64")
+ERRORS = {0: "XTR_OK", -1: "XTR_EINVAL", -2: "XTR_EDTYPE", -3: "XTR_EOVERLAP",
+          -4: "XTR_EALIGN", -5: "XTR_EHIP", -6: "XTR_ENOMEM", -7: "XTR_EBUDGET"}
+
+
+class XtrError(RuntimeError):
+    def __init__(self, code: int, fn: str, msg: str):
+        super().__init__(f"{fn} -> {ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class TposeDesc(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("rows", C.c_int64),
+                ("cols", C.c_int64), ("ld_src", C.c_int64), ("ld_dst", C.c_int64),
+                ("dtype", C.c_int32), ("_pad", C.c_int32)]
+
+
+_lib = None
+
+# C signatures of every entry point in include/xtr.h
+_SIGS = {
+    "tpose": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+               C.c_void_p], C.c_int),
+    "reduce_sum": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "reduce_sum_plain_f32": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
+    "xtr_reduce_workspace_bytes": ([C.c_int64, C.c_int], C.c_size_t),
+    "reduce_sum_ws": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
+                       C.c_void_p], C.c_int),
+    "tpose_batched": ([C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "reduce_sum_segmented": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                              C.c_void_p], C.c_int),
+    "xtr_segmented_workspace_bytes": ([C.c_int64, C.c_int64, C.c_int], C.c_size_t),
+    "reduce_sum_segmented_ws": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                 C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "reduce_sum_batched": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                            C.c_void_p], C.c_int),
+    "xtr_last_error": ([], C.c_char_p),
+    "xtr_elem_bytes": ([C.c_int], C.c_int),
+    "xtr_version": ([], C.c_int),
+    "xtr_release": ([], C.c_int),
+}
+
+
+def load(path: str = LIB_PATH):
+    """Load libxtr.so (once).  torch is imported first so that the process has a
+    single HIP runtime: torch's, which the library then binds to."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    import torch  # noqa: F401  (must precede the library: one HIP runtime per process)
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with "
+                          f"`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = C.CDLL(path)
+    for name, (args, res) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _check(rc: int, fn: str):
+    if rc != 0:
+        raise XtrError(rc, fn, (_lib.xtr_last_error() or b"").decode())
+
+
+def _code(dtype) -> int:
+    if isinstance(dtype, int):
+        return dtype
+    return CODES[dtype]
+
+
+def dtype_of(t) -> str:
+    import torch
+    m = {torch.float32: "f32", torch.float16: "f16", torch.bfloat16: "bf16",
+         torch.float8_e4m3fn: "f8e4m3", torch.int32: "i32", torch.int64: "i64",
+         torch.float64: "f64", torch.uint8: "u8", torch.uint16: "u16", torch.int16: "u16",
+         torch.int8: "u8"}
+    if t.dtype not in m:
+        raise TypeError(f"unsupported tensor dtype {t.dtype}")
+    return m[t.dtype]
+
+
+def _stream(stream):
+    import torch
+    if stream is None:
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if hasattr(stream, "cuda_stream"):
+        return C.c_void_p(stream.cuda_stream)
+    return C.c_void_p(int(stream))
+
+
+# ---------------------------------------------------------------- transpose
+
+def tpose(src, out=None, *, rows=None, cols=None, ld_src=None, ld_dst=None, dtype=None,
+          stream=None):
+    """out[c, r] = src[r, c].  ``src`` is a 2-D tensor (any row stride with unit
+    column stride) or a flat buffer with explicit rows/cols/ld_src; ``out``
+    defaults to a new contiguous (cols, rows) tensor."""
+    import torch
+    lib = load()
+    dt = dtype or dtype_of(src)
+    if rows is None:
+        assert src.dim() == 2 and (src.stride(1) == 1 or src.shape[1] <= 1)
+        rows, cols = src.shape
+        ld_src = src.stride(0) if rows > 1 else max(cols, 1)
+    if ld_src is None:
+        ld_src = cols
+    if out is None:
+        out = torch.empty((cols, rows), dtype=src.dtype, device=src.device)
+    if ld_dst is None:
+        if out.dim() == 2:
+            assert out.stride(1) == 1 or out.shape[1] <= 1
+            ld_dst = out.stride(0) if out.shape[0] > 1 else max(rows, 1)
+        else:
+            ld_dst = rows
+    rc = lib.tpose(C.c_void_p(src.data_ptr()), C.c_void_p(out.data_ptr()), rows, cols, ld_src,
+                   ld_dst, _code(dt), _stream(stream))
+    _check(rc, "tpose")
+    return out
+
+
+def tpose_batched(jobs, *, stream=None):
+    """jobs: list of (src, dst) 2-D tensor pairs, or of dicts with keys
+    src, dst, rows, cols, ld_src, ld_dst, dtype (as tpose)."""
+    lib = load()
+    arr = (TposeDesc * len(jobs))()
+    for i, j in enumerate(jobs):
+        if isinstance(j, dict):
+            s, d = j["src"], j["dst"]
+            rows, cols = j["rows"], j["cols"]
+            lds, ldd = j.get("ld_src", cols), j.get("ld_dst", rows)
+            dt = j.get("dtype") or dtype_of(s)
+        else:
+            s, d = j
+            rows, cols = s.shape
+            lds = s.stride(0) if rows > 1 else max(cols, 1)
+            ldd = d.stride(0) if d.shape[0] > 1 else max(rows, 1)
+            dt = dtype_of(s)
+        arr[i] = TposeDesc(s.data_ptr(), d.data_ptr(), rows, cols, lds, ldd, _code(dt), 0)
+    rc = lib.tpose_batched(C.cast(arr, C.c_void_p), len(jobs), _stream(stream))
+    _check(rc, "tpose_batched")
+
+
+# ---------------------------------------------------------------- sums
+
+def _sum_out(dt, device, count=None):
+    import torch
+    shape = () if count is None else (count,)
+    if dt in INT_SUM:
+        return torch.empty(shape, dtype=torch.int64, device=device)
+    return torch.empty(shape, dtype=torch.float64, device=device)
+
+
+def reduce_sum(src, out=None, *, n=None, dtype=None, stream=None):
+    """Sum of the elements of a contiguous tensor: a 0-d float64 tensor for
+    float formats, int64 for int32/int64."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    n = src.numel() if n is None else n
+    if out is None:
+        out = _sum_out(dt, src.device)
+    rc = lib.reduce_sum(C.c_void_p(src.data_ptr()), n, C.c_void_p(out.data_ptr()), _code(dt),
+                        _stream(stream))
+    _check(rc, "reduce_sum")
+    return out
+
+
+def reduce_sum_plain_f32(src, out=None, *, n=None, dtype=None, stream=None):
+    """Uncompensated fp32 comparator: a 0-d float32 tensor."""
+    import torch
+    lib = load()
+    dt = dtype or dtype_of(src)
+    n = src.numel() if n is None else n
+    if out is None:
+        out = torch.empty((), dtype=torch.float32, device=src.device)
+    rc = lib.reduce_sum_plain_f32(C.c_void_p(src.data_ptr()), n, C.c_void_p(out.data_ptr()),
+                                  _code(dt), _stream(stream))
+    _check(rc, "reduce_sum_plain_f32")
+    return out
+
+
+def reduce_workspace_bytes(n: int, dtype) -> int:
+    return int(load().xtr_reduce_workspace_bytes(n, _code(dtype)))
+
+
+def reduce_sum_ws(src, ws, out=None, *, n=None, dtype=None, stream=None):
+    """reduce_sum with a caller-owned zero-initialised device workspace tensor."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    n = src.numel() if n is None else n
+    if out is None:
+        out = _sum_out(dt, src.device)
+    rc = lib.reduce_sum_ws(C.c_void_p(src.data_ptr()), n, C.c_void_p(out.data_ptr()), _code(dt),
+                           C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                           _stream(stream))
+    _check(rc, "reduce_sum_ws")
+    return out
+
+
+def reduce_sum_segmented(src, offsets, out=None, *, dtype=None, stream=None):
+    """Per-segment sums; ``offsets`` is a device int64 tensor of nseg+1 entries."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    nseg = offsets.numel() - 1
+    if out is None:
+        out = _sum_out(dt, src.device, nseg)
+    rc = lib.reduce_sum_segmented(C.c_void_p(src.data_ptr()), C.c_void_p(offsets.data_ptr()),
+                                  nseg, C.c_void_p(out.data_ptr()), _code(dt), _stream(stream))
+    _check(rc, "reduce_sum_segmented")
+    return out
+
+
+def segmented_workspace_bytes(nseg: int, total: int, dtype) -> int:
+    return int(load().xtr_segmented_workspace_bytes(nseg, total, _code(dtype)))
+
+
+def reduce_sum_segmented_ws(src, offsets, total: int, ws, out=None, *, dtype=None, stream=None):
+    """Segmented sums with the element total given (no host read-back) and a
+    caller-owned zero-initialised workspace."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    nseg = offsets.numel() - 1
+    if out is None:
+        out = _sum_out(dt, src.device, nseg)
+    rc = lib.reduce_sum_segmented_ws(C.c_void_p(src.data_ptr()), C.c_void_p(offsets.data_ptr()),
+                                     nseg, total, C.c_void_p(out.data_ptr()), _code(dt),
+                                     C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
+                                     _stream(stream))
+    _check(rc, "reduce_sum_segmented_ws")
+    return out
+
+
+def reduce_sum_batched(srcs, out=None, *, ns=None, dtype=None, stream=None):
+    """Sums of several independent contiguous tensors of one format."""
+    lib = load()
+    count = len(srcs)
+    dt = dtype or (dtype_of(srcs[0]) if count else "f32")
+    if out is None:
+        import torch
+        dev = srcs[0].device if count else torch.device("cuda")
+        out = _sum_out(dt, dev, count)
+    ptrs = (C.c_void_p * count)(*[s.data_ptr() for s in srcs])
+    lens = (C.c_int64 * count)(*[(s.numel() if ns is None else ns[i]) for i, s in enumerate(srcs)])
+    rc = lib.reduce_sum_batched(C.cast(ptrs, C.c_void_p), C.cast(lens, C.c_void_p), count,
+                                C.c_void_p(out.data_ptr()), _code(dt), _stream(stream))
+    _check(rc, "reduce_sum_batched")
+    return out
+
+
+def release():
+    _check(load().xtr_release(), "xtr_release")
+
+
+def version() -> tuple:
+    v = load().xtr_version()
+    return (v >> 16, v & 0xffff)

@@ -1,0 +1,62 @@
+// Internal helpers shared by the HIP translation units of libxtr.so.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+#include "../../include/xtr.h"
+
+namespace xtr {
+
+// ------------------------------------------------------------------ errors
+// Thread-local message for the last nonzero return (xtr_last_error).
+void set_error(const char *fmt, ...);
+int fail(int code, const char *fmt, ...);          // set_error + return code
+int hip_fail(hipError_t e, const char *what);      // XTR_EHIP with HIP's message
+
+#define XTR_HIP(call)                                           \
+    do {                                                        \
+        hipError_t e_ = (call);                                 \
+        if (e_ != hipSuccess) return ::xtr::hip_fail(e_, #call); \
+    } while (0)
+
+inline int elem_bytes(int dtype) {
+    switch (dtype) {
+    case XTR_F32: case XTR_I32: return 4;
+    case XTR_F16: case XTR_BF16: case XTR_U16: return 2;
+    case XTR_F8E4M3: case XTR_U8: return 1;
+    case XTR_I64: case XTR_F64: return 8;
+    default: return 0;
+    }
+}
+
+inline bool is_float_sum_dtype(int d) {
+    return d == XTR_F32 || d == XTR_F16 || d == XTR_BF16 || d == XTR_F8E4M3;
+}
+inline bool is_int_sum_dtype(int d) { return d == XTR_I32 || d == XTR_I64; }
+
+// ------------------------------------------------------------------ workspace
+// Library-owned device workspace, one buffer per (kind, device, stream).
+//   WS_REDUCE: zero-filled when (re)allocated; the reduction kernels leave it
+//              zeroed again when they finish (counters, partials).
+//   WS_TABLE:  job/descriptor tables uploaded by the batched entry points.
+// Returns XTR_OK and sets *ptr, or an error code.  Growing a buffer waits for
+// the stream (the old buffer may still be in use by enqueued work).
+enum { WS_REDUCE = 0, WS_TABLE = 1, WS_KINDS = 2 };
+int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr);
+
+// Asynchronous host -> device copy of `bytes` from pageable `host` memory:
+// the bytes are first copied into a ring of pinned staging buffers owned by
+// the library (so the caller may reuse `host` at once and the copy does not
+// block on earlier work in the stream), then copied with hipMemcpyAsync.
+int upload(const void *host, size_t bytes, void *dev, hipStream_t stream);
+
+// Zero-fill `bytes` (multiple of 4) at device pointer p on stream (a fill
+// kernel, not a memset node, so the sequence is safe to capture in graphs).
+int zero_fill(void *p, size_t bytes, hipStream_t stream);
+
+// Number of compute units of the current device (cached).
+int cu_count();
+
+}  // namespace xtr

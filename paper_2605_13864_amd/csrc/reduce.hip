@@ -1,0 +1,857 @@
+// Tree-based sum reduction for gfx950 (single, batched, segmented).
+//
+// What is computed: the sequential reduce of Listing 2.1, i.e. its
+// specification reduce_sum(n, A) = A(0) + ... + A(n-1) (Section 2.1), for
+// int32 / int64 (exact, modulo 2^64 for int64) and for fp32 / bf16 / fp16 /
+// fp8-e4m3fn inputs (compensated fp32 accumulation, fp64 only in the final
+// cross-workgroup combine).
+//
+// Structure (the split of Listing 2.2 into partial sums and a combine, with the
+// register accumulator and the halving tree of Section 7.2 / Listing 7.22):
+//   1. Canonical chunking.  A range (ptr, n) is split into a head of at most
+//      V-1 elements up to the first 16-byte boundary, then chunks of
+//      CH = 256 threads x U vectors x V elements.  Every chunk is reduced by
+//      one workgroup of 256 threads (4 wave64s).
+//   2. Thread level: U 16-byte vector loads per thread (vector u of thread t is
+//      vector u*256 + t of the chunk, so each wave-level load reads 1 KiB of
+//      contiguous HBM), decoded to fp32 and accumulated in registers: four
+//      independent (s, c) pairs per thread updated with an error-free two-sum
+//      (Knuth) per element, so the rounding error of every addition is kept
+//      in c.  fp8-e4m3fn takes a shortcut that is exact: every e4m3 value is a
+//      multiple of 2^-9 of magnitude <= 448, so an fp32 sum of up to 73 of them
+//      stays an exact multiple of 2^-9 below 2^15; each accumulator sums at most
+//      47 per chunk exactly and the pair starts from that exact value.
+//      Integers accumulate in 64-bit registers (wrap-around adds).
+//   3. Wave level: a 64-lane butterfly of pair additions built from DPP
+//      (quad_perm xor 1, xor 2; row_half_mirror and row_mirror on data already
+//      uniform across the quad / half-row) and readlane for the four rows.
+//   4. Workgroup level: one LDS slot per wave, a barrier, and the pairwise
+//      combine ((w0 + w1) + (w2 + w3)).
+//   5. Grid level: each chunk's pair becomes one fp64 partial (s + c, exact);
+//      partials are combined in fp64 by a radix-256 tree: the last workgroup
+//      of every group of 256 chunks (atomic ticket) sums the group with a
+//      fixed pairwise tree and passes the result one level up.  The order is
+//      fixed, so the result is a deterministic function of (data, n, dtype,
+//      alignment of ptr) -- the same alone, batched or as a segment.
+// The plain mode repeats the structure with uncompensated fp32 adds
+// everywhere (comparator).
+#include "common.hpp"
+
+#include <vector>
+
+#pragma clang fp contract(off)
+
+namespace xtr {
+namespace {
+
+constexpr int NT = 256;          // threads per workgroup
+constexpr int NW = NT / 64;      // waves per workgroup
+constexpr int U = 8;             // 16-byte vectors per thread per chunk
+constexpr int RADIX = 256;       // fan-in of the grid combine tree
+constexpr int MAXLEV = 5;
+
+enum Mode { COMP = 0, PLAIN = 1, INTM = 2 };
+
+template <int DT> struct DTI;
+template <> struct DTI<XTR_F32>    { static constexpr int EB = 4; };
+template <> struct DTI<XTR_F16>    { static constexpr int EB = 2; };
+template <> struct DTI<XTR_BF16>   { static constexpr int EB = 2; };
+template <> struct DTI<XTR_F8E4M3> { static constexpr int EB = 1; };
+template <> struct DTI<XTR_I32>    { static constexpr int EB = 4; };
+template <> struct DTI<XTR_I64>    { static constexpr int EB = 8; };
+
+template <int DT> constexpr int vec_elems() { return 16 / DTI<DT>::EB; }
+template <int DT> constexpr int64_t chunk_elems() { return (int64_t)NT * U * vec_elems<DT>(); }
+
+int64_t chunk_elems_rt(int dtype) { return (int64_t)NT * U * (16 / elem_bytes(dtype)); }
+
+// ---------------------------------------------------------------- arithmetic
+
+struct Pair {
+    float s, c;
+};
+
+// Knuth's two-sum: s + e == a + b exactly (round-to-nearest, no FMA involved).
+__device__ __forceinline__ void two_sum(float a, float b, float &s, float &e) {
+    s = a + b;
+    const float bb = s - a;
+    e = (a - (s - bb)) + (b - bb);
+}
+
+__device__ __forceinline__ Pair pair_add(Pair x, Pair y) {
+    Pair r;
+    float e;
+    two_sum(x.s, y.s, r.s, e);
+    r.c = (x.c + y.c) + e;
+    return r;
+}
+
+// fp64 value of a compensated pair; a non-finite s carries the IEEE result of
+// the exact sum (inf or NaN) and c is ignored (it is NaN after an inf).
+__device__ __forceinline__ double pair_value(Pair p) {
+    if (!__builtin_isfinite(p.s)) return (double)p.s;
+    return (double)p.s + (double)p.c;
+}
+
+// ---------------------------------------------------------------- cross-lane
+
+template <int CTRL> __device__ __forceinline__ uint32_t dpp(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+template <int CTRL> __device__ __forceinline__ float dppf(float v) {
+    return __uint_as_float(dpp<CTRL>(__float_as_uint(v)));
+}
+template <int CTRL> __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    return (uint64_t)dpp<CTRL>((uint32_t)v) | ((uint64_t)dpp<CTRL>((uint32_t)(v >> 32)) << 32);
+}
+__device__ __forceinline__ float readlane_f(float v, int lane) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), lane));
+}
+__device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
+    return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane) |
+           ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane) << 32);
+}
+
+constexpr int DPP_XOR1 = 0xB1;        // quad_perm [1,0,3,2]
+constexpr int DPP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15-i within each row of 16
+
+// Symmetric butterfly: after xor1/xor2 the four lanes of a quad hold identical
+// values, so the half-row mirror exchanges whole quads (xor 4); after it the
+// half-rows are uniform and the row mirror exchanges them (xor 8).  Pair
+// addition is commutative bit for bit, so every lane of a row ends with the
+// same row total; the rows are then combined as ((r0 + r1) + (r2 + r3)).
+template <int CTRL> __device__ __forceinline__ Pair dpp_step(Pair p) {
+    Pair o{dppf<CTRL>(p.s), dppf<CTRL>(p.c)};
+    return pair_add(p, o);
+}
+__device__ __forceinline__ Pair wave_reduce(Pair p) {
+    p = dpp_step<DPP_XOR1>(p);
+    p = dpp_step<DPP_XOR2>(p);
+    p = dpp_step<DPP_HALF_MIRROR>(p);
+    p = dpp_step<DPP_MIRROR>(p);
+    Pair r0{readlane_f(p.s, 0), readlane_f(p.c, 0)}, r1{readlane_f(p.s, 16), readlane_f(p.c, 16)};
+    Pair r2{readlane_f(p.s, 32), readlane_f(p.c, 32)}, r3{readlane_f(p.s, 48), readlane_f(p.c, 48)};
+    return pair_add(pair_add(r0, r1), pair_add(r2, r3));
+}
+__device__ __forceinline__ float wave_reduce(float v) {
+    v = v + dppf<DPP_XOR1>(v);
+    v = v + dppf<DPP_XOR2>(v);
+    v = v + dppf<DPP_HALF_MIRROR>(v);
+    v = v + dppf<DPP_MIRROR>(v);
+    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
+}
+__device__ __forceinline__ uint64_t wave_reduce(uint64_t v) {
+    v = v + dpp64<DPP_XOR1>(v);
+    v = v + dpp64<DPP_XOR2>(v);
+    v = v + dpp64<DPP_HALF_MIRROR>(v);
+    v = v + dpp64<DPP_MIRROR>(v);
+    return (readlane_u64(v, 0) + readlane_u64(v, 16)) + (readlane_u64(v, 32) + readlane_u64(v, 48));
+}
+// fp64 butterfly for the grid combine (xor 1 .. 32, a balanced pairwise tree)
+__device__ __forceinline__ double wave_reduce_f64(double v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) v = v + __shfl_xor(v, m, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- per-thread state
+
+template <int DT, int MODE> struct Acc;
+
+// compensated float accumulators
+template <int DT> struct Acc<DT, COMP> {
+    Pair p[4];
+    float g[4];   // fp8: exact fp32 group sums
+    __device__ void init() {
+#pragma unroll
+        for (int a = 0; a < 4; a++) p[a] = Pair{0.f, 0.f}, g[a] = 0.f;
+    }
+    __device__ __forceinline__ void add(int a, float x) {
+        if constexpr (DT == XTR_F8E4M3) {
+            g[a] = g[a] + x;
+        } else {
+            float s, e;
+            two_sum(p[a].s, x, s, e);
+            p[a].s = s;
+            p[a].c = p[a].c + e;
+        }
+    }
+    __device__ Pair finish() {
+        if constexpr (DT == XTR_F8E4M3) {
+#pragma unroll
+            for (int a = 0; a < 4; a++) p[a] = Pair{g[a], 0.f};
+        }
+        return pair_add(pair_add(p[0], p[1]), pair_add(p[2], p[3]));
+    }
+};
+
+// plain fp32 accumulators (comparator)
+template <int DT> struct Acc<DT, PLAIN> {
+    float s[4];
+    __device__ void init() {
+#pragma unroll
+        for (int a = 0; a < 4; a++) s[a] = 0.f;
+    }
+    __device__ __forceinline__ void add(int a, float x) { s[a] = s[a] + x; }
+    __device__ float finish() { return (s[0] + s[1]) + (s[2] + s[3]); }
+};
+
+// 64-bit wrap-around integer accumulators
+template <int DT> struct Acc<DT, INTM> {
+    uint64_t s[2];
+    __device__ void init() { s[0] = s[1] = 0; }
+    __device__ __forceinline__ void add(int a, uint64_t x) { s[a & 1] += x; }
+    __device__ uint64_t finish() { return s[0] + s[1]; }
+};
+
+// ---------------------------------------------------------------- decode
+
+__device__ __forceinline__ float f16_lo(uint32_t d) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(d & 0xffffu));
+}
+__device__ __forceinline__ float f16_hi(uint32_t d) {
+    return (float)__builtin_bit_cast(_Float16, (uint16_t)(d >> 16));
+}
+
+// accumulate element i (0 <= i < V) of a decoded vector into accumulator i % 4
+template <int DT, int MODE>
+__device__ __forceinline__ void acc_vec(Acc<DT, MODE> &acc, const uint4 &v) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    if constexpr (DT == XTR_F32) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc.add(i, __uint_as_float(w[i]));
+    } else if constexpr (DT == XTR_BF16) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            acc.add((2 * k) & 3, __uint_as_float(w[k] << 16));
+            acc.add((2 * k + 1) & 3, __uint_as_float(w[k] & 0xffff0000u));
+        }
+    } else if constexpr (DT == XTR_F16) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            acc.add((2 * k) & 3, f16_lo(w[k]));
+            acc.add((2 * k + 1) & 3, f16_hi(w[k]));
+        }
+    } else if constexpr (DT == XTR_F8E4M3) {
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], false);   // bytes 0, 1
+            auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], true);    // bytes 2, 3
+            acc.add(0, lo[0]);
+            acc.add(1, lo[1]);
+            acc.add(2, hi[0]);
+            acc.add(3, hi[1]);
+        }
+    } else if constexpr (DT == XTR_I32) {
+#pragma unroll
+        for (int i = 0; i < 4; i++) acc.add(i, (uint64_t)(int64_t)(int32_t)w[i]);
+    } else {  // I64
+        acc.add(0, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
+        acc.add(1, (uint64_t)w[2] | ((uint64_t)w[3] << 32));
+    }
+}
+
+// one element at byte address p, as element i of its vector
+template <int DT, int MODE>
+__device__ __forceinline__ void acc_elem(Acc<DT, MODE> &acc, const unsigned char *p, int i) {
+    if constexpr (DT == XTR_F32) {
+        acc.add(i & 3, *reinterpret_cast<const float *>(p));
+    } else if constexpr (DT == XTR_BF16) {
+        acc.add(i & 3, __uint_as_float((uint32_t)*reinterpret_cast<const uint16_t *>(p) << 16));
+    } else if constexpr (DT == XTR_F16) {
+        acc.add(i & 3, f16_lo(*reinterpret_cast<const uint16_t *>(p)));
+    } else if constexpr (DT == XTR_F8E4M3) {
+        auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)(uint32_t)*p, false);
+        acc.add(i & 3, f[0]);
+    } else if constexpr (DT == XTR_I32) {
+        acc.add(i, (uint64_t)(int64_t)*reinterpret_cast<const int32_t *>(p));
+    } else {
+        acc.add(i, *reinterpret_cast<const uint64_t *>(p));
+    }
+}
+
+// ---------------------------------------------------------------- ranges
+
+// One array reduced into out[index].
+struct Range {
+    const unsigned char *ptr;  // first element
+    int64_t n;                 // elements
+    int64_t chunk_base;        // global index of its first chunk (slot base in the level arrays)
+    int64_t nchunks;           // >= 1 (an empty range still has one chunk that writes 0)
+    int64_t index;             // output slot
+    int32_t head;              // elements before the first 16-byte boundary
+    int32_t _pad;
+};
+
+// Level arrays of the grid combine: level l has a partial array and a ticket
+// array, both indexed by chunk_base + (group index at that level).
+struct Levels {
+    unsigned char *part[MAXLEV];
+    uint32_t *ctr[MAXLEV];
+};
+
+template <int MODE> struct PartT;
+template <> struct PartT<COMP> { using T = double; };
+template <> struct PartT<PLAIN> { using T = float; };
+template <> struct PartT<INTM> { using T = uint64_t; };
+
+// ---------------------------------------------------------------- one chunk
+
+template <int DT, int MODE>
+__device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg, int64_t j) {
+    constexpr int EB = DTI<DT>::EB;
+    constexpr int V = vec_elems<DT>();
+    constexpr int64_t CH = chunk_elems<DT>();
+    const int t = threadIdx.x;
+    Acc<DT, MODE> acc;
+    acc.init();
+    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
+    const int64_t body_n = rg.n - rg.head;
+    if (j == 0 && t == 0) {
+        for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
+    }
+    const int64_t e0 = j * CH;
+    if (e0 + CH <= body_n) {
+        const uint4 *vp = reinterpret_cast<const uint4 *>(body + e0 * EB) + t;
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = vp[u * NT];
+#pragma unroll
+        for (int u = 0; u < U; u++) acc_vec(acc, v[u]);
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t e = e0 + (int64_t)(u * NT + t) * V;
+            if (e + V <= body_n) {
+                uint4 v = *reinterpret_cast<const uint4 *>(body + e * EB);
+                acc_vec(acc, v);
+            } else if (e < body_n) {
+                const int m = (int)(body_n - e);
+                // compile-time element index: the accumulators stay in registers
+#pragma unroll
+                for (int i = 0; i < V; i++)
+                    if (i < m) acc_elem(acc, body + (e + i) * EB, i);
+            }
+        }
+    }
+    auto tv = acc.finish();
+    auto wv = wave_reduce(tv);
+    // LDS tree across the waves of the workgroup
+    using W = decltype(wv);
+    __shared__ W slot[NW];
+    const int wave = t >> 6, lane = t & 63;
+    if (lane == 0) slot[wave] = wv;
+    __syncthreads();
+    typename PartT<MODE>::T res;
+    if constexpr (MODE == COMP) {
+        Pair b = pair_add(pair_add(slot[0], slot[1]), pair_add(slot[2], slot[3]));
+        res = pair_value(b);
+    } else {
+        res = (slot[0] + slot[1]) + (slot[2] + slot[3]);
+    }
+    __syncthreads();   // slot[] is reused by the grid combine
+    return res;
+}
+
+// ---------------------------------------------------------------- grid combine
+
+template <int MODE>
+__device__ __forceinline__ typename PartT<MODE>::T block_sum(typename PartT<MODE>::T v) {
+    using P = typename PartT<MODE>::T;
+    __shared__ P sl[NW];
+    P w;
+    if constexpr (MODE == COMP) w = wave_reduce_f64(v);
+    else w = wave_reduce(v);
+    const int t = threadIdx.x;
+    if ((t & 63) == 0) sl[t >> 6] = w;
+    __syncthreads();
+    P r = (sl[0] + sl[1]) + (sl[2] + sl[3]);
+    __syncthreads();
+    return r;
+}
+
+template <int MODE>
+__device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T value,
+                             const Levels &lv, void *out) {
+    using P = typename PartT<MODE>::T;
+    __shared__ int s_last;
+    const int t = threadIdx.x;
+    int64_t idx = j, cnt = rg.nchunks;
+    for (int level = 0;; level++) {
+        if (cnt == 1) {
+            if (t == 0) reinterpret_cast<P *>(out)[rg.index] = value;
+            return;
+        }
+        const int64_t g = idx / RADIX;
+        const int64_t gsize = (cnt - g * RADIX) < RADIX ? (cnt - g * RADIX) : RADIX;
+        P *part = reinterpret_cast<P *>(lv.part[level]);
+        uint32_t *ctr = lv.ctr[level];
+        if (t == 0) {
+            part[rg.chunk_base + idx] = value;
+            __threadfence();   // release the partial before taking a ticket
+            uint32_t old = __hip_atomic_fetch_add(&ctr[rg.chunk_base + g], 1u, __ATOMIC_ACQ_REL,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            s_last = (old == (uint32_t)(gsize - 1));
+        }
+        __syncthreads();
+        const int last = s_last;
+        __syncthreads();
+        if (!last) return;
+        __threadfence();       // acquire: every partial of the group is visible
+        P v = (t < gsize) ? part[rg.chunk_base + g * RADIX + t] : (P)0;
+        value = block_sum<MODE>(v);
+        if (t == 0) ctr[rg.chunk_base + g] = 0u;   // leave the workspace zeroed
+        idx = g;
+        cnt = (cnt + RADIX - 1) / RADIX;
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+// Single range (reduce_sum): one workgroup per chunk.
+template <int DT, int MODE>
+__global__ void __launch_bounds__(NT) k_reduce_one(Range rg, Levels lv, void *out) {
+    const int64_t j = blockIdx.x;
+    auto v = reduce_chunk<DT, MODE>(rg, j);
+    grid_combine<MODE>(rg, j, v, lv, out);
+}
+
+// Many ranges from a host-built table (reduce_sum_batched): workgroup b takes
+// global chunk b and finds its range by binary search over chunk_base.
+template <int DT, int MODE>
+__global__ void __launch_bounds__(NT) k_reduce_table(const Range *__restrict__ tab, int nr,
+                                                     Levels lv, void *out) {
+    const int64_t b = blockIdx.x;
+    int lo = 0, hi = nr - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (tab[mid].chunk_base <= b) lo = mid; else hi = mid - 1;
+    }
+    const Range rg = tab[lo];
+    const int64_t j = b - rg.chunk_base;
+    if (j >= rg.nchunks) return;
+    auto v = reduce_chunk<DT, MODE>(rg, j);
+    grid_combine<MODE>(rg, j, v, lv, out);
+}
+
+// ---------------------------------------------------------------- segmented
+
+// Segment geometry, identical to the host-side one used for single ranges.
+__device__ __forceinline__ Range seg_range(const unsigned char *src, const int64_t *off, int64_t s,
+                                           int eb, int64_t ch) {
+    int64_t lo = off[s], hi = off[s + 1];
+    if (hi < lo) hi = lo;   // a decreasing pair reads as empty here; k_seg_count flags it
+    Range r;
+    r.ptr = src + lo * eb;
+    r.n = hi - lo;
+    const int mis = (int)((uintptr_t)r.ptr & 15);
+    int head = mis ? (16 - mis) / eb : 0;
+    if (head > r.n) head = (int)r.n;
+    r.head = head;
+    const int64_t body = r.n - head;
+    r.nchunks = body > 0 ? (body + ch - 1) / ch : 1;
+    r.index = s;
+    r.chunk_base = 0;
+    r._pad = 0;
+    return r;
+}
+
+// Pass 1: chunk count of every segment, and per-block totals.
+__global__ void __launch_bounds__(NT) k_seg_count(const unsigned char *src, const int64_t *off,
+                                                  int64_t nseg, int eb, int64_t ch,
+                                                  int64_t *counts, int64_t *block_tot) {
+    __shared__ int64_t sh[NW];
+    const int64_t base = (int64_t)blockIdx.x * NT * 4;
+    int64_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int64_t s = base + k * NT + threadIdx.x;
+        if (s < nseg) {
+            int64_t c = seg_range(src, off, s, eb, ch).nchunks;
+            // a decreasing pair or a negative start poisons the total so that
+            // the reduction kernel sees it exceed the chunk space (invalid table)
+            if (off[s + 1] < off[s] || off[s] < 0) c = (int64_t)1 << 40;
+            counts[s] = c;
+            sum += c;
+        }
+    }
+    uint64_t w = wave_reduce((uint64_t)sum);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = (int64_t)w;
+    __syncthreads();
+    if (threadIdx.x == 0) block_tot[blockIdx.x] = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+// Pass 2: exclusive scan of the block totals by one workgroup (in place);
+// also writes the grand total after the last block total.
+__global__ void __launch_bounds__(NT) k_seg_scan_blocks(int64_t *block_tot, int64_t nblk) {
+    __shared__ int64_t sh[NT];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nblk; base += NT) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nblk ? block_tot[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < NT; d <<= 1) {   // Hillis-Steele inclusive scan
+            int64_t a = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += a;
+            __syncthreads();
+        }
+        if (i < nblk) block_tot[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[NT - 1];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) block_tot[nblk] = carry;
+}
+
+// Pass 3: chunk_base of every segment and the chunk -> segment map.
+__global__ void __launch_bounds__(NT) k_seg_place(const int64_t *counts, const int64_t *block_tot,
+                                                  int64_t nseg, int64_t cap, int64_t *chunk_base,
+                                                  int32_t *chunk_seg) {
+    __shared__ int64_t sh[NT];
+    const int64_t base = (int64_t)blockIdx.x * NT * 4;
+    const int64_t s0 = base + threadIdx.x * 4;   // this thread's 4 consecutive segments
+    int64_t c[4], tsum = 0;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        c[k] = (s0 + k < nseg) ? counts[s0 + k] : 0;
+        tsum += c[k];
+    }
+    sh[threadIdx.x] = tsum;
+    __syncthreads();
+    for (int d = 1; d < NT; d <<= 1) {
+        int64_t a = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += a;
+        __syncthreads();
+    }
+    int64_t run = block_tot[blockIdx.x] + sh[threadIdx.x] - tsum;
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int64_t s = s0 + k;
+        if (s < nseg) {
+            chunk_base[s] = run;
+            for (int64_t q = 0; q < c[k] && run + q < cap; q++) chunk_seg[run + q] = (int32_t)s;
+            run += c[k];
+        }
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
+        chunk_base[nseg] = block_tot[nblk];
+    }
+}
+
+// Pass 4: one workgroup per global chunk.
+template <int DT, int MODE>
+__global__ void __launch_bounds__(NT) k_reduce_seg(const unsigned char *src, const int64_t *off,
+                                                   const int64_t *chunk_base,
+                                                   const int32_t *chunk_seg, int64_t nseg,
+                                                   int64_t cap, Levels lv, void *out) {
+    const int64_t b = blockIdx.x;
+    const int64_t total = chunk_base[nseg];
+    if (total > cap) {   // invalid offsets table: defined outputs, no reads, no tickets
+        if (b < nseg) {
+            using P = typename PartT<MODE>::T;
+            if constexpr (MODE == INTM) reinterpret_cast<P *>(out)[b] = 0;
+            else reinterpret_cast<P *>(out)[b] = (P)__builtin_nan("");
+        }
+        return;
+    }
+    if (b >= total) return;   // unused tail of the grid
+    const int64_t s = chunk_seg[b];
+    if (s < 0 || s >= nseg) return;
+    Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>());
+    rg.chunk_base = chunk_base[s];
+    const int64_t j = b - rg.chunk_base;
+    if (j < 0 || j >= rg.nchunks) return;
+    auto v = reduce_chunk<DT, MODE>(rg, j);
+    grid_combine<MODE>(rg, j, v, lv, out);
+}
+
+// ---------------------------------------------------------------- host side
+
+int part_bytes(int mode) { return mode == PLAIN ? 4 : 8; }
+
+// Workspace layout for `slots` chunk slots: MAXLEV levels x (partials + tickets).
+size_t levels_bytes(int64_t slots, int mode) {
+    const size_t per = ((size_t)slots * part_bytes(mode) + 255) / 256 * 256 +
+                       ((size_t)slots * 4 + 255) / 256 * 256;
+    return per * MAXLEV;
+}
+
+Levels levels_at(unsigned char *ws, int64_t slots, int mode) {
+    Levels lv;
+    const size_t pb = ((size_t)slots * part_bytes(mode) + 255) / 256 * 256;
+    const size_t cb = ((size_t)slots * 4 + 255) / 256 * 256;
+    for (int l = 0; l < MAXLEV; l++) {
+        lv.part[l] = ws + l * (pb + cb);
+        lv.ctr[l] = reinterpret_cast<uint32_t *>(ws + l * (pb + cb) + pb);
+    }
+    return lv;
+}
+
+Range host_range(const void *p, int64_t n, int dtype, int64_t index) {
+    const int eb = elem_bytes(dtype);
+    const int64_t ch = chunk_elems_rt(dtype);
+    Range r;
+    r.ptr = (const unsigned char *)p;
+    r.n = n;
+    const int mis = (int)((uintptr_t)p & 15);
+    int64_t head = mis ? (16 - mis) / eb : 0;
+    if (head > n) head = n;
+    r.head = (int32_t)head;
+    const int64_t body = n - head;
+    r.nchunks = body > 0 ? (body + ch - 1) / ch : 1;
+    r.chunk_base = 0;
+    r.index = index;
+    r._pad = 0;
+    return r;
+}
+
+int mode_for(int dtype, bool plain) {
+    if (is_int_sum_dtype(dtype)) return INTM;
+    return plain ? PLAIN : COMP;
+}
+
+int check_sum_args(const void *src, int64_t n, const void *out, int dtype, bool plain,
+                   const char *who) {
+    const int eb = elem_bytes(dtype);
+    if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype))
+        return fail(XTR_EDTYPE, "%s: dtype %d is not summable", who, dtype);
+    if (plain && !is_float_sum_dtype(dtype))
+        return fail(XTR_EDTYPE, "%s: plain fp32 comparator takes float dtypes only", who);
+    if (n < 0) return fail(XTR_EINVAL, "%s: negative n", who);
+    if (!out) return fail(XTR_EINVAL, "%s: null out", who);
+    if (n > 0 && !src) return fail(XTR_EINVAL, "%s: null src", who);
+    if ((uintptr_t)src % eb) return fail(XTR_EALIGN, "%s: src not aligned to its element", who);
+    if ((uintptr_t)out % (plain ? 4 : 8)) return fail(XTR_EALIGN, "%s: out misaligned", who);
+    return XTR_OK;
+}
+
+#define XTR_DISPATCH_SUM(DTYPE, MODE, KERNEL, ...)                                           \
+    switch ((DTYPE) * 4 + (MODE)) {                                                          \
+    case XTR_F32 * 4 + COMP: KERNEL<XTR_F32, COMP> __VA_ARGS__; break;                       \
+    case XTR_F16 * 4 + COMP: KERNEL<XTR_F16, COMP> __VA_ARGS__; break;                       \
+    case XTR_BF16 * 4 + COMP: KERNEL<XTR_BF16, COMP> __VA_ARGS__; break;                     \
+    case XTR_F8E4M3 * 4 + COMP: KERNEL<XTR_F8E4M3, COMP> __VA_ARGS__; break;                 \
+    case XTR_F32 * 4 + PLAIN: KERNEL<XTR_F32, PLAIN> __VA_ARGS__; break;                     \
+    case XTR_F16 * 4 + PLAIN: KERNEL<XTR_F16, PLAIN> __VA_ARGS__; break;                     \
+    case XTR_BF16 * 4 + PLAIN: KERNEL<XTR_BF16, PLAIN> __VA_ARGS__; break;                   \
+    case XTR_F8E4M3 * 4 + PLAIN: KERNEL<XTR_F8E4M3, PLAIN> __VA_ARGS__; break;               \
+    case XTR_I32 * 4 + INTM: KERNEL<XTR_I32, INTM> __VA_ARGS__; break;                       \
+    case XTR_I64 * 4 + INTM: KERNEL<XTR_I64, INTM> __VA_ARGS__; break;                       \
+    default: return fail(XTR_EDTYPE, "internal: no kernel for dtype %d mode %d", DTYPE, MODE); \
+    }
+
+template <int DT, int MODE>
+void launch_one(const Range &rg, const Levels &lv, void *out, hipStream_t st) {
+    hipLaunchKernelGGL((k_reduce_one<DT, MODE>), dim3((unsigned)rg.nchunks), dim3(NT), 0, st, rg, lv,
+                       out);
+}
+template <int DT, int MODE>
+void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, void *out,
+                  hipStream_t st) {
+    hipLaunchKernelGGL((k_reduce_table<DT, MODE>), dim3((unsigned)nchunks), dim3(NT), 0, st, tab, nr,
+                       lv, out);
+}
+template <int DT, int MODE>
+void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const int32_t *cs,
+                int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
+    const int64_t grid = cap > nseg ? cap : nseg;
+    hipLaunchKernelGGL((k_reduce_seg<DT, MODE>), dim3((unsigned)grid), dim3(NT), 0, st, src, off, cb,
+                       cs, nseg, cap, lv, out);
+}
+
+int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *ws,
+            size_t ws_bytes, hipStream_t st, const char *who) {
+    int rc = check_sum_args(src, n, out, dtype, plain, who);
+    if (rc) return rc;
+    const int mode = mode_for(dtype, plain);
+    Range rg = host_range(src, n, dtype, 0);
+    if (rg.nchunks > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: n too large", who);
+    const size_t need = levels_bytes(rg.nchunks, mode);
+    if (!ws) {
+        rc = workspace(WS_REDUCE, st, need, &ws);
+        if (rc) return rc;
+    } else if (ws_bytes < need) {
+        return fail(XTR_EBUDGET, "%s: workspace %zu bytes < %zu needed", who, ws_bytes, need);
+    }
+    Levels lv = levels_at((unsigned char *)ws, rg.nchunks, mode);
+    XTR_DISPATCH_SUM(dtype, mode, launch_one, (rg, lv, out, st));
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+}  // namespace
+
+size_t reduce_ws_bytes(int64_t n, int dtype, bool plain) {
+    if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype)) return 0;
+    if (n < 0) return 0;
+    Range rg = host_range((const void *)0, n, dtype, 0);
+    return levels_bytes(rg.nchunks, mode_for(dtype, plain));
+}
+
+int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
+                     int dtype, hipStream_t st) {
+    if (count < 0) return fail(XTR_EINVAL, "reduce_sum_batched: negative count");
+    if (count == 0) return XTR_OK;
+    if (!srcs || !ns) return fail(XTR_EINVAL, "reduce_sum_batched: null host array");
+    std::vector<Range> tab((size_t)count);
+    int64_t total = 0;
+    for (int64_t i = 0; i < count; i++) {
+        int rc = check_sum_args(srcs[i], ns[i], out, dtype, false, "reduce_sum_batched");
+        if (rc) {
+            set_error("reduce_sum_batched: job %lld: %s", (long long)i, xtr_last_error());
+            return rc;
+        }
+        tab[i] = host_range(srcs[i], ns[i], dtype, i);
+        tab[i].chunk_base = total;
+        total += tab[i].nchunks;
+    }
+    if (total > 0x7fffffffLL) return fail(XTR_EINVAL, "reduce_sum_batched: too many chunks");
+    const int mode = mode_for(dtype, false);
+    void *ws = nullptr, *tw = nullptr;
+    int rc = workspace(WS_REDUCE, st, levels_bytes(total, mode), &ws);
+    if (rc) return rc;
+    rc = workspace(WS_TABLE, st, tab.size() * sizeof(Range), &tw);
+    if (rc) return rc;
+    rc = upload(tab.data(), tab.size() * sizeof(Range), tw, st);
+    if (rc) return rc;
+    Levels lv = levels_at((unsigned char *)ws, total, mode);
+    XTR_DISPATCH_SUM(dtype, mode, launch_table, ((const Range *)tw, (int)count, total, lv, out, st));
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+// Segmented workspace: counts, chunk_base (nseg+1), block totals, chunk map, levels.
+struct SegLayout {
+    size_t counts, cbase, btot, cmap, levels, total;
+};
+SegLayout seg_layout(int64_t nseg, int64_t cap, int mode) {
+    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+    const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
+    SegLayout L;
+    L.counts = 0;
+    L.cbase = L.counts + al((size_t)nseg * 8);
+    L.btot = L.cbase + al((size_t)(nseg + 1) * 8);
+    L.cmap = L.btot + al((size_t)(nblk + 1) * 8);
+    L.levels = L.cmap + al((size_t)cap * 4);
+    L.total = L.levels + levels_bytes(cap, mode);
+    return L;
+}
+
+size_t seg_ws_bytes(int64_t nseg, int64_t total_elems, int dtype) {
+    if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype)) return 0;
+    if (nseg < 0 || total_elems < 0) return 0;
+    const int64_t cap = nseg + (total_elems + chunk_elems_rt(dtype) - 1) / chunk_elems_rt(dtype);
+    return seg_layout(nseg, cap, mode_for(dtype, false)).total;
+}
+
+int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, void *out,
+                       int dtype, void *ws, size_t ws_bytes, int64_t total_elems,
+                       hipStream_t st) {
+    const char *who = "reduce_sum_segmented";
+    if (nseg < 0) return fail(XTR_EINVAL, "%s: negative nseg", who);
+    if (nseg == 0) return XTR_OK;
+    if (!offsets || !out) return fail(XTR_EINVAL, "%s: null offsets or out", who);
+    int rc = check_sum_args(src, 0, out, dtype, false, who);
+    if (rc) return rc;
+    if (!src) return fail(XTR_EINVAL, "%s: null src", who);
+    if ((uintptr_t)offsets % 8) return fail(XTR_EALIGN, "%s: offsets misaligned", who);
+    if (nseg > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: too many segments", who);
+    if (total_elems < 0) {   // read offsets[nseg] back to size the chunk space
+        XTR_HIP(hipMemcpyAsync(&total_elems, offsets + nseg, 8, hipMemcpyDeviceToHost, st));
+        XTR_HIP(hipStreamSynchronize(st));
+        if (total_elems < 0) return fail(XTR_EINVAL, "%s: offsets[nseg] < 0", who);
+    }
+    const int mode = mode_for(dtype, false);
+    const int eb = elem_bytes(dtype);
+    const int64_t ch = chunk_elems_rt(dtype);
+    // Each segment has max(1, ceil(body / ch)) chunks, body <= its length, and
+    // lengths (after clamping decreasing pairs to 0) sum to at most offsets[nseg]
+    // minus offsets[0]; so nseg + ceil(total / ch) bounds the chunk space.
+    const int64_t cap = nseg + (total_elems + ch - 1) / ch;
+    if (cap > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: chunk space too large", who);
+    const SegLayout L = seg_layout(nseg, cap, mode);
+    if (!ws) {
+        rc = workspace(WS_REDUCE, st, L.total, &ws);
+        if (rc) return rc;
+    } else if (ws_bytes < L.total) {
+        return fail(XTR_EBUDGET, "%s: workspace %zu bytes < %zu needed", who, ws_bytes, L.total);
+    }
+    unsigned char *w = (unsigned char *)ws;
+    int64_t *counts = (int64_t *)(w + L.counts), *cbase = (int64_t *)(w + L.cbase);
+    int64_t *btot = (int64_t *)(w + L.btot);
+    int32_t *cmap = (int32_t *)(w + L.cmap);
+    const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NT), 0, st,
+                       (const unsigned char *)src, offsets, nseg, eb, ch, counts, btot);
+    hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NT), 0, st, btot, nblk);
+    hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NT), 0, st, (const int64_t *)counts,
+                       (const int64_t *)btot, nseg, cap, cbase, cmap);
+    XTR_HIP(hipGetLastError());
+    Levels lv = levels_at(w + L.levels, cap, mode);
+    XTR_DISPATCH_SUM(dtype, mode, launch_seg,
+                     ((const unsigned char *)src, offsets, (const int64_t *)cbase,
+                      (const int32_t *)cmap, nseg, cap, lv, out, st));
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+int sum_one_impl(const void *src, int64_t n, void *out, int dtype, bool plain, void *ws,
+                 size_t ws_bytes, hipStream_t st, const char *who) {
+    return sum_one(src, n, out, dtype, plain, ws, ws_bytes, st, who);
+}
+
+}  // namespace xtr
+
+extern "C" {
+
+int reduce_sum(const void *src, int64_t n, void *out, int dtype, void *stream) {
+    return xtr::sum_one_impl(src, n, out, dtype, false, nullptr, 0, (hipStream_t)stream,
+                             "reduce_sum");
+}
+
+int reduce_sum_plain_f32(const void *src, int64_t n, float *out, int dtype, void *stream) {
+    return xtr::sum_one_impl(src, n, out, dtype, true, nullptr, 0, (hipStream_t)stream,
+                             "reduce_sum_plain_f32");
+}
+
+size_t xtr_reduce_workspace_bytes(int64_t n, int dtype) {
+    return xtr::reduce_ws_bytes(n, dtype, false);
+}
+
+int reduce_sum_ws(const void *src, int64_t n, void *out, int dtype, void *ws, size_t ws_bytes,
+                  void *stream) {
+    if (!ws) return xtr::fail(XTR_EINVAL, "reduce_sum_ws: null workspace");
+    return xtr::sum_one_impl(src, n, out, dtype, false, ws, ws_bytes, (hipStream_t)stream,
+                             "reduce_sum_ws");
+}
+
+int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
+                       int dtype, void *stream) {
+    return xtr::sum_batched_impl(srcs, ns, count, out, dtype, (hipStream_t)stream);
+}
+
+size_t xtr_segmented_workspace_bytes(int64_t nseg, int64_t total_elems, int dtype) {
+    return xtr::seg_ws_bytes(nseg, total_elems, dtype);
+}
+
+int reduce_sum_segmented(const void *src, const int64_t *offsets, int64_t nseg, void *out,
+                         int dtype, void *stream) {
+    return xtr::sum_segmented_impl(src, offsets, nseg, out, dtype, nullptr, 0, -1,
+                                   (hipStream_t)stream);
+}
+
+int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg,
+                            int64_t total_elems, void *out, int dtype, void *ws, size_t ws_bytes,
+                            void *stream) {
+    if (!ws) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws: null workspace");
+    if (total_elems < 0) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws: total < 0");
+    return xtr::sum_segmented_impl(src, offsets, nseg, out, dtype, ws, ws_bytes, total_elems,
+                                   (hipStream_t)stream);
+}
+
+}  // extern "C"

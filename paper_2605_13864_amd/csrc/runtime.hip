@@ -1,0 +1,202 @@
+// Runtime support of libxtr.so: error strings, the per-(device, stream)
+// workspace pool, the zero-fill kernel and the small informational entry
+// points of the C ABI.
+#include "common.hpp"
+
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <utility>
+
+namespace xtr {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+int fail(int code, const char *fmt, ...) {
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    set_error("%s: %s", what, hipGetErrorString(e));
+    return XTR_EHIP;
+}
+
+// ------------------------------------------------------------------ zero fill
+
+__global__ void __launch_bounds__(256) k_zero_fill(uint32_t *p, size_t words) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * 256;
+    for (; i < words; i += stride) p[i] = 0u;
+}
+
+int zero_fill(void *p, size_t bytes, hipStream_t stream) {
+    if (bytes == 0) return XTR_OK;
+    size_t words = (bytes + 3) / 4;
+    size_t blocks = (words + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_zero_fill, dim3((unsigned)blocks), dim3(256), 0, stream,
+                       (uint32_t *)p, words);
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+// ------------------------------------------------------------------ workspace
+
+namespace {
+struct Buf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+struct Key {
+    int kind, dev;
+    hipStream_t stream;
+    bool operator<(const Key &o) const {
+        if (kind != o.kind) return kind < o.kind;
+        if (dev != o.dev) return dev < o.dev;
+        return (uintptr_t)stream < (uintptr_t)o.stream;
+    }
+};
+std::mutex g_mu;
+std::map<Key, Buf> g_ws;
+
+// pinned host staging ring for upload(): RING slots per (device, stream), each
+// guarded by the event recorded after the copy that last read it
+constexpr int RING = 8;
+struct Stage {
+    void *host[RING] = {};
+    size_t bytes[RING] = {};
+    hipEvent_t done[RING] = {};
+    int next = 0;
+};
+std::map<Key, Stage> g_stage;
+}  // namespace
+
+int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr) {
+    int dev = 0;
+    XTR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    Buf &b = g_ws[Key{kind, dev, stream}];
+    if (b.bytes >= bytes && b.ptr) {
+        *ptr = b.ptr;
+        return XTR_OK;
+    }
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    XTR_HIP(hipStreamIsCapturing(stream, &cs));
+    if (cs != hipStreamCaptureStatusNone)
+        return fail(XTR_ENOMEM, "workspace must grow to %zu bytes while the stream is being "
+                    "captured; use the *_ws entry points with a caller-owned workspace", bytes);
+    if (b.ptr) {
+        XTR_HIP(hipStreamSynchronize(stream));   // old buffer may be in use by queued work
+        XTR_HIP(hipFree(b.ptr));
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = bytes < (1u << 20) ? (1u << 20) : bytes + bytes / 4;   // headroom
+    want = (want + 255) & ~size_t(255);
+    hipError_t e = hipMalloc(&b.ptr, want);
+    if (e != hipSuccess) {
+        b.ptr = nullptr;
+        return fail(XTR_ENOMEM, "hipMalloc(%zu) for workspace: %s", want, hipGetErrorString(e));
+    }
+    b.bytes = want;
+    if (kind == WS_REDUCE) {
+        int rc = zero_fill(b.ptr, want, stream);
+        if (rc) return rc;
+    }
+    *ptr = b.ptr;
+    return XTR_OK;
+}
+
+int upload(const void *host, size_t bytes, void *dev_dst, hipStream_t stream) {
+    if (!bytes) return XTR_OK;
+    int dev = 0;
+    XTR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_mu);
+    Stage &st = g_stage[Key{0, dev, stream}];
+    const int slot = st.next;
+    st.next = (st.next + 1) % RING;
+    if (st.done[slot]) XTR_HIP(hipEventSynchronize(st.done[slot]));   // previous reader finished
+    else XTR_HIP(hipEventCreateWithFlags(&st.done[slot], hipEventDisableTiming));
+    if (st.bytes[slot] < bytes) {
+        if (st.host[slot]) XTR_HIP(hipHostFree(st.host[slot]));
+        st.host[slot] = nullptr;
+        size_t want = bytes < 65536 ? 65536 : bytes * 2;
+        hipError_t e = hipHostMalloc(&st.host[slot], want, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            st.host[slot] = nullptr;
+            st.bytes[slot] = 0;
+            return fail(XTR_ENOMEM, "hipHostMalloc(%zu) for staging: %s", want,
+                        hipGetErrorString(e));
+        }
+        st.bytes[slot] = want;
+    }
+    memcpy(st.host[slot], host, bytes);
+    XTR_HIP(hipMemcpyAsync(dev_dst, st.host[slot], bytes, hipMemcpyHostToDevice, stream));
+    XTR_HIP(hipEventRecord(st.done[slot], stream));
+    return XTR_OK;
+}
+
+int cu_count() {
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    if (!cached[dev]) {
+        int n = 0;
+        if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            n <= 0)
+            n = 256;
+        cached[dev] = n;
+    }
+    return cached[dev];
+}
+
+}  // namespace xtr
+
+extern "C" {
+
+const char *xtr_last_error(void) { return xtr::g_err; }
+
+int xtr_elem_bytes(int dtype) { return xtr::elem_bytes(dtype); }
+
+int xtr_version(void) { return (0 << 16) | 1; }
+
+int xtr_release(void) {
+    std::lock_guard<std::mutex> lk(xtr::g_mu);
+    int cur = 0;
+    if (hipGetDevice(&cur) != hipSuccess) cur = 0;
+    for (auto &kv : xtr::g_ws) {
+        if (kv.second.ptr) {
+            (void)hipSetDevice(kv.first.dev);
+            (void)hipFree(kv.second.ptr);
+        }
+    }
+    xtr::g_ws.clear();
+    for (auto &kv : xtr::g_stage) {
+        (void)hipSetDevice(kv.first.dev);
+        for (int i = 0; i < xtr::RING; i++) {
+            if (kv.second.done[i]) {
+                (void)hipEventSynchronize(kv.second.done[i]);
+                (void)hipEventDestroy(kv.second.done[i]);
+            }
+            if (kv.second.host[i]) (void)hipHostFree(kv.second.host[i]);
+        }
+    }
+    xtr::g_stage.clear();
+    (void)hipSetDevice(cur);
+    return XTR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,396 @@
+// Out-of-place transpose for gfx950 (single and batched).
+//
+// What is computed: the sequential transpose of Listing 3.5,
+//     dst[c*ld_dst + r] = src[r*ld_src + c],  0 <= r < rows, 0 <= c < cols,
+// as a copy of element bits.
+//
+// How (tiled form of Listings 3.8 / 3.10): one workgroup of 256 threads moves
+// one TR x TC tile.  Phase 1 loads the tile from HBM with 16-byte vector loads
+// (16 lanes cover one 256-byte row segment, so every wave-level load is four
+// fully used 128-byte lines) and writes it to LDS.  A block barrier then hands
+// ownership of the LDS tile from the loading threads to the storing threads:
+// Section 3.3 places the barrier exactly where tile ownership changes.  Phase 2
+// reads a V x V element block per thread from LDS with 16-byte reads,
+// transposes it in registers, and writes V 16-byte vectors to V consecutive
+// dst rows, again 16 lanes per 256-byte row segment.
+//
+// Differences from the paper's kernels (Listings 3.6 and 6.21), made for CDNA4:
+//  - the tile is 256 x 256 BYTES whatever the element size (fp32 64 x 64,
+//    bf16 128 x 128, fp8 256 x 256, fp64 32 x 32), so both HBM sides move
+//    whole 16-byte vectors and whole cache lines;
+//  - each thread moves V = 16/elem elements per vector and V vectors per phase
+//    (the paper's kernel moves 2 elements per thread, Section 7.2);
+//  - LDS 16-byte chunks are XOR-swizzled per row group so that both the row
+//    writes and the block reads hit distinct bank groups (the paper's 32 x 32
+//    tile is unpadded);
+//  - tile coordinates come from one division per tile, not per element (the
+//    paper attributes its transpose gap to per-thread index arithmetic,
+//    Section 7.2 / Chapter 6).
+// Edge tiles, and matrices whose pointers or leading dimensions are not
+// 16-byte aligned, go through an element-wise path over the same LDS layout.
+#include "common.hpp"
+
+#include <vector>
+
+namespace xtr {
+namespace {
+
+constexpr int NT = 256;   // threads per workgroup
+
+template <int EB> struct Geo {
+    static constexpr int V = 16 / EB;     // elements per 16-byte vector
+    static constexpr int TC = 16 * V;     // tile columns (src) = 256 bytes
+    static constexpr int TR = 16 * V;     // tile rows (src) = 256 bytes of a dst row
+    static constexpr int CHUNKS = 16;     // 16-byte chunks per tile row
+    static constexpr int LDS_VECS = TR * CHUNKS;
+};
+
+template <int EB> struct Elem;
+template <> struct Elem<1> { using T = uint8_t; };
+template <> struct Elem<2> { using T = uint16_t; };
+template <> struct Elem<4> { using T = uint32_t; };
+template <> struct Elem<8> { using T = uint64_t; };
+
+// Physical 16-byte chunk of logical chunk k in tile row `row`.
+template <int EB> __device__ __forceinline__ int swz(int row, int k) {
+    return k ^ ((row / Geo<EB>::V) & 15);
+}
+
+// ---------------------------------------------------------------- register
+// transposes of one V x V element block: a[i] holds src row i (V elements),
+// out[j] receives dst row j = (a[0][j], a[1][j], ..., a[V-1][j]).
+
+__device__ __forceinline__ uint32_t dw(const uint4 &v, int i) {
+    return i == 0 ? v.x : i == 1 ? v.y : i == 2 ? v.z : v.w;
+}
+
+template <int EB> __device__ __forceinline__ void block_transpose(const uint4 *a, uint4 *out);
+
+template <> __device__ __forceinline__ void block_transpose<8>(const uint4 *a, uint4 *out) {
+    out[0] = make_uint4(a[0].x, a[0].y, a[1].x, a[1].y);
+    out[1] = make_uint4(a[0].z, a[0].w, a[1].z, a[1].w);
+}
+
+template <> __device__ __forceinline__ void block_transpose<4>(const uint4 *a, uint4 *out) {
+    out[0] = make_uint4(a[0].x, a[1].x, a[2].x, a[3].x);
+    out[1] = make_uint4(a[0].y, a[1].y, a[2].y, a[3].y);
+    out[2] = make_uint4(a[0].z, a[1].z, a[2].z, a[3].z);
+    out[3] = make_uint4(a[0].w, a[1].w, a[2].w, a[3].w);
+}
+
+// 16-bit elements: dword m of dst row j packs rows 2m (low half) and 2m+1.
+template <> __device__ __forceinline__ void block_transpose<2>(const uint4 *a, uint4 *out) {
+#pragma unroll
+    for (int j = 0; j < 8; j++) {
+        uint32_t d[4];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            uint32_t A = dw(a[2 * m], j >> 1), B = dw(a[2 * m + 1], j >> 1);
+            d[m] = (j & 1) ? ((A >> 16) | (B & 0xffff0000u)) : ((A & 0xffffu) | (B << 16));
+        }
+        out[j] = make_uint4(d[0], d[1], d[2], d[3]);
+    }
+}
+
+// 8-bit elements: byte k of dword m of dst row j is byte (j & 3) of dword
+// (j >> 2) of src row 4m + k -- a 4 x 4 byte transpose per (m, j >> 2).
+__device__ __forceinline__ void byte4x4(uint32_t x0, uint32_t x1, uint32_t x2, uint32_t x3,
+                                        uint32_t *y) {
+    // t0 = [x0.b0 x1.b0 x0.b2 x1.b2], t1 = [x0.b1 x1.b1 x0.b3 x1.b3], same for t2/t3 on x2/x3
+    uint32_t t0 = (x0 & 0x00ff00ffu) | ((x1 & 0x00ff00ffu) << 8);
+    uint32_t t1 = ((x0 >> 8) & 0x00ff00ffu) | (x1 & 0xff00ff00u);
+    uint32_t t2 = (x2 & 0x00ff00ffu) | ((x3 & 0x00ff00ffu) << 8);
+    uint32_t t3 = ((x2 >> 8) & 0x00ff00ffu) | (x3 & 0xff00ff00u);
+    y[0] = (t0 & 0x0000ffffu) | (t2 << 16);
+    y[1] = (t1 & 0x0000ffffu) | (t3 << 16);
+    y[2] = (t0 >> 16) | (t2 & 0xffff0000u);
+    y[3] = (t1 >> 16) | (t3 & 0xffff0000u);
+}
+
+template <> __device__ __forceinline__ void block_transpose<1>(const uint4 *a, uint4 *out) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {          // src dword column -> dst rows 4q .. 4q+3
+        uint32_t y[4][4];                   // y[m][r]: dword m of dst row 4q + r
+#pragma unroll
+        for (int m = 0; m < 4; m++)
+            byte4x4(dw(a[4 * m], q), dw(a[4 * m + 1], q), dw(a[4 * m + 2], q),
+                    dw(a[4 * m + 3], q), y[m]);
+#pragma unroll
+        for (int r = 0; r < 4; r++) out[4 * q + r] = make_uint4(y[0][r], y[1][r], y[2][r], y[3][r]);
+    }
+}
+
+// ---------------------------------------------------------------- one tile
+
+template <int EB>
+__device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
+                                        unsigned char *__restrict__ dst, int64_t rows,
+                                        int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
+                                        int64_t C0, bool vec_ok, uint4 *lds) {
+    using G = Geo<EB>;
+    using T = typename Elem<EB>::T;
+    constexpr int V = G::V;
+    const int t = threadIdx.x;
+    const bool full = vec_ok && (R0 + G::TR <= rows) && (C0 + G::TC <= cols);
+
+    if (full) {
+        // phase 1: 16 lanes per 256-byte row segment, V rows 16 apart per thread
+        const int k = t & 15, r0 = t >> 4;
+        const int64_t ldsb = ld_src * EB;
+        const unsigned char *base = src + (R0 * ld_src + C0) * EB + k * 16;
+        uint4 v[V];
+#pragma unroll
+        for (int p = 0; p < V; p++)
+            v[p] = *reinterpret_cast<const uint4 *>(base + (int64_t)(r0 + 16 * p) * ldsb);
+#pragma unroll
+        for (int p = 0; p < V; p++) {
+            const int row = r0 + 16 * p;
+            lds[row * 16 + swz<EB>(row, k)] = v[p];
+        }
+    } else {
+        const unsigned char *base = src + (R0 * ld_src + C0) * EB;
+        for (int e = t; e < G::TR * G::TC; e += NT) {
+            const int r = e / G::TC, c = e % G::TC;
+            if (R0 + r < rows && C0 + c < cols) {
+                T val = *reinterpret_cast<const T *>(base + ((int64_t)r * ld_src + c) * EB);
+                reinterpret_cast<T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V] = val;
+            }
+        }
+    }
+
+    __syncthreads();   // ownership of the LDS tile moves from loaders to storers
+
+    if (full) {
+        // phase 2: thread owns the V x V block (rows bq*V.., cols bc*V..)
+        const int bq = t & 15, bc = t >> 4;
+        uint4 a[V], o[V];
+#pragma unroll
+        for (int i = 0; i < V; i++) {
+            const int row = bq * V + i;
+            a[i] = lds[row * 16 + swz<EB>(row, bc)];
+        }
+        block_transpose<EB>(a, o);
+        const int64_t lddb = ld_dst * EB;
+        unsigned char *base = dst + ((C0 + bc * V) * ld_dst + R0 + bq * V) * EB;
+#pragma unroll
+        for (int j = 0; j < V; j++) *reinterpret_cast<uint4 *>(base + (int64_t)j * lddb) = o[j];
+    } else {
+        unsigned char *base = dst + (C0 * ld_dst + R0) * EB;
+        for (int e = t; e < G::TR * G::TC; e += NT) {
+            const int c = e / G::TR, r = e % G::TR;   // dst row c of the tile, dst col r
+            if (R0 + r < rows && C0 + c < cols) {
+                T val = reinterpret_cast<const T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V];
+                *reinterpret_cast<T *>(base + ((int64_t)c * ld_dst + r) * EB) = val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------- kernels
+
+template <int EB>
+__global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ src,
+                                              unsigned char *__restrict__ dst, int64_t rows,
+                                              int64_t cols, int64_t ld_src, int64_t ld_dst,
+                                              int64_t tiles_c, int64_t ntiles, int vec_ok) {
+    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+        const int64_t tr = tile / tiles_c, tc = tile - tr * tiles_c;
+        do_tile<EB>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR, tc * Geo<EB>::TC,
+                    vec_ok != 0, lds);
+        __syncthreads();   // LDS is reused by the next tile of this workgroup
+    }
+}
+
+// Device-side job of a batched launch.
+struct Job {
+    const unsigned char *src;
+    unsigned char *dst;
+    int64_t rows, cols, ld_src, ld_dst;
+    int64_t tiles_c;
+    int64_t tile_base;   // first global tile id of this job
+    int32_t vec_ok, _pad;
+};
+
+template <int EB>
+__global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs, int njobs,
+                                                      int64_t ntiles) {
+    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+    __shared__ int s_job;
+    int64_t tile = blockIdx.x;
+    if (tile >= ntiles) return;
+    if (threadIdx.x == 0) {   // binary search for the first job, then walk forward
+        int lo = 0, hi = njobs - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (jobs[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+        }
+        s_job = lo;
+    }
+    __syncthreads();
+    int j = s_job;
+    for (; tile < ntiles; tile += gridDim.x) {
+        while (j + 1 < njobs && jobs[j + 1].tile_base <= tile) j++;
+        const Job &jb = jobs[j];
+        const int64_t local = tile - jb.tile_base;
+        const int64_t tr = local / jb.tiles_c, tc = local - tr * jb.tiles_c;
+        do_tile<EB>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst, tr * Geo<EB>::TR,
+                    tc * Geo<EB>::TC, jb.vec_ok != 0, lds);
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- host side
+
+int check_one(const void *src, const void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+              int64_t ld_dst, int dtype, const char *who) {
+    const int eb = elem_bytes(dtype);
+    if (!eb) return fail(XTR_EDTYPE, "%s: unknown dtype %d", who, dtype);
+    if (rows < 0 || cols < 0) return fail(XTR_EINVAL, "%s: negative size %lld x %lld", who,
+                                          (long long)rows, (long long)cols);
+    if (rows == 0 || cols == 0) return XTR_OK;
+    if (!src || !dst) return fail(XTR_EINVAL, "%s: null pointer", who);
+    if (ld_src < cols || ld_dst < rows)
+        return fail(XTR_EINVAL, "%s: ld_src=%lld < cols=%lld or ld_dst=%lld < rows=%lld", who,
+                    (long long)ld_src, (long long)cols, (long long)ld_dst, (long long)rows);
+    if (((uintptr_t)src | (uintptr_t)dst) % eb)
+        return fail(XTR_EALIGN, "%s: pointer not aligned to the %d-byte element", who, eb);
+    // byte extents of the two operands
+    const uintptr_t s0 = (uintptr_t)src, s1 = s0 + ((rows - 1) * ld_src + cols) * eb;
+    const uintptr_t d0 = (uintptr_t)dst, d1 = d0 + ((cols - 1) * ld_dst + rows) * eb;
+    if (s0 < d1 && d0 < s1) return fail(XTR_EOVERLAP, "%s: src and dst overlap", who);
+    return XTR_OK;
+}
+
+bool vec_aligned(const void *src, const void *dst, int64_t ld_src, int64_t ld_dst, int eb) {
+    return (((uintptr_t)src | (uintptr_t)dst) % 16 == 0) && ((ld_src * eb) % 16 == 0) &&
+           ((ld_dst * eb) % 16 == 0);
+}
+
+template <int EB> int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
+    const int64_t tr = (rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
+    const int64_t tc = (cols + Geo<EB>::TC - 1) / Geo<EB>::TC;
+    if (tiles_c) *tiles_c = tc;
+    return tr * tc;
+}
+
+int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c) {
+    switch (eb) {
+    case 1: return tiles_of<1>(rows, cols, tiles_c);
+    case 2: return tiles_of<2>(rows, cols, tiles_c);
+    case 4: return tiles_of<4>(rows, cols, tiles_c);
+    default: return tiles_of<8>(rows, cols, tiles_c);
+    }
+}
+
+constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs loop
+
+template <int EB>
+int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+               int64_t ld_dst, hipStream_t stream) {
+    int64_t tiles_c = 0;
+    const int64_t ntiles = tiles_of<EB>(rows, cols, &tiles_c);
+    const int vec = vec_aligned(src, dst, ld_src, ld_dst, EB) ? 1 : 0;
+    const int64_t grid = ntiles < MAX_GRID ? ntiles : MAX_GRID;
+    hipLaunchKernelGGL(k_tpose<EB>, dim3((unsigned)grid), dim3(NT), 0, stream,
+                       (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src, ld_dst,
+                       tiles_c, ntiles, vec);
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+}  // namespace
+
+int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+               int64_t ld_dst, int dtype, hipStream_t stream) {
+    int rc = check_one(src, dst, rows, cols, ld_src, ld_dst, dtype, "tpose");
+    if (rc || rows == 0 || cols == 0) return rc;
+    switch (elem_bytes(dtype)) {
+    case 1: return launch_one<1>(src, dst, rows, cols, ld_src, ld_dst, stream);
+    case 2: return launch_one<2>(src, dst, rows, cols, ld_src, ld_dst, stream);
+    case 4: return launch_one<4>(src, dst, rows, cols, ld_src, ld_dst, stream);
+    default: return launch_one<8>(src, dst, rows, cols, ld_src, ld_dst, stream);
+    }
+}
+
+int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t stream) {
+    if (count < 0) return fail(XTR_EINVAL, "tpose_batched: negative count");
+    if (count == 0) return XTR_OK;
+    if (!descs) return fail(XTR_EINVAL, "tpose_batched: null descriptor array");
+    for (int64_t i = 0; i < count; i++) {
+        const xtr_tpose_desc &d = descs[i];
+        int rc = check_one(d.src, d.dst, d.rows, d.cols, d.ld_src, d.ld_dst, d.dtype,
+                           "tpose_batched");
+        if (rc) {
+            set_error("tpose_batched: descriptor %lld: %s", (long long)i, xtr_last_error());
+            return rc;
+        }
+    }
+    // group by element size; one persistent launch per group
+    std::vector<Job> groups[4];
+    int64_t ntiles[4] = {0, 0, 0, 0};
+    for (int64_t i = 0; i < count; i++) {
+        const xtr_tpose_desc &d = descs[i];
+        if (d.rows == 0 || d.cols == 0) continue;
+        const int eb = elem_bytes(d.dtype);
+        const int g = eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3;
+        Job j;
+        j.src = (const unsigned char *)d.src;
+        j.dst = (unsigned char *)d.dst;
+        j.rows = d.rows; j.cols = d.cols; j.ld_src = d.ld_src; j.ld_dst = d.ld_dst;
+        j.tile_base = ntiles[g];
+        ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
+        j.vec_ok = vec_aligned(d.src, d.dst, d.ld_src, d.ld_dst, eb) ? 1 : 0;
+        j._pad = 0;
+        groups[g].push_back(j);
+    }
+    size_t total = 0;
+    for (auto &g : groups) total += g.size();
+    if (!total) return XTR_OK;
+    std::vector<Job> all;
+    all.reserve(total);
+    for (auto &g : groups) all.insert(all.end(), g.begin(), g.end());
+    void *wsp = nullptr;
+    int rc = workspace(WS_TABLE, stream, total * sizeof(Job), &wsp);
+    if (rc) return rc;
+    Job *dev = (Job *)wsp;
+    rc = upload(all.data(), total * sizeof(Job), dev, stream);
+    if (rc) return rc;
+    size_t at = 0;
+    for (int g = 0; g < 4; g++) {
+        if (groups[g].empty()) continue;
+        // resident workgroups per CU: LDS-limited for 1- and 2-byte tiles (64 / 32 KiB)
+        const int64_t occ = (int64_t)cu_count() * (g == 0 ? 2 : g == 1 ? 4 : 8);
+        int64_t grid = ntiles[g] < occ ? ntiles[g] : occ;
+        if (grid < 1) grid = 1;
+        const int nj = (int)groups[g].size();
+        switch (g) {
+        case 0: hipLaunchKernelGGL(k_tpose_batched<1>, dim3((unsigned)grid), dim3(NT), 0, stream,
+                                   dev + at, nj, ntiles[g]); break;
+        case 1: hipLaunchKernelGGL(k_tpose_batched<2>, dim3((unsigned)grid), dim3(NT), 0, stream,
+                                   dev + at, nj, ntiles[g]); break;
+        case 2: hipLaunchKernelGGL(k_tpose_batched<4>, dim3((unsigned)grid), dim3(NT), 0, stream,
+                                   dev + at, nj, ntiles[g]); break;
+        default: hipLaunchKernelGGL(k_tpose_batched<8>, dim3((unsigned)grid), dim3(NT), 0, stream,
+                                    dev + at, nj, ntiles[g]); break;
+        }
+        XTR_HIP(hipGetLastError());
+        at += groups[g].size();
+    }
+    return XTR_OK;
+}
+
+}  // namespace xtr
+
+extern "C" {
+
+int tpose(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst,
+          int dtype, void *stream) {
+    return xtr::tpose_impl(src, dst, rows, cols, ld_src, ld_dst, dtype, (hipStream_t)stream);
+}
+
+int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream) {
+    return xtr::tpose_batched_impl(descs, count, (hipStream_t)stream);
+}
+
+}  // extern "C"

@@ -1,0 +1,135 @@
+"""The C-ABI library on the CPU: it loads, exports every entry point that
+include/xtr.h declares, and rejects invalid arguments before touching HIP
+(these calls never reach a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+import paper_2605_13864_amd as X
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "xtr.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(",
+                       text, flags=re.M)
+    return sorted(set(n for n in names if n not in ("if", "return")))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(X.LIB_PATH):
+        import __graft_entry__
+        __graft_entry__.build()
+    return X.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ("tpose", "reduce_sum", "reduce_sum_plain_f32", "tpose_batched",
+              "reduce_sum_segmented", "reduce_sum_batched", "reduce_sum_ws",
+              "reduce_sum_segmented_ws", "xtr_reduce_workspace_bytes",
+              "xtr_segmented_workspace_bytes", "xtr_last_error"):
+        assert n in names, n
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+    # and the binding describes every one of them
+    assert sorted(X._SIGS) == names
+
+
+def test_info_entry_points(lib):
+    assert X.version() >= (0, 1)
+    for name, eb in X.ELEM_BYTES.items():
+        assert lib.xtr_elem_bytes(X.CODES[name]) == eb
+    assert lib.xtr_elem_bytes(99) == 0
+
+
+FAKE = 0x7f0000001000   # never dereferenced: every call below fails validation
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, FAKE + (1 << 30), 4, 4, 4, 4, 99), -2),        # unknown dtype
+    ((FAKE, FAKE + (1 << 30), -1, 4, 4, 4, 0), -1),        # negative rows
+    ((FAKE, FAKE + (1 << 30), 4, 8, 7, 4, 0), -1),         # ld_src < cols
+    ((FAKE, FAKE + (1 << 30), 4, 8, 8, 3, 0), -1),         # ld_dst < rows
+    ((0, FAKE, 4, 4, 4, 4, 0), -1),                        # null src
+    ((FAKE + 2, FAKE + (1 << 30), 4, 4, 4, 4, 0), -4),     # fp32 pointer not 4-byte aligned
+    ((FAKE, FAKE + 32, 4, 4, 4, 4, 0), -3),                # dst overlaps src
+])
+def test_tpose_rejects(lib, args, code):
+    rc = lib.tpose(*[C.c_void_p(a) if i < 2 else a for i, a in enumerate(args)], None)
+    assert rc == code
+    assert lib.xtr_last_error()
+
+
+def test_tpose_empty_is_noop(lib):
+    assert lib.tpose(C.c_void_p(FAKE), C.c_void_p(FAKE), 0, 5, 5, 1, 0, None) == 0
+    assert lib.tpose(C.c_void_p(0), C.c_void_p(0), 7, 0, 1, 7, 0, None) == 0
+
+
+def test_tpose_batched_validates_every_descriptor(lib):
+    arr = (X.TposeDesc * 3)()
+    arr[0] = X.TposeDesc(FAKE, FAKE + (1 << 30), 4, 4, 4, 4, 0, 0)
+    arr[1] = X.TposeDesc(FAKE + (1 << 31), FAKE + (3 << 30), 4, 4, 2, 4, 0, 0)   # bad ld
+    arr[2] = X.TposeDesc(FAKE, FAKE + (1 << 30), 4, 4, 4, 4, 0, 0)
+    assert lib.tpose_batched(C.cast(arr, C.c_void_p), 3, None) == -1
+    assert b"descriptor 1" in lib.xtr_last_error()
+    assert lib.tpose_batched(None, 0, None) == 0
+    assert lib.tpose_batched(None, -1, None) == -1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, 10, FAKE + 4096, 99), -2),     # unknown dtype
+    ((FAKE, 10, FAKE + 4096, 6), -2),      # f64 is transpose-only
+    ((FAKE, -1, FAKE + 4096, 0), -1),      # negative n
+    ((FAKE, 10, 0, 0), -1),                # null out
+    ((0, 10, FAKE + 4096, 0), -1),         # null src
+    ((FAKE + 1, 10, FAKE + 4096, 0), -4),  # misaligned fp32 src
+    ((FAKE, 10, FAKE + 4100, 0), -4),      # misaligned double out
+])
+def test_reduce_sum_rejects(lib, args, code):
+    src, n, out, dt = args
+    assert lib.reduce_sum(C.c_void_p(src), n, C.c_void_p(out), dt, None) == code
+
+
+def test_plain_comparator_takes_floats_only(lib):
+    assert lib.reduce_sum_plain_f32(C.c_void_p(FAKE), 8, C.c_void_p(FAKE + 4096), 4, None) == -2
+
+
+def test_workspace_sizes(lib):
+    for dt in ("f32", "bf16", "f8e4m3", "i32", "i64", "f16"):
+        a = lib.xtr_reduce_workspace_bytes(1 << 20, X.CODES[dt])
+        b = lib.xtr_reduce_workspace_bytes(1 << 28, X.CODES[dt])
+        assert 0 < a <= b
+    assert lib.xtr_reduce_workspace_bytes(10, 6) == 0
+    assert lib.xtr_segmented_workspace_bytes(100000, 1 << 27, 0) > 0
+    # too-small caller workspace is refused before any launch
+    assert lib.reduce_sum_ws(C.c_void_p(FAKE), 1 << 20, C.c_void_p(FAKE + (1 << 26)), 0,
+                             C.c_void_p(FAKE + (1 << 27)), 16, None) == -7
+
+
+def test_segmented_and_batched_validation(lib):
+    assert lib.reduce_sum_segmented(C.c_void_p(FAKE), C.c_void_p(FAKE + 4096), 0,
+                                    C.c_void_p(FAKE + 8192), 0, None) == 0
+    assert lib.reduce_sum_segmented(C.c_void_p(FAKE), C.c_void_p(FAKE + 4096), -1,
+                                    C.c_void_p(FAKE + 8192), 0, None) == -1
+    assert lib.reduce_sum_segmented(C.c_void_p(FAKE), C.c_void_p(FAKE + 4097), 5,
+                                    C.c_void_p(FAKE + 8192), 0, None) == -4
+    assert lib.reduce_sum_segmented_ws(C.c_void_p(FAKE), C.c_void_p(FAKE + 4096), 5, 100,
+                                       C.c_void_p(FAKE + 8192), 0, C.c_void_p(FAKE + 16384), 8,
+                                       None) == -7
+    assert lib.reduce_sum_batched(None, None, 0, C.c_void_p(FAKE), 0, None) == 0
+    ptrs = (C.c_void_p * 2)(FAKE, FAKE + 3)
+    ns = (C.c_int64 * 2)(4, 4)
+    assert lib.reduce_sum_batched(C.cast(ptrs, C.c_void_p), C.cast(ns, C.c_void_p), 2,
+                                  C.c_void_p(FAKE + 8192), 0, None) == -4
+    assert b"job 1" in lib.xtr_last_error()

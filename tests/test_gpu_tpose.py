@@ -1,0 +1,139 @@
+"""GPU parity of the transpose path against the CPU oracle: bit-exact in
+every element size, across tiles, ragged edges, padded and unaligned leading
+dimensions, unaligned pointers, batched launches and the full-size shapes."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import to_dev, to_host
+
+pytestmark = pytest.mark.gpu
+
+SD = {1: np.uint8, 2: np.uint16, 4: np.uint32, 8: np.uint64}
+NAME = {1: "u8", 2: "bf16", 4: "f32", 8: "f64"}
+TILE = {1: 256, 2: 128, 4: 64, 8: 32}      # tile side in elements (256 bytes)
+CANARY = 0xA5
+
+
+def run_tpose(xtr, orc, rows, cols, eb, pad_s=0, pad_d=0, off_s=0, off_d=0, seed=0):
+    """Transpose a random-bit rows x cols matrix with leading dimensions
+    cols+pad_s / rows+pad_d, src and dst starting off_s / off_d elements into
+    their buffers; compare every dst byte (padding and canaries included)."""
+    import torch
+    ld_s, ld_d = cols + pad_s, rows + pad_d
+    n_src = off_s + (rows * ld_s if rows else 0)
+    src = W.random_bits(max(n_src, 1), 1000 + seed, eb)
+    dst_len = off_d + (cols * ld_d if cols else 0) + 7
+    canary = np.frombuffer(bytes([CANARY]) * eb, dtype=SD[eb])[0]
+    dst0 = np.full(dst_len, canary, dtype=SD[eb])
+    d_src, d_dst = to_dev(src), to_dev(dst0)
+    rc_src = d_src[off_s:] if off_s else d_src
+    rc_dst = d_dst[off_d:] if off_d else d_dst
+    xtr.tpose(rc_src, rc_dst, rows=rows, cols=cols, ld_src=ld_s, ld_dst=ld_d, dtype=NAME[eb])
+    torch.cuda.synchronize()
+    got = to_host(d_dst, SD[eb])
+    want = dst0.copy()
+    if rows and cols:
+        orc.tpose(src[off_s:], rows, cols, ld_s, ld_d, dst=want[off_d:])
+    assert np.array_equal(got, want), (rows, cols, eb, pad_s, pad_d, off_s, off_d)
+
+
+def test_pr1_fp32_1024(xtr, orc):
+    """PR1 workload: 1024 x 1024 fp32, U[-1, 1], seed 0."""
+    import torch
+    a = W.matrix(1024, 1024, 0, "f32")
+    got = xtr.tpose(to_dev(a))
+    torch.cuda.synchronize()
+    assert np.array_equal(to_host(got, np.uint32), orc.tpose(a).view(np.uint32))
+
+
+@pytest.mark.parametrize("eb", [1, 2, 4, 8])
+def test_shapes_across_tiles(xtr, orc, eb):
+    T = TILE[eb]
+    shapes = [(1, 1), (1, 3 * T + 1), (2 * T + 5, 1), (17, 33), (T, T), (T - 1, T + 1),
+              (2 * T + 3, 3 * T + 5), (3 * T, 2 * T)]
+    for i, (r, c) in enumerate(shapes):
+        run_tpose(xtr, orc, r, c, eb, seed=i)
+
+
+@pytest.mark.parametrize("eb", [1, 2, 4, 8])
+def test_leading_dims_and_alignment(xtr, orc, eb):
+    T = TILE[eb]
+    v = 16 // eb
+    r, c = 2 * T + 7, T + 9
+    run_tpose(xtr, orc, 2 * T, 2 * T, eb, pad_s=v, pad_d=2 * v)          # aligned padding: vector path
+    run_tpose(xtr, orc, 2 * T, 2 * T, eb, pad_s=1, pad_d=0)              # unaligned ld: element path
+    run_tpose(xtr, orc, 2 * T, 2 * T, eb, pad_s=0, pad_d=3)
+    run_tpose(xtr, orc, r, c, eb, pad_s=5, pad_d=11)
+    if eb < 16:
+        run_tpose(xtr, orc, 2 * T, 2 * T, eb, off_s=1, off_d=0)          # unaligned pointers
+        run_tpose(xtr, orc, T + 3, 2 * T, eb, off_s=0, off_d=1)
+
+
+def test_tiny_enumeration(xtr, orc):
+    for eb in (1, 4):
+        for r in range(1, 12):
+            for c in range(1, 12):
+                run_tpose(xtr, orc, r, c, eb, seed=r * 16 + c)
+
+
+def test_empty_is_noop(xtr, orc):
+    run_tpose(xtr, orc, 0, 17, 4)
+    run_tpose(xtr, orc, 9, 0, 2)
+
+
+def test_involution_nan_payloads(xtr):
+    import torch
+    bits = W.random_bits(777 * 1031, 5, 4)
+    a = to_dev(bits.reshape(777, 1031))
+    back = xtr.tpose(xtr.tpose(a, dtype="f32"), dtype="f32")
+    torch.cuda.synchronize()
+    assert torch.equal(back, a)
+
+
+def test_batched_mixed(xtr, orc):
+    import torch
+    rng = np.random.Generator(np.random.PCG64(9))
+    jobs, hosts = [], []
+    for i in range(48):
+        eb = [1, 2, 4, 8][i % 4]
+        r, c = (int(x) for x in rng.integers(1, 600, 2))
+        a = W.random_bits(r * c, 50 + i, eb).reshape(r, c)
+        s = to_dev(a)
+        d = torch.empty((c, r), dtype=s.dtype, device=s.device)
+        jobs.append({"src": s, "dst": d, "rows": r, "cols": c, "dtype": NAME[eb]})
+        hosts.append(a)
+    xtr.tpose_batched(jobs)
+    torch.cuda.synchronize()
+    for j, a in zip(jobs, hosts):
+        got = to_host(j["dst"], a.dtype)
+        assert np.array_equal(got, orc.tpose(a)), (a.shape, a.dtype)
+
+
+def test_batched_fp32_config_shapes(xtr, orc):
+    """Shapes of the batched workload (sides U{16..2048}, fp32), 256 jobs."""
+    import torch
+    shapes = W.batched_shapes(256, 9)
+    jobs, hosts = [], []
+    for i, (r, c) in enumerate(shapes):
+        a = W.matrix(r, c, 100 + i, "f32")
+        s = to_dev(a)
+        jobs.append((s, torch.empty((c, r), dtype=s.dtype, device=s.device)))
+        hosts.append(a)
+    xtr.tpose_batched(jobs)
+    torch.cuda.synchronize()
+    for (s, d), a in zip(jobs, hosts):
+        assert np.array_equal(to_host(d, np.uint32), orc.tpose(a).view(np.uint32))
+
+
+@pytest.mark.parametrize("rows,cols,dt,seed", [(16384, 16384, "f32", 2), (12288, 20000, "bf16", 3)])
+def test_full_size(xtr, orc, rows, cols, dt, seed):
+    """The large single-job shapes, compared in full against the oracle."""
+    import torch
+    a = W.matrix(rows, cols, seed, dt)
+    d = to_dev(a)
+    got = xtr.tpose(d, dtype=dt)
+    torch.cuda.synchronize()
+    del d
+    want = orc.tpose(a)
+    assert np.array_equal(to_host(got, a.dtype), want)
