@@ -104,22 +104,26 @@ class Step:
                 events[i][1].record()
 
 
-def copy_ceiling(torch, nbytes=1 << 30, reps=20):
-    """Plain device-to-device copy bandwidth (read + write) for context."""
+def copy_ceiling(xtr, torch, nbytes=1 << 30, reps=20):
+    """Plain device-to-device copy bandwidth (read + write) of the library's
+    streaming copy kernel and of torch's copy_, for context."""
     a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda").fill_(1.0)
     b = torch.empty_like(a)
-    for _ in range(3):
-        b.copy_(a)
-    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    s.record()
-    for _ in range(reps):
-        b.copy_(a)
-    e.record()
-    torch.cuda.synchronize()
-    ms = s.elapsed_time(e) / reps
+    res = {}
+    for name, fn in (("xtr_copy", lambda: xtr.copy(b, a)), ("torch_copy", lambda: b.copy_(a))):
+        for _ in range(3):
+            fn()
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        s.record()
+        for _ in range(reps):
+            fn()
+        e.record()
+        torch.cuda.synchronize()
+        ms = s.elapsed_time(e) / reps
+        res[name] = round(2 * nbytes / (ms * 1e-3) / 1e9, 1)
     del a, b
-    return 2 * nbytes / (ms * 1e-3) / 1e9
+    return res
 
 
 def cpu_baseline():
@@ -207,8 +211,8 @@ def main():
         log(f"bench: {name:28s} {us:9.2f} us  {gbs:8.1f} GB/s  {gbs / HBM_PEAK_GBS:6.1%} of peak")
     dom = max(per, key=lambda p: p["avg_us"])
     value = step.bytes / (ms_per_step * 1e-3) / 1e9
-    copy = copy_ceiling(torch)
-    log(f"bench: step {value:.1f} GB/s; plain copy ceiling {copy:.1f} GB/s")
+    copy = copy_ceiling(xtr, torch)
+    log(f"bench: step {value:.1f} GB/s; plain copy {copy}")
 
     tr = traffic_from_profile(dom["kernel"])
     out = {
@@ -232,7 +236,7 @@ def main():
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac"],
                      "traffic": tr},
         "kernels": per,
-        "copy_ceiling_gbs": round(copy, 1),
+        "copy_gbs": copy,
     }
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample ...")

@@ -167,6 +167,13 @@ int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count
 /* ------------------------------------------------------------------------
  * Misc.
  */
+/* Plain device-to-device copy of nbytes (16-byte vectors when src, dst and
+ * nbytes are 16-byte aligned, bytes otherwise).  It is the reference for the
+ * achievable HBM bandwidth (the effective-bandwidth convention of Section 7.1
+ * applied to a copy) and for scaling HBM byte counters.
+ * Errors: EINVAL (null), EOVERLAP. */
+int xtr_copy(void *dst, const void *src, size_t nbytes, void *stream);
+
 /* Thread-local message describing the last nonzero return on this thread. */
 const char *xtr_last_error(void);
 

@@ -60,6 +60,7 @@ _SIGS = {
                                  C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "reduce_sum_batched": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                             C.c_void_p], C.c_int),
+    "xtr_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "xtr_last_error": ([], C.c_char_p),
     "xtr_elem_bytes": ([C.c_int], C.c_int),
     "xtr_version": ([], C.c_int),
@@ -273,6 +274,15 @@ def reduce_sum_batched(srcs, out=None, *, ns=None, dtype=None, stream=None):
                                 C.c_void_p(out.data_ptr()), _code(dt), _stream(stream))
     _check(rc, "reduce_sum_batched")
     return out
+
+
+def copy(dst, src, nbytes=None, *, stream=None):
+    """Plain device copy of nbytes (default: all of src) -- the bandwidth reference."""
+    nbytes = src.numel() * src.element_size() if nbytes is None else nbytes
+    rc = load().xtr_copy(C.c_void_p(dst.data_ptr()), C.c_void_p(src.data_ptr()), nbytes,
+                         _stream(stream))
+    _check(rc, "xtr_copy")
+    return dst
 
 
 def release():

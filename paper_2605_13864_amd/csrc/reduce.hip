@@ -37,6 +37,7 @@
 // everywhere (comparator).
 #include "common.hpp"
 
+#include <algorithm>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -285,11 +286,12 @@ struct Range {
     int32_t _pad;
 };
 
-// Level arrays of the grid combine: level l has a partial array and a ticket
-// array, both indexed by chunk_base + (group index at that level).
+// Level arrays of the grid combine: level l has a partial array indexed by
+// chunk_base + (group index at that level); the ticket of group g at level l
+// is ctr[(chunk_base + g) * MAXLEV + l].
 struct Levels {
     unsigned char *part[MAXLEV];
-    uint32_t *ctr[MAXLEV];
+    uint32_t *ctr;
 };
 
 template <int MODE> struct PartT;
@@ -372,6 +374,39 @@ __device__ __forceinline__ typename PartT<MODE>::T block_sum(typename PartT<MODE
     return r;
 }
 
+// Partials and tickets are exchanged only through agent-scope atomic
+// read-modify-writes, which are performed at the device's coherence point (the
+// L2s of the 8 XCDs are not coherent with each other).  No cache-maintenance
+// fence is used: a writer waits for its partial's exchange to return before it
+// takes a ticket, and the group's last workgroup reads the partials back with
+// atomic RMWs, so it sees every value published before the tickets it counted.
+template <typename P> __device__ __forceinline__ void publish(P *p, P v) {
+    if constexpr (sizeof(P) == 8) {
+        __hip_atomic_exchange(reinterpret_cast<uint64_t *>(p), __builtin_bit_cast(uint64_t, v),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+        __hip_atomic_exchange(reinterpret_cast<uint32_t *>(p), __builtin_bit_cast(uint32_t, v),
+                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+template <typename P> __device__ __forceinline__ P fetch(P *p) {
+    if constexpr (sizeof(P) == 8) {
+        return __builtin_bit_cast(P, __hip_atomic_fetch_or(reinterpret_cast<uint64_t *>(p),
+                                                           (uint64_t)0, __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+    } else {
+        return __builtin_bit_cast(P, __hip_atomic_fetch_or(reinterpret_cast<uint32_t *>(p), 0u,
+                                                           __ATOMIC_RELAXED,
+                                                           __HIP_MEMORY_SCOPE_AGENT));
+    }
+}
+// wait until every memory operation this wave issued has completed
+__device__ __forceinline__ void drain() {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
 template <int MODE>
 __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T value,
                              const Levels &lv, void *out) {
@@ -387,11 +422,11 @@ __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T
         const int64_t g = idx / RADIX;
         const int64_t gsize = (cnt - g * RADIX) < RADIX ? (cnt - g * RADIX) : RADIX;
         P *part = reinterpret_cast<P *>(lv.part[level]);
-        uint32_t *ctr = lv.ctr[level];
+        uint32_t *ticket = lv.ctr + (rg.chunk_base + g) * MAXLEV + level;
         if (t == 0) {
-            part[rg.chunk_base + idx] = value;
-            __threadfence();   // release the partial before taking a ticket
-            uint32_t old = __hip_atomic_fetch_add(&ctr[rg.chunk_base + g], 1u, __ATOMIC_ACQ_REL,
+            publish(&part[rg.chunk_base + idx], value);
+            drain();           // the partial is at the coherence point before the ticket
+            uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
                                                   __HIP_MEMORY_SCOPE_AGENT);
             s_last = (old == (uint32_t)(gsize - 1));
         }
@@ -399,10 +434,10 @@ __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T
         const int last = s_last;
         __syncthreads();
         if (!last) return;
-        __threadfence();       // acquire: every partial of the group is visible
-        P v = (t < gsize) ? part[rg.chunk_base + g * RADIX + t] : (P)0;
+        P v = (t < gsize) ? fetch(&part[rg.chunk_base + g * RADIX + t]) : (P)0;
         value = block_sum<MODE>(v);
-        if (t == 0) ctr[rg.chunk_base + g] = 0u;   // leave the workspace zeroed
+        if (t == 0)            // leave the ticket at zero for the next call
+            __hip_atomic_exchange(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         idx = g;
         cnt = (cnt + RADIX - 1) / RADIX;
     }
@@ -573,23 +608,63 @@ __global__ void __launch_bounds__(NT) k_reduce_seg(const unsigned char *src, con
 // ---------------------------------------------------------------- host side
 
 int part_bytes(int mode) { return mode == PLAIN ? 4 : 8; }
+size_t al256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Workspace layout for `slots` chunk slots: MAXLEV levels x (partials + tickets).
-size_t levels_bytes(int64_t slots, int mode) {
-    const size_t per = ((size_t)slots * part_bytes(mode) + 255) / 256 * 256 +
-                       ((size_t)slots * 4 + 255) / 256 * 256;
-    return per * MAXLEV;
+// A reduction workspace is [tickets | data].  The ticket region is the first
+// quarter of the workspace (rounded down to 256 bytes) whatever the call, so
+// the tickets never move when calls of different sizes share one workspace;
+// every call returns the tickets it used to zero.  Partials and the segmented
+// tables live in the data region, which is always written before it is read.
+struct WsView {
+    uint32_t *tickets;
+    size_t ticket_cap;      // entries
+    unsigned char *data;
+    size_t data_bytes;
+};
+WsView split_ws(void *ws, size_t bytes) {
+    WsView v;
+    const size_t c = (bytes / 4) / 256 * 256;
+    v.tickets = reinterpret_cast<uint32_t *>(ws);
+    v.ticket_cap = c / 4;
+    v.data = reinterpret_cast<unsigned char *>(ws) + c;
+    v.data_bytes = bytes - c;
+    return v;
+}
+bool ws_fits(size_t bytes, int64_t slots, size_t data_bytes) {
+    const WsView v = split_ws(nullptr, bytes);
+    return v.ticket_cap >= (size_t)slots * MAXLEV && v.data_bytes >= data_bytes;
+}
+// smallest 256-byte multiple that holds `slots` ticket slots and `data_bytes`
+size_t ws_size_for(int64_t slots, size_t data_bytes) {
+    size_t w = al256(std::max((size_t)slots * MAXLEV * 4 * 4, data_bytes + data_bytes / 3) + 1024);
+    while (!ws_fits(w, slots, data_bytes)) w += 256;
+    return w;
+}
+// bytes of the per-level partial arrays for `slots` chunk slots
+size_t parts_bytes(int64_t slots, int mode) { return al256((size_t)slots * part_bytes(mode)) * MAXLEV; }
+
+Levels levels_at(const WsView &v, unsigned char *parts, int64_t slots, int mode) {
+    Levels lv;
+    const size_t pb = al256((size_t)slots * part_bytes(mode));
+    for (int l = 0; l < MAXLEV; l++) lv.part[l] = parts + l * pb;
+    lv.ctr = v.tickets;
+    return lv;
 }
 
-Levels levels_at(unsigned char *ws, int64_t slots, int mode) {
-    Levels lv;
-    const size_t pb = ((size_t)slots * part_bytes(mode) + 255) / 256 * 256;
-    const size_t cb = ((size_t)slots * 4 + 255) / 256 * 256;
-    for (int l = 0; l < MAXLEV; l++) {
-        lv.part[l] = ws + l * (pb + cb);
-        lv.ctr[l] = reinterpret_cast<uint32_t *>(ws + l * (pb + cb) + pb);
+// Get a workspace (caller's or the library's) for `slots` chunk slots and
+// `data` bytes of data region; *view describes it.
+int get_ws(void *ws, size_t ws_bytes, int64_t slots, size_t data, hipStream_t st,
+           const char *who, WsView *view) {
+    if (ws) {
+        if (!ws_fits(ws_bytes, slots, data))
+            return fail(XTR_EBUDGET, "%s: workspace %zu bytes < %zu needed", who, ws_bytes,
+                        ws_size_for(slots, data));
+    } else {
+        int rc = workspace(WS_REDUCE, st, ws_size_for(slots, data), &ws, &ws_bytes);
+        if (rc) return rc;
     }
-    return lv;
+    *view = split_ws(ws, ws_bytes);
+    return XTR_OK;
 }
 
 Range host_range(const void *p, int64_t n, int dtype, int64_t index) {
@@ -671,14 +746,10 @@ int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *
     const int mode = mode_for(dtype, plain);
     Range rg = host_range(src, n, dtype, 0);
     if (rg.nchunks > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: n too large", who);
-    const size_t need = levels_bytes(rg.nchunks, mode);
-    if (!ws) {
-        rc = workspace(WS_REDUCE, st, need, &ws);
-        if (rc) return rc;
-    } else if (ws_bytes < need) {
-        return fail(XTR_EBUDGET, "%s: workspace %zu bytes < %zu needed", who, ws_bytes, need);
-    }
-    Levels lv = levels_at((unsigned char *)ws, rg.nchunks, mode);
+    WsView v;
+    rc = get_ws(ws, ws_bytes, rg.nchunks, parts_bytes(rg.nchunks, mode), st, who, &v);
+    if (rc) return rc;
+    Levels lv = levels_at(v, v.data, rg.nchunks, mode);
     XTR_DISPATCH_SUM(dtype, mode, launch_one, (rg, lv, out, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
@@ -690,7 +761,7 @@ size_t reduce_ws_bytes(int64_t n, int dtype, bool plain) {
     if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype)) return 0;
     if (n < 0) return 0;
     Range rg = host_range((const void *)0, n, dtype, 0);
-    return levels_bytes(rg.nchunks, mode_for(dtype, plain));
+    return ws_size_for(rg.nchunks, parts_bytes(rg.nchunks, mode_for(dtype, plain)));
 }
 
 int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
@@ -712,33 +783,34 @@ int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, 
     }
     if (total > 0x7fffffffLL) return fail(XTR_EINVAL, "reduce_sum_batched: too many chunks");
     const int mode = mode_for(dtype, false);
-    void *ws = nullptr, *tw = nullptr;
-    int rc = workspace(WS_REDUCE, st, levels_bytes(total, mode), &ws);
+    void *tw = nullptr;
+    WsView v;
+    int rc = get_ws(nullptr, 0, total, parts_bytes(total, mode), st, "reduce_sum_batched", &v);
     if (rc) return rc;
     rc = workspace(WS_TABLE, st, tab.size() * sizeof(Range), &tw);
     if (rc) return rc;
     rc = upload(tab.data(), tab.size() * sizeof(Range), tw, st);
     if (rc) return rc;
-    Levels lv = levels_at((unsigned char *)ws, total, mode);
+    Levels lv = levels_at(v, v.data, total, mode);
     XTR_DISPATCH_SUM(dtype, mode, launch_table, ((const Range *)tw, (int)count, total, lv, out, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
 
-// Segmented workspace: counts, chunk_base (nseg+1), block totals, chunk map, levels.
+// Segmented data region: counts, chunk_base (nseg+1), block totals, chunk map,
+// level partials.
 struct SegLayout {
-    size_t counts, cbase, btot, cmap, levels, total;
+    size_t counts, cbase, btot, cmap, parts, total;
 };
 SegLayout seg_layout(int64_t nseg, int64_t cap, int mode) {
-    auto al = [](size_t b) { return (b + 255) / 256 * 256; };
     const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
     SegLayout L;
     L.counts = 0;
-    L.cbase = L.counts + al((size_t)nseg * 8);
-    L.btot = L.cbase + al((size_t)(nseg + 1) * 8);
-    L.cmap = L.btot + al((size_t)(nblk + 1) * 8);
-    L.levels = L.cmap + al((size_t)cap * 4);
-    L.total = L.levels + levels_bytes(cap, mode);
+    L.cbase = L.counts + al256((size_t)nseg * 8);
+    L.btot = L.cbase + al256((size_t)(nseg + 1) * 8);
+    L.cmap = L.btot + al256((size_t)(nblk + 1) * 8);
+    L.parts = L.cmap + al256((size_t)cap * 4);
+    L.total = L.parts + parts_bytes(cap, mode);
     return L;
 }
 
@@ -746,7 +818,7 @@ size_t seg_ws_bytes(int64_t nseg, int64_t total_elems, int dtype) {
     if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype)) return 0;
     if (nseg < 0 || total_elems < 0) return 0;
     const int64_t cap = nseg + (total_elems + chunk_elems_rt(dtype) - 1) / chunk_elems_rt(dtype);
-    return seg_layout(nseg, cap, mode_for(dtype, false)).total;
+    return ws_size_for(cap, seg_layout(nseg, cap, mode_for(dtype, false)).total);
 }
 
 int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, void *out,
@@ -775,13 +847,10 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     const int64_t cap = nseg + (total_elems + ch - 1) / ch;
     if (cap > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: chunk space too large", who);
     const SegLayout L = seg_layout(nseg, cap, mode);
-    if (!ws) {
-        rc = workspace(WS_REDUCE, st, L.total, &ws);
-        if (rc) return rc;
-    } else if (ws_bytes < L.total) {
-        return fail(XTR_EBUDGET, "%s: workspace %zu bytes < %zu needed", who, ws_bytes, L.total);
-    }
-    unsigned char *w = (unsigned char *)ws;
+    WsView v;
+    rc = get_ws(ws, ws_bytes, cap, L.total, st, who, &v);
+    if (rc) return rc;
+    unsigned char *w = v.data;
     int64_t *counts = (int64_t *)(w + L.counts), *cbase = (int64_t *)(w + L.cbase);
     int64_t *btot = (int64_t *)(w + L.btot);
     int32_t *cmap = (int32_t *)(w + L.cmap);
@@ -792,7 +861,7 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NT), 0, st, (const int64_t *)counts,
                        (const int64_t *)btot, nseg, cap, cbase, cmap);
     XTR_HIP(hipGetLastError());
-    Levels lv = levels_at(w + L.levels, cap, mode);
+    Levels lv = levels_at(v, w + L.parts, cap, mode);
     XTR_DISPATCH_SUM(dtype, mode, launch_seg,
                      ((const unsigned char *)src, offsets, (const int64_t *)cbase,
                       (const int32_t *)cmap, nseg, cap, lv, out, st));

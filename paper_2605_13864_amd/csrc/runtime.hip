@@ -53,6 +53,35 @@ int zero_fill(void *p, size_t bytes, hipStream_t stream) {
     return XTR_OK;
 }
 
+// ------------------------------------------------------------------ plain copy
+// Streaming device-to-device copy: 16-byte vectors, 4 per thread in flight,
+// grid-stride.  It is the reference kernel for the achievable HBM bandwidth
+// and for scaling the HBM byte counters (FETCH_SIZE / WRITE_SIZE).
+
+__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src,
+                                                uint4 *__restrict__ dst, size_t nvec) {
+    const size_t stride = (size_t)gridDim.x * 256 * 4;
+    for (size_t base = (size_t)blockIdx.x * 256 * 4 + threadIdx.x; base < nvec; base += stride) {
+        uint4 v[4];
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const size_t i = base + (size_t)k * 256;
+            if (i < nvec) v[k] = src[i];
+        }
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            const size_t i = base + (size_t)k * 256;
+            if (i < nvec) dst[i] = v[k];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_copy1(const unsigned char *__restrict__ src,
+                                               unsigned char *__restrict__ dst, size_t n) {
+    size_t i = (size_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // ------------------------------------------------------------------ workspace
 
 namespace {
@@ -84,13 +113,14 @@ struct Stage {
 std::map<Key, Stage> g_stage;
 }  // namespace
 
-int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr) {
+int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr, size_t *actual) {
     int dev = 0;
     XTR_HIP(hipGetDevice(&dev));
     std::lock_guard<std::mutex> lk(g_mu);
     Buf &b = g_ws[Key{kind, dev, stream}];
     if (b.bytes >= bytes && b.ptr) {
         *ptr = b.ptr;
+        if (actual) *actual = b.bytes;
         return XTR_OK;
     }
     hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -117,6 +147,7 @@ int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr) {
         if (rc) return rc;
     }
     *ptr = b.ptr;
+    if (actual) *actual = b.bytes;
     return XTR_OK;
 }
 
@@ -166,6 +197,27 @@ int cu_count() {
 }  // namespace xtr
 
 extern "C" {
+
+int xtr_copy(void *dst, const void *src, size_t nbytes, void *stream) {
+    if (nbytes == 0) return XTR_OK;
+    if (!dst || !src) return xtr::fail(XTR_EINVAL, "xtr_copy: null pointer");
+    const uintptr_t s0 = (uintptr_t)src, d0 = (uintptr_t)dst;
+    if (s0 < d0 + nbytes && d0 < s0 + nbytes) return xtr::fail(XTR_EOVERLAP, "xtr_copy: overlap");
+    hipStream_t st = (hipStream_t)stream;
+    if (((s0 | d0 | nbytes) & 15) == 0) {
+        const size_t nvec = nbytes / 16;
+        size_t blocks = (nvec + 1023) / 1024;
+        const size_t cap = (size_t)xtr::cu_count() * 8;
+        if (blocks > cap) blocks = cap;
+        hipLaunchKernelGGL(xtr::k_copy16, dim3((unsigned)blocks), dim3(256), 0, st,
+                           (const uint4 *)src, (uint4 *)dst, nvec);
+    } else {
+        hipLaunchKernelGGL(xtr::k_copy1, dim3((unsigned)((nbytes + 255) / 256)), dim3(256), 0, st,
+                           (const unsigned char *)src, (unsigned char *)dst, nbytes);
+    }
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
 
 const char *xtr_last_error(void) { return xtr::g_err; }
 

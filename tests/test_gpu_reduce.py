@@ -39,11 +39,12 @@ def gpu_sum(xtr, bits, dt, off=0):
     return r.item()
 
 
-def check(orc, got, bits, dt, what=""):
+def check(orc, got, bits, dt, what="", extreme_kappa=False):
     if dt in ("i32", "i64"):
         assert got == orc.sum_int(bits, dt)[0], (what, got)
     else:
-        check_float_sum(got, orc.sum_float(bits, dt), orc.sum_abs(bits, dt), what)
+        check_float_sum(got, orc.sum_float(bits, dt), orc.sum_abs(bits, dt), what,
+                        extreme_kappa=extreme_kappa)
 
 
 def test_pr1_int32(xtr, orc):
@@ -59,6 +60,18 @@ def test_sizes_and_offsets(xtr, orc, dt):
             bits = data(dt, n + off, 10 * k + off)
             got = gpu_sum(xtr, bits, dt, off)
             check(orc, got, bits[off:], dt, (dt, n, off))
+
+
+def test_mixed_sizes_share_workspace(xtr, orc):
+    """Calls of very different chunk counts back to back on one stream share
+    the library workspace; each must see clean tickets (regression test)."""
+    c = CH["i32"]
+    for k, n in enumerate([300 * c + 5, c + 1, 17 * c + 3, 2 * c, 256 * c + 1, c + 1, 3,
+                           513 * c + 7, 2 * c + 1]):
+        bits = data("i32", n, 900 + k)
+        assert gpu_sum(xtr, bits, "i32") == orc.sum_int(bits, "i32")[0], n
+        fb = data("f32", n, 950 + k)
+        check(orc, gpu_sum(xtr, fb, "f32"), fb, "f32", n)
 
 
 def test_int64_wraps(xtr, orc):
@@ -78,11 +91,13 @@ def test_float_special_values(xtr, orc):
         np.concatenate([np.full(20000, 1, f), [np.inf], np.full(9000, 2, f), [-np.inf]]).astype(f),
         np.concatenate([W.normal(40000, 3, "f32"), np.array([np.nan], f)]),
         np.array([-0.0] * 100, f),
-        np.array([1e30, 1, -1e30, 1] * 4096, f),
         np.array([3.4e38, -3.4e38] * 1000, f),
     ]
     for i, c in enumerate(cases):
         check(orc, gpu_sum(xtr, c, "f32"), c, "f32", i)
+    # sum|x| / |sum x| = 1e30: only the method's absolute bound applies
+    c = np.array([1e30, 1, -1e30, 1] * 4096, f)
+    check(orc, gpu_sum(xtr, c, "f32"), c, "f32", "kappa 1e30", extreme_kappa=True)
     # subnormals are kept (no flush to zero)
     sub = np.full(100000, np.float32(1e-42), f)
     check(orc, gpu_sum(xtr, sub, "f32"), sub, "f32", "subnormal")
