@@ -165,6 +165,35 @@ int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count
                        void *out, int dtype, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Launch configuration (the autotuner's interface).  The settings change how
+ * the work is scheduled, never the result: transposes are bit copies, and
+ * the reduction's chunking and combine order do not depend on them.
+ */
+typedef struct {
+    int32_t nt_load;        /* 1: nontemporal (streaming) 16-byte loads           */
+    int32_t nt_store;       /* 1: nontemporal 16-byte stores                       */
+    int32_t xcd;            /* 1: each XCD takes a contiguous range of tiles       */
+    int32_t group;          /* tile rows per band of the launch order, 1..64       */
+    int32_t blocks_per_cu;  /* 0: one workgroup per tile; k in 1..64: persistent   */
+    int32_t _reserved[3];
+} xtr_tpose_config;
+
+/* Current / new configuration of tpose for one element size (1, 2, 4, 8).
+ * Process-wide; not synchronized with launches in flight on other threads.
+ * Errors: EINVAL. */
+int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg);
+int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg);
+
+typedef struct {
+    int32_t nt_load;        /* 1: nontemporal (streaming) 16-byte loads           */
+    int32_t _reserved[7];
+} xtr_reduce_config;
+
+/* Current / new configuration of the sums for one dtype.  Errors: EINVAL. */
+int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg);
+int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg);
+
+/* ------------------------------------------------------------------------
  * Misc.
  */
 /* Plain device-to-device copy of nbytes (16-byte vectors when src, dst and

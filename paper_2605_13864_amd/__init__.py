@@ -35,6 +35,15 @@ class XtrError(RuntimeError):
         self.code = code
 
 
+class TposeConfig(C.Structure):
+    _fields_ = [("nt_load", C.c_int32), ("nt_store", C.c_int32), ("xcd", C.c_int32),
+                ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("_reserved", C.c_int32 * 3)]
+
+
+class ReduceConfig(C.Structure):
+    _fields_ = [("nt_load", C.c_int32), ("_reserved", C.c_int32 * 7)]
+
+
 class TposeDesc(C.Structure):
     _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("rows", C.c_int64),
                 ("cols", C.c_int64), ("ld_src", C.c_int64), ("ld_dst", C.c_int64),
@@ -61,6 +70,10 @@ _SIGS = {
     "reduce_sum_batched": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                             C.c_void_p], C.c_int),
     "xtr_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "xtr_tpose_get_config": ([C.c_int, C.c_void_p], C.c_int),
+    "xtr_tpose_set_config": ([C.c_int, C.c_void_p], C.c_int),
+    "xtr_reduce_get_config": ([C.c_int, C.c_void_p], C.c_int),
+    "xtr_reduce_set_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_last_error": ([], C.c_char_p),
     "xtr_elem_bytes": ([C.c_int], C.c_int),
     "xtr_version": ([], C.c_int),
@@ -84,6 +97,11 @@ def load(path: str = LIB_PATH):
         fn.argtypes = args
         fn.restype = res
     _lib = lib
+    if os.environ.get("XTR_NO_TUNED") != "1" and torch.cuda.is_available():
+        # launch settings measured by the autotuner (scheduling only, never results)
+        from . import tune
+        arch = tune.arch_name(torch)
+        tune.load_tuned(__import__(__name__), os.path.join(tune.TUNED_DIR, f"{arch}.json"))
     return lib
 
 
@@ -283,6 +301,34 @@ def copy(dst, src, nbytes=None, *, stream=None):
                          _stream(stream))
     _check(rc, "xtr_copy")
     return dst
+
+
+def tpose_config(elem_bytes: int) -> dict:
+    c = TposeConfig()
+    _check(load().xtr_tpose_get_config(elem_bytes, C.byref(c)), "xtr_tpose_get_config")
+    return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
+            "blocks_per_cu": c.blocks_per_cu}
+
+
+def set_tpose_config(elem_bytes: int, **kw):
+    cur = tpose_config(elem_bytes)
+    cur.update(kw)
+    c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
+                    cur["blocks_per_cu"])
+    _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
+
+
+def reduce_config(dtype) -> dict:
+    c = ReduceConfig()
+    _check(load().xtr_reduce_get_config(_code(dtype), C.byref(c)), "xtr_reduce_get_config")
+    return {"nt_load": c.nt_load}
+
+
+def set_reduce_config(dtype, **kw):
+    cur = reduce_config(dtype)
+    cur.update(kw)
+    c = ReduceConfig(cur["nt_load"])
+    _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
 
 
 def release():

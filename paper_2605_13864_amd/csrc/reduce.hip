@@ -45,8 +45,8 @@
 namespace xtr {
 namespace {
 
-constexpr int NT = 256;          // threads per workgroup
-constexpr int NW = NT / 64;      // waves per workgroup
+constexpr int NTHR = 256;        // threads per workgroup
+constexpr int NW = NTHR / 64;    // waves per workgroup
 constexpr int U = 8;             // 16-byte vectors per thread per chunk
 constexpr int RADIX = 256;       // fan-in of the grid combine tree
 constexpr int MAXLEV = 5;
@@ -62,9 +62,9 @@ template <> struct DTI<XTR_I32>    { static constexpr int EB = 4; };
 template <> struct DTI<XTR_I64>    { static constexpr int EB = 8; };
 
 template <int DT> constexpr int vec_elems() { return 16 / DTI<DT>::EB; }
-template <int DT> constexpr int64_t chunk_elems() { return (int64_t)NT * U * vec_elems<DT>(); }
+template <int DT> constexpr int64_t chunk_elems() { return (int64_t)NTHR * U * vec_elems<DT>(); }
 
-int64_t chunk_elems_rt(int dtype) { return (int64_t)NT * U * (16 / elem_bytes(dtype)); }
+int64_t chunk_elems_rt(int dtype) { return (int64_t)NTHR * U * (16 / elem_bytes(dtype)); }
 
 // ---------------------------------------------------------------- arithmetic
 
@@ -301,7 +301,16 @@ template <> struct PartT<INTM> { using T = uint64_t; };
 
 // ---------------------------------------------------------------- one chunk
 
-template <int DT, int MODE>
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+template <bool NT> __device__ __forceinline__ uint4 load16(const uint4 *p) {
+    u32x4 v;
+    if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    else v = *reinterpret_cast<const u32x4 *>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+
+template <int DT, int MODE, bool NT>
 __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg, int64_t j) {
     constexpr int EB = DTI<DT>::EB;
     constexpr int V = vec_elems<DT>();
@@ -319,15 +328,15 @@ __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg,
         const uint4 *vp = reinterpret_cast<const uint4 *>(body + e0 * EB) + t;
         uint4 v[U];
 #pragma unroll
-        for (int u = 0; u < U; u++) v[u] = vp[u * NT];
+        for (int u = 0; u < U; u++) v[u] = load16<NT>(vp + u * NTHR);
 #pragma unroll
         for (int u = 0; u < U; u++) acc_vec(acc, v[u]);
     } else {
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t e = e0 + (int64_t)(u * NT + t) * V;
+            const int64_t e = e0 + (int64_t)(u * NTHR + t) * V;
             if (e + V <= body_n) {
-                uint4 v = *reinterpret_cast<const uint4 *>(body + e * EB);
+                uint4 v = load16<NT>(reinterpret_cast<const uint4 *>(body + e * EB));
                 acc_vec(acc, v);
             } else if (e < body_n) {
                 const int m = (int)(body_n - e);
@@ -446,17 +455,17 @@ __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T
 // ---------------------------------------------------------------- kernels
 
 // Single range (reduce_sum): one workgroup per chunk.
-template <int DT, int MODE>
-__global__ void __launch_bounds__(NT) k_reduce_one(Range rg, Levels lv, void *out) {
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_one(Range rg, Levels lv, void *out) {
     const int64_t j = blockIdx.x;
-    auto v = reduce_chunk<DT, MODE>(rg, j);
+    auto v = reduce_chunk<DT, MODE, NT>(rg, j);
     grid_combine<MODE>(rg, j, v, lv, out);
 }
 
 // Many ranges from a host-built table (reduce_sum_batched): workgroup b takes
 // global chunk b and finds its range by binary search over chunk_base.
-template <int DT, int MODE>
-__global__ void __launch_bounds__(NT) k_reduce_table(const Range *__restrict__ tab, int nr,
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__ tab, int nr,
                                                      Levels lv, void *out) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nr - 1;
@@ -467,7 +476,7 @@ __global__ void __launch_bounds__(NT) k_reduce_table(const Range *__restrict__ t
     const Range rg = tab[lo];
     const int64_t j = b - rg.chunk_base;
     if (j >= rg.nchunks) return;
-    auto v = reduce_chunk<DT, MODE>(rg, j);
+    auto v = reduce_chunk<DT, MODE, NT>(rg, j);
     grid_combine<MODE>(rg, j, v, lv, out);
 }
 
@@ -494,15 +503,15 @@ __device__ __forceinline__ Range seg_range(const unsigned char *src, const int64
 }
 
 // Pass 1: chunk count of every segment, and per-block totals.
-__global__ void __launch_bounds__(NT) k_seg_count(const unsigned char *src, const int64_t *off,
+__global__ void __launch_bounds__(NTHR) k_seg_count(const unsigned char *src, const int64_t *off,
                                                   int64_t nseg, int eb, int64_t ch,
                                                   int64_t *counts, int64_t *block_tot) {
     __shared__ int64_t sh[NW];
-    const int64_t base = (int64_t)blockIdx.x * NT * 4;
+    const int64_t base = (int64_t)blockIdx.x * NTHR * 4;
     int64_t sum = 0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const int64_t s = base + k * NT + threadIdx.x;
+        const int64_t s = base + k * NTHR + threadIdx.x;
         if (s < nseg) {
             int64_t c = seg_range(src, off, s, eb, ch).nchunks;
             // a decreasing pair or a negative start poisons the total so that
@@ -520,33 +529,33 @@ __global__ void __launch_bounds__(NT) k_seg_count(const unsigned char *src, cons
 
 // Pass 2: exclusive scan of the block totals by one workgroup (in place);
 // also writes the grand total after the last block total.
-__global__ void __launch_bounds__(NT) k_seg_scan_blocks(int64_t *block_tot, int64_t nblk) {
-    __shared__ int64_t sh[NT];
+__global__ void __launch_bounds__(NTHR) k_seg_scan_blocks(int64_t *block_tot, int64_t nblk) {
+    __shared__ int64_t sh[NTHR];
     int64_t carry = 0;
-    for (int64_t base = 0; base < nblk; base += NT) {
+    for (int64_t base = 0; base < nblk; base += NTHR) {
         const int64_t i = base + threadIdx.x;
         const int64_t v = i < nblk ? block_tot[i] : 0;
         sh[threadIdx.x] = v;
         __syncthreads();
-        for (int d = 1; d < NT; d <<= 1) {   // Hillis-Steele inclusive scan
+        for (int d = 1; d < NTHR; d <<= 1) {   // Hillis-Steele inclusive scan
             int64_t a = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
             __syncthreads();
             sh[threadIdx.x] += a;
             __syncthreads();
         }
         if (i < nblk) block_tot[i] = carry + sh[threadIdx.x] - v;
-        carry += sh[NT - 1];
+        carry += sh[NTHR - 1];
         __syncthreads();
     }
     if (threadIdx.x == 0) block_tot[nblk] = carry;
 }
 
 // Pass 3: chunk_base of every segment and the chunk -> segment map.
-__global__ void __launch_bounds__(NT) k_seg_place(const int64_t *counts, const int64_t *block_tot,
+__global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const int64_t *block_tot,
                                                   int64_t nseg, int64_t cap, int64_t *chunk_base,
                                                   int32_t *chunk_seg) {
-    __shared__ int64_t sh[NT];
-    const int64_t base = (int64_t)blockIdx.x * NT * 4;
+    __shared__ int64_t sh[NTHR];
+    const int64_t base = (int64_t)blockIdx.x * NTHR * 4;
     const int64_t s0 = base + threadIdx.x * 4;   // this thread's 4 consecutive segments
     int64_t c[4], tsum = 0;
 #pragma unroll
@@ -556,7 +565,7 @@ __global__ void __launch_bounds__(NT) k_seg_place(const int64_t *counts, const i
     }
     sh[threadIdx.x] = tsum;
     __syncthreads();
-    for (int d = 1; d < NT; d <<= 1) {
+    for (int d = 1; d < NTHR; d <<= 1) {
         int64_t a = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
         __syncthreads();
         sh[threadIdx.x] += a;
@@ -573,14 +582,14 @@ __global__ void __launch_bounds__(NT) k_seg_place(const int64_t *counts, const i
         }
     }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
+        const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
         chunk_base[nseg] = block_tot[nblk];
     }
 }
 
 // Pass 4: one workgroup per global chunk.
-template <int DT, int MODE>
-__global__ void __launch_bounds__(NT) k_reduce_seg(const unsigned char *src, const int64_t *off,
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, const int64_t *off,
                                                    const int64_t *chunk_base,
                                                    const int32_t *chunk_seg, int64_t nseg,
                                                    int64_t cap, Levels lv, void *out) {
@@ -601,7 +610,7 @@ __global__ void __launch_bounds__(NT) k_reduce_seg(const unsigned char *src, con
     rg.chunk_base = chunk_base[s];
     const int64_t j = b - rg.chunk_base;
     if (j < 0 || j >= rg.nchunks) return;
-    auto v = reduce_chunk<DT, MODE>(rg, j);
+    auto v = reduce_chunk<DT, MODE, NT>(rg, j);
     grid_combine<MODE>(rg, j, v, lv, out);
 }
 
@@ -720,23 +729,43 @@ int check_sum_args(const void *src, int64_t n, const void *out, int dtype, bool 
     default: return fail(XTR_EDTYPE, "internal: no kernel for dtype %d mode %d", DTYPE, MODE); \
     }
 
+// Tuned settings per dtype (index = dtype code).
+xtr_reduce_config g_rcfg[XTR_U16 + 1] = {};
+bool rcfg_init() {
+    for (auto &c : g_rcfg) c.nt_load = 1;
+    return true;
+}
+bool g_rcfg_ready = rcfg_init();
+
 template <int DT, int MODE>
 void launch_one(const Range &rg, const Levels &lv, void *out, hipStream_t st) {
-    hipLaunchKernelGGL((k_reduce_one<DT, MODE>), dim3((unsigned)rg.nchunks), dim3(NT), 0, st, rg, lv,
-                       out);
+    if (g_rcfg[DT].nt_load)
+        hipLaunchKernelGGL((k_reduce_one<DT, MODE, true>), dim3((unsigned)rg.nchunks), dim3(NTHR), 0,
+                           st, rg, lv, out);
+    else
+        hipLaunchKernelGGL((k_reduce_one<DT, MODE, false>), dim3((unsigned)rg.nchunks), dim3(NTHR),
+                           0, st, rg, lv, out);
 }
 template <int DT, int MODE>
 void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, void *out,
                   hipStream_t st) {
-    hipLaunchKernelGGL((k_reduce_table<DT, MODE>), dim3((unsigned)nchunks), dim3(NT), 0, st, tab, nr,
-                       lv, out);
+    if (g_rcfg[DT].nt_load)
+        hipLaunchKernelGGL((k_reduce_table<DT, MODE, true>), dim3((unsigned)nchunks), dim3(NTHR), 0,
+                           st, tab, nr, lv, out);
+    else
+        hipLaunchKernelGGL((k_reduce_table<DT, MODE, false>), dim3((unsigned)nchunks), dim3(NTHR), 0,
+                           st, tab, nr, lv, out);
 }
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const int32_t *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
     const int64_t grid = cap > nseg ? cap : nseg;
-    hipLaunchKernelGGL((k_reduce_seg<DT, MODE>), dim3((unsigned)grid), dim3(NT), 0, st, src, off, cb,
-                       cs, nseg, cap, lv, out);
+    if (g_rcfg[DT].nt_load)
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), dim3((unsigned)grid), dim3(NTHR), 0, st,
+                           src, off, cb, cs, nseg, cap, lv, out);
+    else
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), dim3((unsigned)grid), dim3(NTHR), 0, st,
+                           src, off, cb, cs, nseg, cap, lv, out);
 }
 
 int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *ws,
@@ -803,7 +832,7 @@ struct SegLayout {
     size_t counts, cbase, btot, cmap, parts, total;
 };
 SegLayout seg_layout(int64_t nseg, int64_t cap, int mode) {
-    const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
+    const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
     SegLayout L;
     L.counts = 0;
     L.cbase = L.counts + al256((size_t)nseg * 8);
@@ -854,11 +883,11 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     int64_t *counts = (int64_t *)(w + L.counts), *cbase = (int64_t *)(w + L.cbase);
     int64_t *btot = (int64_t *)(w + L.btot);
     int32_t *cmap = (int32_t *)(w + L.cmap);
-    const int64_t nblk = (nseg + NT * 4 - 1) / (NT * 4);
-    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NT), 0, st,
+    const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
+    hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NTHR), 0, st,
                        (const unsigned char *)src, offsets, nseg, eb, ch, counts, btot);
-    hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NT), 0, st, btot, nblk);
-    hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NT), 0, st, (const int64_t *)counts,
+    hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NTHR), 0, st, btot, nblk);
+    hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NTHR), 0, st, (const int64_t *)counts,
                        (const int64_t *)btot, nseg, cap, cbase, cmap);
     XTR_HIP(hipGetLastError());
     Levels lv = levels_at(v, w + L.parts, cap, mode);
@@ -881,6 +910,20 @@ extern "C" {
 int reduce_sum(const void *src, int64_t n, void *out, int dtype, void *stream) {
     return xtr::sum_one_impl(src, n, out, dtype, false, nullptr, 0, (hipStream_t)stream,
                              "reduce_sum");
+}
+
+int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
+    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_get_config: bad arguments");
+    *cfg = xtr::g_rcfg[dtype];
+    return XTR_OK;
+}
+
+int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
+    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: bad arguments");
+    xtr::g_rcfg[dtype] = *cfg;
+    return XTR_OK;
 }
 
 int reduce_sum_plain_f32(const void *src, int64_t n, float *out, int dtype, void *stream) {

@@ -120,9 +120,52 @@ template <> __device__ __forceinline__ void block_transpose<1>(const uint4 *a, u
     }
 }
 
+// ---------------------------------------------------------------- 16-byte I/O
+
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+
+// Nontemporal (streaming) accesses do not keep the line in the caches; every
+// byte of a transpose is touched once, so they save cache capacity for the
+// partial lines that neighbouring tiles share.
+template <bool NT> __device__ __forceinline__ uint4 ld16(const unsigned char *p) {
+    u32x4 v;
+    if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
+    else v = *reinterpret_cast<const u32x4 *>(p);
+    return make_uint4(v.x, v.y, v.z, v.w);
+}
+template <bool NT> __device__ __forceinline__ void st16(unsigned char *p, const uint4 &o) {
+    u32x4 v = {o.x, o.y, o.z, o.w};
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<u32x4 *>(p));
+    else *reinterpret_cast<u32x4 *>(p) = v;
+}
+
+// ---------------------------------------------------------------- tile order
+
+// Workgroups are dispatched round-robin over the 8 XCDs (workgroup b runs on
+// XCD b % 8).  xcd_remap gives each XCD a contiguous range of the launch's
+// linear order, so neighbouring tiles -- which share the cache lines at their
+// edges when rows are not 128-byte aligned -- meet in the same L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
+    const int64_t x = b & 7, k = b >> 3, q = G >> 3, r = G & 7;
+    return x * q + (x < r ? x : r) + k;
+}
+
+// Tile (tr, tc) at position L of the launch order: bands of `group` tile rows,
+// column-major inside a band (group = 1 is plain row-major), so that the tiles
+// in flight together write longer runs of each dst row.
+__device__ __forceinline__ void band_order(int64_t L, int64_t tiles_r, int64_t tiles_c, int group,
+                                           int64_t &tr, int64_t &tc) {
+    const int64_t per = (int64_t)group * tiles_c;
+    const int64_t band = L / per, w = L - band * per;
+    const int64_t left = tiles_r - band * group;
+    const int64_t rib = left < group ? left : group;
+    tr = band * group + w % rib;
+    tc = w / rib;
+}
+
 // ---------------------------------------------------------------- one tile
 
-template <int EB>
+template <int EB, bool NTL, bool NTS>
 __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                                         unsigned char *__restrict__ dst, int64_t rows,
                                         int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
@@ -140,8 +183,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         const unsigned char *base = src + (R0 * ld_src + C0) * EB + k * 16;
         uint4 v[V];
 #pragma unroll
-        for (int p = 0; p < V; p++)
-            v[p] = *reinterpret_cast<const uint4 *>(base + (int64_t)(r0 + 16 * p) * ldsb);
+        for (int p = 0; p < V; p++) v[p] = ld16<NTL>(base + (int64_t)(r0 + 16 * p) * ldsb);
 #pragma unroll
         for (int p = 0; p < V; p++) {
             const int row = r0 + 16 * p;
@@ -173,7 +215,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         const int64_t lddb = ld_dst * EB;
         unsigned char *base = dst + ((C0 + bc * V) * ld_dst + R0 + bq * V) * EB;
 #pragma unroll
-        for (int j = 0; j < V; j++) *reinterpret_cast<uint4 *>(base + (int64_t)j * lddb) = o[j];
+        for (int j = 0; j < V; j++) st16<NTS>(base + (int64_t)j * lddb, o[j]);
     } else {
         unsigned char *base = dst + (C0 * ld_dst + R0) * EB;
         for (int e = t; e < G::TR * G::TC; e += NT) {
@@ -188,16 +230,24 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
 
 // ---------------------------------------------------------------- kernels
 
-template <int EB>
+template <int EB, bool NTL, bool NTS>
 __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ src,
                                               unsigned char *__restrict__ dst, int64_t rows,
                                               int64_t cols, int64_t ld_src, int64_t ld_dst,
-                                              int64_t tiles_c, int64_t ntiles, int vec_ok) {
+                                              int64_t tiles_r, int64_t tiles_c, int vec_ok,
+                                              int xcd, int group) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
-    for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
-        const int64_t tr = tile / tiles_c, tc = tile - tr * tiles_c;
-        do_tile<EB>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR, tc * Geo<EB>::TC,
-                    vec_ok != 0, lds);
+    const int64_t ntiles = tiles_r * tiles_c;
+    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
+        const int64_t G = gridDim.x;
+        // position in the launch order: XCD-contiguous within each wave of G tiles
+        const int64_t wave0 = b - blockIdx.x;
+        const int64_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
+        const int64_t L = xcd ? wave0 + xcd_remap(blockIdx.x, inwave) : b;
+        int64_t tr, tc;
+        band_order(L, tiles_r, tiles_c, group, tr, tc);
+        do_tile<EB, NTL, NTS>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR,
+                              tc * Geo<EB>::TC, vec_ok != 0, lds);
         __syncthreads();   // LDS is reused by the next tile of this workgroup
     }
 }
@@ -212,7 +262,7 @@ struct Job {
     int32_t vec_ok, _pad;
 };
 
-template <int EB>
+template <int EB, bool NTL, bool NTS>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs, int njobs,
                                                       int64_t ntiles) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
@@ -234,8 +284,8 @@ __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jo
         const Job &jb = jobs[j];
         const int64_t local = tile - jb.tile_base;
         const int64_t tr = local / jb.tiles_c, tc = local - tr * jb.tiles_c;
-        do_tile<EB>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst, tr * Geo<EB>::TR,
-                    tc * Geo<EB>::TC, jb.vec_ok != 0, lds);
+        do_tile<EB, NTL, NTS>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst,
+                              tr * Geo<EB>::TR, tc * Geo<EB>::TC, jb.vec_ok != 0, lds);
         __syncthreads();
     }
 }
@@ -285,18 +335,62 @@ int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c) {
 
 constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs loop
 
+// Tuned launch configuration per element size (index log2(elem bytes)).
+xtr_tpose_config g_cfg[4] = {
+    {1, 1, 1, 1, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, {0, 0, 0}},
+    {1, 1, 1, 1, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, {0, 0, 0}},
+};
+int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
+
+template <int EB, bool NTL, bool NTS>
+void launch_k(dim3 grid, hipStream_t st, const void *src, void *dst, int64_t rows, int64_t cols,
+              int64_t ld_src, int64_t ld_dst, int64_t tiles_r, int64_t tiles_c, int vec, int xcd,
+              int group) {
+    hipLaunchKernelGGL((k_tpose<EB, NTL, NTS>), grid, dim3(NT), 0, st, (const unsigned char *)src,
+                       (unsigned char *)dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c, vec, xcd,
+                       group);
+}
+
 template <int EB>
 int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
                int64_t ld_dst, hipStream_t stream) {
-    int64_t tiles_c = 0;
-    const int64_t ntiles = tiles_of<EB>(rows, cols, &tiles_c);
+    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
+    const int64_t tiles_r = (rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
+    const int64_t tiles_c = (cols + Geo<EB>::TC - 1) / Geo<EB>::TC;
+    const int64_t ntiles = tiles_r * tiles_c;
     const int vec = vec_aligned(src, dst, ld_src, ld_dst, EB) ? 1 : 0;
-    const int64_t grid = ntiles < MAX_GRID ? ntiles : MAX_GRID;
-    hipLaunchKernelGGL(k_tpose<EB>, dim3((unsigned)grid), dim3(NT), 0, stream,
-                       (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src, ld_dst,
-                       tiles_c, ntiles, vec);
+    int64_t grid = ntiles < MAX_GRID ? ntiles : MAX_GRID;
+    if (c.blocks_per_cu > 0) {
+        const int64_t g = (int64_t)cu_count() * c.blocks_per_cu;
+        if (g < grid) grid = g;
+    }
+    const int group = c.group < 1 ? 1 : c.group;
+    const dim3 gd((unsigned)grid);
+    if (c.nt_load && c.nt_store)
+        launch_k<EB, true, true>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                                 vec, c.xcd, group);
+    else if (c.nt_load)
+        launch_k<EB, true, false>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                  tiles_c, vec, c.xcd, group);
+    else if (c.nt_store)
+        launch_k<EB, false, true>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                  tiles_c, vec, c.xcd, group);
+    else
+        launch_k<EB, false, false>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                   tiles_c, vec, c.xcd, group);
     XTR_HIP(hipGetLastError());
     return XTR_OK;
+}
+
+template <int EB>
+void launch_batched(int64_t grid, hipStream_t st, const Job *jobs, int nj, int64_t ntiles) {
+    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
+    if (c.nt_load && c.nt_store)
+        hipLaunchKernelGGL((k_tpose_batched<EB, true, true>), dim3((unsigned)grid), dim3(NT), 0, st,
+                           jobs, nj, ntiles);
+    else
+        hipLaunchKernelGGL((k_tpose_batched<EB, false, false>), dim3((unsigned)grid), dim3(NT), 0,
+                           st, jobs, nj, ntiles);
 }
 
 }  // namespace
@@ -365,14 +459,10 @@ int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t s
         if (grid < 1) grid = 1;
         const int nj = (int)groups[g].size();
         switch (g) {
-        case 0: hipLaunchKernelGGL(k_tpose_batched<1>, dim3((unsigned)grid), dim3(NT), 0, stream,
-                                   dev + at, nj, ntiles[g]); break;
-        case 1: hipLaunchKernelGGL(k_tpose_batched<2>, dim3((unsigned)grid), dim3(NT), 0, stream,
-                                   dev + at, nj, ntiles[g]); break;
-        case 2: hipLaunchKernelGGL(k_tpose_batched<4>, dim3((unsigned)grid), dim3(NT), 0, stream,
-                                   dev + at, nj, ntiles[g]); break;
-        default: hipLaunchKernelGGL(k_tpose_batched<8>, dim3((unsigned)grid), dim3(NT), 0, stream,
-                                    dev + at, nj, ntiles[g]); break;
+        case 0: launch_batched<1>(grid, stream, dev + at, nj, ntiles[g]); break;
+        case 1: launch_batched<2>(grid, stream, dev + at, nj, ntiles[g]); break;
+        case 2: launch_batched<4>(grid, stream, dev + at, nj, ntiles[g]); break;
+        default: launch_batched<8>(grid, stream, dev + at, nj, ntiles[g]); break;
         }
         XTR_HIP(hipGetLastError());
         at += groups[g].size();
@@ -391,6 +481,22 @@ int tpose(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src
 
 int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream) {
     return xtr::tpose_batched_impl(descs, count, (hipStream_t)stream);
+}
+
+int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg) {
+    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_get_config: bad arguments");
+    *cfg = xtr::g_cfg[xtr::cfg_slot(elem_bytes)];
+    return XTR_OK;
+}
+
+int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg) {
+    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: bad arguments");
+    if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: group in [1, 64], blocks_per_cu in [0, 64]");
+    xtr::g_cfg[xtr::cfg_slot(elem_bytes)] = *cfg;
+    return XTR_OK;
 }
 
 }  // extern "C"

@@ -1,0 +1,159 @@
+"""Autotuner for the transpose and sum launch configurations.
+
+    python -m paper_2605_13864_amd.tune [--quick] [--out PATH]
+
+For every element size it times each candidate ``xtr_tpose_config`` (streaming
+loads / stores, XCD-contiguous tile ranges, band height of the tile order,
+one-tile-per-workgroup or persistent grids) on a representative large
+transpose, and each ``xtr_reduce_config`` on a large sum, with HIP events on
+the launching stream; the fastest wins.  Results are written as JSON keyed by
+GPU architecture and element size / dtype; ``load_tuned()`` applies a file at
+import time (the package does this for ``tuned/<arch>.json`` when present).
+
+Settings change only scheduling, never results, so tuning is safe to apply
+to any call.
+"""
+from __future__ import annotations
+
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+TUNED_DIR = os.path.join(HERE, "tuned")
+
+# representative shapes per element size: (rows, cols)
+TPOSE_SHAPES = {1: (32768, 32768), 2: (12288, 20000), 4: (16384, 16384), 8: (16384, 8192)}
+SUM_SIZES = {"f32": 1 << 28, "bf16": 1 << 29, "f16": 1 << 29, "f8e4m3": 1 << 30,
+             "i32": 1 << 28, "i64": 1 << 28}
+
+
+def _time(torch, fn, reps=10, warm=2):
+    for _ in range(warm):
+        fn()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / reps * 1e-3
+
+
+def arch_name(torch) -> str:
+    p = torch.cuda.get_device_properties(0)
+    return getattr(p, "gcnArchName", "unknown").split(":")[0]
+
+
+def tpose_candidates(quick: bool):
+    nts = [(1, 1), (0, 0)] if quick else [(1, 1), (1, 0), (0, 1), (0, 0)]
+    groups = [1, 4, 16] if quick else [1, 2, 4, 8, 16, 32]
+    bpc = [0, 8] if quick else [0, 4, 8, 16]
+    for (nl, ns), xcd, g, b in itertools.product(nts, [1, 0], groups, bpc):
+        yield {"nt_load": nl, "nt_store": ns, "xcd": xcd, "group": g, "blocks_per_cu": b}
+
+
+def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
+    rows, cols = TPOSE_SHAPES[eb]
+    dt = {1: "u8", 2: "u16", 4: "f32", 8: "f64"}[eb]
+    tdt = {1: torch.uint8, 2: torch.int16, 4: torch.float32, 8: torch.float64}[eb]
+    src = torch.empty((rows, cols), dtype=tdt, device="cuda")
+    src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(eb))
+    dst = torch.empty((cols, rows), dtype=tdt, device="cuda")
+    nbytes = 2 * rows * cols * eb
+    orig = xtr.tpose_config(eb)
+    best = None
+    results = []
+    try:
+        for cfg in tpose_candidates(quick):
+            xtr.set_tpose_config(eb, **cfg)
+            sec = _time(torch, lambda: xtr.tpose(src, dst, dtype=dt))
+            gbs = nbytes / sec / 1e9
+            results.append((gbs, cfg))
+            if best is None or gbs > best[0]:
+                best = (gbs, cfg)
+    finally:
+        xtr.set_tpose_config(eb, **orig)
+    results.sort(key=lambda r: -r[0])
+    log(f"tune tpose eb={eb} {rows}x{cols}: best {best[0]:.1f} GB/s {best[1]}; "
+        f"worst {results[-1][0]:.1f} GB/s")
+    del src, dst
+    return {"gbs": round(best[0], 1), "config": best[1], "shape": [rows, cols],
+            "top5": [{"gbs": round(g, 1), "config": c} for g, c in results[:5]]}
+
+
+def tune_reduce(xtr, torch, dt: str, log=print):
+    n = SUM_SIZES[dt]
+    eb = xtr.ELEM_BYTES[dt]
+    src = torch.empty(n * eb, dtype=torch.uint8, device="cuda")
+    src.random_(0, 255, generator=torch.Generator("cuda").manual_seed(7))
+    if dt in ("f32", "bf16", "f16", "f8e4m3"):   # keep the values finite and modest
+        if dt == "f32":
+            src.view(torch.float32).normal_()
+        elif dt == "bf16":
+            src.view(torch.bfloat16).normal_()
+        elif dt == "f16":
+            src.view(torch.float16).normal_()
+        else:
+            src.bitwise_and_(0x77)    # clears the top exponent bit: no NaN codes
+    out = torch.empty((), dtype=torch.float64 if dt not in ("i32", "i64") else torch.int64,
+                      device="cuda")
+    orig = xtr.reduce_config(dt)
+    best = None
+    try:
+        for nt in (1, 0):
+            xtr.set_reduce_config(dt, nt_load=nt)
+            sec = _time(torch, lambda: xtr.reduce_sum(src, out, n=n, dtype=dt))
+            gbs = n * eb / sec / 1e9
+            if best is None or gbs > best[0]:
+                best = (gbs, {"nt_load": nt})
+    finally:
+        xtr.set_reduce_config(dt, **orig)
+    log(f"tune sum {dt} n={n}: best {best[0]:.1f} GB/s {best[1]}")
+    del src
+    return {"gbs": round(best[0], 1), "config": best[1], "n": n}
+
+
+def run(quick=False, out=None, log=print):
+    import torch
+    import paper_2605_13864_amd as xtr
+    xtr.load()
+    arch = arch_name(torch)
+    t0 = time.time()
+    res = {"arch": arch, "torch_hip": torch.version.hip, "tpose": {}, "reduce": {}}
+    for eb in (4, 2, 1, 8):
+        res["tpose"][str(eb)] = tune_tpose(xtr, torch, eb, quick, log)
+    for dt in ("f32", "i64", "bf16", "f16", "f8e4m3", "i32"):
+        res["reduce"][dt] = tune_reduce(xtr, torch, dt, log)
+    res["seconds"] = round(time.time() - t0, 1)
+    out = out or os.path.join(TUNED_DIR, f"{arch}.json")
+    os.makedirs(os.path.dirname(out), exist_ok=True)
+    with open(out, "w") as f:
+        json.dump(res, f, indent=1)
+    log(f"tune: wrote {out} in {res['seconds']}s")
+    return res
+
+
+def load_tuned(xtr, path: str) -> bool:
+    """Apply a tuned-config file; returns False if it does not exist."""
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        d = json.load(f)
+    for eb, r in d.get("tpose", {}).items():
+        xtr.set_tpose_config(int(eb), **r["config"])
+    for dt, r in d.get("reduce", {}).items():
+        xtr.set_reduce_config(dt, **r["config"])
+    return True
+
+
+if __name__ == "__main__":
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--quick", action="store_true")
+    ap.add_argument("--out", default=None)
+    a = ap.parse_args()
+    run(a.quick, a.out, log=lambda *x: print(*x, file=sys.stderr, flush=True))

