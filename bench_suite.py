@@ -1,0 +1,246 @@
+"""Extra measurements for `bench.py --suite full`: the precision sweep, batched
+transposes and segmented sums against one launch per job, the serving loop,
+and the paper's own workload shapes.  Each function returns a small dict that
+bench.py puts under "suite" in its JSON line.
+
+Large batched inputs are drawn on the device with torch's seeded generator
+(the values do not change a transpose's or a sum's speed); the precision
+sweep uses the seeded host generators of `workloads`, because its result is
+compared with the CPU oracle.
+"""
+from __future__ import annotations
+
+import time
+
+HBM_PEAK_GBS = 8000.0
+
+
+def _events(torch):
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def _time_dev(torch, fn, reps=5, warm=1):
+    for _ in range(warm):
+        fn()
+    s, e = _events(torch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s.record()
+    for _ in range(reps):
+        fn()
+    e.record()
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / reps
+    return s.elapsed_time(e) / reps * 1e-3, wall
+
+
+def _graph(torch, fn):
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            fn()
+    torch.cuda.synchronize()
+    return g
+
+
+# ---------------------------------------------------------------- precision
+
+def precision(xtr, torch, log, n=1 << 30):
+    """Relative error of the compensated sum and of the plain fp32 comparators
+    against the fp64 oracle on +-lognormal(0, 2) data, per format."""
+    import numpy as np
+    import oracle
+    import workloads as W
+    o = oracle.get()
+    out = {}
+    for dt, seed in (("bf16", 6), ("f16", 7), ("f8e4m3", 8)):
+        t0 = time.time()
+        bits, scale = W.signed_lognormal(n, seed, dt)
+        ref = o.sum_float(bits, dt)
+        sabs = o.sum_abs(bits, dt)
+        seq = o.sum_plain_f32(bits, dt)
+        d = torch.from_numpy(bits.view(np.int16) if bits.dtype == np.uint16 else bits).cuda()
+        comp = xtr.reduce_sum(d, dtype=dt).item()
+        plain = xtr.reduce_sum_plain_f32(d, dtype=dt).item()
+        sec_c, _ = _time_dev(torch, lambda: xtr.reduce_sum(d, dtype=dt))
+        sec_p, _ = _time_dev(torch, lambda: xtr.reduce_sum_plain_f32(d, dtype=dt))
+        nbytes = bits.nbytes
+        rel = lambda x: abs(x - ref) / abs(ref)
+        out[dt] = {"n": n, "scale": scale, "kappa": sabs / abs(ref), "ref": ref,
+                   "rel_err_compensated": rel(comp), "rel_err_plain_gpu_tree": rel(plain),
+                   "rel_err_plain_sequential_cpu": rel(seq),
+                   "gbs_compensated": round(nbytes / sec_c / 1e9, 1),
+                   "gbs_plain": round(nbytes / sec_p / 1e9, 1),
+                   "pass_1e-6": rel(comp) <= 1e-6}
+        log(f"suite precision {dt}: kappa {sabs / abs(ref):.3g} rel err comp {rel(comp):.2e} "
+            f"plain-gpu {rel(plain):.2e} plain-seq {rel(seq):.2e}; "
+            f"{nbytes / sec_c / 1e9:.0f} GB/s ({time.time() - t0:.0f}s)")
+        del d, bits
+    return out
+
+
+# ---------------------------------------------------------------- batched transposes
+
+def batched_tpose(xtr, torch, log, count=4096, seed=9):
+    """4096 fp32 transposes, sides iid U{16..2048}: one persistent launch per
+    batch (direct, plan, graph-replayed plan) vs one launch per job (eager and
+    graph-replayed)."""
+    import workloads as W
+    shapes = W.batched_shapes(count, seed)
+    gen = torch.Generator("cuda").manual_seed(seed)
+    srcs, dsts = [], []
+    nbytes = 0
+    for r, c in shapes:
+        srcs.append(torch.rand((r, c), generator=gen, device="cuda") * 2 - 1)
+        dsts.append(torch.empty((c, r), device="cuda"))
+        nbytes += 2 * r * c * 4
+    jobs = list(zip(srcs, dsts))
+    res = {"count": count, "bytes": nbytes}
+
+    sec, wall = _time_dev(torch, lambda: xtr.tpose_batched(jobs), reps=5)
+    res["batched_direct"] = {"gbs": round(nbytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3),
+                             "host_ms": round(wall * 1e3, 3)}
+    plan = xtr.TposePlan(jobs)
+    sec, wall = _time_dev(torch, plan.run, reps=5)
+    res["batched_plan"] = {"gbs": round(nbytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3)}
+    g = _graph(torch, plan.run)
+    sec, wall = _time_dev(torch, g.replay, reps=5)
+    res["batched_graph"] = {"gbs": round(nbytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3)}
+    del g
+
+    def per_job():
+        for s, d in jobs:
+            xtr.tpose(s, d, dtype="f32")
+    sec, wall = _time_dev(torch, per_job, reps=2)
+    res["per_job_eager"] = {"gbs": round(nbytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3),
+                            "host_ms": round(wall * 1e3, 3)}
+    g = _graph(torch, per_job)
+    sec, wall = _time_dev(torch, g.replay, reps=3)
+    res["per_job_graph"] = {"gbs": round(nbytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3)}
+    del g
+    # spot-check correctness of the batched path on a few jobs
+    xtr.tpose_batched(jobs)
+    torch.cuda.synchronize()
+    for k in (0, count // 2, count - 1):
+        assert torch.equal(dsts[k], srcs[k].t()), k
+    plan.close()
+    res["speedup_batched_vs_per_job_graph"] = round(res["per_job_graph"]["ms"] /
+                                                    res["batched_graph"]["ms"], 2)
+    log(f"suite batched tpose: {count} jobs {nbytes / 1e9:.1f} GB: batched {res['batched_direct']['gbs']}"
+        f" / plan {res['batched_plan']['gbs']} / graph {res['batched_graph']['gbs']} GB/s; per-job eager "
+        f"{res['per_job_eager']['gbs']} / graph {res['per_job_graph']['gbs']} GB/s")
+    del srcs, dsts, jobs
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------- segmented sums
+
+def segmented(xtr, torch, log, total=1 << 27, nseg=100000):
+    """2^27 fp32 N(0,1) values in 100k lognormal(6, 1.5) segments: one
+    segmented launch vs one reduce_sum launch per segment."""
+    import workloads as W
+    off = W.segment_offsets(total, nseg, 11)
+    gen = torch.Generator("cuda").manual_seed(10)
+    x = torch.randn(total, generator=gen, device="cuda")
+    doff = torch.from_numpy(off).cuda()
+    nbytes = total * 4
+    res = {"total": total, "nseg": nseg, "bytes": nbytes}
+    ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, "f32"), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    fn = lambda: xtr.reduce_sum_segmented_ws(x, doff, total, ws, out, dtype="f32")
+    sec, wall = _time_dev(torch, fn, reps=10)
+    res["segmented_ws"] = {"gbs": round(nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
+    g = _graph(torch, fn)
+    sec, wall = _time_dev(torch, g.replay, reps=10)
+    res["segmented_graph"] = {"gbs": round(nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
+    del g
+    sec, wall = _time_dev(torch, lambda: xtr.reduce_sum_segmented(x, doff, out, dtype="f32"),
+                          reps=5)
+    res["segmented_readback"] = {"gbs": round(nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 1),
+                                 "host_us": round(wall * 1e6, 1)}
+    seg_out = out.clone()
+    views = [x[off[i]:off[i + 1]] for i in range(nseg)]
+    per = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    outs = [per[i:i + 1] for i in range(nseg)]
+
+    def per_job():
+        for v, o in zip(views, outs):
+            xtr.reduce_sum(v, o.view(()), dtype="f32")
+    sec, wall = _time_dev(torch, per_job, reps=1, warm=1)
+    res["per_job_eager"] = {"gbs": round(nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 1),
+                            "host_us": round(wall * 1e6, 1)}
+    same = bool(torch.equal(per, seg_out))
+    res["per_segment_bit_identical_to_alone"] = same
+    res["speedup_segmented_vs_per_job"] = round(res["per_job_eager"]["us"] /
+                                                res["segmented_ws"]["us"], 1)
+    log(f"suite segmented: {res['segmented_ws']['gbs']} GB/s ({res['segmented_ws']['us']} us); "
+        f"graph {res['segmented_graph']['gbs']}; per-job {res['per_job_eager']['gbs']} GB/s; "
+        f"bit-identical to alone: {same}")
+    del x, ws
+    torch.cuda.empty_cache()
+    return res
+
+
+# ---------------------------------------------------------------- paper shapes
+
+def paper_shapes(xtr, torch, log):
+    """The paper's workloads (a 4096 x 4096 fp32 transpose and a 16M-element
+    sum, Section 7.1), rotating over enough buffers (> 1 GiB in total) that
+    the 256 MB last-level cache cannot serve repeats."""
+    res = {}
+    k = 12
+    srcs = [torch.rand((4096, 4096), device="cuda") for _ in range(k)]
+    dsts = [torch.empty((4096, 4096), device="cuda") for _ in range(k)]
+    it = [0]
+
+    def tp():
+        i = it[0] % k
+        it[0] += 1
+        xtr.tpose(srcs[i], dsts[i], dtype="f32")
+    sec, _ = _time_dev(torch, tp, reps=48, warm=12)
+    nb = 2 * 4096 * 4096 * 4
+    res["tpose_f32_4096"] = {"gbs": round(nb / sec / 1e9, 1), "us": round(sec * 1e6, 2)}
+    del srcs, dsts
+    sums = [torch.randn(1 << 24, device="cuda") for _ in range(k)]
+    o = torch.empty((), dtype=torch.float64, device="cuda")
+    it[0] = 0
+
+    def sm():
+        i = it[0] % k
+        it[0] += 1
+        xtr.reduce_sum(sums[i], o, dtype="f32")
+    sec, _ = _time_dev(torch, sm, reps=48, warm=12)
+    nb = (1 << 24) * 4
+    res["sum_f32_2^24"] = {"gbs": round(nb / sec / 1e9, 1), "us": round(sec * 1e6, 2)}
+    res["paper_rtx5060_context_gbs"] = {"tpose_optigpu": 297.7, "tpose_cuda_samples": 340.6,
+                                        "reduce_optigpu": 297.9, "reduce3": 349.4,
+                                        "reduce6": 376.8}
+    log(f"suite paper shapes: tpose 4096^2 f32 {res['tpose_f32_4096']['gbs']} GB/s, "
+        f"sum 2^24 f32 {res['sum_f32_2^24']['gbs']} GB/s")
+    del sums
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_all(xtr, torch, log, parts=("paper", "batched", "segmented", "precision", "serving")):
+    out = {}
+    for name, fn in (("paper", paper_shapes), ("batched", batched_tpose),
+                     ("segmented", segmented), ("precision", precision)):
+        if name in parts:
+            t0 = time.time()
+            out[name] = fn(xtr, torch, log)
+            log(f"suite: {name} done in {time.time() - t0:.1f}s")
+    if "serving" in parts:
+        try:
+            from paper_2605_13864_amd import serve
+        except ImportError:
+            serve = None
+        if serve is not None:
+            t0 = time.time()
+            out["serving"] = serve.bench(xtr, torch, log)
+            log(f"suite: serving done in {time.time() - t0:.1f}s")
+    return out

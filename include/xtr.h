@@ -164,6 +164,43 @@ int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nse
 int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count,
                        void *out, int dtype, void *stream);
 
+/* reduce_sum_batched with one output location per job: outs is a host array
+ * of `count` device pointers (double* for float dtypes, int64_t* for
+ * integer dtypes, each 8-byte aligned).  Lets a request loop write each
+ * result straight into the job's own output slot. */
+int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void *const *outs,
+                               int64_t count, int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Batch plans: a batch whose buffers and shapes repeat (a serving slot, a
+ * training step) is validated and uploaded once; each run then only launches
+ * kernels, with no host allocation, copy or memset, so a run can be captured
+ * in a hipGraph and replayed.  The plan owns its device job table (and, for
+ * sums, a zeroed workspace that every run leaves reusable); the caller owns
+ * the data buffers, which must stay valid for the plan's lifetime.  Runs of
+ * one plan must not overlap in time (they share its workspace).
+ */
+typedef struct xtr_tpose_plan xtr_tpose_plan;
+
+/* Validates and uploads descs[0..count) (host array, as tpose_batched); the
+ * upload is synchronous on `stream`.  *plan = NULL on error.
+ * Errors: as tpose_batched, plus ENOMEM. */
+int xtr_tpose_plan_create(const xtr_tpose_desc *descs, int64_t count, void *stream,
+                          xtr_tpose_plan **plan);
+/* Enqueues the plan's persistent launches on `stream` (kernels only). */
+int xtr_tpose_plan_run(const xtr_tpose_plan *plan, void *stream);
+int xtr_tpose_plan_destroy(xtr_tpose_plan *plan);
+
+typedef struct xtr_sum_plan xtr_sum_plan;
+
+/* A plan for reduce_sum_batched(srcs, ns, count, out, dtype); same arguments
+ * and errors, plus ENOMEM.  The setup is synchronous on `stream`. */
+int xtr_sum_plan_create(const void *const *srcs, const int64_t *ns, int64_t count, int dtype,
+                        void *out, void *stream, xtr_sum_plan **plan);
+/* Enqueues the plan's reduction on `stream` (one kernel, no other work). */
+int xtr_sum_plan_run(const xtr_sum_plan *plan, void *stream);
+int xtr_sum_plan_destroy(xtr_sum_plan *plan);
+
 /* ------------------------------------------------------------------------
  * Launch configuration (the autotuner's interface).  The settings change how
  * the work is scheduled, never the result: transposes are bit copies, and

@@ -69,7 +69,16 @@ _SIGS = {
                                  C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
     "reduce_sum_batched": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                             C.c_void_p], C.c_int),
+    "reduce_sum_batched_scatter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
+                                    C.c_void_p], C.c_int),
     "xtr_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "xtr_tpose_plan_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_tpose_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_tpose_plan_destroy": ([C.c_void_p], C.c_int),
+    "xtr_sum_plan_create": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int, C.c_void_p, C.c_void_p,
+                             C.c_void_p], C.c_int),
+    "xtr_sum_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_sum_plan_destroy": ([C.c_void_p], C.c_int),
     "xtr_tpose_get_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_tpose_set_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_reduce_get_config": ([C.c_int, C.c_void_p], C.c_int),
@@ -166,10 +175,7 @@ def tpose(src, out=None, *, rows=None, cols=None, ld_src=None, ld_dst=None, dtyp
     return out
 
 
-def tpose_batched(jobs, *, stream=None):
-    """jobs: list of (src, dst) 2-D tensor pairs, or of dicts with keys
-    src, dst, rows, cols, ld_src, ld_dst, dtype (as tpose)."""
-    lib = load()
+def _tpose_descs(jobs):
     arr = (TposeDesc * len(jobs))()
     for i, j in enumerate(jobs):
         if isinstance(j, dict):
@@ -184,8 +190,81 @@ def tpose_batched(jobs, *, stream=None):
             ldd = d.stride(0) if d.shape[0] > 1 else max(rows, 1)
             dt = dtype_of(s)
         arr[i] = TposeDesc(s.data_ptr(), d.data_ptr(), rows, cols, lds, ldd, _code(dt), 0)
+    return arr
+
+
+def tpose_batched(jobs, *, stream=None):
+    """jobs: list of (src, dst) 2-D tensor pairs, or of dicts with keys
+    src, dst, rows, cols, ld_src, ld_dst, dtype (as tpose)."""
+    lib = load()
+    arr = _tpose_descs(jobs)
     rc = lib.tpose_batched(C.cast(arr, C.c_void_p), len(jobs), _stream(stream))
     _check(rc, "tpose_batched")
+
+
+class TposePlan:
+    """A validated, uploaded batch of transposes; run() only launches kernels
+    (capturable in a graph).  Keep the tensors alive while the plan lives."""
+
+    def __init__(self, jobs, *, stream=None):
+        lib = load()
+        self._jobs = jobs
+        arr = _tpose_descs(jobs)
+        h = C.c_void_p()
+        _check(lib.xtr_tpose_plan_create(C.cast(arr, C.c_void_p), len(jobs), _stream(stream),
+                                         C.byref(h)), "xtr_tpose_plan_create")
+        self._h = h
+
+    def run(self, *, stream=None):
+        _check(_lib.xtr_tpose_plan_run(self._h, _stream(stream)), "xtr_tpose_plan_run")
+
+    def close(self):
+        if self._h:
+            _lib.xtr_tpose_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class SumPlan:
+    """A validated batch of sums with its own workspace; run() launches one
+    kernel (capturable).  Keep the tensors alive while the plan lives."""
+
+    def __init__(self, srcs, out=None, *, ns=None, dtype=None, stream=None):
+        lib = load()
+        count = len(srcs)
+        dt = dtype or (dtype_of(srcs[0]) if count else "f32")
+        if out is None:
+            out = _sum_out(dt, srcs[0].device if count else "cuda", count)
+        self.out = out
+        self._srcs = srcs
+        ptrs = (C.c_void_p * count)(*[s.data_ptr() for s in srcs])
+        lens = (C.c_int64 * count)(*[(s.numel() if ns is None else ns[i])
+                                     for i, s in enumerate(srcs)])
+        h = C.c_void_p()
+        _check(lib.xtr_sum_plan_create(C.cast(ptrs, C.c_void_p), C.cast(lens, C.c_void_p), count,
+                                       _code(dt), C.c_void_p(out.data_ptr()), _stream(stream),
+                                       C.byref(h)), "xtr_sum_plan_create")
+        self._h = h
+
+    def run(self, *, stream=None):
+        _check(_lib.xtr_sum_plan_run(self._h, _stream(stream)), "xtr_sum_plan_run")
+        return self.out
+
+    def close(self):
+        if self._h:
+            _lib.xtr_sum_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 # ---------------------------------------------------------------- sums
@@ -329,6 +408,20 @@ def set_reduce_config(dtype, **kw):
     cur.update(kw)
     c = ReduceConfig(cur["nt_load"])
     _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
+
+
+def reduce_sum_batched_scatter(srcs, outs, *, ns=None, dtype=None, stream=None):
+    """Sums of several tensors, result i written to the 0-d tensor outs[i]."""
+    lib = load()
+    count = len(srcs)
+    dt = dtype or (dtype_of(srcs[0]) if count else "f32")
+    ptrs = (C.c_void_p * count)(*[s.data_ptr() for s in srcs])
+    lens = (C.c_int64 * count)(*[(s.numel() if ns is None else ns[i]) for i, s in enumerate(srcs)])
+    optr = (C.c_void_p * count)(*[o.data_ptr() for o in outs])
+    rc = lib.reduce_sum_batched_scatter(C.cast(ptrs, C.c_void_p), C.cast(lens, C.c_void_p),
+                                        C.cast(optr, C.c_void_p), count, _code(dt),
+                                        _stream(stream))
+    _check(rc, "reduce_sum_batched_scatter")
 
 
 def release():

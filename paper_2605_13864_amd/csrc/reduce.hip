@@ -38,6 +38,7 @@
 #include "common.hpp"
 
 #include <algorithm>
+#include <new>
 #include <vector>
 
 #pragma clang fp contract(off)
@@ -275,13 +276,13 @@ __device__ __forceinline__ void acc_elem(Acc<DT, MODE> &acc, const unsigned char
 
 // ---------------------------------------------------------------- ranges
 
-// One array reduced into out[index].
+// One array reduced into *dst.
 struct Range {
     const unsigned char *ptr;  // first element
     int64_t n;                 // elements
     int64_t chunk_base;        // global index of its first chunk (slot base in the level arrays)
     int64_t nchunks;           // >= 1 (an empty range still has one chunk that writes 0)
-    int64_t index;             // output slot
+    unsigned char *dst;        // where the result goes (double, float or int64)
     int32_t head;              // elements before the first 16-byte boundary
     int32_t _pad;
 };
@@ -418,14 +419,14 @@ __device__ __forceinline__ void drain() {
 
 template <int MODE>
 __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T value,
-                             const Levels &lv, void *out) {
+                             const Levels &lv) {
     using P = typename PartT<MODE>::T;
     __shared__ int s_last;
     const int t = threadIdx.x;
     int64_t idx = j, cnt = rg.nchunks;
     for (int level = 0;; level++) {
         if (cnt == 1) {
-            if (t == 0) reinterpret_cast<P *>(out)[rg.index] = value;
+            if (t == 0) *reinterpret_cast<P *>(rg.dst) = value;
             return;
         }
         const int64_t g = idx / RADIX;
@@ -456,17 +457,17 @@ __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T
 
 // Single range (reduce_sum): one workgroup per chunk.
 template <int DT, int MODE, bool NT>
-__global__ void __launch_bounds__(NTHR) k_reduce_one(Range rg, Levels lv, void *out) {
+__global__ void __launch_bounds__(NTHR) k_reduce_one(Range rg, Levels lv) {
     const int64_t j = blockIdx.x;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
-    grid_combine<MODE>(rg, j, v, lv, out);
+    grid_combine<MODE>(rg, j, v, lv);
 }
 
 // Many ranges from a host-built table (reduce_sum_batched): workgroup b takes
 // global chunk b and finds its range by binary search over chunk_base.
 template <int DT, int MODE, bool NT>
 __global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__ tab, int nr,
-                                                     Levels lv, void *out) {
+                                                     Levels lv) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nr - 1;
     while (lo < hi) {
@@ -477,14 +478,15 @@ __global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__
     const int64_t j = b - rg.chunk_base;
     if (j >= rg.nchunks) return;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
-    grid_combine<MODE>(rg, j, v, lv, out);
+    grid_combine<MODE>(rg, j, v, lv);
 }
 
 // ---------------------------------------------------------------- segmented
 
 // Segment geometry, identical to the host-side one used for single ranges.
 __device__ __forceinline__ Range seg_range(const unsigned char *src, const int64_t *off, int64_t s,
-                                           int eb, int64_t ch) {
+                                           int eb, int64_t ch, unsigned char *out = nullptr,
+                                           int osz = 8) {
     int64_t lo = off[s], hi = off[s + 1];
     if (hi < lo) hi = lo;   // a decreasing pair reads as empty here; k_seg_count flags it
     Range r;
@@ -496,7 +498,7 @@ __device__ __forceinline__ Range seg_range(const unsigned char *src, const int64
     r.head = head;
     const int64_t body = r.n - head;
     r.nchunks = body > 0 ? (body + ch - 1) / ch : 1;
-    r.index = s;
+    r.dst = out + s * osz;
     r.chunk_base = 0;
     r._pad = 0;
     return r;
@@ -606,12 +608,13 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, c
     if (b >= total) return;   // unused tail of the grid
     const int64_t s = chunk_seg[b];
     if (s < 0 || s >= nseg) return;
-    Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>());
+    Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(), (unsigned char *)out,
+                         (int)sizeof(typename PartT<MODE>::T));
     rg.chunk_base = chunk_base[s];
     const int64_t j = b - rg.chunk_base;
     if (j < 0 || j >= rg.nchunks) return;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
-    grid_combine<MODE>(rg, j, v, lv, out);
+    grid_combine<MODE>(rg, j, v, lv);
 }
 
 // ---------------------------------------------------------------- host side
@@ -676,7 +679,7 @@ int get_ws(void *ws, size_t ws_bytes, int64_t slots, size_t data, hipStream_t st
     return XTR_OK;
 }
 
-Range host_range(const void *p, int64_t n, int dtype, int64_t index) {
+Range host_range(const void *p, int64_t n, int dtype, void *dst) {
     const int eb = elem_bytes(dtype);
     const int64_t ch = chunk_elems_rt(dtype);
     Range r;
@@ -689,7 +692,7 @@ Range host_range(const void *p, int64_t n, int dtype, int64_t index) {
     const int64_t body = n - head;
     r.nchunks = body > 0 ? (body + ch - 1) / ch : 1;
     r.chunk_base = 0;
-    r.index = index;
+    r.dst = (unsigned char *)dst;
     r._pad = 0;
     return r;
 }
@@ -738,23 +741,22 @@ bool rcfg_init() {
 bool g_rcfg_ready = rcfg_init();
 
 template <int DT, int MODE>
-void launch_one(const Range &rg, const Levels &lv, void *out, hipStream_t st) {
+void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
     if (g_rcfg[DT].nt_load)
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, true>), dim3((unsigned)rg.nchunks), dim3(NTHR), 0,
-                           st, rg, lv, out);
+                           st, rg, lv);
     else
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, false>), dim3((unsigned)rg.nchunks), dim3(NTHR),
-                           0, st, rg, lv, out);
+                           0, st, rg, lv);
 }
 template <int DT, int MODE>
-void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, void *out,
-                  hipStream_t st) {
+void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, hipStream_t st) {
     if (g_rcfg[DT].nt_load)
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, true>), dim3((unsigned)nchunks), dim3(NTHR), 0,
-                           st, tab, nr, lv, out);
+                           st, tab, nr, lv);
     else
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, false>), dim3((unsigned)nchunks), dim3(NTHR), 0,
-                           st, tab, nr, lv, out);
+                           st, tab, nr, lv);
 }
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const int32_t *cs,
@@ -773,13 +775,13 @@ int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *
     int rc = check_sum_args(src, n, out, dtype, plain, who);
     if (rc) return rc;
     const int mode = mode_for(dtype, plain);
-    Range rg = host_range(src, n, dtype, 0);
+    Range rg = host_range(src, n, dtype, out);
     if (rg.nchunks > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: n too large", who);
     WsView v;
     rc = get_ws(ws, ws_bytes, rg.nchunks, parts_bytes(rg.nchunks, mode), st, who, &v);
     if (rc) return rc;
     Levels lv = levels_at(v, v.data, rg.nchunks, mode);
-    XTR_DISPATCH_SUM(dtype, mode, launch_one, (rg, lv, out, st));
+    XTR_DISPATCH_SUM(dtype, mode, launch_one, (rg, lv, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
@@ -789,39 +791,54 @@ int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *
 size_t reduce_ws_bytes(int64_t n, int dtype, bool plain) {
     if (!is_float_sum_dtype(dtype) && !is_int_sum_dtype(dtype)) return 0;
     if (n < 0) return 0;
-    Range rg = host_range((const void *)0, n, dtype, 0);
+    Range rg = host_range((const void *)0, n, dtype, nullptr);
     return ws_size_for(rg.nchunks, parts_bytes(rg.nchunks, mode_for(dtype, plain)));
 }
 
-int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
-                     int dtype, hipStream_t st) {
-    if (count < 0) return fail(XTR_EINVAL, "reduce_sum_batched: negative count");
-    if (count == 0) return XTR_OK;
-    if (!srcs || !ns) return fail(XTR_EINVAL, "reduce_sum_batched: null host array");
-    std::vector<Range> tab((size_t)count);
-    int64_t total = 0;
+// Host table of a batch of ranges; returns the total chunk count in *total.
+// outs == nullptr: range i writes out + i * (result size); else it writes outs[i].
+int build_ranges(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
+                 void *const *outs, int dtype, const char *who, std::vector<Range> &tab,
+                 int64_t *total) {
+    if (count < 0) return fail(XTR_EINVAL, "%s: negative count", who);
+    if (count > 0 && (!srcs || !ns)) return fail(XTR_EINVAL, "%s: null host array", who);
+    if (count > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: too many jobs", who);
+    tab.resize((size_t)count);
+    *total = 0;
+    if (count > 0 && outs == nullptr && out == nullptr) return fail(XTR_EINVAL, "%s: null out", who);
     for (int64_t i = 0; i < count; i++) {
-        int rc = check_sum_args(srcs[i], ns[i], out, dtype, false, "reduce_sum_batched");
+        void *dst = outs ? outs[i] : (void *)((unsigned char *)out + i * 8);
+        int rc = check_sum_args(srcs[i], ns[i], dst, dtype, false, who);
         if (rc) {
-            set_error("reduce_sum_batched: job %lld: %s", (long long)i, xtr_last_error());
+            set_error("%s: job %lld: %s", who, (long long)i, xtr_last_error());
             return rc;
         }
-        tab[i] = host_range(srcs[i], ns[i], dtype, i);
-        tab[i].chunk_base = total;
-        total += tab[i].nchunks;
+        tab[i] = host_range(srcs[i], ns[i], dtype, dst);
+        tab[i].chunk_base = *total;
+        *total += tab[i].nchunks;
     }
-    if (total > 0x7fffffffLL) return fail(XTR_EINVAL, "reduce_sum_batched: too many chunks");
+    if (*total > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: too many chunks", who);
+    return XTR_OK;
+}
+
+int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
+                     void *const *outs, int dtype, hipStream_t st, const char *who) {
+    std::vector<Range> tab;
+    int64_t total = 0;
+    if (count == 0) return XTR_OK;
+    int rc0 = build_ranges(srcs, ns, count, out, outs, dtype, who, tab, &total);
+    if (rc0) return rc0;
     const int mode = mode_for(dtype, false);
     void *tw = nullptr;
     WsView v;
-    int rc = get_ws(nullptr, 0, total, parts_bytes(total, mode), st, "reduce_sum_batched", &v);
+    int rc = get_ws(nullptr, 0, total, parts_bytes(total, mode), st, who, &v);
     if (rc) return rc;
     rc = workspace(WS_TABLE, st, tab.size() * sizeof(Range), &tw);
     if (rc) return rc;
     rc = upload(tab.data(), tab.size() * sizeof(Range), tw, st);
     if (rc) return rc;
     Levels lv = levels_at(v, v.data, total, mode);
-    XTR_DISPATCH_SUM(dtype, mode, launch_table, ((const Range *)tw, (int)count, total, lv, out, st));
+    XTR_DISPATCH_SUM(dtype, mode, launch_table, ((const Range *)tw, (int)count, total, lv, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
@@ -912,6 +929,76 @@ int reduce_sum(const void *src, int64_t n, void *out, int dtype, void *stream) {
                              "reduce_sum");
 }
 
+struct xtr_sum_plan {
+    xtr::Range *tab = nullptr;     // device table
+    int nr = 0;
+    int64_t total = 0;             // chunks
+    int dtype = 0, mode = 0;
+    void *ws = nullptr;            // plan-owned workspace
+    size_t ws_bytes = 0;
+    void *out = nullptr;
+};
+
+int xtr_sum_plan_create(const void *const *srcs, const int64_t *ns, int64_t count, int dtype,
+                        void *out, void *stream, xtr_sum_plan **plan) {
+    using namespace xtr;
+    if (!plan) return fail(XTR_EINVAL, "xtr_sum_plan_create: null plan");
+    *plan = nullptr;
+    std::vector<Range> tab;
+    int64_t total = 0;
+    if (count > 0 && !out) return fail(XTR_EINVAL, "xtr_sum_plan_create: null out");
+    int rc = build_ranges(srcs, ns, count, out, nullptr, dtype, "xtr_sum_plan_create", tab, &total);
+    if (rc) return rc;
+    auto *p = new (std::nothrow) xtr_sum_plan();
+    if (!p) return fail(XTR_ENOMEM, "xtr_sum_plan_create: out of host memory");
+    p->nr = (int)count;
+    p->total = total;
+    p->dtype = dtype;
+    p->mode = mode_for(dtype, false);
+    p->out = out;
+    hipStream_t st = (hipStream_t)stream;
+    hipError_t e = hipSuccess;
+    if (count > 0) {
+        p->ws_bytes = ws_size_for(total, parts_bytes(total, p->mode));
+        e = hipMalloc(&p->ws, p->ws_bytes);
+        if (e == hipSuccess) e = hipMalloc(&p->tab, tab.size() * sizeof(Range));
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(p->tab, tab.data(), tab.size() * sizeof(Range),
+                               hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) rc = zero_fill(p->ws, p->ws_bytes, st);
+        if (e == hipSuccess && !rc) e = hipStreamSynchronize(st);
+    }
+    if (e != hipSuccess || rc) {
+        if (!rc) rc = hip_fail(e, "xtr_sum_plan_create");
+        if (p->ws) (void)hipFree(p->ws);
+        if (p->tab) (void)hipFree(p->tab);
+        delete p;
+        return rc;
+    }
+    *plan = p;
+    return XTR_OK;
+}
+
+int xtr_sum_plan_run(const xtr_sum_plan *p, void *stream) {
+    using namespace xtr;
+    if (!p) return fail(XTR_EINVAL, "xtr_sum_plan_run: null plan");
+    if (p->nr == 0) return XTR_OK;
+    const WsView v = split_ws(p->ws, p->ws_bytes);
+    Levels lv = levels_at(v, v.data, p->total, p->mode);
+    hipStream_t st = (hipStream_t)stream;
+    XTR_DISPATCH_SUM(p->dtype, p->mode, launch_table, (p->tab, p->nr, p->total, lv, st));
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+int xtr_sum_plan_destroy(xtr_sum_plan *p) {
+    if (!p) return XTR_OK;
+    if (p->ws) (void)hipFree(p->ws);
+    if (p->tab) (void)hipFree(p->tab);
+    delete p;
+    return XTR_OK;
+}
+
 int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
     if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
         return xtr::fail(XTR_EINVAL, "xtr_reduce_get_config: bad arguments");
@@ -944,7 +1031,15 @@ int reduce_sum_ws(const void *src, int64_t n, void *out, int dtype, void *ws, si
 
 int reduce_sum_batched(const void *const *srcs, const int64_t *ns, int64_t count, void *out,
                        int dtype, void *stream) {
-    return xtr::sum_batched_impl(srcs, ns, count, out, dtype, (hipStream_t)stream);
+    return xtr::sum_batched_impl(srcs, ns, count, out, nullptr, dtype, (hipStream_t)stream,
+                                 "reduce_sum_batched");
+}
+
+int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void *const *outs,
+                               int64_t count, int dtype, void *stream) {
+    if (count > 0 && !outs) return xtr::fail(XTR_EINVAL, "reduce_sum_batched_scatter: null outs");
+    return xtr::sum_batched_impl(srcs, ns, count, nullptr, outs, dtype, (hipStream_t)stream,
+                                 "reduce_sum_batched_scatter");
 }
 
 size_t xtr_segmented_workspace_bytes(int64_t nseg, int64_t total_elems, int dtype) {

@@ -30,6 +30,7 @@
 // 16-byte aligned, go through an element-wise path over the same LDS layout.
 #include "common.hpp"
 
+#include <new>
 #include <vector>
 
 namespace xtr {
@@ -407,67 +408,82 @@ int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     }
 }
 
-int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t stream) {
-    if (count < 0) return fail(XTR_EINVAL, "tpose_batched: negative count");
-    if (count == 0) return XTR_OK;
-    if (!descs) return fail(XTR_EINVAL, "tpose_batched: null descriptor array");
+// Host-side form of a batch: jobs grouped by element size, each group with its
+// own slice of the device table and its own concatenated tile space.
+struct BatchTable {
+    std::vector<Job> all;          // groups concatenated: 1-, 2-, 4-, 8-byte elements
+    size_t at[4] = {0, 0, 0, 0};   // first job of each group in `all`
+    int nj[4] = {0, 0, 0, 0};
+    int64_t ntiles[4] = {0, 0, 0, 0};
+};
+
+int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, BatchTable &bt) {
+    if (count < 0) return fail(XTR_EINVAL, "%s: negative count", who);
+    if (count > 0 && !descs) return fail(XTR_EINVAL, "%s: null descriptor array", who);
+    if (count > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: too many descriptors", who);
     for (int64_t i = 0; i < count; i++) {
         const xtr_tpose_desc &d = descs[i];
-        int rc = check_one(d.src, d.dst, d.rows, d.cols, d.ld_src, d.ld_dst, d.dtype,
-                           "tpose_batched");
+        int rc = check_one(d.src, d.dst, d.rows, d.cols, d.ld_src, d.ld_dst, d.dtype, who);
         if (rc) {
-            set_error("tpose_batched: descriptor %lld: %s", (long long)i, xtr_last_error());
+            set_error("%s: descriptor %lld: %s", who, (long long)i, xtr_last_error());
             return rc;
         }
     }
-    // group by element size; one persistent launch per group
     std::vector<Job> groups[4];
-    int64_t ntiles[4] = {0, 0, 0, 0};
     for (int64_t i = 0; i < count; i++) {
         const xtr_tpose_desc &d = descs[i];
         if (d.rows == 0 || d.cols == 0) continue;
         const int eb = elem_bytes(d.dtype);
-        const int g = eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3;
+        const int g = cfg_slot(eb);
         Job j;
         j.src = (const unsigned char *)d.src;
         j.dst = (unsigned char *)d.dst;
         j.rows = d.rows; j.cols = d.cols; j.ld_src = d.ld_src; j.ld_dst = d.ld_dst;
-        j.tile_base = ntiles[g];
-        ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
+        j.tile_base = bt.ntiles[g];
+        bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
         j.vec_ok = vec_aligned(d.src, d.dst, d.ld_src, d.ld_dst, eb) ? 1 : 0;
         j._pad = 0;
         groups[g].push_back(j);
     }
-    size_t total = 0;
-    for (auto &g : groups) total += g.size();
-    if (!total) return XTR_OK;
-    std::vector<Job> all;
-    all.reserve(total);
-    for (auto &g : groups) all.insert(all.end(), g.begin(), g.end());
-    void *wsp = nullptr;
-    int rc = workspace(WS_TABLE, stream, total * sizeof(Job), &wsp);
-    if (rc) return rc;
-    Job *dev = (Job *)wsp;
-    rc = upload(all.data(), total * sizeof(Job), dev, stream);
-    if (rc) return rc;
-    size_t at = 0;
     for (int g = 0; g < 4; g++) {
-        if (groups[g].empty()) continue;
-        // resident workgroups per CU: LDS-limited for 1- and 2-byte tiles (64 / 32 KiB)
-        const int64_t occ = (int64_t)cu_count() * (g == 0 ? 2 : g == 1 ? 4 : 8);
-        int64_t grid = ntiles[g] < occ ? ntiles[g] : occ;
-        if (grid < 1) grid = 1;
-        const int nj = (int)groups[g].size();
-        switch (g) {
-        case 0: launch_batched<1>(grid, stream, dev + at, nj, ntiles[g]); break;
-        case 1: launch_batched<2>(grid, stream, dev + at, nj, ntiles[g]); break;
-        case 2: launch_batched<4>(grid, stream, dev + at, nj, ntiles[g]); break;
-        default: launch_batched<8>(grid, stream, dev + at, nj, ntiles[g]); break;
-        }
-        XTR_HIP(hipGetLastError());
-        at += groups[g].size();
+        bt.at[g] = bt.all.size();
+        bt.nj[g] = (int)groups[g].size();
+        bt.all.insert(bt.all.end(), groups[g].begin(), groups[g].end());
     }
     return XTR_OK;
+}
+
+// One persistent launch per non-empty element-size group; `dev` is the device
+// copy of bt.all.
+int launch_batch(const BatchTable &bt, const Job *dev, hipStream_t stream) {
+    for (int g = 0; g < 4; g++) {
+        if (!bt.nj[g]) continue;
+        // resident workgroups per CU: LDS-limited for 1- and 2-byte tiles (64 / 32 KiB)
+        const int64_t occ = (int64_t)cu_count() * (g == 0 ? 2 : g == 1 ? 4 : 8);
+        int64_t grid = bt.ntiles[g] < occ ? bt.ntiles[g] : occ;
+        if (grid < 1) grid = 1;
+        const Job *jobs = dev + bt.at[g];
+        switch (g) {
+        case 0: launch_batched<1>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        case 1: launch_batched<2>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        case 2: launch_batched<4>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        default: launch_batched<8>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        }
+        XTR_HIP(hipGetLastError());
+    }
+    return XTR_OK;
+}
+
+int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t stream) {
+    BatchTable bt;
+    int rc = build_batch(descs, count, "tpose_batched", bt);
+    if (rc || bt.all.empty()) return rc;
+    void *wsp = nullptr;
+    rc = workspace(WS_TABLE, stream, bt.all.size() * sizeof(Job), &wsp);
+    if (rc) return rc;
+    rc = upload(bt.all.data(), bt.all.size() * sizeof(Job), wsp, stream);
+    if (rc) return rc;
+    return launch_batch(bt, (const Job *)wsp, stream);
 }
 
 }  // namespace xtr
@@ -481,6 +497,56 @@ int tpose(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src
 
 int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream) {
     return xtr::tpose_batched_impl(descs, count, (hipStream_t)stream);
+}
+
+struct xtr_tpose_plan {
+    xtr::BatchTable bt;
+    xtr::Job *dev = nullptr;
+    int device = 0;
+};
+
+int xtr_tpose_plan_create(const xtr_tpose_desc *descs, int64_t count, void *stream,
+                          xtr_tpose_plan **plan) {
+    if (!plan) return xtr::fail(XTR_EINVAL, "xtr_tpose_plan_create: null plan");
+    *plan = nullptr;
+    auto *p = new (std::nothrow) xtr_tpose_plan();
+    if (!p) return xtr::fail(XTR_ENOMEM, "xtr_tpose_plan_create: out of host memory");
+    int rc = xtr::build_batch(descs, count, "xtr_tpose_plan_create", p->bt);
+    if (!rc && hipGetDevice(&p->device) != hipSuccess) rc = xtr::fail(XTR_EHIP, "hipGetDevice");
+    if (!rc && !p->bt.all.empty()) {
+        const size_t bytes = p->bt.all.size() * sizeof(xtr::Job);
+        hipError_t e = hipMalloc(&p->dev, bytes);
+        if (e != hipSuccess) {
+            p->dev = nullptr;
+            rc = xtr::fail(XTR_ENOMEM, "xtr_tpose_plan_create: hipMalloc(%zu): %s", bytes,
+                           hipGetErrorString(e));
+        } else {
+            e = hipMemcpyAsync(p->dev, p->bt.all.data(), bytes, hipMemcpyHostToDevice,
+                               (hipStream_t)stream);
+            if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+            if (e != hipSuccess) rc = xtr::hip_fail(e, "xtr_tpose_plan_create: table upload");
+        }
+    }
+    if (rc) {
+        if (p->dev) (void)hipFree(p->dev);
+        delete p;
+        return rc;
+    }
+    *plan = p;
+    return XTR_OK;
+}
+
+int xtr_tpose_plan_run(const xtr_tpose_plan *plan, void *stream) {
+    if (!plan) return xtr::fail(XTR_EINVAL, "xtr_tpose_plan_run: null plan");
+    if (plan->bt.all.empty()) return XTR_OK;
+    return xtr::launch_batch(plan->bt, plan->dev, (hipStream_t)stream);
+}
+
+int xtr_tpose_plan_destroy(xtr_tpose_plan *plan) {
+    if (!plan) return XTR_OK;
+    if (plan->dev) (void)hipFree(plan->dev);
+    delete plan;
+    return XTR_OK;
 }
 
 int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg) {
