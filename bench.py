@@ -166,6 +166,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--suite", choices=["step", "full"], default="step")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--parts", default="paper,batched,segmented,precision,serving",
+                    help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
@@ -243,7 +245,7 @@ def main():
         out["cpu_baseline"] = cpu_baseline()
     if args.suite == "full":
         import bench_suite
-        out["suite"] = bench_suite.run_all(xtr, torch, log)
+        out["suite"] = bench_suite.run_all(xtr, torch, log, tuple(args.parts.split(",")))
     print(json.dumps(out), flush=True)
 
 

@@ -223,7 +223,9 @@ int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg);
 
 typedef struct {
     int32_t nt_load;        /* 1: nontemporal (streaming) 16-byte loads           */
-    int32_t _reserved[7];
+    int32_t blocks_per_cu;  /* 0: one workgroup per chunk; k in 1..64: persistent  */
+                            /*    workgroups, k per CU, next chunk prefetched      */
+    int32_t _reserved[6];
 } xtr_reduce_config;
 
 /* Current / new configuration of the sums for one dtype.  Errors: EINVAL. */

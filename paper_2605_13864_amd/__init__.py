@@ -41,7 +41,7 @@ class TposeConfig(C.Structure):
 
 
 class ReduceConfig(C.Structure):
-    _fields_ = [("nt_load", C.c_int32), ("_reserved", C.c_int32 * 7)]
+    _fields_ = [("nt_load", C.c_int32), ("blocks_per_cu", C.c_int32), ("_reserved", C.c_int32 * 6)]
 
 
 class TposeDesc(C.Structure):
@@ -400,13 +400,13 @@ def set_tpose_config(elem_bytes: int, **kw):
 def reduce_config(dtype) -> dict:
     c = ReduceConfig()
     _check(load().xtr_reduce_get_config(_code(dtype), C.byref(c)), "xtr_reduce_get_config")
-    return {"nt_load": c.nt_load}
+    return {"nt_load": c.nt_load, "blocks_per_cu": c.blocks_per_cu}
 
 
 def set_reduce_config(dtype, **kw):
     cur = reduce_config(dtype)
     cur.update(kw)
-    c = ReduceConfig(cur["nt_load"])
+    c = ReduceConfig(cur["nt_load"], cur["blocks_per_cu"])
     _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
 
 

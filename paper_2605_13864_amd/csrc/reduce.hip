@@ -302,6 +302,29 @@ template <> struct PartT<INTM> { using T = uint64_t; };
 
 // ---------------------------------------------------------------- one chunk
 
+// Thread accumulators -> wave butterfly -> LDS tree over the 4 waves: the
+// chunk's value (fp64 for compensated pairs, fp32 plain, int64).
+template <int DT, int MODE>
+__device__ __forceinline__ typename PartT<MODE>::T chunk_tree(Acc<DT, MODE> &acc) {
+    auto tv = acc.finish();
+    auto wv = wave_reduce(tv);
+    using W = decltype(wv);
+    __shared__ W slot[NW];
+    const int t = threadIdx.x;
+    const int wave = t >> 6, lane = t & 63;
+    if (lane == 0) slot[wave] = wv;
+    __syncthreads();
+    typename PartT<MODE>::T res;
+    if constexpr (MODE == COMP) {
+        Pair b = pair_add(pair_add(slot[0], slot[1]), pair_add(slot[2], slot[3]));
+        res = pair_value(b);
+    } else {
+        res = (slot[0] + slot[1]) + (slot[2] + slot[3]);
+    }
+    __syncthreads();   // slot[] is reused by the next chunk
+    return res;
+}
+
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 template <bool NT> __device__ __forceinline__ uint4 load16(const uint4 *p) {
@@ -348,40 +371,52 @@ __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg,
             }
         }
     }
-    auto tv = acc.finish();
-    auto wv = wave_reduce(tv);
-    // LDS tree across the waves of the workgroup
-    using W = decltype(wv);
-    __shared__ W slot[NW];
-    const int wave = t >> 6, lane = t & 63;
-    if (lane == 0) slot[wave] = wv;
-    __syncthreads();
-    typename PartT<MODE>::T res;
-    if constexpr (MODE == COMP) {
-        Pair b = pair_add(pair_add(slot[0], slot[1]), pair_add(slot[2], slot[3]));
-        res = pair_value(b);
-    } else {
-        res = (slot[0] + slot[1]) + (slot[2] + slot[3]);
+    return chunk_tree<DT, MODE>(acc);
+}
+
+// The 16-byte vectors of full chunk j (vector u of thread t is vector
+// u * 256 + t of the chunk), for the software-pipelined persistent kernel.
+template <int DT, bool NT>
+__device__ __forceinline__ void load_chunk(uint4 *v, const unsigned char *body, int64_t j) {
+    constexpr int EB = DTI<DT>::EB;
+    constexpr int64_t CH = chunk_elems<DT>();
+    const uint4 *vp = reinterpret_cast<const uint4 *>(body + j * CH * EB) + threadIdx.x;
+#pragma unroll
+    for (int u = 0; u < U; u++) v[u] = load16<NT>(vp + u * NTHR);
+}
+
+// Value of full chunk j from its preloaded vectors: identical arithmetic to
+// reduce_chunk (head elements first, then the vectors in order).
+template <int DT, int MODE>
+__device__ __forceinline__ typename PartT<MODE>::T full_chunk_value(const uint4 *v, const Range &rg,
+                                                                     int64_t j) {
+    constexpr int EB = DTI<DT>::EB;
+    Acc<DT, MODE> acc;
+    acc.init();
+    if (j == 0 && threadIdx.x == 0) {
+        for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
     }
-    __syncthreads();   // slot[] is reused by the grid combine
-    return res;
+#pragma unroll
+    for (int u = 0; u < U; u++) acc_vec(acc, v[u]);
+    return chunk_tree<DT, MODE>(acc);
 }
 
 // ---------------------------------------------------------------- grid combine
 
-template <int MODE>
-__device__ __forceinline__ typename PartT<MODE>::T block_sum(typename PartT<MODE>::T v) {
-    using P = typename PartT<MODE>::T;
-    __shared__ P sl[NW];
-    P w;
-    if constexpr (MODE == COMP) w = wave_reduce_f64(v);
-    else w = wave_reduce(v);
-    const int t = threadIdx.x;
-    if ((t & 63) == 0) sl[t >> 6] = w;
-    __syncthreads();
-    P r = (sl[0] + sl[1]) + (sl[2] + sl[3]);
-    __syncthreads();
-    return r;
+// Wave-level butterfly for the grid combine (xor 1 .. 32).
+template <typename P> __device__ __forceinline__ P wave_butterfly(P v) {
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) {
+        if constexpr (sizeof(P) == 8) {
+            const uint64_t b = __builtin_bit_cast(uint64_t, v);
+            const uint64_t o = (uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)b, m, 64) |
+                               ((uint64_t)(uint32_t)__shfl_xor((int)(uint32_t)(b >> 32), m, 64) << 32);
+            v = v + __builtin_bit_cast(P, o);
+        } else {
+            v = v + __builtin_bit_cast(P, __shfl_xor(__builtin_bit_cast(int, v), m, 64));
+        }
+    }
+    return v;
 }
 
 // Partials and tickets are exchanged only through agent-scope atomic
@@ -417,36 +452,56 @@ __device__ __forceinline__ void drain() {
     __atomic_signal_fence(__ATOMIC_SEQ_CST);
 }
 
+// Group sum of up to 256 partials by one wave: lane l adds its four
+// consecutive partials as (p[4l] + p[4l+1]) + (p[4l+2] + p[4l+3]), then the
+// xor butterfly over the 64 lanes -- a balanced pairwise tree over the 256
+// indices (zero-padded), the same association at every call site.
+template <typename P>
+__device__ __forceinline__ P group_sum(P *part, int64_t gsize) {
+    const int l = threadIdx.x & 63;
+    P q[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) q[i] = (4 * l + i < gsize) ? fetch(&part[4 * l + i]) : (P)0;
+    return wave_butterfly<P>((q[0] + q[1]) + (q[2] + q[3]));
+}
+
+// Grid combine, run by the first wave of a workgroup only (the other waves
+// have already left, so they never wait on the atomics' round trips).
+// `published`: the level-0 partial of chunk j is already published and
+// drained (the persistent kernel defers its tickets); `last0` then tells
+// whether this wave took the group's last level-0 ticket.
 template <int MODE>
 __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T value,
-                             const Levels &lv) {
+                             const Levels &lv, bool published = false, bool last0 = false) {
     using P = typename PartT<MODE>::T;
-    __shared__ int s_last;
-    const int t = threadIdx.x;
+    const int l = threadIdx.x & 63;
     int64_t idx = j, cnt = rg.nchunks;
     for (int level = 0;; level++) {
         if (cnt == 1) {
-            if (t == 0) *reinterpret_cast<P *>(rg.dst) = value;
+            if (l == 0) *reinterpret_cast<P *>(rg.dst) = value;
             return;
         }
         const int64_t g = idx / RADIX;
         const int64_t gsize = (cnt - g * RADIX) < RADIX ? (cnt - g * RADIX) : RADIX;
         P *part = reinterpret_cast<P *>(lv.part[level]);
         uint32_t *ticket = lv.ctr + (rg.chunk_base + g) * MAXLEV + level;
-        if (t == 0) {
-            publish(&part[rg.chunk_base + idx], value);
-            drain();           // the partial is at the coherence point before the ticket
-            uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-            s_last = (old == (uint32_t)(gsize - 1));
+        int last;
+        if (published && level == 0) {
+            last = last0;
+        } else {
+            int mine = 0;
+            if (l == 0) {
+                publish(&part[rg.chunk_base + idx], value);
+                drain();       // the partial is at the coherence point before the ticket
+                uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
+                                                      __HIP_MEMORY_SCOPE_AGENT);
+                mine = (old == (uint32_t)(gsize - 1));
+            }
+            last = __shfl(mine, 0, 64);
         }
-        __syncthreads();
-        const int last = s_last;
-        __syncthreads();
         if (!last) return;
-        P v = (t < gsize) ? fetch(&part[rg.chunk_base + g * RADIX + t]) : (P)0;
-        value = block_sum<MODE>(v);
-        if (t == 0)            // leave the ticket at zero for the next call
+        value = group_sum<P>(part + rg.chunk_base + g * RADIX, gsize);
+        if (l == 0)            // leave the ticket at zero for the next call
             __hip_atomic_exchange(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         idx = g;
         cnt = (cnt + RADIX - 1) / RADIX;
@@ -460,7 +515,63 @@ template <int DT, int MODE, bool NT>
 __global__ void __launch_bounds__(NTHR) k_reduce_one(Range rg, Levels lv) {
     const int64_t j = blockIdx.x;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
+    if (threadIdx.x >= 64) return;
     grid_combine<MODE>(rg, j, v, lv);
+}
+
+// Single range, persistent: workgroup b takes chunks b, b + G, b + 2G, ...
+// with the next chunk's loads in flight while the current one is reduced.
+// Each chunk's value is published without waiting; after its last chunk the
+// workgroup waits once and then takes the tickets of all its chunks (the
+// per-chunk values and the combine order are those of k_reduce_one).
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_pers(Range rg, Levels lv) {
+    using P = typename PartT<MODE>::T;
+    constexpr int EB = DTI<DT>::EB;
+    constexpr int64_t CH = chunk_elems<DT>();
+    const int64_t G = gridDim.x, n = rg.nchunks;
+    const int t = threadIdx.x;
+    if ((int64_t)blockIdx.x >= n) return;
+    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
+    const int64_t body_n = rg.n - rg.head;
+    const int64_t nfull = body_n > 0 ? body_n / CH : 0;   // chunks 0 .. nfull-1 are full
+    P *part0 = reinterpret_cast<P *>(lv.part[0]);
+    uint4 cur[U], nxt[U];
+    int64_t j = blockIdx.x;
+    if (j < nfull) load_chunk<DT, NT>(cur, body, j);
+    for (; j < nfull; j += G) {
+        if (j + G < nfull) load_chunk<DT, NT>(nxt, body, j + G);     // prefetch
+        const P val = full_chunk_value<DT, MODE>(cur, rg, j);
+        if (t == 0) publish(&part0[rg.chunk_base + j], val);
+#pragma unroll
+        for (int u = 0; u < U; u++) cur[u] = nxt[u];
+    }
+    if (j == nfull && nfull < n) {   // the one partial (or empty) last chunk
+        const P val = reduce_chunk<DT, MODE, NT>(rg, j);
+        if (t == 0) publish(&part0[rg.chunk_base + j], val);
+    }
+    if (t >= 64) return;
+    if (t == 0) drain();   // every partial of this workgroup is at the coherence point
+    // the level-0 tickets of all this workgroup's chunks, 64 at a time, one per lane
+    const int64_t nmine = (n - 1 - blockIdx.x) / G + 1;
+    for (int64_t base = 0; base < nmine; base += 64) {
+        const int64_t i = base + t;
+        int last = 0;
+        if (i < nmine) {
+            const int64_t jj = blockIdx.x + i * G;
+            const int64_t g = jj / RADIX;
+            const int64_t gsize = (n - g * RADIX) < RADIX ? (n - g * RADIX) : RADIX;
+            uint32_t old = __hip_atomic_fetch_add(lv.ctr + (rg.chunk_base + g) * MAXLEV, 1u,
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            last = (old == (uint32_t)(gsize - 1));
+        }
+        uint64_t mask = __ballot(last);
+        while (mask) {                 // finish the groups whose last ticket we took
+            const int lane = __builtin_ctzll(mask);
+            mask &= mask - 1;
+            grid_combine<MODE>(rg, blockIdx.x + (base + lane) * G, P(0), lv, true, true);
+        }
+    }
 }
 
 // Many ranges from a host-built table (reduce_sum_batched): workgroup b takes
@@ -478,6 +589,7 @@ __global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__
     const int64_t j = b - rg.chunk_base;
     if (j >= rg.nchunks) return;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
+    if (threadIdx.x >= 64) return;
     grid_combine<MODE>(rg, j, v, lv);
 }
 
@@ -614,6 +726,7 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, c
     const int64_t j = b - rg.chunk_base;
     if (j < 0 || j >= rg.nchunks) return;
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
+    if (threadIdx.x >= 64) return;
     grid_combine<MODE>(rg, j, v, lv);
 }
 
@@ -735,14 +848,25 @@ int check_sum_args(const void *src, int64_t n, const void *out, int dtype, bool 
 // Tuned settings per dtype (index = dtype code).
 xtr_reduce_config g_rcfg[XTR_U16 + 1] = {};
 bool rcfg_init() {
-    for (auto &c : g_rcfg) c.nt_load = 1;
+    for (auto &c : g_rcfg) {
+        c.nt_load = 1;
+        c.blocks_per_cu = 0;
+    }
     return true;
 }
 bool g_rcfg_ready = rcfg_init();
 
 template <int DT, int MODE>
 void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
-    if (g_rcfg[DT].nt_load)
+    const xtr_reduce_config &c = g_rcfg[DT];
+    const int64_t pers = (int64_t)cu_count() * c.blocks_per_cu;
+    if (c.blocks_per_cu > 0 && rg.nchunks > pers) {
+        const dim3 g((unsigned)pers);
+        if (c.nt_load) hipLaunchKernelGGL((k_reduce_pers<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
+        else hipLaunchKernelGGL((k_reduce_pers<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
+        return;
+    }
+    if (c.nt_load)
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, true>), dim3((unsigned)rg.nchunks), dim3(NTHR), 0,
                            st, rg, lv);
     else
@@ -1009,6 +1133,8 @@ int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
 int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
     if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: bad arguments");
+    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: blocks_per_cu in [0, 64]");
     xtr::g_rcfg[dtype] = *cfg;
     return XTR_OK;
 }

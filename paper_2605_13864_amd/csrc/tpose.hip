@@ -31,6 +31,7 @@
 #include "common.hpp"
 
 #include <new>
+#include <type_traits>
 #include <vector>
 
 namespace xtr {
@@ -164,47 +165,106 @@ __device__ __forceinline__ void band_order(int64_t L, int64_t tiles_r, int64_t t
     tc = w / rib;
 }
 
+// ---------------------------------------------------------------- W-byte pieces
+
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+// Global accesses move W-byte pieces, W in {4, 8, 16}: the largest power of
+// two that divides both base pointers and both row pitches (in bytes).  A
+// 16-byte vector is split into 16 / W pieces on the store side.
+template <int W> struct PieceT;
+template <> struct PieceT<4> { using T = uint32_t; };
+template <> struct PieceT<8> { using T = u32x2; };
+template <> struct PieceT<16> { using T = u32x4; };
+
+template <int W, bool NT> __device__ __forceinline__ typename PieceT<W>::T ldw(const unsigned char *p) {
+    using T = typename PieceT<W>::T;
+    if constexpr (NT) return __builtin_nontemporal_load(reinterpret_cast<const T *>(p));
+    else return *reinterpret_cast<const T *>(p);
+}
+template <int W, bool NT> __device__ __forceinline__ void stw(unsigned char *p, typename PieceT<W>::T v) {
+    using T = typename PieceT<W>::T;
+    if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<T *>(p));
+    else *reinterpret_cast<T *>(p) = v;
+}
+// piece q of a 16-byte vector
+template <int W> __device__ __forceinline__ typename PieceT<W>::T piece(const uint4 &o, int q) {
+    if constexpr (W == 16) return u32x4{o.x, o.y, o.z, o.w};
+    else if constexpr (W == 8) return q == 0 ? u32x2{o.x, o.y} : u32x2{o.z, o.w};
+    else return dw(o, q);
+}
+
 // ---------------------------------------------------------------- one tile
 
-template <int EB, bool NTL, bool NTS>
+// Moves the TR x TC tile at (R0, C0).  Interior tiles run without any bounds
+// test; tiles on the right or bottom edge mask whole pieces and fall back to
+// single elements only for the one piece a matrix edge cuts.
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
 __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                                         unsigned char *__restrict__ dst, int64_t rows,
                                         int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
-                                        int64_t C0, bool vec_ok, uint4 *lds) {
+                                        int64_t C0, uint4 *lds) {
     using G = Geo<EB>;
     using T = typename Elem<EB>::T;
+    using PT = typename PieceT<W>::T;
+    // per-lane part of an address: 32 bits when the host guarantees it fits
+    using LaneOff = typename std::conditional<OFF32, uint32_t, int64_t>::type;
     constexpr int V = G::V;
+    constexpr int P = 256 / W;          // pieces per 256-byte row segment
+    constexpr int RP = NT / P;          // tile rows per pass of the workgroup
+    constexpr int PASSES = G::TR / RP;
+    constexpr int EPW = W / EB;         // elements per piece
     const int t = threadIdx.x;
-    const bool full = vec_ok && (R0 + G::TR <= rows) && (C0 + G::TC <= cols);
+    const bool full = (R0 + G::TR <= rows) && (C0 + G::TC <= cols);
+    unsigned char *ldsb = reinterpret_cast<unsigned char *>(lds);
 
-    if (full) {
-        // phase 1: 16 lanes per 256-byte row segment, V rows 16 apart per thread
-        const int k = t & 15, r0 = t >> 4;
-        const int64_t ldsb = ld_src * EB;
-        const unsigned char *base = src + (R0 * ld_src + C0) * EB + k * 16;
-        uint4 v[V];
+    // Addresses are (uniform tile base + uniform per-pass offset) + lane offset:
+    // the first two live in scalar registers, the lane offset is computed once.
+
+    // phase 1: P lanes per 256-byte row segment, rows RP apart per pass
+    {
+        const int k = t % P, r0 = t / P;
+        const int64_t ldsrc = ld_src * EB;
+        const unsigned char *tb = src + (R0 * ld_src + C0) * EB;           // uniform
+        const LaneOff lane = (LaneOff)r0 * (LaneOff)ldsrc + (LaneOff)(k * W);
+        const int inner = (k * W) & 15, chunk = (k * W) >> 4;
+        if (full) {
+            // all loads first (PASSES pieces in flight per lane), then the LDS writes
+            PT v[PASSES];
 #pragma unroll
-        for (int p = 0; p < V; p++) v[p] = ld16<NTL>(base + (int64_t)(r0 + 16 * p) * ldsb);
+            for (int p = 0; p < PASSES; p++) v[p] = ldw<W, NTL>((tb + (int64_t)(RP * p) * ldsrc) + lane);
 #pragma unroll
-        for (int p = 0; p < V; p++) {
-            const int row = r0 + 16 * p;
-            lds[row * 16 + swz<EB>(row, k)] = v[p];
-        }
-    } else {
-        const unsigned char *base = src + (R0 * ld_src + C0) * EB;
-        for (int e = t; e < G::TR * G::TC; e += NT) {
-            const int r = e / G::TC, c = e % G::TC;
-            if (R0 + r < rows && C0 + c < cols) {
-                T val = *reinterpret_cast<const T *>(base + ((int64_t)r * ld_src + c) * EB);
-                reinterpret_cast<T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V] = val;
+            for (int p = 0; p < PASSES; p++) {
+                const int row = r0 + RP * p;
+                *reinterpret_cast<PT *>(ldsb + (row * 16 + swz<EB>(row, chunk)) * 16 + inner) = v[p];
+            }
+        } else {
+            const int64_t c = C0 + (int64_t)k * EPW;
+#pragma unroll 4
+            for (int p = 0; p < PASSES; p++) {   // edge tile: one piece at a time
+                const int row = r0 + RP * p;
+                if (R0 + row >= rows || c >= cols) continue;   // never stored: LDS left as is
+                const unsigned char *a = (tb + (int64_t)(RP * p) * ldsrc) + lane;
+                PT pv;
+                if (c + EPW <= cols) {
+                    pv = ldw<W, NTL>(a);
+                } else {
+                    union { PT pt; T e[EPW]; } u;
+                    u.pt = PT{};
+#pragma unroll
+                    for (int i = 0; i < EPW; i++)
+                        if (c + i < cols) u.e[i] = reinterpret_cast<const T *>(a)[i];
+                    pv = u.pt;
+                }
+                *reinterpret_cast<PT *>(ldsb + (row * 16 + swz<EB>(row, chunk)) * 16 + inner) = pv;
             }
         }
     }
 
     __syncthreads();   // ownership of the LDS tile moves from loaders to storers
 
-    if (full) {
-        // phase 2: thread owns the V x V block (rows bq*V.., cols bc*V..)
+    // phase 2: thread owns the V x V block (rows bq*V.., cols bc*V..)
+    {
         const int bq = t & 15, bc = t >> 4;
         uint4 a[V], o[V];
 #pragma unroll
@@ -213,30 +273,89 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
             a[i] = lds[row * 16 + swz<EB>(row, bc)];
         }
         block_transpose<EB>(a, o);
-        const int64_t lddb = ld_dst * EB;
-        unsigned char *base = dst + ((C0 + bc * V) * ld_dst + R0 + bq * V) * EB;
+        const int64_t lddst = ld_dst * EB;
+        unsigned char *tb = dst + (C0 * ld_dst + R0) * EB;                  // uniform
+        const LaneOff lane = (LaneOff)(bc * V) * (LaneOff)lddst + (LaneOff)(bq * V * EB);
+        if (full) {
 #pragma unroll
-        for (int j = 0; j < V; j++) st16<NTS>(base + (int64_t)j * lddb, o[j]);
-    } else {
-        unsigned char *base = dst + (C0 * ld_dst + R0) * EB;
-        for (int e = t; e < G::TR * G::TC; e += NT) {
-            const int c = e / G::TR, r = e % G::TR;   // dst row c of the tile, dst col r
-            if (R0 + r < rows && C0 + c < cols) {
-                T val = reinterpret_cast<const T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V];
-                *reinterpret_cast<T *>(base + ((int64_t)c * ld_dst + r) * EB) = val;
+            for (int j = 0; j < V; j++)
+#pragma unroll
+                for (int q = 0; q < 16 / W; q++)
+                    stw<W, NTS>((tb + (int64_t)j * lddst + q * W) + lane, piece<W>(o[j], q));
+        } else {
+            const int64_t cs = R0 + bq * V;
+#pragma unroll
+            for (int j = 0; j < V; j++) {
+                if (C0 + bc * V + j >= cols) continue;
+#pragma unroll
+                for (int q = 0; q < 16 / W; q++) {
+                    unsigned char *a2 = (tb + (int64_t)j * lddst + q * W) + lane;
+                    const int64_t cq = cs + q * EPW;
+                    if (cq + EPW <= rows) {
+                        stw<W, NTS>(a2, piece<W>(o[j], q));
+                    } else if (cq < rows) {
+                        union { PT pt; T e[EPW]; } u;
+                        u.pt = piece<W>(o[j], q);
+#pragma unroll
+                        for (int i = 0; i < EPW; i++)
+                            if (cq + i < rows) reinterpret_cast<T *>(a2)[i] = u.e[i];
+                    }
+                }
             }
         }
     }
 }
 
+// Element-wise form of the same tile for 1- and 2-byte elements whose
+// pointers or pitches are not 4-byte aligned (coalesced, one element per
+// lane per access, same LDS layout).
+template <int EB>
+__device__ __forceinline__ void do_tile_elem(const unsigned char *__restrict__ src,
+                                             unsigned char *__restrict__ dst, int64_t rows,
+                                             int64_t cols, int64_t ld_src, int64_t ld_dst,
+                                             int64_t R0, int64_t C0, uint4 *lds) {
+    using G = Geo<EB>;
+    using T = typename Elem<EB>::T;
+    constexpr int V = G::V;
+    const int t = threadIdx.x;
+    const unsigned char *sb = src + (R0 * ld_src + C0) * EB;
+    for (int e = t; e < G::TR * G::TC; e += NT) {
+        const int r = e / G::TC, c = e % G::TC;
+        if (R0 + r < rows && C0 + c < cols) {
+            T val = *reinterpret_cast<const T *>(sb + ((int64_t)r * ld_src + c) * EB);
+            reinterpret_cast<T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V] = val;
+        }
+    }
+    __syncthreads();
+    unsigned char *db = dst + (C0 * ld_dst + R0) * EB;
+    for (int e = t; e < G::TR * G::TC; e += NT) {
+        const int c = e / G::TR, r = e % G::TR;   // dst row c of the tile, dst col r
+        if (R0 + r < rows && C0 + c < cols) {
+            T val = reinterpret_cast<const T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V];
+            *reinterpret_cast<T *>(db + ((int64_t)c * ld_dst + r) * EB) = val;
+        }
+    }
+}
+
+// W = 0 selects the element-wise form.  OFF32: every per-lane offset inside a
+// tile fits in 32 bits (the host checks the pitches), so addresses are a
+// uniform 64-bit tile base plus a 32-bit lane offset.
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+__device__ __forceinline__ void tile_any(const unsigned char *src, unsigned char *dst, int64_t rows,
+                                         int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
+                                         int64_t C0, uint4 *lds) {
+    if constexpr (W == 0) do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+    else do_tile<EB, W, NTL, NTS, OFF32>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+}
+
 // ---------------------------------------------------------------- kernels
 
-template <int EB, bool NTL, bool NTS>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
 __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ src,
                                               unsigned char *__restrict__ dst, int64_t rows,
                                               int64_t cols, int64_t ld_src, int64_t ld_dst,
-                                              int64_t tiles_r, int64_t tiles_c, int vec_ok,
-                                              int xcd, int group) {
+                                              int64_t tiles_r, int64_t tiles_c, int xcd,
+                                              int group) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
     const int64_t ntiles = tiles_r * tiles_c;
     for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
@@ -247,8 +366,8 @@ __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ 
         const int64_t L = xcd ? wave0 + xcd_remap(blockIdx.x, inwave) : b;
         int64_t tr, tc;
         band_order(L, tiles_r, tiles_c, group, tr, tc);
-        do_tile<EB, NTL, NTS>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR,
-                              tc * Geo<EB>::TC, vec_ok != 0, lds);
+        tile_any<EB, W, NTL, NTS, OFF32>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR,
+                                         tc * Geo<EB>::TC, lds);
         __syncthreads();   // LDS is reused by the next tile of this workgroup
     }
 }
@@ -260,10 +379,10 @@ struct Job {
     int64_t rows, cols, ld_src, ld_dst;
     int64_t tiles_c;
     int64_t tile_base;   // first global tile id of this job
-    int32_t vec_ok, _pad;
+    int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = element-wise
 };
 
-template <int EB, bool NTL, bool NTS>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs, int njobs,
                                                       int64_t ntiles) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
@@ -285,8 +404,8 @@ __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jo
         const Job &jb = jobs[j];
         const int64_t local = tile - jb.tile_base;
         const int64_t tr = local / jb.tiles_c, tc = local - tr * jb.tiles_c;
-        do_tile<EB, NTL, NTS>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst,
-                              tr * Geo<EB>::TR, tc * Geo<EB>::TC, jb.vec_ok != 0, lds);
+        tile_any<EB, W, NTL, NTS, OFF32>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst,
+                                         tr * Geo<EB>::TR, tc * Geo<EB>::TC, lds);
         __syncthreads();
     }
 }
@@ -313,9 +432,30 @@ int check_one(const void *src, const void *dst, int64_t rows, int64_t cols, int6
     return XTR_OK;
 }
 
-bool vec_aligned(const void *src, const void *dst, int64_t ld_src, int64_t ld_dst, int eb) {
-    return (((uintptr_t)src | (uintptr_t)dst) % 16 == 0) && ((ld_src * eb) % 16 == 0) &&
-           ((ld_dst * eb) % 16 == 0);
+// Per-lane offsets inside a tile stay below 2^31 (so the 32-bit addressing of
+// do_tile is exact): tile rows x row pitch on either side, plus one row.
+template <int EB> bool off32_ok(int64_t ld_src, int64_t ld_dst) {
+    const int64_t lim = (int64_t)1 << 31;
+    return (int64_t)Geo<EB>::TR * ld_src * EB + 256 < lim &&
+           (int64_t)Geo<EB>::TC * ld_dst * EB + 256 < lim;
+}
+bool off32_rt(int eb, int64_t ld_src, int64_t ld_dst) {
+    switch (eb) {
+    case 1: return off32_ok<1>(ld_src, ld_dst);
+    case 2: return off32_ok<2>(ld_src, ld_dst);
+    case 4: return off32_ok<4>(ld_src, ld_dst);
+    default: return off32_ok<8>(ld_src, ld_dst);
+    }
+}
+
+// Widest piece (16, 8 or 4 bytes, and >= the element) that divides both base
+// pointers and both row pitches; 0 = element-wise (1- or 2-byte elements only).
+int piece_width(const void *src, const void *dst, int64_t ld_src, int64_t ld_dst, int eb) {
+    const uint64_t a = (uint64_t)(uintptr_t)src | (uint64_t)(uintptr_t)dst |
+                       (uint64_t)(ld_src * eb) | (uint64_t)(ld_dst * eb);
+    for (int w = 16; w >= 4; w >>= 1)
+        if (w >= eb && (a % w) == 0) return w;
+    return 0;
 }
 
 template <int EB> int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
@@ -343,13 +483,36 @@ xtr_tpose_config g_cfg[4] = {
 };
 int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
-template <int EB, bool NTL, bool NTS>
+template <int EB, int W, bool NTL, bool NTS>
 void launch_k(dim3 grid, hipStream_t st, const void *src, void *dst, int64_t rows, int64_t cols,
-              int64_t ld_src, int64_t ld_dst, int64_t tiles_r, int64_t tiles_c, int vec, int xcd,
+              int64_t ld_src, int64_t ld_dst, int64_t tiles_r, int64_t tiles_c, int xcd,
               int group) {
-    hipLaunchKernelGGL((k_tpose<EB, NTL, NTS>), grid, dim3(NT), 0, st, (const unsigned char *)src,
-                       (unsigned char *)dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c, vec, xcd,
-                       group);
+    if (off32_ok<EB>(ld_src, ld_dst))
+        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, true>), grid, dim3(NT), 0, st,
+                           (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
+                           ld_dst, tiles_r, tiles_c, xcd, group);
+    else
+        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, false>), grid, dim3(NT), 0, st,
+                           (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
+                           ld_dst, tiles_r, tiles_c, xcd, group);
+}
+
+template <int EB, int W>
+void launch_w(const xtr_tpose_config &c, dim3 gd, hipStream_t st, const void *src, void *dst,
+              int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t tiles_r,
+              int64_t tiles_c, int group) {
+    if (c.nt_load && c.nt_store && W == 16)
+        launch_k<EB, W, true, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                                    c.xcd, group);
+    else if (c.nt_load)
+        launch_k<EB, W, true, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                     tiles_c, c.xcd, group);
+    else if (c.nt_store && W == 16)
+        launch_k<EB, W, false, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                     tiles_c, c.xcd, group);
+    else
+        launch_k<EB, W, false, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
+                                      tiles_c, c.xcd, group);
 }
 
 template <int EB>
@@ -359,7 +522,6 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     const int64_t tiles_r = (rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
     const int64_t tiles_c = (cols + Geo<EB>::TC - 1) / Geo<EB>::TC;
     const int64_t ntiles = tiles_r * tiles_c;
-    const int vec = vec_aligned(src, dst, ld_src, ld_dst, EB) ? 1 : 0;
     int64_t grid = ntiles < MAX_GRID ? ntiles : MAX_GRID;
     if (c.blocks_per_cu > 0) {
         const int64_t g = (int64_t)cu_count() * c.blocks_per_cu;
@@ -367,31 +529,66 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     }
     const int group = c.group < 1 ? 1 : c.group;
     const dim3 gd((unsigned)grid);
-    if (c.nt_load && c.nt_store)
-        launch_k<EB, true, true>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                                 vec, c.xcd, group);
-    else if (c.nt_load)
-        launch_k<EB, true, false>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                  tiles_c, vec, c.xcd, group);
-    else if (c.nt_store)
-        launch_k<EB, false, true>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                  tiles_c, vec, c.xcd, group);
-    else
-        launch_k<EB, false, false>(gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                   tiles_c, vec, c.xcd, group);
+    switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
+    case 16: launch_w<EB, 16>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                              group); break;
+    case 8:
+        if constexpr (EB <= 8)
+            launch_w<EB, 8>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                            group);
+        break;
+    case 4:
+        if constexpr (EB <= 4)
+            launch_w<EB, 4>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                            group);
+        break;
+    default:
+        if constexpr (EB <= 2)
+            launch_w<EB, 0>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
+                            group);
+        break;
+    }
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
 
-template <int EB>
-void launch_batched(int64_t grid, hipStream_t st, const Job *jobs, int nj, int64_t ntiles) {
+// Streaming (nontemporal) stores only for whole 16-byte pieces: narrower
+// pieces leave each store instruction covering part of every line, and those
+// lines must merge in L2 before they go to HBM.
+template <int EB, int W, bool OFF32>
+void launch_batched_w(int64_t grid, hipStream_t st, const Job *jobs, int nj, int64_t ntiles) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
-    if (c.nt_load && c.nt_store)
-        hipLaunchKernelGGL((k_tpose_batched<EB, true, true>), dim3((unsigned)grid), dim3(NT), 0, st,
-                           jobs, nj, ntiles);
+    constexpr bool WIDE = (W == 16);
+    if (c.nt_load && c.nt_store && WIDE)
+        hipLaunchKernelGGL((k_tpose_batched<EB, W, true, WIDE, OFF32>), dim3((unsigned)grid),
+                           dim3(NT), 0, st, jobs, nj, ntiles);
+    else if (c.nt_load)
+        hipLaunchKernelGGL((k_tpose_batched<EB, W, true, false, OFF32>), dim3((unsigned)grid),
+                           dim3(NT), 0, st, jobs, nj, ntiles);
     else
-        hipLaunchKernelGGL((k_tpose_batched<EB, false, false>), dim3((unsigned)grid), dim3(NT), 0,
-                           st, jobs, nj, ntiles);
+        hipLaunchKernelGGL((k_tpose_batched<EB, W, false, false, OFF32>), dim3((unsigned)grid),
+                           dim3(NT), 0, st, jobs, nj, ntiles);
+}
+
+template <int EB>
+void launch_batched(int w, bool off32, int64_t grid, hipStream_t st, const Job *jobs, int nj,
+                    int64_t ntiles) {
+#define XTR_BW(WW)                                                                        \
+    if (off32) launch_batched_w<EB, WW, true>(grid, st, jobs, nj, ntiles);                \
+    else launch_batched_w<EB, WW, false>(grid, st, jobs, nj, ntiles);
+    switch (w) {
+    case 16: XTR_BW(16) break;
+    case 8:
+        if constexpr (EB <= 8) { XTR_BW(8) }
+        break;
+    case 4:
+        if constexpr (EB <= 4) { XTR_BW(4) }
+        break;
+    default:
+        if constexpr (EB <= 2) { XTR_BW(0) }
+        break;
+    }
+#undef XTR_BW
 }
 
 }  // namespace
@@ -408,13 +605,18 @@ int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     }
 }
 
-// Host-side form of a batch: jobs grouped by element size, each group with its
-// own slice of the device table and its own concatenated tile space.
+// Host-side form of a batch: jobs grouped by (element size, piece width,
+// 32-bit offsets); each group has its own slice of the device table, its own
+// concatenated tile space and one persistent launch.
+constexpr int NGROUPS = 4 * 4 * 2;   // eb slot x piece class (16, 8, 4, elem) x off32
+int wclass(int w) { return w == 16 ? 0 : w == 8 ? 1 : w == 4 ? 2 : 3; }
+int wof(int wc) { return wc == 0 ? 16 : wc == 1 ? 8 : wc == 2 ? 4 : 0; }
+
 struct BatchTable {
-    std::vector<Job> all;          // groups concatenated: 1-, 2-, 4-, 8-byte elements
-    size_t at[4] = {0, 0, 0, 0};   // first job of each group in `all`
-    int nj[4] = {0, 0, 0, 0};
-    int64_t ntiles[4] = {0, 0, 0, 0};
+    std::vector<Job> all;                // groups concatenated
+    size_t at[NGROUPS] = {};             // first job of each group in `all`
+    int nj[NGROUPS] = {};
+    int64_t ntiles[NGROUPS] = {};
 };
 
 int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, BatchTable &bt) {
@@ -429,23 +631,23 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
             return rc;
         }
     }
-    std::vector<Job> groups[4];
+    std::vector<Job> groups[NGROUPS];
     for (int64_t i = 0; i < count; i++) {
         const xtr_tpose_desc &d = descs[i];
         if (d.rows == 0 || d.cols == 0) continue;
         const int eb = elem_bytes(d.dtype);
-        const int g = cfg_slot(eb);
         Job j;
         j.src = (const unsigned char *)d.src;
         j.dst = (unsigned char *)d.dst;
         j.rows = d.rows; j.cols = d.cols; j.ld_src = d.ld_src; j.ld_dst = d.ld_dst;
+        j.w = piece_width(d.src, d.dst, d.ld_src, d.ld_dst, eb);
+        j._pad = 0;
+        const int g = (cfg_slot(eb) * 4 + wclass(j.w)) * 2 + (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0);
         j.tile_base = bt.ntiles[g];
         bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
-        j.vec_ok = vec_aligned(d.src, d.dst, d.ld_src, d.ld_dst, eb) ? 1 : 0;
-        j._pad = 0;
         groups[g].push_back(j);
     }
-    for (int g = 0; g < 4; g++) {
+    for (int g = 0; g < NGROUPS; g++) {
         bt.at[g] = bt.all.size();
         bt.nj[g] = (int)groups[g].size();
         bt.all.insert(bt.all.end(), groups[g].begin(), groups[g].end());
@@ -453,21 +655,21 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
     return XTR_OK;
 }
 
-// One persistent launch per non-empty element-size group; `dev` is the device
-// copy of bt.all.
+// One persistent launch per non-empty group; `dev` is the device copy of bt.all.
 int launch_batch(const BatchTable &bt, const Job *dev, hipStream_t stream) {
-    for (int g = 0; g < 4; g++) {
+    for (int g = 0; g < NGROUPS; g++) {
         if (!bt.nj[g]) continue;
-        // resident workgroups per CU: LDS-limited for 1- and 2-byte tiles (64 / 32 KiB)
-        const int64_t occ = (int64_t)cu_count() * (g == 0 ? 2 : g == 1 ? 4 : 8);
+        const int slot = g / 8, w = wof((g / 2) % 4);
+        const bool off32 = (g & 1) != 0;
+        const int64_t occ = (int64_t)cu_count() * 8;
         int64_t grid = bt.ntiles[g] < occ ? bt.ntiles[g] : occ;
         if (grid < 1) grid = 1;
         const Job *jobs = dev + bt.at[g];
-        switch (g) {
-        case 0: launch_batched<1>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        case 1: launch_batched<2>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        case 2: launch_batched<4>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        default: launch_batched<8>(grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        switch (slot) {
+        case 0: launch_batched<1>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        case 1: launch_batched<2>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        case 2: launch_batched<4>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        default: launch_batched<8>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
         }
         XTR_HIP(hipGetLastError());
     }

@@ -105,12 +105,12 @@ def tune_reduce(xtr, torch, dt: str, log=print):
     orig = xtr.reduce_config(dt)
     best = None
     try:
-        for nt in (1, 0):
-            xtr.set_reduce_config(dt, nt_load=nt)
+        for nt, bpc in itertools.product((1, 0), (0, 2, 3, 4, 5, 6, 8)):
+            xtr.set_reduce_config(dt, nt_load=nt, blocks_per_cu=bpc)
             sec = _time(torch, lambda: xtr.reduce_sum(src, out, n=n, dtype=dt))
             gbs = n * eb / sec / 1e9
             if best is None or gbs > best[0]:
-                best = (gbs, {"nt_load": nt})
+                best = (gbs, {"nt_load": nt, "blocks_per_cu": bpc})
     finally:
         xtr.set_reduce_config(dt, **orig)
     log(f"tune sum {dt} n={n}: best {best[0]:.1f} GB/s {best[1]}")

@@ -74,6 +74,27 @@ def test_mixed_sizes_share_workspace(xtr, orc):
         check(orc, gpu_sum(xtr, fb, "f32"), fb, "f32", n)
 
 
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i32", "i64", "f16"])
+def test_persistent_matches_one_chunk_per_workgroup(xtr, orc, dt):
+    """The persistent, prefetching kernel gives bit-identical results to one
+    workgroup per chunk, for many chunks per workgroup, ragged tails and heads."""
+    orig = xtr.reduce_config(dt)
+    c = CH[dt]
+    try:
+        for k, (n, off) in enumerate([(3 * c, 0), (1000 * c + 17, 1), (2 * c - 1, 3),
+                                      (777 * c, 2), (5 * c + c // 2, 0)]):
+            bits = data(dt, n + off, 1100 + k)
+            xtr.set_reduce_config(dt, blocks_per_cu=0)
+            a = gpu_sum(xtr, bits, dt, off)
+            for bpc in (1, 3):
+                xtr.set_reduce_config(dt, blocks_per_cu=bpc)
+                b = gpu_sum(xtr, bits, dt, off)
+                assert a == b or (math.isnan(a) and math.isnan(b)), (dt, n, off, bpc, a, b)
+            check(orc, a, bits[off:], dt, (dt, n, off))
+    finally:
+        xtr.set_reduce_config(dt, **orig)
+
+
 def test_int64_wraps(xtr, orc):
     big = np.full(10000, 2 ** 62 + 12345, dtype=np.int64)
     want, ov = orc.sum_int(big, "i64")
