@@ -166,11 +166,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--suite", choices=["step", "full"], default="step")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--parts", default="paper,batched,segmented,precision,serving",
+    ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (this build has no multi-GPU path); "
+        print(f"bench.py measures one GPU only (the library has no multi-GPU path); "
               f"--gpus {args.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
 

@@ -185,6 +185,35 @@ def segmented(xtr, torch, log, total=1 << 27, nseg=100000):
     return res
 
 
+# ---------------------------------------------------------------- piece widths
+
+def piece_widths(xtr, torch, log):
+    """Large single transposes whose row pitches allow 16-, 8-, 4-byte or only
+    element-wide global accesses (the tile routine picks the widest piece that
+    divides both pointers and both pitches)."""
+    cases = [("f32", 16384, 16384, 16), ("f32", 16382, 16382, 8), ("f32", 16383, 16383, 4),
+             ("bf16", 12288, 20000, 16), ("bf16", 12292, 20004, 8), ("bf16", 12290, 20002, 4),
+             ("bf16", 12289, 20001, 0), ("u8", 32768, 32768, 16), ("u8", 32764, 32764, 4),
+             ("u8", 32767, 32767, 0), ("f64", 16384, 8192, 16), ("f64", 16383, 8191, 8)]
+    tdt = {"f32": torch.float32, "bf16": torch.int16, "u8": torch.uint8, "f64": torch.float64}
+    eb = {"f32": 4, "bf16": 2, "u8": 1, "f64": 8}
+    res = {}
+    for dt, r, c, w in cases:
+        src = torch.empty((r, c), dtype=tdt[dt], device="cuda")
+        src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(r))
+        dst = torch.empty((c, r), dtype=tdt[dt], device="cuda")
+        sec, _ = _time_dev(torch, lambda: xtr.tpose(src, dst, dtype=dt), reps=10, warm=2)
+        nb = 2 * r * c * eb[dt]
+        key = f"{dt}_{r}x{c}_w{w}"
+        res[key] = {"gbs": round(nb / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
+        if r == 16383 and dt == "f32":   # bit comparison (random bits include NaNs)
+            assert torch.equal(dst.view(torch.int32), src.view(torch.int32).t()), key
+        del src, dst
+    torch.cuda.empty_cache()
+    log("suite piece widths: " + ", ".join(f"{k} {v['gbs']}" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- paper shapes
 
 def paper_shapes(xtr, torch, log):
@@ -226,9 +255,10 @@ def paper_shapes(xtr, torch, log):
     return res
 
 
-def run_all(xtr, torch, log, parts=("paper", "batched", "segmented", "precision", "serving")):
+def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "precision",
+                                   "serving")):
     out = {}
-    for name, fn in (("paper", paper_shapes), ("batched", batched_tpose),
+    for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
                      ("segmented", segmented), ("precision", precision)):
         if name in parts:
             t0 = time.time()

@@ -70,9 +70,11 @@ enum {
  * The copy is of element bits (NaN payloads, -0.0 survive).  Elements of dst
  * in columns [rows, ld_dst) of each dst row are not written.
  * rows == 0 or cols == 0 is a no-op returning XTR_OK.
- * Any alignment of src/dst (to the element size) and any ld is accepted; the
- * 16-byte vector path is used when src, dst, ld_src*elem and ld_dst*elem are
- * 16-byte aligned, and an element-wise path (same result) otherwise.
+ * Any alignment of src/dst (to the element size) and any ld is accepted.
+ * Global accesses move the widest piece (16, 8 or 4 bytes, and at least one
+ * element) that divides src, dst, ld_src*elem and ld_dst*elem; 1- and 2-byte
+ * elements with no such piece are moved one element per lane.  The result is
+ * the same whichever width is used; only the speed differs.
  * Errors: EINVAL (null, negative, small ld), EDTYPE, EOVERLAP, EALIGN.
  */
 int tpose(const void *src, void *dst, int64_t rows, int64_t cols,
@@ -126,8 +128,9 @@ typedef struct {
 } xtr_tpose_desc;
 
 /* Transposes descs[0..count) (host array), each as tpose().  Jobs are grouped
- * by element size; each group runs as one persistent launch whose workgroups
- * stride over the concatenated tile space of its jobs.  count == 0 is a no-op.
+ * by (element size, piece width, whether 32-bit offsets suffice); each group
+ * runs as one persistent launch whose workgroups stride over the concatenated
+ * tile space of its jobs.  count == 0 is a no-op.
  * Every descriptor is validated before anything is enqueued.  dst ranges of
  * different jobs must not overlap each other or any src. */
 int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream);
@@ -222,9 +225,12 @@ int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg);
 int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg);
 
 typedef struct {
-    int32_t nt_load;        /* 1: nontemporal (streaming) 16-byte loads           */
-    int32_t blocks_per_cu;  /* 0: one workgroup per chunk; k in 1..64: persistent  */
-                            /*    workgroups, k per CU, next chunk prefetched      */
+    int32_t nt_load;        /* 1: nontemporal (streaming) 16-byte loads            */
+    int32_t split_chunks;   /* single ranges of >= split_chunks chunks (and > 1):   */
+                            /*    workgroups store plain per-chunk partials and     */
+                            /*    small follow-up kernels add them level by level;  */
+                            /*    smaller ranges (or 0 = always) combine in-kernel  */
+                            /*    through atomic tickets.  Same result either way.  */
     int32_t _reserved[6];
 } xtr_reduce_config;
 

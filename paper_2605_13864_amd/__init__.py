@@ -41,7 +41,7 @@ class TposeConfig(C.Structure):
 
 
 class ReduceConfig(C.Structure):
-    _fields_ = [("nt_load", C.c_int32), ("blocks_per_cu", C.c_int32), ("_reserved", C.c_int32 * 6)]
+    _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("_reserved", C.c_int32 * 6)]
 
 
 class TposeDesc(C.Structure):
@@ -391,6 +391,9 @@ def tpose_config(elem_bytes: int) -> dict:
 
 def set_tpose_config(elem_bytes: int, **kw):
     cur = tpose_config(elem_bytes)
+    bad = set(kw) - set(cur)
+    if bad:
+        raise TypeError(f"set_tpose_config: unknown settings {sorted(bad)}")
     cur.update(kw)
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
                     cur["blocks_per_cu"])
@@ -400,13 +403,16 @@ def set_tpose_config(elem_bytes: int, **kw):
 def reduce_config(dtype) -> dict:
     c = ReduceConfig()
     _check(load().xtr_reduce_get_config(_code(dtype), C.byref(c)), "xtr_reduce_get_config")
-    return {"nt_load": c.nt_load, "blocks_per_cu": c.blocks_per_cu}
+    return {"nt_load": c.nt_load, "split_chunks": c.split_chunks}
 
 
 def set_reduce_config(dtype, **kw):
     cur = reduce_config(dtype)
+    bad = set(kw) - set(cur)
+    if bad:
+        raise TypeError(f"set_reduce_config: unknown settings {sorted(bad)}")
     cur.update(kw)
-    c = ReduceConfig(cur["nt_load"], cur["blocks_per_cu"])
+    c = ReduceConfig(cur["nt_load"], cur["split_chunks"])
     _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
 
 

@@ -34,7 +34,7 @@ def hipcc() -> str:
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-fno-gpu-rdc",
     "-ffp-contract=off", "-Wall", "-Wno-unused-function",
-    # packed fp32 instructions off (wrong results observed on the test machines)
+    # packed fp32 instructions off: some of their forms have given silently wrong results
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     f"-I{os.path.join(ROOT, 'include')}",
 ]
@@ -60,7 +60,7 @@ def build(jobs: int = 4, save_temps: str | None = None) -> str:
     extra = []
     if save_temps:
         os.makedirs(save_temps, exist_ok=True)
-        extra = [f"-save-temps={save_temps}"] if False else ["-save-temps"]
+        extra = ["-save-temps"]      # intermediates land in the current directory
     cwd = os.getcwd()
     if save_temps:
         os.chdir(save_temps)

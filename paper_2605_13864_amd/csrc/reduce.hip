@@ -374,31 +374,64 @@ __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg,
     return chunk_tree<DT, MODE>(acc);
 }
 
-// The 16-byte vectors of full chunk j (vector u of thread t is vector
-// u * 256 + t of the chunk), for the software-pipelined persistent kernel.
-template <int DT, bool NT>
-__device__ __forceinline__ void load_chunk(uint4 *v, const unsigned char *body, int64_t j) {
-    constexpr int EB = DTI<DT>::EB;
-    constexpr int64_t CH = chunk_elems<DT>();
-    const uint4 *vp = reinterpret_cast<const uint4 *>(body + j * CH * EB) + threadIdx.x;
-#pragma unroll
-    for (int u = 0; u < U; u++) v[u] = load16<NT>(vp + u * NTHR);
-}
+// Ranges whose body fits in the first two vector rows of a chunk
+// (body <= 2 * 256 * V elements) are "small": one wave computes their value.
+template <int DT> constexpr int64_t small_max() { return (int64_t)2 * NTHR * vec_elems<DT>(); }
 
-// Value of full chunk j from its preloaded vectors: identical arithmetic to
-// reduce_chunk (head elements first, then the vectors in order).
-template <int DT, int MODE>
-__device__ __forceinline__ typename PartT<MODE>::T full_chunk_value(const uint4 *v, const Range &rg,
-                                                                     int64_t j) {
+// Value of the single chunk of a small range, computed by ONE wave with
+// exactly the arithmetic of reduce_chunk + chunk_tree on a whole workgroup:
+// lane l plays threads l, l + 64, l + 128 and l + 192, keeps their
+// accumulators apart, reduces each set of 64 with the same wave butterfly,
+// and adds the four wave values in the order of the LDS tree.  The result is
+// therefore bit-identical to the workgroup form (and to reduce_sum alone).
+template <int DT, int MODE, bool NT>
+__device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range &rg) {
     constexpr int EB = DTI<DT>::EB;
-    Acc<DT, MODE> acc;
-    acc.init();
-    if (j == 0 && threadIdx.x == 0) {
-        for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
-    }
+    constexpr int V = vec_elems<DT>();
+    constexpr int US = 2;                       // vector rows a small body can reach
+    static_assert(US <= U, "small ranges use the first rows of a chunk");
+    const int l = threadIdx.x & 63;
+    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
+    const int64_t body_n = rg.n - rg.head;
+    uint4 v[US][NW];
 #pragma unroll
-    for (int u = 0; u < U; u++) acc_vec(acc, v[u]);
-    return chunk_tree<DT, MODE>(acc);
+    for (int u = 0; u < US; u++)
+#pragma unroll
+        for (int w = 0; w < NW; w++) {
+            const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
+            v[u][w] = (e + V <= body_n) ? load16<NT>(reinterpret_cast<const uint4 *>(body + e * EB))
+                                        : make_uint4(0, 0, 0, 0);
+        }
+    Acc<DT, MODE> a0;
+    a0.init();
+    using WV = decltype(wave_reduce(a0.finish()));
+    WV wv[NW];
+#pragma unroll
+    for (int w = 0; w < NW; w++) {
+        Acc<DT, MODE> acc;
+        acc.init();
+        if (w == 0 && l == 0) {
+            for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
+        }
+#pragma unroll
+        for (int u = 0; u < US; u++) {
+            const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
+            if (e + V <= body_n) {
+                acc_vec(acc, v[u][w]);
+            } else if (e < body_n) {
+                const int m = (int)(body_n - e);
+#pragma unroll
+                for (int i = 0; i < V; i++)
+                    if (i < m) acc_elem(acc, body + (e + i) * EB, i);
+            }
+        }
+        wv[w] = wave_reduce(acc.finish());
+    }
+    if constexpr (MODE == COMP) {
+        return pair_value(pair_add(pair_add(wv[0], wv[1]), pair_add(wv[2], wv[3])));
+    } else {
+        return (wv[0] + wv[1]) + (wv[2] + wv[3]);
+    }
 }
 
 // ---------------------------------------------------------------- grid combine
@@ -456,23 +489,27 @@ __device__ __forceinline__ void drain() {
 // consecutive partials as (p[4l] + p[4l+1]) + (p[4l+2] + p[4l+3]), then the
 // xor butterfly over the 64 lanes -- a balanced pairwise tree over the 256
 // indices (zero-padded), the same association at every call site.
-template <typename P>
-__device__ __forceinline__ P group_sum(P *part, int64_t gsize) {
+// ATOMIC: read through agent-scope RMWs (partials published by workgroups of
+// the same launch); otherwise plain loads (partials written by an earlier
+// launch on the stream).  The arithmetic is the same either way.
+template <typename P, bool ATOMIC = true>
+__device__ __forceinline__ P group_sum(const P *part, int64_t gsize) {
     const int l = threadIdx.x & 63;
     P q[4];
 #pragma unroll
-    for (int i = 0; i < 4; i++) q[i] = (4 * l + i < gsize) ? fetch(&part[4 * l + i]) : (P)0;
+    for (int i = 0; i < 4; i++) {
+        if (4 * l + i >= gsize) q[i] = (P)0;
+        else if constexpr (ATOMIC) q[i] = fetch(const_cast<P *>(&part[4 * l + i]));
+        else q[i] = part[4 * l + i];
+    }
     return wave_butterfly<P>((q[0] + q[1]) + (q[2] + q[3]));
 }
 
 // Grid combine, run by the first wave of a workgroup only (the other waves
 // have already left, so they never wait on the atomics' round trips).
-// `published`: the level-0 partial of chunk j is already published and
-// drained (the persistent kernel defers its tickets); `last0` then tells
-// whether this wave took the group's last level-0 ticket.
 template <int MODE>
 __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T value,
-                             const Levels &lv, bool published = false, bool last0 = false) {
+                             const Levels &lv) {
     using P = typename PartT<MODE>::T;
     const int l = threadIdx.x & 63;
     int64_t idx = j, cnt = rg.nchunks;
@@ -485,21 +522,15 @@ __device__ void grid_combine(const Range &rg, int64_t j, typename PartT<MODE>::T
         const int64_t gsize = (cnt - g * RADIX) < RADIX ? (cnt - g * RADIX) : RADIX;
         P *part = reinterpret_cast<P *>(lv.part[level]);
         uint32_t *ticket = lv.ctr + (rg.chunk_base + g) * MAXLEV + level;
-        int last;
-        if (published && level == 0) {
-            last = last0;
-        } else {
-            int mine = 0;
-            if (l == 0) {
-                publish(&part[rg.chunk_base + idx], value);
-                drain();       // the partial is at the coherence point before the ticket
-                uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
-                                                      __HIP_MEMORY_SCOPE_AGENT);
-                mine = (old == (uint32_t)(gsize - 1));
-            }
-            last = __shfl(mine, 0, 64);
+        int mine = 0;
+        if (l == 0) {
+            publish(&part[rg.chunk_base + idx], value);
+            drain();           // the partial is at the coherence point before the ticket
+            uint32_t old = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
+                                                  __HIP_MEMORY_SCOPE_AGENT);
+            mine = (old == (uint32_t)(gsize - 1));
         }
-        if (!last) return;
+        if (!__shfl(mine, 0, 64)) return;
         value = group_sum<P>(part + rg.chunk_base + g * RADIX, gsize);
         if (l == 0)            // leave the ticket at zero for the next call
             __hip_atomic_exchange(ticket, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -519,58 +550,31 @@ __global__ void __launch_bounds__(NTHR) k_reduce_one(Range rg, Levels lv) {
     grid_combine<MODE>(rg, j, v, lv);
 }
 
-// Single range, persistent: workgroup b takes chunks b, b + G, b + 2G, ...
-// with the next chunk's loads in flight while the current one is reduced.
-// Each chunk's value is published without waiting; after its last chunk the
-// workgroup waits once and then takes the tickets of all its chunks (the
-// per-chunk values and the combine order are those of k_reduce_one).
+// Single range, split combine: each workgroup writes its chunk's value with a
+// plain store and retires at once (no atomics, no waiting); k_combine_level
+// launches then add the partials level by level.
 template <int DT, int MODE, bool NT>
-__global__ void __launch_bounds__(NTHR) k_reduce_pers(Range rg, Levels lv) {
+__global__ void __launch_bounds__(NTHR) k_reduce_parts(Range rg, Levels lv) {
     using P = typename PartT<MODE>::T;
-    constexpr int EB = DTI<DT>::EB;
-    constexpr int64_t CH = chunk_elems<DT>();
-    const int64_t G = gridDim.x, n = rg.nchunks;
-    const int t = threadIdx.x;
-    if ((int64_t)blockIdx.x >= n) return;
-    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
-    const int64_t body_n = rg.n - rg.head;
-    const int64_t nfull = body_n > 0 ? body_n / CH : 0;   // chunks 0 .. nfull-1 are full
-    P *part0 = reinterpret_cast<P *>(lv.part[0]);
-    uint4 cur[U], nxt[U];
-    int64_t j = blockIdx.x;
-    if (j < nfull) load_chunk<DT, NT>(cur, body, j);
-    for (; j < nfull; j += G) {
-        if (j + G < nfull) load_chunk<DT, NT>(nxt, body, j + G);     // prefetch
-        const P val = full_chunk_value<DT, MODE>(cur, rg, j);
-        if (t == 0) publish(&part0[rg.chunk_base + j], val);
-#pragma unroll
-        for (int u = 0; u < U; u++) cur[u] = nxt[u];
-    }
-    if (j == nfull && nfull < n) {   // the one partial (or empty) last chunk
-        const P val = reduce_chunk<DT, MODE, NT>(rg, j);
-        if (t == 0) publish(&part0[rg.chunk_base + j], val);
-    }
-    if (t >= 64) return;
-    if (t == 0) drain();   // every partial of this workgroup is at the coherence point
-    // the level-0 tickets of all this workgroup's chunks, 64 at a time, one per lane
-    const int64_t nmine = (n - 1 - blockIdx.x) / G + 1;
-    for (int64_t base = 0; base < nmine; base += 64) {
-        const int64_t i = base + t;
-        int last = 0;
-        if (i < nmine) {
-            const int64_t jj = blockIdx.x + i * G;
-            const int64_t g = jj / RADIX;
-            const int64_t gsize = (n - g * RADIX) < RADIX ? (n - g * RADIX) : RADIX;
-            uint32_t old = __hip_atomic_fetch_add(lv.ctr + (rg.chunk_base + g) * MAXLEV, 1u,
-                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            last = (old == (uint32_t)(gsize - 1));
-        }
-        uint64_t mask = __ballot(last);
-        while (mask) {                 // finish the groups whose last ticket we took
-            const int lane = __builtin_ctzll(mask);
-            mask &= mask - 1;
-            grid_combine<MODE>(rg, blockIdx.x + (base + lane) * G, P(0), lv, true, true);
-        }
+    const int64_t j = blockIdx.x;
+    const P v = reduce_chunk<DT, MODE, NT>(rg, j);
+    if (threadIdx.x == 0) reinterpret_cast<P *>(lv.part[0])[j] = v;
+}
+
+// One level of the combine tree: wave g sums partials [256 g, 256 g + 256) of
+// `in` (cnt of them) exactly as the last workgroup of a ticket group does, and
+// writes the level's partial g, or the result when the level has one group.
+template <typename P>
+__global__ void __launch_bounds__(NTHR) k_combine_level(const P *__restrict__ in, int64_t cnt,
+                                                        P *__restrict__ out, P *__restrict__ dst) {
+    const int64_t g = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
+    const int64_t ng = (cnt + RADIX - 1) / RADIX;
+    if (g >= ng) return;
+    const int64_t gsize = (cnt - g * RADIX) < RADIX ? (cnt - g * RADIX) : RADIX;
+    const P v = group_sum<P, false>(in + g * RADIX, gsize);
+    if ((threadIdx.x & 63) == 0) {
+        if (ng == 1) *dst = v;
+        else out[g] = v;
     }
 }
 
@@ -619,7 +623,8 @@ __device__ __forceinline__ Range seg_range(const unsigned char *src, const int64
 // Pass 1: chunk count of every segment, and per-block totals.
 __global__ void __launch_bounds__(NTHR) k_seg_count(const unsigned char *src, const int64_t *off,
                                                   int64_t nseg, int eb, int64_t ch,
-                                                  int64_t *counts, int64_t *block_tot) {
+                                                  int64_t small, int64_t *counts,
+                                                  int64_t *block_tot) {
     __shared__ int64_t sh[NW];
     const int64_t base = (int64_t)blockIdx.x * NTHR * 4;
     int64_t sum = 0;
@@ -627,7 +632,9 @@ __global__ void __launch_bounds__(NTHR) k_seg_count(const unsigned char *src, co
     for (int k = 0; k < 4; k++) {
         const int64_t s = base + k * NTHR + threadIdx.x;
         if (s < nseg) {
-            int64_t c = seg_range(src, off, s, eb, ch).nchunks;
+            const Range r = seg_range(src, off, s, eb, ch);
+            // small segments are reduced by one wave each and take no chunk slot
+            int64_t c = (r.n - r.head <= small) ? 0 : r.nchunks;
             // a decreasing pair or a negative start poisons the total so that
             // the reduction kernel sees it exceed the chunk space (invalid table)
             if (off[s + 1] < off[s] || off[s] < 0) c = (int64_t)1 << 40;
@@ -701,33 +708,53 @@ __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const
     }
 }
 
-// Pass 4: one workgroup per global chunk.
+// Pass 4a: small segments, one wave each (grid-stride over segments).
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *src,
+                                                         const int64_t *off,
+                                                         const int64_t *chunk_base, int64_t nseg,
+                                                         int64_t cap, void *out) {
+    using P = typename PartT<MODE>::T;
+    if (chunk_base[nseg] > cap) return;   // invalid table: k_reduce_seg writes every output
+    const int64_t nwaves = (int64_t)gridDim.x * NW;
+    for (int64_t s = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); s < nseg; s += nwaves) {
+        const Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(),
+                                   (unsigned char *)out, (int)sizeof(P));
+        if (rg.n - rg.head > small_max<DT>()) continue;   // a chunked segment (pass 4b)
+        const P v = small_chunk_value<DT, MODE, NT>(rg);
+        if ((threadIdx.x & 63) == 0) *reinterpret_cast<P *>(rg.dst) = v;
+    }
+}
+
+// Pass 4b: the chunks of the other segments, workgroups striding over the
+// chunk space.  The first wave runs the grid combine of each chunk while the
+// others go on to the next chunk (they meet again at its LDS barrier).
 template <int DT, int MODE, bool NT>
 __global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, const int64_t *off,
                                                    const int64_t *chunk_base,
                                                    const int32_t *chunk_seg, int64_t nseg,
                                                    int64_t cap, Levels lv, void *out) {
-    const int64_t b = blockIdx.x;
+    using P = typename PartT<MODE>::T;
     const int64_t total = chunk_base[nseg];
     if (total > cap) {   // invalid offsets table: defined outputs, no reads, no tickets
-        if (b < nseg) {
-            using P = typename PartT<MODE>::T;
-            if constexpr (MODE == INTM) reinterpret_cast<P *>(out)[b] = 0;
-            else reinterpret_cast<P *>(out)[b] = (P)__builtin_nan("");
+        for (int64_t s = (int64_t)blockIdx.x * NTHR + threadIdx.x; s < nseg;
+             s += (int64_t)gridDim.x * NTHR) {
+            if constexpr (MODE == INTM) reinterpret_cast<P *>(out)[s] = 0;
+            else reinterpret_cast<P *>(out)[s] = (P)__builtin_nan("");
         }
         return;
     }
-    if (b >= total) return;   // unused tail of the grid
-    const int64_t s = chunk_seg[b];
-    if (s < 0 || s >= nseg) return;
-    Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(), (unsigned char *)out,
-                         (int)sizeof(typename PartT<MODE>::T));
-    rg.chunk_base = chunk_base[s];
-    const int64_t j = b - rg.chunk_base;
-    if (j < 0 || j >= rg.nchunks) return;
-    auto v = reduce_chunk<DT, MODE, NT>(rg, j);
-    if (threadIdx.x >= 64) return;
-    grid_combine<MODE>(rg, j, v, lv);
+    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+        const int64_t s = chunk_seg[b];
+        if (s < 0 || s >= nseg) continue;
+        Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(), (unsigned char *)out,
+                             (int)sizeof(P));
+        rg.chunk_base = chunk_base[s];
+        const int64_t j = b - rg.chunk_base;
+        if (j < 0 || j >= rg.nchunks) continue;
+        auto v = reduce_chunk<DT, MODE, NT>(rg, j);
+        if (threadIdx.x < 64) grid_combine<MODE>(rg, j, v, lv);
+    }
 }
 
 // ---------------------------------------------------------------- host side
@@ -846,24 +873,36 @@ int check_sum_args(const void *src, int64_t n, const void *out, int dtype, bool 
     }
 
 // Tuned settings per dtype (index = dtype code).
+constexpr int SPLIT_DEFAULT = 1024;
 xtr_reduce_config g_rcfg[XTR_U16 + 1] = {};
 bool rcfg_init() {
     for (auto &c : g_rcfg) {
         c.nt_load = 1;
-        c.blocks_per_cu = 0;
+        c.split_chunks = SPLIT_DEFAULT;
     }
     return true;
 }
 bool g_rcfg_ready = rcfg_init();
 
+// A range of at least split_chunks chunks (and more than one) uses the split
+// combine; the others combine in-kernel through tickets.  Same value either way.
 template <int DT, int MODE>
 void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
+    using P = typename PartT<MODE>::T;
     const xtr_reduce_config &c = g_rcfg[DT];
-    const int64_t pers = (int64_t)cu_count() * c.blocks_per_cu;
-    if (c.blocks_per_cu > 0 && rg.nchunks > pers) {
-        const dim3 g((unsigned)pers);
-        if (c.nt_load) hipLaunchKernelGGL((k_reduce_pers<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
-        else hipLaunchKernelGGL((k_reduce_pers<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
+    if (c.split_chunks > 0 && rg.nchunks >= c.split_chunks && rg.nchunks > 1) {
+        const dim3 g((unsigned)rg.nchunks);
+        if (c.nt_load) hipLaunchKernelGGL((k_reduce_parts<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
+        else hipLaunchKernelGGL((k_reduce_parts<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
+        int64_t cnt = rg.nchunks;
+        for (int level = 0; cnt > 1; level++) {
+            const int64_t ng = (cnt + RADIX - 1) / RADIX;
+            const dim3 gl((unsigned)((ng + NW - 1) / NW));
+            hipLaunchKernelGGL((k_combine_level<P>), gl, dim3(NTHR), 0, st,
+                               reinterpret_cast<const P *>(lv.part[level]), cnt,
+                               reinterpret_cast<P *>(lv.part[level + 1]), reinterpret_cast<P *>(rg.dst));
+            cnt = ng;
+        }
         return;
     }
     if (c.nt_load)
@@ -882,16 +921,27 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, false>), dim3((unsigned)nchunks), dim3(NTHR), 0,
                            st, tab, nr, lv);
 }
+// Both passes run as resident grids (8 workgroups per CU at most) that stride
+// over their segments / chunks: the chunk space is only known on the device.
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const int32_t *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
-    const int64_t grid = cap > nseg ? cap : nseg;
-    if (g_rcfg[DT].nt_load)
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), dim3((unsigned)grid), dim3(NTHR), 0, st,
-                           src, off, cb, cs, nseg, cap, lv, out);
-    else
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), dim3((unsigned)grid), dim3(NTHR), 0, st,
-                           src, off, cb, cs, nseg, cap, lv, out);
+    const int64_t occ = (int64_t)cu_count() * 8;
+    const int64_t gs_n = (nseg + NW - 1) / NW;
+    const dim3 gs((unsigned)(gs_n < occ ? gs_n : occ));
+    const int64_t gc_n = cap > nseg ? cap : nseg;
+    const dim3 gc((unsigned)(gc_n < occ ? gc_n : occ));
+    if (g_rcfg[DT].nt_load) {
+        hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, true>), gs, dim3(NTHR), 0, st, src, off,
+                           cb, nseg, cap, out);
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), gc, dim3(NTHR), 0, st, src, off, cb, cs,
+                           nseg, cap, lv, out);
+    } else {
+        hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, false>), gs, dim3(NTHR), 0, st, src, off,
+                           cb, nseg, cap, out);
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), gc, dim3(NTHR), 0, st, src, off, cb, cs,
+                           nseg, cap, lv, out);
+    }
 }
 
 int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *ws,
@@ -1025,8 +1075,9 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     int64_t *btot = (int64_t *)(w + L.btot);
     int32_t *cmap = (int32_t *)(w + L.cmap);
     const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
+    const int64_t small = (int64_t)2 * NTHR * (16 / eb);   // small_max<DT>() of the kernels
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NTHR), 0, st,
-                       (const unsigned char *)src, offsets, nseg, eb, ch, counts, btot);
+                       (const unsigned char *)src, offsets, nseg, eb, ch, small, counts, btot);
     hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NTHR), 0, st, btot, nblk);
     hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NTHR), 0, st, (const int64_t *)counts,
                        (const int64_t *)btot, nseg, cap, cbase, cmap);
@@ -1133,8 +1184,8 @@ int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
 int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
     if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: bad arguments");
-    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
-        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: blocks_per_cu in [0, 64]");
+    if (cfg->split_chunks < 0)
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: split_chunks must be >= 0");
     xtr::g_rcfg[dtype] = *cfg;
     return XTR_OK;
 }

@@ -53,9 +53,16 @@ template <> struct Elem<2> { using T = uint16_t; };
 template <> struct Elem<4> { using T = uint32_t; };
 template <> struct Elem<8> { using T = uint64_t; };
 
-// Physical 16-byte chunk of logical chunk k in tile row `row`.
+// Physical 16-byte chunk of logical chunk k in tile row `row`: XOR with a
+// per-row key, so each row holds a permutation of its chunks.  The key
+// (row / V) ^ (row % V) * (16 / V) takes 16 distinct values both over the rows
+// {b * V + i : b = 0..15} (fixed i) that a 16-lane group reads in the V x V
+// block layout, and over the rows that 8 consecutive lanes read in the narrow
+// piece layout (rows k * E + e for k = 0..7, E = 1, 2, 4 or 8 elements per
+// piece), so neither read pattern serialises on LDS banks.
 template <int EB> __device__ __forceinline__ int swz(int row, int k) {
-    return k ^ ((row / Geo<EB>::V) & 15);
+    constexpr int V = Geo<EB>::V;
+    return k ^ (((row / V) ^ ((row % V) * (16 / V))) & 15);
 }
 
 // ---------------------------------------------------------------- register
@@ -187,11 +194,35 @@ template <int W, bool NT> __device__ __forceinline__ void stw(unsigned char *p, 
     if constexpr (NT) __builtin_nontemporal_store(v, reinterpret_cast<T *>(p));
     else *reinterpret_cast<T *>(p) = v;
 }
-// piece q of a 16-byte vector
-template <int W> __device__ __forceinline__ typename PieceT<W>::T piece(const uint4 &o, int q) {
-    if constexpr (W == 16) return u32x4{o.x, o.y, o.z, o.w};
-    else if constexpr (W == 8) return q == 0 ? u32x2{o.x, o.y} : u32x2{o.z, o.w};
-    else return dw(o, q);
+// Element i of a 16-byte vector of EB-byte elements (i known at compile time).
+template <int EB> __device__ __forceinline__ uint64_t elem_at(const uint4 &v, int i) {
+    if constexpr (EB == 8) return i == 0 ? ((uint64_t)v.y << 32 | v.x) : ((uint64_t)v.w << 32 | v.z);
+    else if constexpr (EB == 4) return dw(v, i);
+    else if constexpr (EB == 2) return (dw(v, i >> 1) >> (16 * (i & 1))) & 0xffffu;
+    else return (dw(v, i >> 2) >> (8 * (i & 3))) & 0xffu;
+}
+
+// Narrow-piece transpose: a[e] holds V elements of tile row e (e < E = W / EB
+// rows); out[i] is the W-byte piece (a[0][i], a[1][i], ..., a[E-1][i]), i.e.
+// E consecutive elements of dst row i.  W = 16 is block_transpose.
+template <int EB, int W>
+__device__ __forceinline__ void piece_transpose(const uint4 *a, typename PieceT<W>::T *out) {
+    constexpr int V = 16 / EB, E = W / EB;
+    if constexpr (W == 16) {
+        uint4 o[V];
+        block_transpose<EB>(a, o);
+#pragma unroll
+        for (int i = 0; i < V; i++) out[i] = u32x4{o[i].x, o[i].y, o[i].z, o[i].w};
+    } else {
+#pragma unroll
+        for (int i = 0; i < V; i++) {
+            uint64_t r = 0;
+#pragma unroll
+            for (int e = 0; e < E; e++) r |= elem_at<EB>(a[e], i) << (8 * EB * e);
+            if constexpr (W == 8) out[i] = u32x2{(uint32_t)r, (uint32_t)(r >> 32)};
+            else out[i] = (uint32_t)r;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- one tile
@@ -263,42 +294,48 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
 
     __syncthreads();   // ownership of the LDS tile moves from loaders to storers
 
-    // phase 2: thread owns the V x V block (rows bq*V.., cols bc*V..)
+    // phase 2: P lanes per 256-byte dst row segment.  Lane k stores piece k,
+    // i.e. src rows k*E .. k*E+E-1 of one src column, so the lanes of a store
+    // instruction write consecutive W-byte pieces of a dst row (whole lines
+    // per instruction whatever W is).  The lane reads E 16-byte row chunks
+    // from LDS and transposes them in registers into V pieces, one per dst
+    // row of the chunk.  With W = 16 this is the V x V block transpose.
     {
-        const int bq = t & 15, bc = t >> 4;
-        uint4 a[V], o[V];
-#pragma unroll
-        for (int i = 0; i < V; i++) {
-            const int row = bq * V + i;
-            a[i] = lds[row * 16 + swz<EB>(row, bc)];
-        }
-        block_transpose<EB>(a, o);
+        constexpr int CPT = 16 / RP;                 // 16-byte column chunks per lane
+        const int k = t % P, g = t / P;
         const int64_t lddst = ld_dst * EB;
         unsigned char *tb = dst + (C0 * ld_dst + R0) * EB;                  // uniform
-        const LaneOff lane = (LaneOff)(bc * V) * (LaneOff)lddst + (LaneOff)(bq * V * EB);
-        if (full) {
+        const LaneOff lane = (LaneOff)(g * V) * (LaneOff)lddst + (LaneOff)(k * W);
+        const int64_t rk = R0 + (int64_t)k * EPW;    // first src row of the piece
 #pragma unroll
-            for (int j = 0; j < V; j++)
+        for (int cc = 0; cc < CPT; cc++) {
+            const int m = g + RP * cc;               // src cols m*V .. m*V+V-1
+            uint4 a[EPW];
 #pragma unroll
-                for (int q = 0; q < 16 / W; q++)
-                    stw<W, NTS>((tb + (int64_t)j * lddst + q * W) + lane, piece<W>(o[j], q));
-        } else {
-            const int64_t cs = R0 + bq * V;
+            for (int e = 0; e < EPW; e++) {
+                const int row = k * EPW + e;
+                a[e] = lds[row * 16 + swz<EB>(row, m)];
+            }
+            PT o[V];
+            piece_transpose<EB, W>(a, o);
+            unsigned char *cb = tb + (int64_t)(RP * cc * V) * lddst;        // uniform
+            if (full) {
 #pragma unroll
-            for (int j = 0; j < V; j++) {
-                if (C0 + bc * V + j >= cols) continue;
+                for (int i = 0; i < V; i++) stw<W, NTS>((cb + (int64_t)i * lddst) + lane, o[i]);
+            } else {
+                if (rk >= rows) continue;
 #pragma unroll
-                for (int q = 0; q < 16 / W; q++) {
-                    unsigned char *a2 = (tb + (int64_t)j * lddst + q * W) + lane;
-                    const int64_t cq = cs + q * EPW;
-                    if (cq + EPW <= rows) {
-                        stw<W, NTS>(a2, piece<W>(o[j], q));
-                    } else if (cq < rows) {
+                for (int i = 0; i < V; i++) {
+                    if (C0 + m * V + i >= cols) continue;
+                    unsigned char *a2 = (cb + (int64_t)i * lddst) + lane;
+                    if (rk + EPW <= rows) {
+                        stw<W, NTS>(a2, o[i]);
+                    } else {
                         union { PT pt; T e[EPW]; } u;
-                        u.pt = piece<W>(o[j], q);
+                        u.pt = o[i];
 #pragma unroll
-                        for (int i = 0; i < EPW; i++)
-                            if (cq + i < rows) reinterpret_cast<T *>(a2)[i] = u.e[i];
+                        for (int e = 0; e < EPW; e++)
+                            if (rk + e < rows) reinterpret_cast<T *>(a2)[e] = u.e[e];
                     }
                 }
             }

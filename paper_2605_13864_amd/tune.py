@@ -87,6 +87,9 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
 
 
 def tune_reduce(xtr, torch, dt: str, log=print):
+    """Streaming loads on / off at the large size, then the smallest chunk
+    count from which the split combine (plain partials + combine launches)
+    beats the in-kernel ticket combine."""
     n = SUM_SIZES[dt]
     eb = xtr.ELEM_BYTES[dt]
     src = torch.empty(n * eb, dtype=torch.uint8, device="cuda")
@@ -103,19 +106,47 @@ def tune_reduce(xtr, torch, dt: str, log=print):
     out = torch.empty((), dtype=torch.float64 if dt not in ("i32", "i64") else torch.int64,
                       device="cuda")
     orig = xtr.reduce_config(dt)
+    ch = 256 * 8 * (16 // eb)
     best = None
     try:
-        for nt, bpc in itertools.product((1, 0), (0, 2, 3, 4, 5, 6, 8)):
-            xtr.set_reduce_config(dt, nt_load=nt, blocks_per_cu=bpc)
+        for nt, sc in itertools.product((1, 0), (0, 1)):
+            xtr.set_reduce_config(dt, nt_load=nt, split_chunks=sc)
             sec = _time(torch, lambda: xtr.reduce_sum(src, out, n=n, dtype=dt))
             gbs = n * eb / sec / 1e9
             if best is None or gbs > best[0]:
-                best = (gbs, {"nt_load": nt, "blocks_per_cu": bpc})
+                best = (gbs, nt, sc)
+        nt = best[1]
+        # crossover: time both combines at growing chunk counts (rotating over
+        # disjoint slices so the last-level cache does not serve repeats)
+        split_from = 0
+        for chunks in (4, 16, 64, 256, 1024, 4096, 16384):
+            m = chunks * ch
+            k = max(1, min(8, n // m))
+            t = {}
+            for sc in (0, 1):
+                xtr.set_reduce_config(dt, nt_load=nt, split_chunks=sc)
+                it = [0]
+
+                def fn():
+                    i = it[0] % k
+                    it[0] += 1
+                    xtr.reduce_sum(src[i * m * eb:(i + 1) * m * eb], out, n=m, dtype=dt)
+                t[sc] = _time(torch, fn, reps=4 * k, warm=k)
+            if t[1] < t[0]:
+                if split_from == 0:
+                    split_from = chunks
+            else:
+                split_from = 0
+        if best[2] == 0:
+            split_from = 0              # the large size itself prefers the tickets
+        elif split_from == 0:
+            split_from = 16384
     finally:
         xtr.set_reduce_config(dt, **orig)
-    log(f"tune sum {dt} n={n}: best {best[0]:.1f} GB/s {best[1]}")
+    cfg = {"nt_load": nt, "split_chunks": split_from}
+    log(f"tune sum {dt} n={n}: best {best[0]:.1f} GB/s {cfg}")
     del src
-    return {"gbs": round(best[0], 1), "config": best[1], "n": n}
+    return {"gbs": round(best[0], 1), "config": cfg, "n": n}
 
 
 def run(quick=False, out=None, log=print):

@@ -75,24 +75,44 @@ def test_mixed_sizes_share_workspace(xtr, orc):
 
 
 @pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i32", "i64", "f16"])
-def test_persistent_matches_one_chunk_per_workgroup(xtr, orc, dt):
-    """The persistent, prefetching kernel gives bit-identical results to one
-    workgroup per chunk, for many chunks per workgroup, ragged tails and heads."""
+def test_split_combine_matches_tickets(xtr, orc, dt):
+    """Plain partials + combine launches give bit-identical results to the
+    in-kernel ticket combine, over one, two and three combine levels, ragged
+    tails and unaligned heads."""
     orig = xtr.reduce_config(dt)
     c = CH[dt]
     try:
         for k, (n, off) in enumerate([(3 * c, 0), (1000 * c + 17, 1), (2 * c - 1, 3),
-                                      (777 * c, 2), (5 * c + c // 2, 0)]):
+                                      (256 * c, 2), (5 * c + c // 2, 0), (70000 * c + 5, 1)]):
+            if n * np.dtype(data(dt, 1, 0).dtype).itemsize > (1 << 31):
+                continue
             bits = data(dt, n + off, 1100 + k)
-            xtr.set_reduce_config(dt, blocks_per_cu=0)
+            xtr.set_reduce_config(dt, split_chunks=0)
             a = gpu_sum(xtr, bits, dt, off)
-            for bpc in (1, 3):
-                xtr.set_reduce_config(dt, blocks_per_cu=bpc)
+            for sc in (1, 2, 3 * c):
+                xtr.set_reduce_config(dt, split_chunks=sc)
                 b = gpu_sum(xtr, bits, dt, off)
-                assert a == b or (math.isnan(a) and math.isnan(b)), (dt, n, off, bpc, a, b)
+                assert a == b or (math.isnan(a) and math.isnan(b)), (dt, n, off, sc, a, b)
             check(orc, a, bits[off:], dt, (dt, n, off))
     finally:
         xtr.set_reduce_config(dt, **orig)
+
+
+def test_split_combine_three_levels(xtr, orc):
+    """More than 256^2 chunks (three combine levels): int32 against the oracle
+    bit for bit, and the split and ticket combines agree."""
+    orig = xtr.reduce_config("i32")
+    n = 65537 * CH["i32"] + 3
+    bits = data("i32", n, 1200)
+    d = to_dev(bits)
+    try:
+        xtr.set_reduce_config("i32", split_chunks=1)
+        a = xtr.reduce_sum(d, dtype="i32").item()
+        xtr.set_reduce_config("i32", split_chunks=0)
+        b = xtr.reduce_sum(d, dtype="i32").item()
+    finally:
+        xtr.set_reduce_config("i32", **orig)
+    assert a == b == orc.sum_int(bits, "i32")[0]
 
 
 def test_int64_wraps(xtr, orc):
@@ -195,6 +215,31 @@ def test_segmented_small(xtr, orc, dt):
         alone = xtr.reduce_sum(d[off[i]:off[i + 1]], dtype=dt).item()
         assert alone == got[i] or (isinstance(alone, float) and math.isnan(alone)
                                    and math.isnan(got[i])), i
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i64"])
+def test_segmented_wave_and_chunk_paths(xtr, orc, dt):
+    """Segments around the size where one wave instead of a workgroup chunk
+    takes a segment (bodies of 2 * 256 * V elements, V = 16 / element size),
+    starting at every alignment: every result equals reduce_sum on that
+    segment alone, bit for bit, and the oracle to the usual bar."""
+    eb = {"f32": 4, "bf16": 2, "f8e4m3": 1, "i64": 8}[dt]
+    v = 16 // eb
+    sm = 2 * 256 * v
+    lens = []
+    for base in (0, 1, 5, v - 1, v, 256 * v - 1, 256 * v + 1, sm - v, sm - 1, sm, sm + 1,
+                 sm + v, 2 * sm, 4 * sm - 1, 4 * sm + 3, 9 * sm + 7):
+        lens += [base, base + 1, max(base - 1, 0)]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64) + 3    # odd start
+    total = int(off[-1]) + 5
+    bits = data(dt, total, 91)
+    d = to_dev(bits)
+    got = xtr.reduce_sum_segmented(d, to_dev(off), dtype=dt).cpu().numpy()
+    for i in range(len(lens)):
+        seg = bits[off[i]:off[i + 1]]
+        alone = xtr.reduce_sum(d[off[i]:off[i + 1]], dtype=dt).item()
+        assert alone == got[i], (i, lens[i], alone, got[i])
+        check(orc, float(got[i]) if dt != "i64" else int(got[i]), seg, dt, (i, lens[i]))
 
 
 def test_segmented_ws_and_invalid_table(xtr):

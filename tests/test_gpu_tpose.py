@@ -70,6 +70,28 @@ def test_leading_dims_and_alignment(xtr, orc, eb):
         run_tpose(xtr, orc, T + 3, 2 * T, eb, off_s=0, off_d=1)
 
 
+def _ld_with_piece(n, eb, w):
+    """Smallest leading dimension >= n whose byte pitch admits W-byte pieces
+    exactly (divisible by w, and not by 2w unless w = 16)."""
+    ld = n
+    while (ld * eb) % w or (w < 16 and (ld * eb) % (2 * w) == 0):
+        ld += 1
+    return ld
+
+
+@pytest.mark.parametrize("eb,w", [(1, 4), (1, 8), (1, 16), (2, 4), (2, 8), (2, 16), (4, 4),
+                                  (4, 8), (4, 16), (8, 8), (8, 16)])
+def test_every_piece_width(xtr, orc, eb, w):
+    """Each (element size, piece width) of the tile routine: whole tiles, and
+    ragged rows / cols that cut a piece (partial pieces stored per element)."""
+    T = TILE[eb]
+    epw = w // eb
+    for i, (r, c) in enumerate([(2 * T, 2 * T), (2 * T + epw - 1 if epw > 1 else 2 * T + 1, T + 3),
+                                (T + 1, 3 * T - 1)]):
+        ld_s, ld_d = _ld_with_piece(c, eb, w), _ld_with_piece(r, eb, w)
+        run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=40 + i)
+
+
 def test_tiny_enumeration(xtr, orc):
     for eb in (1, 4):
         for r in range(1, 12):
