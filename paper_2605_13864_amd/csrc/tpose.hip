@@ -419,28 +419,39 @@ struct Job {
     int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = element-wise
 };
 
+// Persistent over the concatenated tile space of a group of jobs.  Round i
+// of the grid covers positions [i G, i G + G) of the launch order; within a
+// round each XCD takes a contiguous range (xcd_remap), and within a job tiles
+// follow the band order, so tiles that share cache lines at their edges (rows
+// of a job whose pitch is not a multiple of the line) meet in one L2.
 template <int EB, int W, bool NTL, bool NTS, bool OFF32>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs, int njobs,
-                                                      int64_t ntiles) {
+                                                      int64_t ntiles, int xcd, int group) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
     __shared__ int s_job;
-    int64_t tile = blockIdx.x;
-    if (tile >= ntiles) return;
-    if (threadIdx.x == 0) {   // binary search for the first job, then walk forward
-        int lo = 0, hi = njobs - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (jobs[mid].tile_base <= tile) lo = mid; else hi = mid - 1;
+    const int64_t G = gridDim.x;
+    int j = -1;
+    for (int64_t wave0 = 0; wave0 < ntiles; wave0 += G) {
+        const int64_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
+        if ((int64_t)blockIdx.x >= inwave) break;          // only in the last round
+        const int64_t L = wave0 + (xcd ? xcd_remap(blockIdx.x, inwave) : (int64_t)blockIdx.x);
+        if (j < 0) {   // first tile: binary search for its job, then walk forward
+            if (threadIdx.x == 0) {
+                int lo = 0, hi = njobs - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (jobs[mid].tile_base <= L) lo = mid; else hi = mid - 1;
+                }
+                s_job = lo;
+            }
+            __syncthreads();
+            j = s_job;
         }
-        s_job = lo;
-    }
-    __syncthreads();
-    int j = s_job;
-    for (; tile < ntiles; tile += gridDim.x) {
-        while (j + 1 < njobs && jobs[j + 1].tile_base <= tile) j++;
+        while (j + 1 < njobs && jobs[j + 1].tile_base <= L) j++;
         const Job &jb = jobs[j];
-        const int64_t local = tile - jb.tile_base;
-        const int64_t tr = local / jb.tiles_c, tc = local - tr * jb.tiles_c;
+        const int64_t tiles_r = (jb.rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
+        int64_t tr, tc;
+        band_order(L - jb.tile_base, tiles_r, jb.tiles_c, group, tr, tc);
         tile_any<EB, W, NTL, NTS, OFF32>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst,
                                          tr * Geo<EB>::TR, tc * Geo<EB>::TC, lds);
         __syncthreads();
@@ -515,8 +526,8 @@ constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs lo
 
 // Tuned launch configuration per element size (index log2(elem bytes)).
 xtr_tpose_config g_cfg[4] = {
-    {1, 1, 1, 1, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, {0, 0, 0}},
-    {1, 1, 1, 1, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, {0, 0, 0}},
+    {1, 1, 1, 1, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, {0, 0}},
+    {1, 1, 1, 1, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, {0, 0}},
 };
 int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
@@ -538,13 +549,14 @@ template <int EB, int W>
 void launch_w(const xtr_tpose_config &c, dim3 gd, hipStream_t st, const void *src, void *dst,
               int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t tiles_r,
               int64_t tiles_c, int group) {
-    if (c.nt_load && c.nt_store && W == 16)
+    const bool nts = (W == 16) ? c.nt_store != 0 : c.nt_store_narrow != 0;
+    if (c.nt_load && nts)
         launch_k<EB, W, true, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
                                     c.xcd, group);
     else if (c.nt_load)
         launch_k<EB, W, true, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
                                      tiles_c, c.xcd, group);
-    else if (c.nt_store && W == 16)
+    else if (nts)
         launch_k<EB, W, false, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
                                      tiles_c, c.xcd, group);
     else
@@ -589,22 +601,22 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     return XTR_OK;
 }
 
-// Streaming (nontemporal) stores only for whole 16-byte pieces: narrower
-// pieces leave each store instruction covering part of every line, and those
-// lines must merge in L2 before they go to HBM.
+// Streaming stores for 16-byte pieces follow nt_store; narrower pieces
+// (rows whose pitch is not a multiple of 16 bytes, so lines are shared with
+// the neighbouring tiles) follow nt_store_narrow.
 template <int EB, int W, bool OFF32>
 void launch_batched_w(int64_t grid, hipStream_t st, const Job *jobs, int nj, int64_t ntiles) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
-    constexpr bool WIDE = (W == 16);
-    if (c.nt_load && c.nt_store && WIDE)
-        hipLaunchKernelGGL((k_tpose_batched<EB, W, true, WIDE, OFF32>), dim3((unsigned)grid),
-                           dim3(NT), 0, st, jobs, nj, ntiles);
-    else if (c.nt_load)
-        hipLaunchKernelGGL((k_tpose_batched<EB, W, true, false, OFF32>), dim3((unsigned)grid),
-                           dim3(NT), 0, st, jobs, nj, ntiles);
-    else
-        hipLaunchKernelGGL((k_tpose_batched<EB, W, false, false, OFF32>), dim3((unsigned)grid),
-                           dim3(NT), 0, st, jobs, nj, ntiles);
+    const bool nts = (W == 16) ? c.nt_store != 0 : c.nt_store_narrow != 0;
+    const int group = c.group < 1 ? 1 : c.group;
+#define XTR_KB(NL, NS)                                                                     \
+    hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>), dim3((unsigned)grid), dim3(NT), \
+                       0, st, jobs, nj, ntiles, c.xcd, group)
+    if (c.nt_load && nts) XTR_KB(true, true);
+    else if (c.nt_load) XTR_KB(true, false);
+    else if (nts) XTR_KB(false, true);
+    else XTR_KB(false, false);
+#undef XTR_KB
 }
 
 template <int EB>

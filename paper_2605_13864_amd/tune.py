@@ -27,6 +27,8 @@ TUNED_DIR = os.path.join(HERE, "tuned")
 
 # representative shapes per element size: (rows, cols)
 TPOSE_SHAPES = {1: (32768, 32768), 2: (12288, 20000), 4: (16384, 16384), 8: (16384, 8192)}
+# shapes whose row pitches allow only 4-byte (8-byte for fp64) pieces
+NARROW_SHAPES = {1: (32764, 32764), 2: (12290, 20002), 4: (16383, 16383), 8: (16383, 8191)}
 SUM_SIZES = {"f32": 1 << 28, "bf16": 1 << 29, "f16": 1 << 29, "f8e4m3": 1 << 30,
              "i32": 1 << 28, "i64": 1 << 28}
 
@@ -82,7 +84,26 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
     log(f"tune tpose eb={eb} {rows}x{cols}: best {best[0]:.1f} GB/s {best[1]}; "
         f"worst {results[-1][0]:.1f} GB/s")
     del src, dst
-    return {"gbs": round(best[0], 1), "config": best[1], "shape": [rows, cols],
+    # streaming stores for narrow pieces, timed on a shape that needs them
+    nr, nc = NARROW_SHAPES[eb]
+    src = torch.empty((nr, nc), dtype=tdt, device="cuda")
+    src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(eb + 8))
+    dst = torch.empty((nc, nr), dtype=tdt, device="cuda")
+    narrow = {}
+    try:
+        for nsn in (0, 1):
+            xtr.set_tpose_config(eb, **dict(best[1], nt_store_narrow=nsn))
+            sec = _time(torch, lambda: xtr.tpose(src, dst, dtype=dt))
+            narrow[nsn] = 2 * nr * nc * eb / sec / 1e9
+    finally:
+        xtr.set_tpose_config(eb, **orig)
+    nsn = max(narrow, key=narrow.get)
+    cfg = dict(best[1], nt_store_narrow=nsn)
+    log(f"tune tpose eb={eb} narrow {nr}x{nc}: " +
+        ", ".join(f"nt_store_narrow={k} {v:.1f} GB/s" for k, v in narrow.items()))
+    del src, dst
+    return {"gbs": round(best[0], 1), "config": cfg, "shape": [rows, cols],
+            "narrow_shape": [nr, nc], "narrow_gbs": round(narrow[nsn], 1),
             "top5": [{"gbs": round(g, 1), "config": c} for g, c in results[:5]]}
 
 
