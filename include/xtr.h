@@ -210,13 +210,16 @@ int xtr_sum_plan_destroy(xtr_sum_plan *plan);
  * the reduction's chunking and combine order do not depend on them.
  */
 typedef struct {
-    int32_t nt_load;        /* 1: nontemporal (streaming) loads                    */
-    int32_t nt_store;       /* 1: nontemporal stores of 16-byte pieces             */
+    int32_t nt_load;        /* 1: nontemporal (streaming) loads of src rows that   */
+                            /*    start on 128-byte lines (base and pitch)         */
+    int32_t nt_store;       /* 1: nontemporal stores of such dst rows              */
     int32_t xcd;            /* 1: each XCD takes a contiguous range of tiles       */
     int32_t group;          /* tile rows per band of the launch order, 1..64       */
     int32_t blocks_per_cu;  /* 0: one workgroup per tile; k in 1..64: persistent   */
-    int32_t nt_store_narrow;/* 1: nontemporal stores of 8- and 4-byte pieces       */
-    int32_t _reserved[2];
+    int32_t nt_store_shared;/* 1: nontemporal stores of dst rows that do not start */
+                            /*    on lines (neighbouring tiles share edge lines)   */
+    int32_t nt_load_shared; /* 1: nontemporal loads of such src rows               */
+    int32_t _reserved[1];
 } xtr_tpose_config;
 
 /* Current / new configuration of tpose for one element size (1, 2, 4, 8).

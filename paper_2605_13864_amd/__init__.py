@@ -37,8 +37,8 @@ class XtrError(RuntimeError):
 
 class TposeConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("nt_store", C.c_int32), ("xcd", C.c_int32),
-                ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("nt_store_narrow", C.c_int32),
-                ("_reserved", C.c_int32 * 2)]
+                ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("nt_store_shared", C.c_int32),
+                ("nt_load_shared", C.c_int32), ("_reserved", C.c_int32 * 1)]
 
 
 class ReduceConfig(C.Structure):
@@ -387,7 +387,8 @@ def tpose_config(elem_bytes: int) -> dict:
     c = TposeConfig()
     _check(load().xtr_tpose_get_config(elem_bytes, C.byref(c)), "xtr_tpose_get_config")
     return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
-            "blocks_per_cu": c.blocks_per_cu, "nt_store_narrow": c.nt_store_narrow}
+            "blocks_per_cu": c.blocks_per_cu, "nt_store_shared": c.nt_store_shared,
+            "nt_load_shared": c.nt_load_shared}
 
 
 def set_tpose_config(elem_bytes: int, **kw):
@@ -397,7 +398,7 @@ def set_tpose_config(elem_bytes: int, **kw):
         raise TypeError(f"set_tpose_config: unknown settings {sorted(bad)}")
     cur.update(kw)
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
-                    cur["blocks_per_cu"], cur["nt_store_narrow"])
+                    cur["blocks_per_cu"], cur["nt_store_shared"], cur["nt_load_shared"])
     _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
 
 

@@ -599,12 +599,13 @@ __global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__
 
 // ---------------------------------------------------------------- segmented
 
-// Segment geometry, identical to the host-side one used for single ranges.
-__device__ __forceinline__ Range seg_range(const unsigned char *src, const int64_t *off, int64_t s,
-                                           int eb, int64_t ch, unsigned char *out = nullptr,
-                                           int osz = 8) {
-    int64_t lo = off[s], hi = off[s + 1];
-    if (hi < lo) hi = lo;   // a decreasing pair reads as empty here; k_seg_count flags it
+// Segment geometry from its bounds [lo, hi) (a decreasing pair reads as
+// empty here; k_seg_count flags it), identical to the host-side one of single
+// ranges.
+__device__ __forceinline__ Range seg_range_lh(const unsigned char *src, int64_t lo, int64_t hi,
+                                              int64_t s, int eb, int64_t ch, unsigned char *out,
+                                              int osz) {
+    if (hi < lo) hi = lo;
     Range r;
     r.ptr = src + lo * eb;
     r.n = hi - lo;
@@ -619,6 +620,19 @@ __device__ __forceinline__ Range seg_range(const unsigned char *src, const int64
     r._pad = 0;
     return r;
 }
+__device__ __forceinline__ Range seg_range(const unsigned char *src, const int64_t *off, int64_t s,
+                                           int eb, int64_t ch, unsigned char *out = nullptr,
+                                           int osz = 8) {
+    return seg_range_lh(src, off[s], off[s + 1], s, eb, ch, out, osz);
+}
+
+// Chunk j of segment s, whose elements are [lo, hi) of the source: one
+// record per chunk of the chunked segments, so the reducing workgroup needs a
+// single metadata load.
+struct ChunkRec {
+    int64_t lo, hi;
+    int32_t s, j;
+};
 
 // Pass 1: chunk count of every segment, and per-block totals.
 __global__ void __launch_bounds__(NTHR) k_seg_count(const unsigned char *src, const int64_t *off,
@@ -671,10 +685,10 @@ __global__ void __launch_bounds__(NTHR) k_seg_scan_blocks(int64_t *block_tot, in
     if (threadIdx.x == 0) block_tot[nblk] = carry;
 }
 
-// Pass 3: chunk_base of every segment and the chunk -> segment map.
+// Pass 3: chunk_base of every segment and the chunk records.
 __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const int64_t *block_tot,
-                                                  int64_t nseg, int64_t cap, int64_t *chunk_base,
-                                                  int32_t *chunk_seg) {
+                                                  const int64_t *off, int64_t nseg, int64_t cap,
+                                                  int64_t *chunk_base, ChunkRec *recs) {
     __shared__ int64_t sh[NTHR];
     const int64_t base = (int64_t)blockIdx.x * NTHR * 4;
     const int64_t s0 = base + threadIdx.x * 4;   // this thread's 4 consecutive segments
@@ -698,7 +712,11 @@ __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const
         const int64_t s = s0 + k;
         if (s < nseg) {
             chunk_base[s] = run;
-            for (int64_t q = 0; q < c[k] && run + q < cap; q++) chunk_seg[run + q] = (int32_t)s;
+            if (c[k] > 0 && run + c[k] <= cap) {
+                const int64_t lo = off[s], hi = off[s + 1];
+                for (int64_t q = 0; q < c[k]; q++)
+                    recs[run + q] = ChunkRec{lo, hi, (int32_t)s, (int32_t)q};
+            }
             run += c[k];
         }
     }
@@ -708,7 +726,9 @@ __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const
     }
 }
 
-// Pass 4a: small segments, one wave each (grid-stride over segments).
+// Pass 4a: small segments, one wave each (grid-stride over segments); the
+// next segment's bounds are loaded before this one's data, so each segment
+// costs one memory round trip.
 template <int DT, int MODE, bool NT>
 __global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *src,
                                                          const int64_t *off,
@@ -717,22 +737,32 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *
     using P = typename PartT<MODE>::T;
     if (chunk_base[nseg] > cap) return;   // invalid table: k_reduce_seg writes every output
     const int64_t nwaves = (int64_t)gridDim.x * NW;
-    for (int64_t s = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6); s < nseg; s += nwaves) {
-        const Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(),
-                                   (unsigned char *)out, (int)sizeof(P));
-        if (rg.n - rg.head > small_max<DT>()) continue;   // a chunked segment (pass 4b)
-        const P v = small_chunk_value<DT, MODE, NT>(rg);
-        if ((threadIdx.x & 63) == 0) *reinterpret_cast<P *>(rg.dst) = v;
+    int64_t s = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
+    int64_t lo = 0, hi = 0;
+    if (s < nseg) lo = off[s], hi = off[s + 1];
+    for (; s < nseg; s += nwaves) {
+        const int64_t sn = s + nwaves;
+        int64_t lo_n = 0, hi_n = 0;
+        if (sn < nseg) lo_n = off[sn], hi_n = off[sn + 1];
+        const Range rg = seg_range_lh(src, lo, hi, s, DTI<DT>::EB, chunk_elems<DT>(),
+                                      (unsigned char *)out, (int)sizeof(P));
+        if (rg.n - rg.head <= small_max<DT>()) {   // else a chunked segment (pass 4b)
+            const P v = small_chunk_value<DT, MODE, NT>(rg);
+            if ((threadIdx.x & 63) == 0) *reinterpret_cast<P *>(rg.dst) = v;
+        }
+        lo = lo_n;
+        hi = hi_n;
     }
 }
 
 // Pass 4b: the chunks of the other segments, workgroups striding over the
-// chunk space.  The first wave runs the grid combine of each chunk while the
-// others go on to the next chunk (they meet again at its LDS barrier).
+// chunk records (the next record is loaded before this chunk's data).  The
+// first wave runs the grid combine of each chunk while the others go on to
+// the next chunk (they meet again at its LDS barrier).
 template <int DT, int MODE, bool NT>
-__global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, const int64_t *off,
+__global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src,
                                                    const int64_t *chunk_base,
-                                                   const int32_t *chunk_seg, int64_t nseg,
+                                                   const ChunkRec *__restrict__ recs, int64_t nseg,
                                                    int64_t cap, Levels lv, void *out) {
     using P = typename PartT<MODE>::T;
     const int64_t total = chunk_base[nseg];
@@ -744,16 +774,18 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src, c
         }
         return;
     }
-    for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
-        const int64_t s = chunk_seg[b];
-        if (s < 0 || s >= nseg) continue;
-        Range rg = seg_range(src, off, s, DTI<DT>::EB, chunk_elems<DT>(), (unsigned char *)out,
-                             (int)sizeof(P));
-        rg.chunk_base = chunk_base[s];
-        const int64_t j = b - rg.chunk_base;
-        if (j < 0 || j >= rg.nchunks) continue;
-        auto v = reduce_chunk<DT, MODE, NT>(rg, j);
-        if (threadIdx.x < 64) grid_combine<MODE>(rg, j, v, lv);
+    int64_t b = blockIdx.x;
+    ChunkRec cr{};
+    if (b < total) cr = recs[b];
+    for (; b < total; b += gridDim.x) {
+        ChunkRec nx{};
+        if (b + gridDim.x < total) nx = recs[b + gridDim.x];
+        Range rg = seg_range_lh(src, cr.lo, cr.hi, cr.s, DTI<DT>::EB, chunk_elems<DT>(),
+                                (unsigned char *)out, (int)sizeof(P));
+        rg.chunk_base = b - cr.j;
+        auto v = reduce_chunk<DT, MODE, NT>(rg, cr.j);
+        if (threadIdx.x < 64) grid_combine<MODE>(rg, cr.j, v, lv);
+        cr = nx;
     }
 }
 
@@ -924,7 +956,7 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
 // Both passes run as resident grids (8 workgroups per CU at most) that stride
 // over their segments / chunks: the chunk space is only known on the device.
 template <int DT, int MODE>
-void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const int32_t *cs,
+void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const ChunkRec *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
     const int64_t occ = (int64_t)cu_count() * 8;
     const int64_t gs_n = (nseg + NW - 1) / NW;
@@ -934,12 +966,12 @@ void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb,
     if (g_rcfg[DT].nt_load) {
         hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, true>), gs, dim3(NTHR), 0, st, src, off,
                            cb, nseg, cap, out);
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), gc, dim3(NTHR), 0, st, src, off, cb, cs,
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), gc, dim3(NTHR), 0, st, src, cb, cs,
                            nseg, cap, lv, out);
     } else {
         hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, false>), gs, dim3(NTHR), 0, st, src, off,
                            cb, nseg, cap, out);
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), gc, dim3(NTHR), 0, st, src, off, cb, cs,
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), gc, dim3(NTHR), 0, st, src, cb, cs,
                            nseg, cap, lv, out);
     }
 }
@@ -1029,7 +1061,7 @@ SegLayout seg_layout(int64_t nseg, int64_t cap, int mode) {
     L.cbase = L.counts + al256((size_t)nseg * 8);
     L.btot = L.cbase + al256((size_t)(nseg + 1) * 8);
     L.cmap = L.btot + al256((size_t)(nblk + 1) * 8);
-    L.parts = L.cmap + al256((size_t)cap * 4);
+    L.parts = L.cmap + al256((size_t)cap * sizeof(ChunkRec));
     L.total = L.parts + parts_bytes(cap, mode);
     return L;
 }
@@ -1073,19 +1105,19 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     unsigned char *w = v.data;
     int64_t *counts = (int64_t *)(w + L.counts), *cbase = (int64_t *)(w + L.cbase);
     int64_t *btot = (int64_t *)(w + L.btot);
-    int32_t *cmap = (int32_t *)(w + L.cmap);
+    ChunkRec *cmap = (ChunkRec *)(w + L.cmap);
     const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
     const int64_t small = (int64_t)2 * NTHR * (16 / eb);   // small_max<DT>() of the kernels
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NTHR), 0, st,
                        (const unsigned char *)src, offsets, nseg, eb, ch, small, counts, btot);
     hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NTHR), 0, st, btot, nblk);
     hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NTHR), 0, st, (const int64_t *)counts,
-                       (const int64_t *)btot, nseg, cap, cbase, cmap);
+                       (const int64_t *)btot, offsets, nseg, cap, cbase, cmap);
     XTR_HIP(hipGetLastError());
     Levels lv = levels_at(v, w + L.parts, cap, mode);
     XTR_DISPATCH_SUM(dtype, mode, launch_seg,
                      ((const unsigned char *)src, offsets, (const int64_t *)cbase,
-                      (const int32_t *)cmap, nseg, cap, lv, out, st));
+                      (const ChunkRec *)cmap, nseg, cap, lv, out, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }

@@ -58,21 +58,22 @@ int zero_fill(void *p, size_t bytes, hipStream_t stream) {
 // grid-stride.  It is the reference kernel for the achievable HBM bandwidth
 // and for scaling the HBM byte counters (FETCH_SIZE / WRITE_SIZE).
 
-__global__ void __launch_bounds__(256) k_copy16(const uint4 *__restrict__ src,
-                                                uint4 *__restrict__ dst, size_t nvec) {
-    const size_t stride = (size_t)gridDim.x * 256 * 4;
-    for (size_t base = (size_t)blockIdx.x * 256 * 4 + threadIdx.x; base < nvec; base += stride) {
-        uint4 v[4];
+// One 16 KiB chunk per workgroup (4 vectors per thread, all in flight),
+// streaming loads and stores: the fastest plain copy shape measured on gfx950.
+typedef uint32_t cu32x4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(256) k_copy16(const cu32x4 *__restrict__ src,
+                                                cu32x4 *__restrict__ dst, size_t nvec) {
+    const size_t base = (size_t)blockIdx.x * 256 * 4 + threadIdx.x;
+    cu32x4 v[4];
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const size_t i = base + (size_t)k * 256;
-            if (i < nvec) v[k] = src[i];
-        }
+    for (int k = 0; k < 4; k++) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < nvec) v[k] = __builtin_nontemporal_load(src + i);
+    }
 #pragma unroll
-        for (int k = 0; k < 4; k++) {
-            const size_t i = base + (size_t)k * 256;
-            if (i < nvec) dst[i] = v[k];
-        }
+    for (int k = 0; k < 4; k++) {
+        const size_t i = base + (size_t)k * 256;
+        if (i < nvec) __builtin_nontemporal_store(v[k], dst + i);
     }
 }
 
@@ -206,11 +207,10 @@ int xtr_copy(void *dst, const void *src, size_t nbytes, void *stream) {
     hipStream_t st = (hipStream_t)stream;
     if (((s0 | d0 | nbytes) & 15) == 0) {
         const size_t nvec = nbytes / 16;
-        size_t blocks = (nvec + 1023) / 1024;
-        const size_t cap = (size_t)xtr::cu_count() * 8;
-        if (blocks > cap) blocks = cap;
+        const size_t blocks = (nvec + 1023) / 1024;
+        if (blocks > 0xffffffffull) return xtr::fail(XTR_EINVAL, "xtr_copy: too large");
         hipLaunchKernelGGL(xtr::k_copy16, dim3((unsigned)blocks), dim3(256), 0, st,
-                           (const uint4 *)src, (uint4 *)dst, nvec);
+                           (const xtr::cu32x4 *)src, (xtr::cu32x4 *)dst, nvec);
     } else {
         hipLaunchKernelGGL(xtr::k_copy1, dim3((unsigned)((nbytes + 255) / 256)), dim3(256), 0, st,
                            (const unsigned char *)src, (unsigned char *)dst, nbytes);

@@ -419,35 +419,49 @@ struct Job {
     int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = element-wise
 };
 
+// Job of linear tile L within a group: the last j with bases[j] <= L
+// (bases[0] = 0, increasing; bases[j] = first tile of job j).  Every lane of
+// a wave probes one candidate per step, so both searches cost one memory
+// round trip per step and give the same j in every lane.
+__device__ __forceinline__ int job_search(const int64_t *bases, int nj, int64_t L) {
+    const int l = threadIdx.x & 63;
+    int lo = 0, hi = nj;   // bases[lo] <= L, and L < bases[hi] (bases[nj] is past the end)
+    while (hi - lo > 1) {
+        const int step = (hi - lo + 63) / 64;
+        const int c = lo + l * step;
+        const bool le = c < hi && bases[c] <= L;
+        lo += (__popcll(__ballot(le)) - 1) * step;   // lane 0 probes lo itself
+        hi = (lo + step) < hi ? (lo + step) : hi;
+    }
+    return lo;
+}
+__device__ __forceinline__ int job_forward(const int64_t *bases, int nj, int j, int64_t L) {
+    const int l = threadIdx.x & 63;
+    for (;;) {
+        const int c = j + 1 + l;
+        const int k = __popcll(__ballot(c < nj && bases[c] <= L));
+        j += k;
+        if (k < 64) return j;
+    }
+}
+
 // Persistent over the concatenated tile space of a group of jobs.  Round i
 // of the grid covers positions [i G, i G + G) of the launch order; within a
 // round each XCD takes a contiguous range (xcd_remap), and within a job tiles
 // follow the band order, so tiles that share cache lines at their edges (rows
 // of a job whose pitch is not a multiple of the line) meet in one L2.
 template <int EB, int W, bool NTL, bool NTS, bool OFF32>
-__global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs, int njobs,
+__global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
+                                                      const int64_t *__restrict__ bases, int njobs,
                                                       int64_t ntiles, int xcd, int group) {
     __shared__ uint4 lds[Geo<EB>::LDS_VECS];
-    __shared__ int s_job;
     const int64_t G = gridDim.x;
     int j = -1;
     for (int64_t wave0 = 0; wave0 < ntiles; wave0 += G) {
         const int64_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
         if ((int64_t)blockIdx.x >= inwave) break;          // only in the last round
         const int64_t L = wave0 + (xcd ? xcd_remap(blockIdx.x, inwave) : (int64_t)blockIdx.x);
-        if (j < 0) {   // first tile: binary search for its job, then walk forward
-            if (threadIdx.x == 0) {
-                int lo = 0, hi = njobs - 1;
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if (jobs[mid].tile_base <= L) lo = mid; else hi = mid - 1;
-                }
-                s_job = lo;
-            }
-            __syncthreads();
-            j = s_job;
-        }
-        while (j + 1 < njobs && jobs[j + 1].tile_base <= L) j++;
+        j = (j < 0) ? job_search(bases, njobs, L) : job_forward(bases, njobs, j, L);
         const Job &jb = jobs[j];
         const int64_t tiles_r = (jb.rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
         int64_t tr, tc;
@@ -526,8 +540,8 @@ constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs lo
 
 // Tuned launch configuration per element size (index log2(elem bytes)).
 xtr_tpose_config g_cfg[4] = {
-    {1, 1, 1, 1, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, {0, 0}},
-    {1, 1, 1, 1, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, {0, 0}},
+    {1, 1, 1, 1, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, {0}},
+    {1, 1, 1, 1, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, {0}},
 };
 int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
@@ -545,15 +559,24 @@ void launch_k(dim3 grid, hipStream_t st, const void *src, void *dst, int64_t row
                            ld_dst, tiles_r, tiles_c, xcd, group);
 }
 
+// Rows of a matrix start on 128-byte cache lines (base and pitch), so no
+// line is shared by two tiles.  Streaming (nontemporal) accesses suit such
+// rows; where tiles share the lines at their edges, the neighbour tile wants
+// those lines to stay cached, and the *_shared settings apply.
+bool lines_ok(const void *p, int64_t ld, int eb) {
+    return (((uint64_t)(uintptr_t)p | (uint64_t)(ld * eb)) & 127) == 0;
+}
+
 template <int EB, int W>
 void launch_w(const xtr_tpose_config &c, dim3 gd, hipStream_t st, const void *src, void *dst,
               int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t tiles_r,
               int64_t tiles_c, int group) {
-    const bool nts = (W == 16) ? c.nt_store != 0 : c.nt_store_narrow != 0;
-    if (c.nt_load && nts)
+    const bool ntl = lines_ok(src, ld_src, EB) ? c.nt_load != 0 : c.nt_load_shared != 0;
+    const bool nts = lines_ok(dst, ld_dst, EB) ? c.nt_store != 0 : c.nt_store_shared != 0;
+    if (ntl && nts)
         launch_k<EB, W, true, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
                                     c.xcd, group);
-    else if (c.nt_load)
+    else if (ntl)
         launch_k<EB, W, true, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
                                      tiles_c, c.xcd, group);
     else if (nts)
@@ -601,30 +624,30 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     return XTR_OK;
 }
 
-// Streaming stores for 16-byte pieces follow nt_store; narrower pieces
-// (rows whose pitch is not a multiple of 16 bytes, so lines are shared with
-// the neighbouring tiles) follow nt_store_narrow.
+// `lines`: every job of the group has line-aligned src and dst rows.
 template <int EB, int W, bool OFF32>
-void launch_batched_w(int64_t grid, hipStream_t st, const Job *jobs, int nj, int64_t ntiles) {
+void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
+                      const int64_t *bases, int nj, int64_t ntiles) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
-    const bool nts = (W == 16) ? c.nt_store != 0 : c.nt_store_narrow != 0;
+    const bool ntl = lines ? c.nt_load != 0 : c.nt_load_shared != 0;
+    const bool nts = lines ? c.nt_store != 0 : c.nt_store_shared != 0;
     const int group = c.group < 1 ? 1 : c.group;
 #define XTR_KB(NL, NS)                                                                     \
     hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>), dim3((unsigned)grid), dim3(NT), \
-                       0, st, jobs, nj, ntiles, c.xcd, group)
-    if (c.nt_load && nts) XTR_KB(true, true);
-    else if (c.nt_load) XTR_KB(true, false);
+                       0, st, jobs, bases, nj, ntiles, c.xcd, group)
+    if (ntl && nts) XTR_KB(true, true);
+    else if (ntl) XTR_KB(true, false);
     else if (nts) XTR_KB(false, true);
     else XTR_KB(false, false);
 #undef XTR_KB
 }
 
 template <int EB>
-void launch_batched(int w, bool off32, int64_t grid, hipStream_t st, const Job *jobs, int nj,
-                    int64_t ntiles) {
+void launch_batched(int w, bool off32, bool lines, int64_t grid, hipStream_t st, const Job *jobs,
+                    const int64_t *bases, int nj, int64_t ntiles) {
 #define XTR_BW(WW)                                                                        \
-    if (off32) launch_batched_w<EB, WW, true>(grid, st, jobs, nj, ntiles);                \
-    else launch_batched_w<EB, WW, false>(grid, st, jobs, nj, ntiles);
+    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles);  \
+    else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles);
     switch (w) {
     case 16: XTR_BW(16) break;
     case 8:
@@ -657,15 +680,20 @@ int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 // Host-side form of a batch: jobs grouped by (element size, piece width,
 // 32-bit offsets); each group has its own slice of the device table, its own
 // concatenated tile space and one persistent launch.
-constexpr int NGROUPS = 4 * 4 * 2;   // eb slot x piece class (16, 8, 4, elem) x off32
+// eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows
+constexpr int NGROUPS = 4 * 4 * 2 * 2;
 int wclass(int w) { return w == 16 ? 0 : w == 8 ? 1 : w == 4 ? 2 : 3; }
 int wof(int wc) { return wc == 0 ? 16 : wc == 1 ? 8 : wc == 2 ? 4 : 0; }
 
 struct BatchTable {
     std::vector<Job> all;                // groups concatenated
-    size_t at[NGROUPS] = {};             // first job of each group in `all`
+    std::vector<int64_t> bases;          // tile_base of every job of `all` (same order)
+    size_t at[NGROUPS] = {};             // first job of each group in `all` / `bases`
     int nj[NGROUPS] = {};
     int64_t ntiles[NGROUPS] = {};
+    // device image: the Job array, then (at a 256-byte boundary) the bases
+    size_t jobs_bytes() const { return (all.size() * sizeof(Job) + 255) / 256 * 256; }
+    size_t bytes() const { return jobs_bytes() + bases.size() * sizeof(int64_t); }
 };
 
 int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, BatchTable &bt) {
@@ -691,7 +719,9 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         j.rows = d.rows; j.cols = d.cols; j.ld_src = d.ld_src; j.ld_dst = d.ld_dst;
         j.w = piece_width(d.src, d.dst, d.ld_src, d.ld_dst, eb);
         j._pad = 0;
-        const int g = (cfg_slot(eb) * 4 + wclass(j.w)) * 2 + (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0);
+        const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
+        const int g = ((cfg_slot(eb) * 4 + wclass(j.w)) * 2 +
+                       (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0)) * 2 + (lines ? 1 : 0);
         j.tile_base = bt.ntiles[g];
         bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
         groups[g].push_back(j);
@@ -701,24 +731,38 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         bt.nj[g] = (int)groups[g].size();
         bt.all.insert(bt.all.end(), groups[g].begin(), groups[g].end());
     }
+    bt.bases.resize(bt.all.size());
+    for (size_t i = 0; i < bt.all.size(); i++) bt.bases[i] = bt.all[i].tile_base;
     return XTR_OK;
 }
 
-// One persistent launch per non-empty group; `dev` is the device copy of bt.all.
-int launch_batch(const BatchTable &bt, const Job *dev, hipStream_t stream) {
+// Copies the device image of bt (jobs, then bases) to dev with upload().
+int upload_batch(const BatchTable &bt, void *dev, hipStream_t stream) {
+    int rc = upload(bt.all.data(), bt.all.size() * sizeof(Job), dev, stream);
+    if (rc) return rc;
+    return upload(bt.bases.data(), bt.bases.size() * sizeof(int64_t),
+                  static_cast<unsigned char *>(dev) + bt.jobs_bytes(), stream);
+}
+
+// One persistent launch per non-empty group; `dev` is the device image of bt.
+int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
+    const Job *djobs = static_cast<const Job *>(dev);
+    const int64_t *dbases = reinterpret_cast<const int64_t *>(
+        static_cast<const unsigned char *>(dev) + bt.jobs_bytes());
     for (int g = 0; g < NGROUPS; g++) {
         if (!bt.nj[g]) continue;
-        const int slot = g / 8, w = wof((g / 2) % 4);
-        const bool off32 = (g & 1) != 0;
+        const int slot = g / 16, w = wof((g / 4) % 4);
+        const bool off32 = ((g / 2) & 1) != 0, lines = (g & 1) != 0;
         const int64_t occ = (int64_t)cu_count() * 8;
         int64_t grid = bt.ntiles[g] < occ ? bt.ntiles[g] : occ;
         if (grid < 1) grid = 1;
-        const Job *jobs = dev + bt.at[g];
+        const Job *jobs = djobs + bt.at[g];
+        const int64_t *bases = dbases + bt.at[g];
         switch (slot) {
-        case 0: launch_batched<1>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        case 1: launch_batched<2>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        case 2: launch_batched<4>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
-        default: launch_batched<8>(w, off32, grid, stream, jobs, bt.nj[g], bt.ntiles[g]); break;
+        case 0: launch_batched<1>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
+        case 1: launch_batched<2>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
+        case 2: launch_batched<4>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
+        default: launch_batched<8>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
         }
         XTR_HIP(hipGetLastError());
     }
@@ -730,11 +774,11 @@ int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t s
     int rc = build_batch(descs, count, "tpose_batched", bt);
     if (rc || bt.all.empty()) return rc;
     void *wsp = nullptr;
-    rc = workspace(WS_TABLE, stream, bt.all.size() * sizeof(Job), &wsp);
+    rc = workspace(WS_TABLE, stream, bt.bytes(), &wsp);
     if (rc) return rc;
-    rc = upload(bt.all.data(), bt.all.size() * sizeof(Job), wsp, stream);
+    rc = upload_batch(bt, wsp, stream);
     if (rc) return rc;
-    return launch_batch(bt, (const Job *)wsp, stream);
+    return launch_batch(bt, wsp, stream);
 }
 
 }  // namespace xtr
@@ -752,7 +796,7 @@ int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream) {
 
 struct xtr_tpose_plan {
     xtr::BatchTable bt;
-    xtr::Job *dev = nullptr;
+    void *dev = nullptr;    // device image of bt
     int device = 0;
 };
 
@@ -765,16 +809,21 @@ int xtr_tpose_plan_create(const xtr_tpose_desc *descs, int64_t count, void *stre
     int rc = xtr::build_batch(descs, count, "xtr_tpose_plan_create", p->bt);
     if (!rc && hipGetDevice(&p->device) != hipSuccess) rc = xtr::fail(XTR_EHIP, "hipGetDevice");
     if (!rc && !p->bt.all.empty()) {
-        const size_t bytes = p->bt.all.size() * sizeof(xtr::Job);
+        const size_t bytes = p->bt.bytes();
         hipError_t e = hipMalloc(&p->dev, bytes);
         if (e != hipSuccess) {
             p->dev = nullptr;
             rc = xtr::fail(XTR_ENOMEM, "xtr_tpose_plan_create: hipMalloc(%zu): %s", bytes,
                            hipGetErrorString(e));
         } else {
-            e = hipMemcpyAsync(p->dev, p->bt.all.data(), bytes, hipMemcpyHostToDevice,
-                               (hipStream_t)stream);
-            if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+            hipStream_t st = (hipStream_t)stream;
+            e = hipMemcpyAsync(p->dev, p->bt.all.data(), p->bt.all.size() * sizeof(xtr::Job),
+                               hipMemcpyHostToDevice, st);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(static_cast<unsigned char *>(p->dev) + p->bt.jobs_bytes(),
+                                   p->bt.bases.data(), p->bt.bases.size() * sizeof(int64_t),
+                                   hipMemcpyHostToDevice, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) rc = xtr::hip_fail(e, "xtr_tpose_plan_create: table upload");
         }
     }
