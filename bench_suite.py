@@ -190,8 +190,10 @@ def segmented(xtr, torch, log, total=1 << 27, nseg=100000):
 def piece_widths(xtr, torch, log):
     """Large single transposes whose row pitches allow 16-, 8-, 4-byte or only
     element-wide global accesses (the tile routine picks the widest piece that
-    divides both pointers and both pitches)."""
-    cases = [("f32", 16384, 16384, 16), ("f32", 16382, 16382, 8), ("f32", 16383, 16383, 4),
+    divides both pointers and both pitches), and line-aligned fp32 rows whose
+    pitch is not a power of two (16416) or not a multiple of the line (16388)."""
+    cases = [("f32", 16384, 16384, 16), ("f32", 16416, 16416, 16), ("f32", 16388, 16388, 16),
+             ("f32", 16382, 16382, 8), ("f32", 16383, 16383, 4),
              ("bf16", 12288, 20000, 16), ("bf16", 12292, 20004, 8), ("bf16", 12290, 20002, 4),
              ("bf16", 12289, 20001, 0), ("u8", 32768, 32768, 16), ("u8", 32764, 32764, 4),
              ("u8", 32767, 32767, 0), ("f64", 16384, 8192, 16), ("f64", 16383, 8191, 8)]

@@ -9,16 +9,20 @@ input (a pool generated once) and an operation.  Each scheduler step
   3. admits pending jobs in FIFO order while the in-flight bytes (input +
      output of every admitted, unfinished job) stay within the HBM budget and
      an output slot of the job's class is free;
-  4. launches every job admitted in this step at once: one persistent launch
-     per element size for the transposes (tpose_batched) and one per dtype for
-     the sums (reduce_sum_batched_scatter, straight into each job's slot), on
-     the next of K streams, followed by a completion event.
+  4. splits the jobs admitted in this step into launch units by kind and
+     size class (jobs under 4 MiB apart from larger ones, so a small job never
+     waits for a large one in its unit) and launches each unit at once on the
+     next of K streams: transposes as one persistent launch per element size
+     (tpose_batched), sums as one launch per dtype (reduce_sum_batched_scatter,
+     straight into each job's output slot); each unit ends with its own
+     completion event.
 
-Jobs that arrive while others run therefore join the next batch as soon as
-budget and slots free up, and batches on different streams overlap on the
-device.  Latency is arrival -> completion, the completion time read from the
-device event (elapsed time since a reference event whose host time is known).
-With ``batching=False`` every admitted job is its own launch (the comparison).
+Jobs that arrive while others run therefore join the next unit as soon as
+budget and slots free up, and units on different streams overlap on the
+device.  Latency is arrival -> completion of the job's unit, the completion
+time read from the device event (elapsed time since a reference event whose
+host time is known).  With ``batching=False`` every admitted job is its own
+unit and launch, with its own event (the comparison).
 
 The policy (`Scheduler`) is separate from the device (`GpuExecutor`), so the
 admission and batching rules are tested on the CPU with a fake clock and a
@@ -50,6 +54,20 @@ class Batch:
 
 def job_class(j) -> tuple:
     return ("tpose", j.dtype, j.rows) if j.kind == "tpose" else ("sum", j.dtype)
+
+
+SMALL_JOB_BYTES = 4 << 20
+
+
+def launch_units(group, batching: bool) -> list:
+    """The launch units of the jobs admitted in one step: with batching, one
+    unit per (kind, small / large) in admission order; without, one per job."""
+    if not batching:
+        return [[p] for p in group]
+    units = {}
+    for p in group:
+        units.setdefault((p.job.kind, p.nbytes < SMALL_JOB_BYTES), []).append(p)
+    return list(units.values())
 
 
 class SlotPool:
@@ -121,11 +139,12 @@ class Scheduler:
         self.max_used = max(self.max_used, self.used)
         if not group:
             return False
-        h, nl = self.ex.launch(group, self.si, self.batching)
-        self.launches += nl
-        self.inflight.append(Batch(group, h))
-        self.si = (self.si + 1) % self.nstreams
-        self.batches += 1
+        for unit in launch_units(group, self.batching):
+            h, nl = self.ex.launch(unit, self.si, self.batching)
+            self.launches += nl
+            self.inflight.append(Batch(unit, h))
+            self.si = (self.si + 1) % self.nstreams
+            self.batches += 1
         return True
 
     def next_arrival(self):
@@ -286,9 +305,12 @@ def run(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=No
     return stats
 
 
-def bench(xtr, torch, log, count=200000, seed=12, rate=20000.0):
+def bench(xtr, torch, log, count=200000, seed=12, rate=20000.0,
+          sweep=((60000.0, 120000), (200000.0, 100000))):
     """The serving workload: a Poisson stream (mean 20k jobs/s) of mixed jobs,
-    continuous batching vs one launch per job on the same GPU."""
+    continuous batching vs one launch per job on the same GPU; then the same
+    mix at higher arrival rates (the last one beyond what the GPU can serve),
+    where the cost of one launch per job shows."""
     import workloads as W
     jobs = W.serving_jobs(count, seed, rate=rate)
     pool = InputPool(torch, jobs)
@@ -299,4 +321,13 @@ def bench(xtr, torch, log, count=200000, seed=12, rate=20000.0):
     out = {"offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1), "rate_jobs_per_s": rate}
     out["batched"] = run(xtr, torch, jobs, batching=True, pool=pool, outs=outs, log=log)
     out["per_job"] = run(xtr, torch, jobs, batching=False, pool=pool, outs=outs, log=log)
+    out["sweep"] = []
+    for r, c in sweep:
+        js = [j for j in W.serving_jobs(c, seed + int(r), rate=r) if InputPool.key(j) in pool.t]
+        ent = {"rate_jobs_per_s": r, "offered_gbs": round(W.mean_job_bytes() * r / 1e9, 1)}
+        for name, b in (("batched", True), ("per_job", False)):
+            st = run(xtr, torch, js, batching=b, pool=pool, outs=outs, log=log)
+            ent[name] = {k: st[k] for k in ("jobs", "p50_ms", "p99_ms", "throughput_gbs",
+                                            "achieved_jobs_per_s", "launches", "batches")}
+        out["sweep"].append(ent)
     return out

@@ -5,7 +5,8 @@ admitted in its step, and one-launch-per-job mode launches each job alone."""
 import numpy as np
 
 import workloads as W
-from paper_2605_13864_amd.serve import Scheduler, SlotPool, job_class
+from paper_2605_13864_amd.serve import (SMALL_JOB_BYTES, Pending, Scheduler, SlotPool, job_class,
+                                        launch_units)
 
 
 class FakeExecutor:
@@ -20,6 +21,7 @@ class FakeExecutor:
         t_done = self.clock[0] + 5e-6 + nbytes / (self.gbs * 1e9)
         self.launched.append((list(p.idx for p in group), si))
         return t_done, (len({job_class(p.job)[:2] for p in group}) if batching else len(group))
+
 
     def done(self, t_done):
         return t_done if self.clock[0] >= t_done else None
@@ -96,3 +98,23 @@ def test_budget_blocks_head_of_line():
     assert ok
     # a budget of one largest job admits exactly one job at a time when needed
     assert sch.max_used <= big
+
+
+def test_launch_units_partition_by_kind_and_size():
+    jobs = W.serving_jobs(400, 9, tpose_k=(5, 12), sum_k=(10, 24))
+    group = [Pending(i, j, j.nbytes, job_class(j)) for i, j in enumerate(jobs)]
+    units = launch_units(group, True)
+    assert sorted(p.idx for u in units for p in u) == list(range(len(jobs)))   # a partition
+    for u in units:
+        assert len({(p.job.kind, p.nbytes < SMALL_JOB_BYTES) for p in u}) == 1
+        assert [p.idx for p in u] == sorted(p.idx for p in u)                  # admission order
+    assert len(units) == 4
+    per = launch_units(group, False)
+    assert [[p.idx] for p in group] == [[p.idx for p in u] for u in per]
+
+
+def test_per_job_units_each_have_their_own_completion():
+    jobs = W.serving_jobs(500, 10, tpose_k=(5, 9), sum_k=(10, 16))
+    sch, ex, _ = simulate(jobs, 1 << 40, slots_for(jobs, 64), batching=False, dt=1e-4)
+    assert all(len(ix) == 1 for ix, _ in ex.launched)
+    assert sch.batches == len(jobs) == sch.launches
