@@ -59,4 +59,10 @@ int zero_fill(void *p, size_t bytes, hipStream_t stream);
 // Number of compute units of the current device (cached).
 int cu_count();
 
+// Workgroups of `kernel` (block_threads threads, static LDS only) that are
+// resident on the current device at once: the occupancy per CU (at most
+// cap_per_cu when > 0) times the CU count.  A persistent grid of exactly this
+// size has no workgroup that starts only after others finish.  Cached.
+int resident_blocks(const void *kernel, int block_threads, int cap_per_cu = 0);
+
 }  // namespace xtr

@@ -958,12 +958,17 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const ChunkRec *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
-    const int64_t occ = (int64_t)cu_count() * 8;
+    const bool nt = g_rcfg[DT].nt_load != 0;
+    const void *ks = nt ? (const void *)&k_reduce_seg_small<DT, MODE, true>
+                        : (const void *)&k_reduce_seg_small<DT, MODE, false>;
+    const void *kc = nt ? (const void *)&k_reduce_seg<DT, MODE, true>
+                        : (const void *)&k_reduce_seg<DT, MODE, false>;
+    const int64_t occ_s = resident_blocks(ks, NTHR), occ_c = resident_blocks(kc, NTHR);
     const int64_t gs_n = (nseg + NW - 1) / NW;
-    const dim3 gs((unsigned)(gs_n < occ ? gs_n : occ));
+    const dim3 gs((unsigned)(gs_n < occ_s ? gs_n : occ_s));
     const int64_t gc_n = cap > nseg ? cap : nseg;
-    const dim3 gc((unsigned)(gc_n < occ ? gc_n : occ));
-    if (g_rcfg[DT].nt_load) {
+    const dim3 gc((unsigned)(gc_n < occ_c ? gc_n : occ_c));
+    if (nt) {
         hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, true>), gs, dim3(NTHR), 0, st, src, off,
                            cb, nseg, cap, out);
         hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), gc, dim3(NTHR), 0, st, src, cb, cs,

@@ -195,6 +195,30 @@ int cu_count() {
     return cached[dev];
 }
 
+int resident_blocks(const void *kernel, int block_threads, int cap_per_cu) {
+    static std::mutex mu;
+    static std::map<std::pair<const void *, int>, int> cache;   // (kernel, device) -> per CU
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+    int per_cu = 0;
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        auto it = cache.find({kernel, dev});
+        if (it != cache.end()) per_cu = it->second;
+    }
+    if (per_cu == 0) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, block_threads, 0) != hipSuccess ||
+            n <= 0)
+            n = 1;
+        per_cu = n;
+        std::lock_guard<std::mutex> lk(mu);
+        cache[{kernel, dev}] = per_cu;
+    }
+    if (cap_per_cu > 0 && per_cu > cap_per_cu) per_cu = cap_per_cu;
+    return per_cu * cu_count();
+}
+
 }  // namespace xtr
 
 extern "C" {

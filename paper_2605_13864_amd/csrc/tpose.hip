@@ -39,12 +39,14 @@ namespace {
 
 constexpr int NT = 256;   // threads per workgroup
 
-template <int EB> struct Geo {
+// Tile geometry: SC 16-byte chunks per src row segment and DC per dst row
+// segment (16 = 256 bytes, the default on both sides; 32 = 512 bytes).
+template <int EB, int SC = 16, int DC = 16> struct Geo {
     static constexpr int V = 16 / EB;     // elements per 16-byte vector
-    static constexpr int TC = 16 * V;     // tile columns (src) = 256 bytes
-    static constexpr int TR = 16 * V;     // tile rows (src) = 256 bytes of a dst row
-    static constexpr int CHUNKS = 16;     // 16-byte chunks per tile row
-    static constexpr int LDS_VECS = TR * CHUNKS;
+    static constexpr int TC = SC * V;     // tile columns (src) = 16 * SC bytes of a src row
+    static constexpr int TR = DC * V;     // tile rows (src) = 16 * DC bytes of a dst row
+    static constexpr int CHUNKS = SC;     // 16-byte chunks per LDS tile row
+    static constexpr int LDS_VECS = TR * SC;
 };
 
 template <int EB> struct Elem;
@@ -230,21 +232,22 @@ __device__ __forceinline__ void piece_transpose(const uint4 *a, typename PieceT<
 // Moves the TR x TC tile at (R0, C0).  Interior tiles run without any bounds
 // test; tiles on the right or bottom edge mask whole pieces and fall back to
 // single elements only for the one piece a matrix edge cuts.
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                                         unsigned char *__restrict__ dst, int64_t rows,
                                         int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                         int64_t C0, uint4 *lds) {
-    using G = Geo<EB>;
+    using G = Geo<EB, SC, DC>;
     using T = typename Elem<EB>::T;
     using PT = typename PieceT<W>::T;
     // per-lane part of an address: 32 bits when the host guarantees it fits
     using LaneOff = typename std::conditional<OFF32, uint32_t, int64_t>::type;
     constexpr int V = G::V;
-    constexpr int P = 256 / W;          // pieces per 256-byte row segment
+    constexpr int P = 16 * SC / W;      // pieces per src row segment
     constexpr int RP = NT / P;          // tile rows per pass of the workgroup
     constexpr int PASSES = G::TR / RP;
     constexpr int EPW = W / EB;         // elements per piece
+    static_assert(RP >= 1 && PASSES >= 1 && G::TR % RP == 0, "phase-1 lane layout");
     const int t = threadIdx.x;
     const bool full = (R0 + G::TR <= rows) && (C0 + G::TC <= cols);
     unsigned char *ldsb = reinterpret_cast<unsigned char *>(lds);
@@ -252,7 +255,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     // Addresses are (uniform tile base + uniform per-pass offset) + lane offset:
     // the first two live in scalar registers, the lane offset is computed once.
 
-    // phase 1: P lanes per 256-byte row segment, rows RP apart per pass
+    // phase 1: P lanes per src row segment, rows RP apart per pass
     {
         const int k = t % P, r0 = t / P;
         const int64_t ldsrc = ld_src * EB;
@@ -267,7 +270,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
 #pragma unroll
             for (int p = 0; p < PASSES; p++) {
                 const int row = r0 + RP * p;
-                *reinterpret_cast<PT *>(ldsb + (row * 16 + swz<EB>(row, chunk)) * 16 + inner) = v[p];
+                *reinterpret_cast<PT *>(ldsb + (row * SC + swz<EB>(row, chunk)) * 16 + inner) = v[p];
             }
         } else {
             const int64_t c = C0 + (int64_t)k * EPW;
@@ -287,38 +290,41 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                         if (c + i < cols) u.e[i] = reinterpret_cast<const T *>(a)[i];
                     pv = u.pt;
                 }
-                *reinterpret_cast<PT *>(ldsb + (row * 16 + swz<EB>(row, chunk)) * 16 + inner) = pv;
+                *reinterpret_cast<PT *>(ldsb + (row * SC + swz<EB>(row, chunk)) * 16 + inner) = pv;
             }
         }
     }
 
     __syncthreads();   // ownership of the LDS tile moves from loaders to storers
 
-    // phase 2: P lanes per 256-byte dst row segment.  Lane k stores piece k,
+    // phase 2: P2 lanes per dst row segment.  Lane k stores piece k,
     // i.e. src rows k*E .. k*E+E-1 of one src column, so the lanes of a store
     // instruction write consecutive W-byte pieces of a dst row (whole lines
     // per instruction whatever W is).  The lane reads E 16-byte row chunks
     // from LDS and transposes them in registers into V pieces, one per dst
     // row of the chunk.  With W = 16 this is the V x V block transpose.
     {
-        constexpr int CPT = 16 / RP;                 // 16-byte column chunks per lane
-        const int k = t % P, g = t / P;
+        constexpr int P2 = 16 * DC / W;              // pieces per dst row segment
+        constexpr int RP2 = NT / P2;                 // column chunks per pass
+        constexpr int CPT = SC / RP2;                // 16-byte column chunks per lane
+        static_assert(RP2 >= 1 && CPT >= 1 && SC % RP2 == 0, "phase-2 lane layout");
+        const int k = t % P2, g = t / P2;
         const int64_t lddst = ld_dst * EB;
         unsigned char *tb = dst + (C0 * ld_dst + R0) * EB;                  // uniform
         const LaneOff lane = (LaneOff)(g * V) * (LaneOff)lddst + (LaneOff)(k * W);
         const int64_t rk = R0 + (int64_t)k * EPW;    // first src row of the piece
 #pragma unroll
         for (int cc = 0; cc < CPT; cc++) {
-            const int m = g + RP * cc;               // src cols m*V .. m*V+V-1
+            const int m = g + RP2 * cc;              // src cols m*V .. m*V+V-1
             uint4 a[EPW];
 #pragma unroll
             for (int e = 0; e < EPW; e++) {
                 const int row = k * EPW + e;
-                a[e] = lds[row * 16 + swz<EB>(row, m)];
+                a[e] = lds[row * SC + swz<EB>(row, m)];
             }
             PT o[V];
             piece_transpose<EB, W>(a, o);
-            unsigned char *cb = tb + (int64_t)(RP * cc * V) * lddst;        // uniform
+            unsigned char *cb = tb + (int64_t)(RP2 * cc * V) * lddst;       // uniform
             if (full) {
 #pragma unroll
                 for (int i = 0; i < V; i++) stw<W, NTS>((cb + (int64_t)i * lddst) + lane, o[i]);
@@ -377,23 +383,28 @@ __device__ __forceinline__ void do_tile_elem(const unsigned char *__restrict__ s
 // W = 0 selects the element-wise form.  OFF32: every per-lane offset inside a
 // tile fits in 32 bits (the host checks the pitches), so addresses are a
 // uniform 64-bit tile base plus a 32-bit lane offset.
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __device__ __forceinline__ void tile_any(const unsigned char *src, unsigned char *dst, int64_t rows,
                                          int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                          int64_t C0, uint4 *lds) {
-    if constexpr (W == 0) do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
-    else do_tile<EB, W, NTL, NTS, OFF32>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+    if constexpr (W == 0) {
+        static_assert(SC == 16 && DC == 16, "element-wise tiles use the default geometry");
+        do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+    } else {
+        do_tile<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+    }
 }
 
 // ---------------------------------------------------------------- kernels
 
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ src,
                                               unsigned char *__restrict__ dst, int64_t rows,
                                               int64_t cols, int64_t ld_src, int64_t ld_dst,
                                               int64_t tiles_r, int64_t tiles_c, int xcd,
                                               int group) {
-    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+    using G = Geo<EB, SC, DC>;
+    __shared__ uint4 lds[G::LDS_VECS];
     const int64_t ntiles = tiles_r * tiles_c;
     for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
         const int64_t G = gridDim.x;
@@ -403,8 +414,8 @@ __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ 
         const int64_t L = xcd ? wave0 + xcd_remap(blockIdx.x, inwave) : b;
         int64_t tr, tc;
         band_order(L, tiles_r, tiles_c, group, tr, tc);
-        tile_any<EB, W, NTL, NTS, OFF32>(src, dst, rows, cols, ld_src, ld_dst, tr * Geo<EB>::TR,
-                                         tc * Geo<EB>::TC, lds);
+        tile_any<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, tr * G::TR,
+                                                 tc * G::TC, lds);
         __syncthreads();   // LDS is reused by the next tile of this workgroup
     }
 }
@@ -496,10 +507,11 @@ int check_one(const void *src, const void *dst, int64_t rows, int64_t cols, int6
 
 // Per-lane offsets inside a tile stay below 2^31 (so the 32-bit addressing of
 // do_tile is exact): tile rows x row pitch on either side, plus one row.
-template <int EB> bool off32_ok(int64_t ld_src, int64_t ld_dst) {
+template <int EB, int SC = 16, int DC = 16> bool off32_ok(int64_t ld_src, int64_t ld_dst) {
+    using G = Geo<EB, SC, DC>;
     const int64_t lim = (int64_t)1 << 31;
-    return (int64_t)Geo<EB>::TR * ld_src * EB + 256 < lim &&
-           (int64_t)Geo<EB>::TC * ld_dst * EB + 256 < lim;
+    return (int64_t)G::TR * ld_src * EB + 16 * SC < lim &&
+           (int64_t)G::TC * ld_dst * EB + 16 * DC < lim;
 }
 bool off32_rt(int eb, int64_t ld_src, int64_t ld_dst) {
     switch (eb) {
@@ -540,21 +552,21 @@ constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs lo
 
 // Tuned launch configuration per element size (index log2(elem bytes)).
 xtr_tpose_config g_cfg[4] = {
-    {1, 1, 1, 1, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, {0}},
-    {1, 1, 1, 1, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, {0}},
+    {1, 1, 1, 1, 0, 0, 0, 0}, {1, 1, 1, 1, 0, 0, 0, 0},
+    {1, 1, 1, 1, 0, 0, 0, 0}, {1, 1, 1, 1, 0, 0, 0, 0},
 };
 int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
-template <int EB, int W, bool NTL, bool NTS>
+template <int EB, int W, bool NTL, bool NTS, int SC, int DC>
 void launch_k(dim3 grid, hipStream_t st, const void *src, void *dst, int64_t rows, int64_t cols,
               int64_t ld_src, int64_t ld_dst, int64_t tiles_r, int64_t tiles_c, int xcd,
               int group) {
-    if (off32_ok<EB>(ld_src, ld_dst))
-        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, true>), grid, dim3(NT), 0, st,
+    if (off32_ok<EB, SC, DC>(ld_src, ld_dst))
+        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, true, SC, DC>), grid, dim3(NT), 0, st,
                            (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
                            ld_dst, tiles_r, tiles_c, xcd, group);
     else
-        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, false>), grid, dim3(NT), 0, st,
+        hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, false, SC, DC>), grid, dim3(NT), 0, st,
                            (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
                            ld_dst, tiles_r, tiles_c, xcd, group);
 }
@@ -567,32 +579,12 @@ bool lines_ok(const void *p, int64_t ld, int eb) {
     return (((uint64_t)(uintptr_t)p | (uint64_t)(ld * eb)) & 127) == 0;
 }
 
-template <int EB, int W>
-void launch_w(const xtr_tpose_config &c, dim3 gd, hipStream_t st, const void *src, void *dst,
-              int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t tiles_r,
-              int64_t tiles_c, int group) {
-    const bool ntl = lines_ok(src, ld_src, EB) ? c.nt_load != 0 : c.nt_load_shared != 0;
-    const bool nts = lines_ok(dst, ld_dst, EB) ? c.nt_store != 0 : c.nt_store_shared != 0;
-    if (ntl && nts)
-        launch_k<EB, W, true, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                                    c.xcd, group);
-    else if (ntl)
-        launch_k<EB, W, true, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                     tiles_c, c.xcd, group);
-    else if (nts)
-        launch_k<EB, W, false, true>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                     tiles_c, c.xcd, group);
-    else
-        launch_k<EB, W, false, false>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,
-                                      tiles_c, c.xcd, group);
-}
-
-template <int EB>
-int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
-               int64_t ld_dst, hipStream_t stream) {
-    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
-    const int64_t tiles_r = (rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
-    const int64_t tiles_c = (cols + Geo<EB>::TC - 1) / Geo<EB>::TC;
+template <int EB, int W, int SC = 16, int DC = 16>
+void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *dst,
+              int64_t rows, int64_t cols, int64_t ld_src, int64_t ld_dst) {
+    using G = Geo<EB, SC, DC>;
+    const int64_t tiles_r = (rows + G::TR - 1) / G::TR;
+    const int64_t tiles_c = (cols + G::TC - 1) / G::TC;
     const int64_t ntiles = tiles_r * tiles_c;
     int64_t grid = ntiles < MAX_GRID ? ntiles : MAX_GRID;
     if (c.blocks_per_cu > 0) {
@@ -601,23 +593,47 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     }
     const int group = c.group < 1 ? 1 : c.group;
     const dim3 gd((unsigned)grid);
+    const bool ntl = lines_ok(src, ld_src, EB) ? c.nt_load != 0 : c.nt_load_shared != 0;
+    const bool nts = lines_ok(dst, ld_dst, EB) ? c.nt_store != 0 : c.nt_store_shared != 0;
+#define XTR_K(NL, NS)                                                                        \
+    launch_k<EB, W, NL, NS, SC, DC>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,    \
+                                    tiles_c, c.xcd, group)
+    if (ntl && nts) XTR_K(true, true);
+    else if (ntl) XTR_K(true, false);
+    else if (nts) XTR_K(false, true);
+    else XTR_K(false, false);
+#undef XTR_K
+}
+
+// Tile geometry of a single transpose: tile 1 = 512-byte src row segments,
+// 2 = 512-byte dst row segments (16-byte pieces, 2- to 8-byte elements only),
+// else 256 x 256 bytes.
+template <int EB>
+int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+               int64_t ld_dst, hipStream_t stream) {
+    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
     switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
-    case 16: launch_w<EB, 16>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                              group); break;
+    case 16:
+        if constexpr (EB >= 2) {
+            if (c.tile == 1) {
+                launch_w<EB, 16, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+            if (c.tile == 2) {
+                launch_w<EB, 16, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
+        launch_w<EB, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+        break;
     case 8:
-        if constexpr (EB <= 8)
-            launch_w<EB, 8>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                            group);
+        if constexpr (EB <= 8) launch_w<EB, 8>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     case 4:
-        if constexpr (EB <= 4)
-            launch_w<EB, 4>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                            group);
+        if constexpr (EB <= 4) launch_w<EB, 4>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     default:
-        if constexpr (EB <= 2)
-            launch_w<EB, 0>(c, gd, stream, src, dst, rows, cols, ld_src, ld_dst, tiles_r, tiles_c,
-                            group);
+        if constexpr (EB <= 2) launch_w<EB, 0>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     }
     XTR_HIP(hipGetLastError());
@@ -632,9 +648,14 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
     const bool ntl = lines ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines ? c.nt_store != 0 : c.nt_store_shared != 0;
     const int group = c.group < 1 ? 1 : c.group;
-#define XTR_KB(NL, NS)                                                                     \
-    hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>), dim3((unsigned)grid), dim3(NT), \
-                       0, st, jobs, bases, nj, ntiles, c.xcd, group)
+#define XTR_KB(NL, NS)                                                                      \
+    do {                                                                                    \
+        const int64_t occ = resident_blocks(                                                \
+            (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32>, NT);                       \
+        hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>),                         \
+                           dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st, jobs, \
+                           bases, nj, ntiles, c.xcd, group);                                \
+    } while (0)
     if (ntl && nts) XTR_KB(true, true);
     else if (ntl) XTR_KB(true, false);
     else if (nts) XTR_KB(false, true);
@@ -753,8 +774,8 @@ int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
         if (!bt.nj[g]) continue;
         const int slot = g / 16, w = wof((g / 4) % 4);
         const bool off32 = ((g / 2) & 1) != 0, lines = (g & 1) != 0;
-        const int64_t occ = (int64_t)cu_count() * 8;
-        int64_t grid = bt.ntiles[g] < occ ? bt.ntiles[g] : occ;
+        // at most the resident capacity of the group's kernel (clamped at launch)
+        int64_t grid = bt.ntiles[g] < 0x7fffffff ? bt.ntiles[g] : 0x7fffffff;
         if (grid < 1) grid = 1;
         const Job *jobs = djobs + bt.at[g];
         const int64_t *bases = dbases + bt.at[g];
@@ -859,8 +880,10 @@ int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg) {
 int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg) {
     if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: bad arguments");
-    if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64)
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: group in [1, 64], blocks_per_cu in [0, 64]");
+    if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
+        cfg->tile < 0 || cfg->tile > 2)
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: group in [1, 64], blocks_per_cu in "
+                                     "[0, 64], tile in [0, 2]");
     xtr::g_cfg[xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

@@ -4,7 +4,7 @@
 
 For every element size it times each candidate ``xtr_tpose_config`` (streaming
 loads / stores, XCD-contiguous tile ranges, band height of the tile order,
-one-tile-per-workgroup or persistent grids) on a representative large
+one-tile-per-workgroup or persistent grids, tile geometry) on a representative large
 transpose, and each ``xtr_reduce_config`` on a large sum, with HIP events on
 the launching stream; the fastest wins.  Results are written as JSON keyed by
 GPU architecture and element size / dtype; ``load_tuned()`` applies a file at
@@ -53,15 +53,16 @@ def arch_name(torch) -> str:
     return getattr(p, "gcnArchName", "unknown").split(":")[0]
 
 
-def tpose_candidates(quick: bool):
+def tpose_candidates(quick: bool, eb: int = 4):
     nts = [(1, 1), (0, 0)] if quick else [(1, 1), (1, 0), (0, 1), (0, 0)]
     groups = [1, 4, 16] if quick else [1, 2, 4, 8, 16, 32]
     bpc = [0, 8] if quick else [0, 4, 8, 16]
-    for (nl, ns), xcd, g, b in itertools.product(nts, [1, 0], groups, bpc):
+    tiles = [0] if eb == 1 else [0, 1, 2]
+    for (nl, ns), xcd, g, b, tl in itertools.product(nts, [1, 0], groups, bpc, tiles):
         # the *_shared flags follow along here (the main shape may have rows
         # that share lines); they are refined on a shared-line shape afterwards
         yield {"nt_load": nl, "nt_store": ns, "xcd": xcd, "group": g, "blocks_per_cu": b,
-               "nt_load_shared": nl, "nt_store_shared": ns}
+               "nt_load_shared": nl, "nt_store_shared": ns, "tile": tl}
 
 
 def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
@@ -76,7 +77,7 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
     best = None
     results = []
     try:
-        for cfg in tpose_candidates(quick):
+        for cfg in tpose_candidates(quick, eb):
             xtr.set_tpose_config(eb, **cfg)
             sec = _time(torch, lambda: xtr.tpose(src, dst, dtype=dt))
             gbs = nbytes / sec / 1e9

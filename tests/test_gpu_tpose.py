@@ -92,6 +92,25 @@ def test_every_piece_width(xtr, orc, eb, w):
         run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=40 + i)
 
 
+@pytest.mark.parametrize("eb", [2, 4, 8])
+@pytest.mark.parametrize("tile", [1, 2])
+def test_tile_geometries(xtr, orc, eb, tile):
+    """512-byte src (tile 1) or dst (tile 2) row segments: whole and ragged
+    tiles, 16-byte pieces, against the oracle."""
+    orig = xtr.tpose_config(eb)
+    T = TILE[eb]
+    try:
+        xtr.set_tpose_config(eb, tile=tile)
+        for i, (r, c) in enumerate([(2 * T, 4 * T), (4 * T + 3, 2 * T + 5), (T - 1, 3 * T + 1),
+                                    (1, 1)]):
+            v = 16 // eb
+            pad_s = (-c) % v + v * (i % 2)          # keep 16-byte pitches: 16-byte pieces
+            pad_d = (-r) % v
+            run_tpose(xtr, orc, r, c, eb, pad_s=pad_s, pad_d=pad_d, seed=60 + i)
+    finally:
+        xtr.set_tpose_config(eb, **orig)
+
+
 def test_tiny_enumeration(xtr, orc):
     for eb in (1, 4):
         for r in range(1, 12):
