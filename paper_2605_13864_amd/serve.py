@@ -9,13 +9,13 @@ input (a pool generated once) and an operation.  Each scheduler step
   3. admits pending jobs in FIFO order while the in-flight bytes (input +
      output of every admitted, unfinished job) stay within the HBM budget and
      an output slot of the job's class is free;
-  4. splits the jobs admitted in this step into launch units by kind and
-     size class (jobs under 4 MiB apart from larger ones, so a small job never
-     waits for a large one in its unit) and launches each unit at once on the
-     next of K streams: transposes as one persistent launch per element size
-     (tpose_batched), sums as one launch per dtype (reduce_sum_batched_scatter,
-     straight into each job's output slot); each unit ends with its own
-     completion event.
+  4. splits the jobs admitted in this step into launch units -- the jobs
+     under 4 MiB of each kind together, every larger job alone (it is
+     bandwidth-bound and gains nothing from sharing a launch) -- and launches
+     each unit at once on the next of K streams: transposes as one persistent
+     launch per element size (tpose_batched), sums as one launch per dtype
+     (reduce_sum_batched_scatter, straight into each job's output slot); each
+     unit ends with its own completion event.
 
 Jobs that arrive while others run therefore join the next unit as soon as
 budget and slots free up, and units on different streams overlap on the
@@ -60,14 +60,23 @@ SMALL_JOB_BYTES = 4 << 20
 
 
 def launch_units(group, batching: bool) -> list:
-    """The launch units of the jobs admitted in one step: with batching, one
-    unit per (kind, small / large) in admission order; without, one per job."""
+    """The launch units of the jobs admitted in one step: with batching, the
+    small jobs of each kind form one unit (one launch per element size or
+    dtype instead of one per job) and every large job is a unit of its own (it
+    is bandwidth-bound, so sharing a launch would only make it wait for the
+    others); without batching, one unit per job.  Admission order is kept."""
     if not batching:
         return [[p] for p in group]
-    units = {}
+    small, units = {}, []
     for p in group:
-        units.setdefault((p.job.kind, p.nbytes < SMALL_JOB_BYTES), []).append(p)
-    return list(units.values())
+        if p.nbytes < SMALL_JOB_BYTES:
+            if p.job.kind not in small:
+                small[p.job.kind] = []
+                units.append(small[p.job.kind])
+            small[p.job.kind].append(p)
+        else:
+            units.append([p])
+    return units
 
 
 class SlotPool:

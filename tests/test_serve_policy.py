@@ -108,7 +108,10 @@ def test_launch_units_partition_by_kind_and_size():
     for u in units:
         assert len({(p.job.kind, p.nbytes < SMALL_JOB_BYTES) for p in u}) == 1
         assert [p.idx for p in u] == sorted(p.idx for p in u)                  # admission order
-    assert len(units) == 4
+        assert len(u) == 1 or u[0].nbytes < SMALL_JOB_BYTES                    # large jobs alone
+    n_large = sum(1 for p in group if p.nbytes >= SMALL_JOB_BYTES)
+    assert 0 < n_large < len(group)
+    assert len(units) == n_large + 2
     per = launch_units(group, False)
     assert [[p.idx] for p in group] == [[p.idx for p in u] for u in per]
 
