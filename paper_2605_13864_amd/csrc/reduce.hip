@@ -581,8 +581,7 @@ __global__ void __launch_bounds__(NTHR) k_combine_level(const P *__restrict__ in
 // Many ranges from a host-built table (reduce_sum_batched): workgroup b takes
 // global chunk b and finds its range by binary search over chunk_base.
 template <int DT, int MODE, bool NT>
-__global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__ tab, int nr,
-                                                     Levels lv) {
+__device__ __forceinline__ void table_chunk(const Range *tab, int nr, const Levels &lv) {
     const int64_t b = blockIdx.x;
     int lo = 0, hi = nr - 1;
     while (lo < hi) {
@@ -595,6 +594,24 @@ __global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__
     auto v = reduce_chunk<DT, MODE, NT>(rg, j);
     if (threadIdx.x >= 64) return;
     grid_combine<MODE>(rg, j, v, lv);
+}
+
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_table(const Range *__restrict__ tab, int nr,
+                                                     Levels lv) {
+    table_chunk<DT, MODE, NT>(tab, nr, lv);
+}
+
+// A small batch passes its ranges inside the kernel arguments: no table
+// upload (no host-to-device copy ahead of the kernel in the stream).
+constexpr int INLINE_RANGES = 32;
+struct RangePack {
+    Range r[INLINE_RANGES];
+};
+
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_table_inl(RangePack pk, int nr, Levels lv) {
+    table_chunk<DT, MODE, NT>(pk.r, nr, lv);
 }
 
 // ---------------------------------------------------------------- segmented
@@ -945,6 +962,16 @@ void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
                            0, st, rg, lv);
 }
 template <int DT, int MODE>
+void launch_table_inl(const RangePack &pk, int nr, int64_t nchunks, const Levels &lv,
+                      hipStream_t st) {
+    if (g_rcfg[DT].nt_load)
+        hipLaunchKernelGGL((k_reduce_table_inl<DT, MODE, true>), dim3((unsigned)nchunks),
+                           dim3(NTHR), 0, st, pk, nr, lv);
+    else
+        hipLaunchKernelGGL((k_reduce_table_inl<DT, MODE, false>), dim3((unsigned)nchunks),
+                           dim3(NTHR), 0, st, pk, nr, lv);
+}
+template <int DT, int MODE>
 void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, hipStream_t st) {
     if (g_rcfg[DT].nt_load)
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, true>), dim3((unsigned)nchunks), dim3(NTHR), 0,
@@ -1044,6 +1071,14 @@ int sum_batched_impl(const void *const *srcs, const int64_t *ns, int64_t count, 
     WsView v;
     int rc = get_ws(nullptr, 0, total, parts_bytes(total, mode), st, who, &v);
     if (rc) return rc;
+    if (count <= INLINE_RANGES) {
+        RangePack pk;
+        for (int64_t i = 0; i < count; i++) pk.r[i] = tab[i];
+        Levels lv = levels_at(v, v.data, total, mode);
+        XTR_DISPATCH_SUM(dtype, mode, launch_table_inl, (pk, (int)count, total, lv, st));
+        XTR_HIP(hipGetLastError());
+        return XTR_OK;
+    }
     rc = workspace(WS_TABLE, st, tab.size() * sizeof(Range), &tw);
     if (rc) return rc;
     rc = upload(tab.data(), tab.size() * sizeof(Range), tw, st);

@@ -462,10 +462,8 @@ __device__ __forceinline__ int job_forward(const int64_t *bases, int nj, int j, 
 // follow the band order, so tiles that share cache lines at their edges (rows
 // of a job whose pitch is not a multiple of the line) meet in one L2.
 template <int EB, int W, bool NTL, bool NTS, bool OFF32>
-__global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
-                                                      const int64_t *__restrict__ bases, int njobs,
-                                                      int64_t ntiles, int xcd, int group) {
-    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+__device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *bases, int njobs,
+                                              int64_t ntiles, int xcd, int group, uint4 *lds) {
     const int64_t G = gridDim.x;
     int j = -1;
     for (int64_t wave0 = 0; wave0 < ntiles; wave0 += G) {
@@ -481,6 +479,29 @@ __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jo
                                          tr * Geo<EB>::TR, tc * Geo<EB>::TC, lds);
         __syncthreads();
     }
+}
+
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+__global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
+                                                      const int64_t *__restrict__ bases, int njobs,
+                                                      int64_t ntiles, int xcd, int group) {
+    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32>(jobs, bases, njobs, ntiles, xcd, group, lds);
+}
+
+// A small group passes its jobs inside the kernel arguments: no table upload
+// (no host-to-device copy ahead of the kernel in the stream).
+constexpr int INLINE_JOBS = 24;
+struct JobPack {
+    Job jobs[INLINE_JOBS];
+    int64_t bases[INLINE_JOBS];
+};
+
+template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+__global__ void __launch_bounds__(NT) k_tpose_batched_inl(JobPack pk, int njobs, int64_t ntiles,
+                                                          int xcd, int group) {
+    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
 }
 
 // ---------------------------------------------------------------- host side
@@ -640,21 +661,30 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     return XTR_OK;
 }
 
-// `lines`: every job of the group has line-aligned src and dst rows.
+// `lines`: every job of the group has line-aligned src and dst rows.  `pk`
+// (host) non-null: the group's jobs travel in the kernel arguments.
 template <int EB, int W, bool OFF32>
 void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
-                      const int64_t *bases, int nj, int64_t ntiles) {
+                      const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
     const bool ntl = lines ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines ? c.nt_store != 0 : c.nt_store_shared != 0;
     const int group = c.group < 1 ? 1 : c.group;
 #define XTR_KB(NL, NS)                                                                      \
     do {                                                                                    \
-        const int64_t occ = resident_blocks(                                                \
-            (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32>, NT);                       \
-        hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>),                         \
-                           dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st, jobs, \
-                           bases, nj, ntiles, c.xcd, group);                                \
+        if (pk) {                                                                           \
+            const int64_t occ = resident_blocks(                                            \
+                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32>, NT);               \
+            hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32>),                 \
+                               dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
+                               *pk, nj, ntiles, c.xcd, group);                              \
+        } else {                                                                            \
+            const int64_t occ = resident_blocks(                                            \
+                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32>, NT);                   \
+            hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>),                     \
+                               dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
+                               jobs, bases, nj, ntiles, c.xcd, group);                      \
+        }                                                                                   \
     } while (0)
     if (ntl && nts) XTR_KB(true, true);
     else if (ntl) XTR_KB(true, false);
@@ -665,10 +695,10 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
 
 template <int EB>
 void launch_batched(int w, bool off32, bool lines, int64_t grid, hipStream_t st, const Job *jobs,
-                    const int64_t *bases, int nj, int64_t ntiles) {
-#define XTR_BW(WW)                                                                        \
-    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles);  \
-    else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles);
+                    const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
+#define XTR_BW(WW)                                                                           \
+    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+    else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles, pk);
     switch (w) {
     case 16: XTR_BW(16) break;
     case 8:
@@ -765,25 +795,43 @@ int upload_batch(const BatchTable &bt, void *dev, hipStream_t stream) {
                   static_cast<unsigned char *>(dev) + bt.jobs_bytes(), stream);
 }
 
-// One persistent launch per non-empty group; `dev` is the device image of bt.
+// Every group has at most INLINE_JOBS jobs (the batch can run without a table).
+bool batch_inline(const BatchTable &bt) {
+    for (int g = 0; g < NGROUPS; g++)
+        if (bt.nj[g] > INLINE_JOBS) return false;
+    return true;
+}
+
+// One persistent launch per non-empty group; `dev` is the device image of bt,
+// or nullptr when batch_inline(bt) (jobs in the kernel arguments).
 int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
     const Job *djobs = static_cast<const Job *>(dev);
-    const int64_t *dbases = reinterpret_cast<const int64_t *>(
-        static_cast<const unsigned char *>(dev) + bt.jobs_bytes());
+    const int64_t *dbases = dev ? reinterpret_cast<const int64_t *>(
+                                      static_cast<const unsigned char *>(dev) + bt.jobs_bytes())
+                                : nullptr;
+    JobPack pack;
     for (int g = 0; g < NGROUPS; g++) {
         if (!bt.nj[g]) continue;
+        const JobPack *pk = nullptr;
+        if (!dev) {
+            for (int i = 0; i < bt.nj[g]; i++) {
+                pack.jobs[i] = bt.all[bt.at[g] + i];
+                pack.bases[i] = bt.bases[bt.at[g] + i];
+            }
+            pk = &pack;
+        }
         const int slot = g / 16, w = wof((g / 4) % 4);
         const bool off32 = ((g / 2) & 1) != 0, lines = (g & 1) != 0;
         // at most the resident capacity of the group's kernel (clamped at launch)
         int64_t grid = bt.ntiles[g] < 0x7fffffff ? bt.ntiles[g] : 0x7fffffff;
         if (grid < 1) grid = 1;
-        const Job *jobs = djobs + bt.at[g];
-        const int64_t *bases = dbases + bt.at[g];
+        const Job *jobs = dev ? djobs + bt.at[g] : nullptr;
+        const int64_t *bases = dev ? dbases + bt.at[g] : nullptr;
         switch (slot) {
-        case 0: launch_batched<1>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
-        case 1: launch_batched<2>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
-        case 2: launch_batched<4>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
-        default: launch_batched<8>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g]); break;
+        case 0: launch_batched<1>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 1: launch_batched<2>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 2: launch_batched<4>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        default: launch_batched<8>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
         }
         XTR_HIP(hipGetLastError());
     }
@@ -794,6 +842,7 @@ int tpose_batched_impl(const xtr_tpose_desc *descs, int64_t count, hipStream_t s
     BatchTable bt;
     int rc = build_batch(descs, count, "tpose_batched", bt);
     if (rc || bt.all.empty()) return rc;
+    if (batch_inline(bt)) return launch_batch(bt, nullptr, stream);
     void *wsp = nullptr;
     rc = workspace(WS_TABLE, stream, bt.bytes(), &wsp);
     if (rc) return rc;

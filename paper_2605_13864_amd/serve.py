@@ -11,7 +11,9 @@ input (a pool generated once) and an operation.  Each scheduler step
      an output slot of the job's class is free;
   4. splits the jobs admitted in this step into launch units -- the jobs
      under 4 MiB of each kind together, every larger job alone (it is
-     bandwidth-bound and gains nothing from sharing a launch) -- and launches
+     bandwidth-bound and gains nothing from sharing a launch) unless jobs are
+     left waiting, when the larger jobs of a kind share a unit as well (then
+     launches are the scarce resource) -- and launches
      each unit at once on the next of K streams: transposes as one persistent
      launch per element size (tpose_batched), sums as one launch per dtype
      (reduce_sum_batched_scatter, straight into each job's output slot); each
@@ -59,21 +61,24 @@ def job_class(j) -> tuple:
 SMALL_JOB_BYTES = 4 << 20
 
 
-def launch_units(group, batching: bool) -> list:
+def launch_units(group, batching: bool, backlog: bool = False) -> list:
     """The launch units of the jobs admitted in one step: with batching, the
     small jobs of each kind form one unit (one launch per element size or
     dtype instead of one per job) and every large job is a unit of its own (it
     is bandwidth-bound, so sharing a launch would only make it wait for the
-    others); without batching, one unit per job.  Admission order is kept."""
+    others) -- unless jobs are left waiting (`backlog`): then launches are the
+    scarce resource and the large jobs of a kind share a unit too.  Without
+    batching, one unit per job.  Admission order is kept."""
     if not batching:
         return [[p] for p in group]
-    small, units = {}, []
+    shared, units = {}, []
     for p in group:
-        if p.nbytes < SMALL_JOB_BYTES:
-            if p.job.kind not in small:
-                small[p.job.kind] = []
-                units.append(small[p.job.kind])
-            small[p.job.kind].append(p)
+        if backlog or p.nbytes < SMALL_JOB_BYTES:
+            key = (p.job.kind, p.nbytes < SMALL_JOB_BYTES)
+            if key not in shared:
+                shared[key] = []
+                units.append(shared[key])
+            shared[key].append(p)
         else:
             units.append([p])
     return units
@@ -148,7 +153,7 @@ class Scheduler:
         self.max_used = max(self.max_used, self.used)
         if not group:
             return False
-        for unit in launch_units(group, self.batching):
+        for unit in launch_units(group, self.batching, backlog=bool(self.pending)):
             h, nl = self.ex.launch(unit, self.si, self.batching)
             self.launches += nl
             self.inflight.append(Batch(unit, h))
@@ -294,6 +299,7 @@ def run(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=No
     stats = {
         "jobs": len(jobs), "batching": batching, "streams": nstreams,
         "budget_gib": budget / 2 ** 30, "max_inflight_gib": round(sch.max_used / 2 ** 30, 3),
+        "max_inflight_bytes": int(sch.max_used),
         "p50_ms": round(float(np.nanpercentile(lat, 50)) * 1e3, 4),
         "p99_ms": round(float(np.nanpercentile(lat, 99)) * 1e3, 4),
         "mean_ms": round(float(np.nanmean(lat)) * 1e3, 4),

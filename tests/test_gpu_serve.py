@@ -18,7 +18,7 @@ def test_results_same_alone_and_in_mix(xtr, orc, batching):
     jobs = W.serving_jobs(600, 21, rate=20000.0, tpose_k=(5, 10), sum_k=(10, 20))
     budget = 96 << 20
     st = serve.run(xtr, torch, jobs, batching=batching, budget=budget, keep_results=True)
-    assert st["max_inflight_gib"] * 2 ** 30 <= budget
+    assert st["max_inflight_bytes"] <= budget
     assert sorted(st["results"]) == list(range(len(jobs)))
     assert st["admit_order"] == sorted(st["admit_order"])
     pool = serve.InputPool(torch, jobs)           # same seed: same inputs

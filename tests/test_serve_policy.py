@@ -114,6 +114,12 @@ def test_launch_units_partition_by_kind_and_size():
     assert len(units) == n_large + 2
     per = launch_units(group, False)
     assert [[p.idx] for p in group] == [[p.idx for p in u] for u in per]
+    # with a backlog the large jobs of a kind share a unit as well
+    busy = launch_units(group, True, backlog=True)
+    assert sorted(p.idx for u in busy for p in u) == list(range(len(jobs)))
+    assert len(busy) == 4
+    for u in busy:
+        assert len({(p.job.kind, p.nbytes < SMALL_JOB_BYTES) for p in u}) == 1
 
 
 def test_per_job_units_each_have_their_own_completion():
