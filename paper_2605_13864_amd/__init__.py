@@ -38,7 +38,8 @@ class XtrError(RuntimeError):
 class TposeConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("nt_store", C.c_int32), ("xcd", C.c_int32),
                 ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("nt_store_shared", C.c_int32),
-                ("nt_load_shared", C.c_int32), ("tile", C.c_int32)]
+                ("nt_load_shared", C.c_int32), ("tile", C.c_int32), ("tile_shared", C.c_int32),
+                ("_reserved", C.c_int32 * 3)]
 
 
 class ReduceConfig(C.Structure):
@@ -388,7 +389,7 @@ def tpose_config(elem_bytes: int) -> dict:
     _check(load().xtr_tpose_get_config(elem_bytes, C.byref(c)), "xtr_tpose_get_config")
     return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
             "blocks_per_cu": c.blocks_per_cu, "nt_store_shared": c.nt_store_shared,
-            "nt_load_shared": c.nt_load_shared, "tile": c.tile}
+            "nt_load_shared": c.nt_load_shared, "tile": c.tile, "tile_shared": c.tile_shared}
 
 
 def set_tpose_config(elem_bytes: int, **kw):
@@ -399,7 +400,7 @@ def set_tpose_config(elem_bytes: int, **kw):
     cur.update(kw)
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
                     cur["blocks_per_cu"], cur["nt_store_shared"], cur["nt_load_shared"],
-                    cur["tile"])
+                    cur["tile"], cur["tile_shared"])
     _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
 
 

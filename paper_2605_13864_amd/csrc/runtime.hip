@@ -247,7 +247,7 @@ const char *xtr_last_error(void) { return xtr::g_err; }
 
 int xtr_elem_bytes(int dtype) { return xtr::elem_bytes(dtype); }
 
-int xtr_version(void) { return (0 << 16) | 1; }
+int xtr_version(void) { return (0 << 16) | 2; }
 
 int xtr_release(void) {
     std::lock_guard<std::mutex> lk(xtr::g_mu);

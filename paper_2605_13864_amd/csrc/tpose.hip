@@ -461,9 +461,10 @@ __device__ __forceinline__ int job_forward(const int64_t *bases, int nj, int j, 
 // round each XCD takes a contiguous range (xcd_remap), and within a job tiles
 // follow the band order, so tiles that share cache lines at their edges (rows
 // of a job whose pitch is not a multiple of the line) meet in one L2.
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC>
 __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *bases, int njobs,
                                               int64_t ntiles, int xcd, int group, uint4 *lds) {
+    using Gm = Geo<EB, 16, DC>;
     const int64_t G = gridDim.x;
     int j = -1;
     for (int64_t wave0 = 0; wave0 < ntiles; wave0 += G) {
@@ -472,21 +473,22 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
         const int64_t L = wave0 + (xcd ? xcd_remap(blockIdx.x, inwave) : (int64_t)blockIdx.x);
         j = (j < 0) ? job_search(bases, njobs, L) : job_forward(bases, njobs, j, L);
         const Job &jb = jobs[j];
-        const int64_t tiles_r = (jb.rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
+        const int64_t tiles_r = (jb.rows + Gm::TR - 1) / Gm::TR;
         int64_t tr, tc;
         band_order(L - jb.tile_base, tiles_r, jb.tiles_c, group, tr, tc);
-        tile_any<EB, W, NTL, NTS, OFF32>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src, jb.ld_dst,
-                                         tr * Geo<EB>::TR, tc * Geo<EB>::TC, lds);
+        tile_any<EB, W, NTL, NTS, OFF32, 16, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
+                                                 jb.ld_dst, tr * Gm::TR, tc * Gm::TC, lds);
         __syncthreads();
     }
 }
 
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+// DC = 32: 512-byte dst row segments (the tile_shared = 2 geometry).
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
                                                       const int64_t *__restrict__ bases, int njobs,
                                                       int64_t ntiles, int xcd, int group) {
-    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32>(jobs, bases, njobs, ntiles, xcd, group, lds);
+    __shared__ uint4 lds[Geo<EB, 16, DC>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32, DC>(jobs, bases, njobs, ntiles, xcd, group, lds);
 }
 
 // A small group passes its jobs inside the kernel arguments: no table upload
@@ -497,11 +499,11 @@ struct JobPack {
     int64_t bases[INLINE_JOBS];
 };
 
-template <int EB, int W, bool NTL, bool NTS, bool OFF32>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched_inl(JobPack pk, int njobs, int64_t ntiles,
                                                           int xcd, int group) {
-    __shared__ uint4 lds[Geo<EB>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
+    __shared__ uint4 lds[Geo<EB, 16, DC>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
 }
 
 // ---------------------------------------------------------------- host side
@@ -553,19 +555,30 @@ int piece_width(const void *src, const void *dst, int64_t ld_src, int64_t ld_dst
     return 0;
 }
 
-template <int EB> int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
-    const int64_t tr = (rows + Geo<EB>::TR - 1) / Geo<EB>::TR;
-    const int64_t tc = (cols + Geo<EB>::TC - 1) / Geo<EB>::TC;
+template <int EB, int DC = 16> int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
+    using G = Geo<EB, 16, DC>;
+    const int64_t tr = (rows + G::TR - 1) / G::TR;
+    const int64_t tc = (cols + G::TC - 1) / G::TC;
     if (tiles_c) *tiles_c = tc;
     return tr * tc;
 }
 
-int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c) {
+// wide: the DC = 32 geometry (2- to 8-byte elements)
+int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, bool wide = false) {
     switch (eb) {
     case 1: return tiles_of<1>(rows, cols, tiles_c);
-    case 2: return tiles_of<2>(rows, cols, tiles_c);
-    case 4: return tiles_of<4>(rows, cols, tiles_c);
-    default: return tiles_of<8>(rows, cols, tiles_c);
+    case 2: return wide ? tiles_of<2, 32>(rows, cols, tiles_c) : tiles_of<2>(rows, cols, tiles_c);
+    case 4: return wide ? tiles_of<4, 32>(rows, cols, tiles_c) : tiles_of<4>(rows, cols, tiles_c);
+    default: return wide ? tiles_of<8, 32>(rows, cols, tiles_c) : tiles_of<8>(rows, cols, tiles_c);
+    }
+}
+
+bool off32_wide(int eb, int64_t ld_src, int64_t ld_dst) {
+    switch (eb) {
+    case 2: return off32_ok<2, 16, 32>(ld_src, ld_dst);
+    case 4: return off32_ok<4, 16, 32>(ld_src, ld_dst);
+    case 8: return off32_ok<8, 16, 32>(ld_src, ld_dst);
+    default: return false;
     }
 }
 
@@ -573,8 +586,8 @@ constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs lo
 
 // Tuned launch configuration per element size (index log2(elem bytes)).
 xtr_tpose_config g_cfg[4] = {
-    {1, 1, 1, 1, 0, 0, 0, 0}, {1, 1, 1, 1, 0, 0, 0, 0},
-    {1, 1, 1, 1, 0, 0, 0, 0}, {1, 1, 1, 1, 0, 0, 0, 0},
+    {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
+    {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
 };
 int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
@@ -626,21 +639,31 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
 #undef XTR_K
 }
 
-// Tile geometry of a single transpose: tile 1 = 512-byte src row segments,
-// 2 = 512-byte dst row segments (16-byte pieces, 2- to 8-byte elements only),
-// else 256 x 256 bytes.
+// Tile geometry of a single transpose (`tile` for line-aligned rows,
+// `tile_shared` otherwise): 1 = 512-byte src row segments (16-byte pieces
+// only), 2 = 512-byte dst row segments, else 256 x 256 bytes.  Wider segments
+// halve the share of edge lines that neighbouring tiles split.  2- to 8-byte
+// elements only.
+// A matrix of fewer default tiles than SINGLE_WIDE_MIN_TILES (8 per CU on
+// MI355X) keeps the default geometry: wider tiles would leave CUs idle.
+constexpr int64_t SINGLE_WIDE_MIN_TILES = 2048;
+
 template <int EB>
 int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
                int64_t ld_dst, hipStream_t stream) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
+    const bool lines = lines_ok(src, ld_src, EB) && lines_ok(dst, ld_dst, EB);
+    const int64_t ntiles = ((rows + Geo<EB>::TR - 1) / Geo<EB>::TR) *
+                           ((cols + Geo<EB>::TC - 1) / Geo<EB>::TC);
+    const int tile = ntiles < SINGLE_WIDE_MIN_TILES ? 0 : lines ? c.tile : c.tile_shared;
     switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
     case 16:
         if constexpr (EB >= 2) {
-            if (c.tile == 1) {
+            if (tile == 1) {
                 launch_w<EB, 16, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
             }
-            if (c.tile == 2) {
+            if (tile == 2) {
                 launch_w<EB, 16, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
             }
@@ -648,9 +671,21 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         launch_w<EB, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     case 8:
+        if constexpr (EB >= 2 && EB <= 8) {
+            if (tile == 2) {
+                launch_w<EB, 8, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
         if constexpr (EB <= 8) launch_w<EB, 8>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     case 4:
+        if constexpr (EB >= 2 && EB <= 4) {
+            if (tile == 2) {
+                launch_w<EB, 4, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
         if constexpr (EB <= 4) launch_w<EB, 4>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     default:
@@ -663,7 +698,7 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 
 // `lines`: every job of the group has line-aligned src and dst rows.  `pk`
 // (host) non-null: the group's jobs travel in the kernel arguments.
-template <int EB, int W, bool OFF32>
+template <int EB, int W, bool OFF32, int DC = 16>
 void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
                       const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
     const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
@@ -674,14 +709,14 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
     do {                                                                                    \
         if (pk) {                                                                           \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32>, NT);               \
-            hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32>),                 \
+                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>, NT);           \
+            hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>),             \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                *pk, nj, ntiles, c.xcd, group);                              \
         } else {                                                                            \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32>, NT);                   \
-            hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32>),                     \
+                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, DC>, NT);               \
+            hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, DC>),                 \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                jobs, bases, nj, ntiles, c.xcd, group);                      \
         }                                                                                   \
@@ -694,10 +729,17 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
 }
 
 template <int EB>
-void launch_batched(int w, bool off32, bool lines, int64_t grid, hipStream_t st, const Job *jobs,
-                    const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
-#define XTR_BW(WW)                                                                           \
-    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+void launch_batched(int w, bool off32, bool lines, bool wide, int64_t grid, hipStream_t st,
+                    const Job *jobs, const int64_t *bases, int nj, int64_t ntiles,
+                    const JobPack *pk) {
+#define XTR_BW(WW)                                                                             \
+    if constexpr (EB >= 2 && WW >= 4) {                                                        \
+        if (wide) {                                                                            \
+            launch_batched_w<EB, WW, true, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk);  \
+            return;                                                                            \
+        }                                                                                      \
+    }                                                                                          \
+    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles, pk);   \
     else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles, pk);
     switch (w) {
     case 16: XTR_BW(16) break;
@@ -731,8 +773,11 @@ int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 // Host-side form of a batch: jobs grouped by (element size, piece width,
 // 32-bit offsets); each group has its own slice of the device table, its own
 // concatenated tile space and one persistent launch.
-// eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows
-constexpr int NGROUPS = 4 * 4 * 2 * 2;
+// eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows x wide
+// (512-byte dst row segments)
+constexpr int NGROUPS = 4 * 4 * 2 * 2 * 2;
+// jobs of at least this many default tiles may take the wide geometry
+constexpr int64_t WIDE_MIN_TILES = 16;
 int wclass(int w) { return w == 16 ? 0 : w == 8 ? 1 : w == 4 ? 2 : 3; }
 int wof(int wc) { return wc == 0 ? 16 : wc == 1 ? 8 : wc == 2 ? 4 : 0; }
 
@@ -771,10 +816,15 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         j.w = piece_width(d.src, d.dst, d.ld_src, d.ld_dst, eb);
         j._pad = 0;
         const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
-        const int g = ((cfg_slot(eb) * 4 + wclass(j.w)) * 2 +
-                       (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0)) * 2 + (lines ? 1 : 0);
+        const xtr_tpose_config &c = g_cfg[cfg_slot(eb)];
+        const bool wide = eb >= 2 && j.w >= 4 && (lines ? c.tile : c.tile_shared) == 2 &&
+                          tiles_for(eb, d.rows, d.cols, nullptr) >= WIDE_MIN_TILES &&
+                          off32_wide(eb, d.ld_src, d.ld_dst);
+        const int g = (((cfg_slot(eb) * 4 + wclass(j.w)) * 2 +
+                        (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0)) * 2 + (lines ? 1 : 0)) * 2 +
+                      (wide ? 1 : 0);
         j.tile_base = bt.ntiles[g];
-        bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c);
+        bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c, wide);
         groups[g].push_back(j);
     }
     for (int g = 0; g < NGROUPS; g++) {
@@ -820,18 +870,18 @@ int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
             }
             pk = &pack;
         }
-        const int slot = g / 16, w = wof((g / 4) % 4);
-        const bool off32 = ((g / 2) & 1) != 0, lines = (g & 1) != 0;
+        const int slot = g / 32, w = wof((g / 8) % 4);
+        const bool off32 = ((g / 4) & 1) != 0, lines = ((g / 2) & 1) != 0, wide = (g & 1) != 0;
         // at most the resident capacity of the group's kernel (clamped at launch)
         int64_t grid = bt.ntiles[g] < 0x7fffffff ? bt.ntiles[g] : 0x7fffffff;
         if (grid < 1) grid = 1;
         const Job *jobs = dev ? djobs + bt.at[g] : nullptr;
         const int64_t *bases = dev ? dbases + bt.at[g] : nullptr;
         switch (slot) {
-        case 0: launch_batched<1>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 1: launch_batched<2>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 2: launch_batched<4>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        default: launch_batched<8>(w, off32, lines, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 0: launch_batched<1>(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 1: launch_batched<2>(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 2: launch_batched<4>(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        default: launch_batched<8>(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
         }
         XTR_HIP(hipGetLastError());
     }
@@ -930,9 +980,9 @@ int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg) {
     if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: bad arguments");
     if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
-        cfg->tile < 0 || cfg->tile > 2)
+        cfg->tile < 0 || cfg->tile > 2 || cfg->tile_shared < 0 || cfg->tile_shared > 2)
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: group in [1, 64], blocks_per_cu in "
-                                     "[0, 64], tile in [0, 2]");
+                                     "[0, 64], tile and tile_shared in [0, 2]");
     xtr::g_cfg[xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

@@ -99,24 +99,25 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
             src = torch.empty((nr, nc), dtype=tdt, device="cuda")
             src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(nr))
             dst = torch.empty((nc, nr), dtype=tdt, device="cuda")
-            for nls, nss in itertools.product((0, 1), (0, 1)):
-                xtr.set_tpose_config(eb, **dict(best[1], nt_load_shared=nls, nt_store_shared=nss))
-                pairs[(nls, nss)] = pairs.get((nls, nss), 0.0) + _time(
+            for nls, nss, ts in itertools.product((0, 1), (0, 1), (0, 2) if eb > 1 else (0,)):
+                xtr.set_tpose_config(eb, **dict(best[1], nt_load_shared=nls, nt_store_shared=nss,
+                                                tile_shared=ts))
+                pairs[(nls, nss, ts)] = pairs.get((nls, nss, ts), 0.0) + _time(
                     torch, lambda: xtr.tpose(src, dst, dtype=dt))
             del src, dst
     finally:
         xtr.set_tpose_config(eb, **orig)
-    nls, nss = min(pairs, key=pairs.get)
-    if pairs[(nls, nss)] > 0.98 * pairs[(0, 0)]:
-        nls, nss = 0, 0
-    cfg = dict(best[1], nt_load_shared=nls, nt_store_shared=nss)
+    nls, nss, ts = min(pairs, key=pairs.get)
+    if pairs[(nls, nss, ts)] > 0.98 * pairs[(0, 0, 0)]:
+        nls, nss, ts = 0, 0, 0
+    cfg = dict(best[1], nt_load_shared=nls, nt_store_shared=nss, tile_shared=ts)
     shared_bytes = sum(2 * r * c * eb for r, c in NARROW_SHAPES[eb])
     log(f"tune tpose eb={eb} shared-line rows {NARROW_SHAPES[eb]}: " +
         ", ".join(f"{k} {shared_bytes / v / 1e9:.1f} GB/s" for k, v in pairs.items()) +
-        f" -> {(nls, nss)}")
+        f" -> {(nls, nss, ts)}")
     return {"gbs": round(best[0], 1), "config": cfg, "shape": [rows, cols],
             "shared_shapes": NARROW_SHAPES[eb],
-            "shared_gbs": round(shared_bytes / pairs[(nls, nss)] / 1e9, 1),
+            "shared_gbs": round(shared_bytes / pairs[(nls, nss, ts)] / 1e9, 1),
             "top5": [{"gbs": round(g, 1), "config": c} for g, c in results[:5]]}
 
 

@@ -101,14 +101,75 @@ def test_tile_geometries(xtr, orc, eb, tile):
     T = TILE[eb]
     try:
         xtr.set_tpose_config(eb, tile=tile)
-        for i, (r, c) in enumerate([(2 * T, 4 * T), (4 * T + 3, 2 * T + 5), (T - 1, 3 * T + 1),
-                                    (1, 1)]):
+        # >= 2048 default tiles (smaller matrices keep the default geometry)
+        for i, (r, c) in enumerate([(32 * T, 64 * T), (64 * T + 3, 32 * T + 5),
+                                    (48 * T - 1, 48 * T + 1), (1, 1)]):
             v = 16 // eb
             pad_s = (-c) % v + v * (i % 2)          # keep 16-byte pitches: 16-byte pieces
             pad_d = (-r) % v
             run_tpose(xtr, orc, r, c, eb, pad_s=pad_s, pad_d=pad_d, seed=60 + i)
     finally:
         xtr.set_tpose_config(eb, **orig)
+
+
+@pytest.mark.parametrize("eb,w", [(2, 4), (2, 8), (2, 16), (4, 4), (4, 8), (4, 16), (8, 8),
+                                  (8, 16)])
+def test_tile_geometry_shared_rows(xtr, orc, eb, w):
+    """512-byte dst row segments (tile_shared = 2) for rows that do not start
+    on cache lines, with every piece width, whole and ragged tiles."""
+    orig = xtr.tpose_config(eb)
+    T = TILE[eb]
+    try:
+        xtr.set_tpose_config(eb, tile_shared=2)
+        # >= 2048 default tiles, and a small one that keeps the default geometry
+        for i, (r, c) in enumerate([(64 * T, 32 * T), (64 * T + 3, 32 * T + 5),
+                                    (50 * T - 1, 48 * T + 1), (2 * T - 1, T + 1)]):
+            ld_s, ld_d = _ld_with_piece(c, eb, w), _ld_with_piece(r, eb, w)
+            if (ld_s * eb) % 128 == 0:
+                ld_s += 16 // eb                     # rows must not start on lines
+            run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=80 + i)
+    finally:
+        xtr.set_tpose_config(eb, **orig)
+
+
+@pytest.mark.parametrize("wide", [0, 2])
+def test_batched_geometries(xtr, orc, wide):
+    """Batched transposes with the wide (512-byte dst rows) geometry for jobs
+    whose rows share lines, mixed with small and aligned jobs and every
+    element size; each job against the oracle."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(19))
+    origs = {eb: xtr.tpose_config(eb) for eb in (1, 2, 4, 8)}
+    try:
+        for eb in (2, 4, 8):
+            xtr.set_tpose_config(eb, tile_shared=wide, tile=wide)
+        jobs, hosts = [], []
+        for i in range(40):
+            eb = [1, 2, 4, 8][i % 4]
+            r, c = (int(x) for x in rng.integers(1, 1500, 2))
+            if i % 5 == 0:
+                r, c = 8 * TILE[eb] + 3, 6 * TILE[eb] + 1      # many tiles: takes the geometry
+            a = W.random_bits(r * c, 700 + i, eb).reshape(r, c)
+            s = to_dev(a)
+            d = torch.empty((c, r), dtype=s.dtype, device=s.device)
+            jobs.append({"src": s, "dst": d, "rows": r, "cols": c, "dtype": NAME[eb]})
+            hosts.append(a)
+        for use_plan in (False, True):
+            for j in jobs:
+                j["dst"].fill_(0)
+            if use_plan:
+                p = xtr.TposePlan(jobs)
+                p.run()
+            else:
+                xtr.tpose_batched(jobs)
+            torch.cuda.synchronize()
+            for j, a in zip(jobs, hosts):
+                assert np.array_equal(to_host(j["dst"], a.dtype), orc.tpose(a)), (a.shape, a.dtype)
+            if use_plan:
+                p.close()
+    finally:
+        for eb, o in origs.items():
+            xtr.set_tpose_config(eb, **o)
 
 
 def test_tiny_enumeration(xtr, orc):
