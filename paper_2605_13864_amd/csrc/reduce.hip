@@ -384,30 +384,49 @@ template <int DT> constexpr int64_t small_max() { return (int64_t)2 * NTHR * vec
 // accumulators apart, reduces each set of 64 with the same wave butterfly,
 // and adds the four wave values in the order of the LDS tree.  The result is
 // therefore bit-identical to the workgroup form (and to reduce_sum alone).
-template <int DT, int MODE, bool NT>
-__device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range &rg) {
+// A set of 64 threads that holds no element (its first vector lies past the
+// body, and it does not take the head) has zero accumulators, whose butterfly
+// gives exactly zero: it is skipped, and so is a vector row no lane reaches.
+// US: vector rows loaded (1 for bodies of at most 256 * V elements, else 2).
+template <int DT, int US, bool NT>
+__device__ __forceinline__ void small_load(const Range &rg, uint4 (&v)[US][NW]) {
     constexpr int EB = DTI<DT>::EB;
     constexpr int V = vec_elems<DT>();
-    constexpr int US = 2;                       // vector rows a small body can reach
-    static_assert(US <= U, "small ranges use the first rows of a chunk");
     const int l = threadIdx.x & 63;
-    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
+    const uint4 *body = reinterpret_cast<const uint4 *>(rg.ptr + (int64_t)rg.head * EB);
     const int64_t body_n = rg.n - rg.head;
-    uint4 v[US][NW];
 #pragma unroll
     for (int u = 0; u < US; u++)
 #pragma unroll
         for (int w = 0; w < NW; w++) {
-            const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
-            v[u][w] = (e + V <= body_n) ? load16<NT>(reinterpret_cast<const uint4 *>(body + e * EB))
-                                        : make_uint4(0, 0, 0, 0);
+            v[u][w] = make_uint4(0, 0, 0, 0);
+            if ((int64_t)(u * NTHR + w * 64) * V < body_n) {     // uniform: the row is reached
+                const uint32_t q = (uint32_t)(u * NTHR + w * 64 + l);
+                if ((int64_t)(q + 1) * V <= body_n) v[u][w] = load16<NT>(body + q);
+            }
         }
+}
+
+template <int DT, int MODE, int US>
+__device__ __forceinline__ typename PartT<MODE>::T small_value(const Range &rg,
+                                                               const uint4 (&v)[US][NW]) {
+    constexpr int EB = DTI<DT>::EB;
+    constexpr int V = vec_elems<DT>();
+    const int l = threadIdx.x & 63;
+    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
+    const int64_t body_n = rg.n - rg.head;
     Acc<DT, MODE> a0;
     a0.init();
     using WV = decltype(wave_reduce(a0.finish()));
     WV wv[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
+        const bool any = (w == 0 && rg.head > 0) || (int64_t)(w * 64) * V < body_n;   // uniform
+        if (!any) {
+            if constexpr (MODE == COMP) wv[w] = Pair{0.f, 0.f};
+            else wv[w] = WV(0);
+            continue;
+        }
         Acc<DT, MODE> acc;
         acc.init();
         if (w == 0 && l == 0) {
@@ -415,6 +434,7 @@ __device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range
         }
 #pragma unroll
         for (int u = 0; u < US; u++) {
+            if ((int64_t)(u * NTHR + w * 64) * V >= body_n) continue;   // uniform
             const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
             if (e + V <= body_n) {
                 acc_vec(acc, v[u][w]);
@@ -432,6 +452,13 @@ __device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range
     } else {
         return (wv[0] + wv[1]) + (wv[2] + wv[3]);
     }
+}
+
+template <int DT, int MODE, bool NT>
+__device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range &rg) {
+    uint4 v[2][NW];
+    small_load<DT, 2, NT>(rg, v);
+    return small_value<DT, MODE, 2>(rg, v);
 }
 
 // ---------------------------------------------------------------- grid combine
@@ -986,26 +1013,22 @@ template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const ChunkRec *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
     const bool nt = g_rcfg[DT].nt_load != 0;
-    const void *ks = nt ? (const void *)&k_reduce_seg_small<DT, MODE, true>
-                        : (const void *)&k_reduce_seg_small<DT, MODE, false>;
-    const void *kc = nt ? (const void *)&k_reduce_seg<DT, MODE, true>
-                        : (const void *)&k_reduce_seg<DT, MODE, false>;
-    const int64_t occ_s = resident_blocks(ks, NTHR), occ_c = resident_blocks(kc, NTHR);
-    const int64_t gs_n = (nseg + NW - 1) / NW;
-    const dim3 gs((unsigned)(gs_n < occ_s ? gs_n : occ_s));
+    const int64_t gs_n = (nseg + NW - 1) / NW;                 // workgroups, one wave per segment
     const int64_t gc_n = cap > nseg ? cap : nseg;
-    const dim3 gc((unsigned)(gc_n < occ_c ? gc_n : occ_c));
-    if (nt) {
-        hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, true>), gs, dim3(NTHR), 0, st, src, off,
-                           cb, nseg, cap, out);
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, true>), gc, dim3(NTHR), 0, st, src, cb, cs,
-                           nseg, cap, lv, out);
-    } else {
-        hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, false>), gs, dim3(NTHR), 0, st, src, off,
-                           cb, nseg, cap, out);
-        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, false>), gc, dim3(NTHR), 0, st, src, cb, cs,
-                           nseg, cap, lv, out);
-    }
+#define XTR_SEG(NTV)                                                                             \
+    do {                                                                                         \
+        const int64_t o1 = resident_blocks((const void *)&k_reduce_seg_small<DT, MODE, NTV>, NTHR); \
+        const int64_t o2 = resident_blocks((const void *)&k_reduce_seg<DT, MODE, NTV>, NTHR);   \
+        hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, NTV>),                                 \
+                           dim3((unsigned)(gs_n < o1 ? gs_n : o1)), dim3(NTHR), 0, st, src, off, \
+                           cb, nseg, cap, out);                                                  \
+        hipLaunchKernelGGL((k_reduce_seg<DT, MODE, NTV>),                                       \
+                           dim3((unsigned)(gc_n < o2 ? gc_n : o2)), dim3(NTHR), 0, st, src, cb,  \
+                           cs, nseg, cap, lv, out);                                              \
+    } while (0)
+    if (nt) XTR_SEG(true);
+    else XTR_SEG(false);
+#undef XTR_SEG
 }
 
 int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *ws,
