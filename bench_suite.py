@@ -216,6 +216,52 @@ def piece_widths(xtr, torch, log):
     return res
 
 
+# ---------------------------------------------------------------- host buffers
+
+def host_buffers(xtr, torch, log):
+    """End-to-end rates (copy in + kernel + copy out, wall clock) of the
+    host-buffer entry points on the bench step's fp32 shapes, for page-locked
+    and pageable host memory, beside plain page-locked copy rates."""
+    import numpy as np
+    res = {}
+
+    def wall(fn, reps):
+        fn()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            fn()
+        return (time.perf_counter() - t0) / reps
+
+    nb = 1 << 30
+    hp = torch.empty(nb // 4, dtype=torch.float32, pin_memory=True)
+    d = torch.empty(nb // 4, dtype=torch.float32, device="cuda")
+    sec = wall(lambda: (d.copy_(hp, non_blocking=True), torch.cuda.synchronize()), 5)
+    res["pinned_h2d_gbs"] = round(nb / sec / 1e9, 1)
+    sec = wall(lambda: (hp.copy_(d, non_blocking=True), torch.cuda.synchronize()), 5)
+    res["pinned_d2h_gbs"] = round(nb / sec / 1e9, 1)
+    del d
+    n = 16384
+    for pinned in (True, False):
+        tag = "pinned" if pinned else "pageable"
+        src = (torch.empty(n * n, dtype=torch.float32, pin_memory=pinned) if pinned
+               else torch.empty(n * n, dtype=torch.float32))
+        src.view(torch.int32).random_(0, 1 << 30)
+        dst = (torch.empty(n * n, dtype=torch.float32, pin_memory=pinned) if pinned
+               else torch.empty(n * n, dtype=torch.float32))
+        sec = wall(lambda: xtr.tpose_host(src, dst, rows=n, cols=n, dtype="f32"), 3)
+        res[f"tpose_host_f32_16384_{tag}_gbs"] = round(2 * n * n * 4 / sec / 1e9, 1)
+        if not pinned:
+            s2 = src.view(n, n)
+            assert torch.equal(dst.view(n, n)[:64, :64].view(torch.int32),
+                               s2[:64, :64].t().contiguous().view(torch.int32))
+        m = 1 << 28
+        sec = wall(lambda: xtr.reduce_sum_host(src[:m], n=m, dtype="f32"), 3)
+        res[f"sum_host_f32_2^28_{tag}_gbs"] = round(m * 4 / sec / 1e9, 1)
+        del src, dst
+    log("suite host buffers: " + ", ".join(f"{k} {v}" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- paper shapes
 
 def paper_shapes(xtr, torch, log):
@@ -258,9 +304,10 @@ def paper_shapes(xtr, torch, log):
 
 
 def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "precision",
-                                   "serving")):
+                                   "host", "serving")):
     out = {}
     for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
+                     ("host", host_buffers),
                      ("segmented", segmented), ("precision", precision)):
         if name in parts:
             t0 = time.time()

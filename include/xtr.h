@@ -175,6 +175,32 @@ int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void 
                                int64_t count, int dtype, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Host buffers: the end-to-end form of the paper's host code (Listing 3.6:
+ * copy in, kernel, copy out), for data that lives in host memory.
+ *
+ * src / dst / out are HOST pointers, page-locked (hipHostMalloc, or torch's
+ * pin_memory) or pageable.  The calls are synchronous: they return when the
+ * result is in host memory.  The data moves in panels of about 32 MiB
+ * through library-owned device buffers on three internal streams (copy in,
+ * kernel, copy out), so the copies of one panel overlap the kernel of the
+ * next; page-locked buffers are copied by DMA directly, pageable ones pass
+ * through the library's pinned staging (one host memcpy per panel).  The
+ * internal streams have default priority and are ordered only against each
+ * other, not against caller streams.  Calls on one device are serialized.
+ */
+
+/* Host transpose: as tpose(), with src and dst in host memory.
+ * Errors: as tpose(), plus ENOMEM and EHIP. */
+int xtr_tpose_host(const void *src, void *dst, int64_t rows, int64_t cols,
+                   int64_t ld_src, int64_t ld_dst, int dtype);
+
+/* Host sum: as reduce_sum(), with src and *out (double or int64_t) in host
+ * memory.  The result equals reduce_sum() of the same n values at a
+ * 16-byte-aligned device address, bit for bit.
+ * Errors: as reduce_sum(), plus EHIP. */
+int xtr_reduce_sum_host(const void *src, int64_t n, void *out, int dtype);
+
+/* ------------------------------------------------------------------------
  * Batch plans: a batch whose buffers and shapes repeat (a serving slot, a
  * training step) is validated and uploaded once; each run then only launches
  * kernels, with no host allocation, copy or memset, so a run can be captured

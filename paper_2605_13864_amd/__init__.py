@@ -74,6 +74,9 @@ _SIGS = {
     "reduce_sum_batched_scatter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
                                     C.c_void_p], C.c_int),
     "xtr_copy": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "xtr_tpose_host": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                        C.c_int], C.c_int),
+    "xtr_reduce_sum_host": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int], C.c_int),
     "xtr_tpose_plan_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_destroy": ([C.c_void_p], C.c_int),
@@ -129,6 +132,12 @@ def _code(dtype) -> int:
 
 def dtype_of(t) -> str:
     import torch
+    if not isinstance(t, torch.Tensor):   # numpy array
+        m = {"float32": "f32", "float16": "f16", "int32": "i32", "int64": "i64",
+             "float64": "f64", "uint8": "u8", "uint16": "u16", "int16": "u16", "int8": "u8"}
+        if str(t.dtype) not in m:
+            raise TypeError(f"unsupported array dtype {t.dtype}; pass dtype=")
+        return m[str(t.dtype)]
     m = {torch.float32: "f32", torch.float16: "f16", torch.bfloat16: "bf16",
          torch.float8_e4m3fn: "f8e4m3", torch.int32: "i32", torch.int64: "i64",
          torch.float64: "f64", torch.uint8: "u8", torch.uint16: "u16", torch.int16: "u16",
@@ -432,6 +441,43 @@ def reduce_sum_batched_scatter(srcs, outs, *, ns=None, dtype=None, stream=None):
                                         C.cast(optr, C.c_void_p), count, _code(dt),
                                         _stream(stream))
     _check(rc, "reduce_sum_batched_scatter")
+
+
+def _host_ptr(a):
+    """Address of a host buffer: a CPU torch tensor or a numpy array."""
+    if hasattr(a, "data_ptr"):
+        assert not a.is_cuda, "host-buffer entry points take CPU tensors"
+        return a.data_ptr()
+    return a.ctypes.data
+
+
+def tpose_host(src, dst, *, rows=None, cols=None, ld_src=None, ld_dst=None, dtype=None):
+    """dst[c, r] = src[r, c] for host arrays (CPU tensors or numpy arrays, page-
+    locked or not), through the GPU; returns when dst is written."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    if rows is None:
+        rows, cols = src.shape
+    if ld_src is None:
+        ld_src = cols
+    if ld_dst is None:
+        ld_dst = rows
+    _check(lib.xtr_tpose_host(C.c_void_p(_host_ptr(src)), C.c_void_p(_host_ptr(dst)), rows, cols,
+                              ld_src, ld_dst, _code(dt)), "xtr_tpose_host")
+    return dst
+
+
+def reduce_sum_host(src, *, n=None, dtype=None):
+    """Sum of a host array (CPU tensor or numpy array) through the GPU: a Python
+    float (float dtypes) or int (integer dtypes)."""
+    lib = load()
+    dt = dtype or dtype_of(src)
+    if n is None:
+        n = src.numel() if hasattr(src, "numel") else src.size
+    res = C.c_double() if dt in FLOAT_SUM else C.c_int64()
+    _check(lib.xtr_reduce_sum_host(C.c_void_p(_host_ptr(src)), n, C.byref(res), _code(dt)),
+           "xtr_reduce_sum_host")
+    return res.value
 
 
 def release():

@@ -5,6 +5,8 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <mutex>
+
 #include "../../include/xtr.h"
 
 namespace xtr {
@@ -58,6 +60,34 @@ int zero_fill(void *p, size_t bytes, hipStream_t stream);
 
 // Number of compute units of the current device (cached).
 int cu_count();
+
+// ------------------------------------------------------------------ host buffers
+// Resources of the entry points that take host buffers, one set per device
+// (created on first use, kept until xtr_release): copies in, kernels and
+// copies out run on three streams of default priority, so the copy of one
+// panel overlaps the kernel of the previous one and the copy out of the one
+// before.  Panels are double-buffered: slot b = panel index % 2.  A call holds
+// `mu` from start to end (the calls are synchronous).
+struct HostPipe {
+    std::mutex mu;
+    int device = 0;
+    hipStream_t in = nullptr, comp = nullptr, out = nullptr;
+    hipEvent_t in_done[2] = {}, k_done[2] = {}, out_done[2] = {};
+    void *dev[4] = {};         // device panels: 0/1 input, 2/3 output
+    size_t dev_bytes[4] = {};
+    void *pin[4] = {};         // pinned staging for pageable host buffers: 0/1 in, 2/3 out
+    size_t pin_bytes[4] = {};
+};
+// The current device's pipe (created on first use).
+int host_pipe(HostPipe **pipe);
+// Device panel / pinned staging buffer i of at least `bytes` (grown as needed;
+// the caller has synchronized every stream of the pipe that used it).
+int pipe_dev(HostPipe *p, int i, size_t bytes, void **ptr);
+int pipe_pin(HostPipe *p, int i, size_t bytes, void **ptr);
+// Whether host pointer p lies in page-locked memory the GPU can reach by DMA.
+bool host_pinned(const void *p);
+// Waits for every stream of the pipe.
+int pipe_sync(HostPipe *p);
 
 // Workgroups of `kernel` (block_threads threads, static LDS only) that are
 // resident on the current device at once: the occupancy per CU (at most

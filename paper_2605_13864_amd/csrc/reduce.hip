@@ -37,6 +37,8 @@
 // everywhere (comparator).
 #include "common.hpp"
 
+#include <cstring>
+
 #include <algorithm>
 #include <new>
 #include <vector>
@@ -585,7 +587,7 @@ __global__ void __launch_bounds__(NTHR) k_reduce_parts(Range rg, Levels lv) {
     using P = typename PartT<MODE>::T;
     const int64_t j = blockIdx.x;
     const P v = reduce_chunk<DT, MODE, NT>(rg, j);
-    if (threadIdx.x == 0) reinterpret_cast<P *>(lv.part[0])[j] = v;
+    if (threadIdx.x == 0) reinterpret_cast<P *>(lv.part[0])[rg.chunk_base + j] = v;
 }
 
 // One level of the combine tree: wave g sums partials [256 g, 256 g + 256) of
@@ -960,33 +962,51 @@ bool rcfg_init() {
 }
 bool g_rcfg_ready = rcfg_init();
 
-// A range of at least split_chunks chunks (and more than one) uses the split
-// combine; the others combine in-kernel through tickets.  Same value either way.
+// In-kernel ticket combine: one workgroup per chunk of rg.
 template <int DT, int MODE>
-void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
-    using P = typename PartT<MODE>::T;
-    const xtr_reduce_config &c = g_rcfg[DT];
-    if (c.split_chunks > 0 && rg.nchunks >= c.split_chunks && rg.nchunks > 1) {
-        const dim3 g((unsigned)rg.nchunks);
-        if (c.nt_load) hipLaunchKernelGGL((k_reduce_parts<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
-        else hipLaunchKernelGGL((k_reduce_parts<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
-        int64_t cnt = rg.nchunks;
-        for (int level = 0; cnt > 1; level++) {
-            const int64_t ng = (cnt + RADIX - 1) / RADIX;
-            const dim3 gl((unsigned)((ng + NW - 1) / NW));
-            hipLaunchKernelGGL((k_combine_level<P>), gl, dim3(NTHR), 0, st,
-                               reinterpret_cast<const P *>(lv.part[level]), cnt,
-                               reinterpret_cast<P *>(lv.part[level + 1]), reinterpret_cast<P *>(rg.dst));
-            cnt = ng;
-        }
-        return;
-    }
-    if (c.nt_load)
+void launch_one_ticket(const Range &rg, const Levels &lv, hipStream_t st) {
+    if (g_rcfg[DT].nt_load)
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, true>), dim3((unsigned)rg.nchunks), dim3(NTHR), 0,
                            st, rg, lv);
     else
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, false>), dim3((unsigned)rg.nchunks), dim3(NTHR),
                            0, st, rg, lv);
+}
+
+// A range of at least split_chunks chunks (and more than one) uses the split
+// combine; the others combine in-kernel through tickets.  Same value either way.
+// Plain partials of the chunks of rg (written at chunk_base + j of level 0).
+template <int DT, int MODE>
+void launch_parts(const Range &rg, const Levels &lv, hipStream_t st) {
+    const dim3 g((unsigned)rg.nchunks);
+    if (g_rcfg[DT].nt_load)
+        hipLaunchKernelGGL((k_reduce_parts<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
+    else
+        hipLaunchKernelGGL((k_reduce_parts<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
+}
+// The combine levels over cnt > 1 level-0 partials; the last writes *dst.
+template <int MODE>
+void launch_combine(const Levels &lv, int64_t cnt, void *dst, hipStream_t st) {
+    using P = typename PartT<MODE>::T;
+    for (int level = 0; cnt > 1; level++) {
+        const int64_t ng = (cnt + RADIX - 1) / RADIX;
+        const dim3 gl((unsigned)((ng + NW - 1) / NW));
+        hipLaunchKernelGGL((k_combine_level<P>), gl, dim3(NTHR), 0, st,
+                           reinterpret_cast<const P *>(lv.part[level]), cnt,
+                           reinterpret_cast<P *>(lv.part[level + 1]), reinterpret_cast<P *>(dst));
+        cnt = ng;
+    }
+}
+
+template <int DT, int MODE>
+void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
+    const xtr_reduce_config &c = g_rcfg[DT];
+    if (c.split_chunks > 0 && rg.nchunks >= c.split_chunks && rg.nchunks > 1) {
+        launch_parts<DT, MODE>(rg, lv, st);
+        launch_combine<MODE>(lv, rg.nchunks, rg.dst, st);
+        return;
+    }
+    launch_one_ticket<DT, MODE>(rg, lv, st);
 }
 template <int DT, int MODE>
 void launch_table_inl(const RangePack &pk, int nr, int64_t nchunks, const Levels &lv,
@@ -1045,6 +1065,87 @@ int sum_one(const void *src, int64_t n, void *out, int dtype, bool plain, void *
     XTR_DISPATCH_SUM(dtype, mode, launch_one, (rg, lv, st));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
+}
+
+// Panels of the host-buffer sum hold this many chunks (32 MiB).
+constexpr int64_t HOST_PANEL_CHUNKS = 1024;
+
+template <int DT, int MODE>
+void launch_host_panel(const Range &rg, const Levels &lv, bool single, hipStream_t st) {
+    if (single) launch_one_ticket<DT, MODE>(rg, lv, st);
+    else launch_parts<DT, MODE>(rg, lv, st);
+}
+template <int DT, int MODE>
+void launch_host_combine(const Levels &lv, int64_t cnt, void *dst, hipStream_t st) {
+    launch_combine<MODE>(lv, cnt, dst, st);
+}
+
+// Sum of a host array through the device, panel by panel (the copy in of
+// panel k+1 overlaps the reduction of panel k).  The chunking is that of the
+// same n values at a 16-byte-aligned device address (no head): each panel's
+// chunks write their partials at their global chunk index, and the combine
+// levels then run over all of them, so the result equals reduce_sum of an
+// aligned device copy bit for bit.
+int sum_host_impl(const void *src, int64_t n, void *out, int dtype) {
+    const char *who = "xtr_reduce_sum_host";
+    int rc = check_sum_args(src, n, out, dtype, false, who);
+    if (rc) return rc;
+    const int mode = mode_for(dtype, false);
+    const int64_t eb = elem_bytes(dtype), ch = chunk_elems_rt(dtype);
+    const int64_t nchunks = n > 0 ? (n + ch - 1) / ch : 1;
+    if (nchunks > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: n too large", who);
+    HostPipe *p = nullptr;
+    rc = host_pipe(&p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if ((rc = pipe_sync(p))) return rc;
+    const bool spin = host_pinned(src);
+    const int64_t pc = nchunks < HOST_PANEL_CHUNKS ? nchunks : HOST_PANEL_CHUNKS;
+    const size_t pbytes = (size_t)(pc * ch * eb);
+    void *din[2], *sin[2] = {nullptr, nullptr}, *dres = nullptr;
+    for (int b = 0; b < 2; b++) {
+        if ((rc = pipe_dev(p, b, pbytes, &din[b]))) return rc;
+        if (!spin && (rc = pipe_pin(p, b, pbytes, &sin[b]))) return rc;
+    }
+    if ((rc = pipe_dev(p, 2, 256, &dres))) return rc;
+    WsView v;
+    if ((rc = get_ws(nullptr, 0, nchunks, parts_bytes(nchunks, mode), p->comp, who, &v))) return rc;
+    const Levels lv = levels_at(v, v.data, nchunks, mode);
+    const unsigned char *hs = static_cast<const unsigned char *>(src);
+    const int64_t np = (nchunks + pc - 1) / pc;
+    for (int64_t k = 0; k < np; k++) {
+        const int b = (int)(k & 1);
+        const int64_t c0 = k * pc, ck = (nchunks - c0) < pc ? (nchunks - c0) : pc;
+        const int64_t e0 = c0 * ch, nk = (n - e0) < ck * ch ? (n - e0) : ck * ch;
+        if (k >= 2) XTR_HIP(hipStreamWaitEvent(p->in, p->k_done[b], 0));
+        if (nk > 0) {
+            if (spin) {
+                XTR_HIP(hipMemcpyAsync(din[b], hs + e0 * eb, (size_t)(nk * eb),
+                                       hipMemcpyHostToDevice, p->in));
+            } else {
+                if (k >= 2) XTR_HIP(hipEventSynchronize(p->in_done[b]));
+                memcpy(sin[b], hs + e0 * eb, (size_t)(nk * eb));
+                XTR_HIP(hipMemcpyAsync(din[b], sin[b], (size_t)(nk * eb), hipMemcpyHostToDevice,
+                                       p->in));
+            }
+        }
+        XTR_HIP(hipEventRecord(p->in_done[b], p->in));
+        XTR_HIP(hipStreamWaitEvent(p->comp, p->in_done[b], 0));
+        Range rg;
+        rg.ptr = static_cast<const unsigned char *>(din[b]);
+        rg.n = nk;
+        rg.chunk_base = c0;
+        rg.nchunks = ck;
+        rg.dst = static_cast<unsigned char *>(dres);
+        rg.head = 0;
+        rg._pad = 0;
+        XTR_DISPATCH_SUM(dtype, mode, launch_host_panel, (rg, lv, nchunks == 1, p->comp));
+        XTR_HIP(hipEventRecord(p->k_done[b], p->comp));
+    }
+    if (nchunks > 1) XTR_DISPATCH_SUM(dtype, mode, launch_host_combine, (lv, nchunks, dres, p->comp));
+    XTR_HIP(hipGetLastError());
+    XTR_HIP(hipMemcpyAsync(out, dres, 8, hipMemcpyDeviceToHost, p->comp));
+    return pipe_sync(p);
 }
 
 }  // namespace
@@ -1283,6 +1384,10 @@ int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: split_chunks must be >= 0");
     xtr::g_rcfg[dtype] = *cfg;
     return XTR_OK;
+}
+
+int xtr_reduce_sum_host(const void *src, int64_t n, void *out, int dtype) {
+    return xtr::sum_host_impl(src, n, out, dtype);
 }
 
 int reduce_sum_plain_f32(const void *src, int64_t n, float *out, int dtype, void *stream) {

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <new>
 #include <mutex>
 #include <utility>
 
@@ -195,6 +196,91 @@ int cu_count() {
     return cached[dev];
 }
 
+// ------------------------------------------------------------------ host buffers
+
+namespace {
+std::mutex g_pipe_mu;
+std::map<int, HostPipe *> g_pipes;   // by device; never moved once created
+}  // namespace
+
+int host_pipe(HostPipe **pipe) {
+    int dev = 0;
+    XTR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_pipe_mu);
+    HostPipe *&p = g_pipes[dev];
+    if (!p) {
+        HostPipe *q = new (std::nothrow) HostPipe();
+        if (!q) return fail(XTR_ENOMEM, "host buffers: out of host memory");
+        q->device = dev;
+        hipError_t e = hipStreamCreateWithFlags(&q->in, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->comp, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&q->out, hipStreamNonBlocking);
+        for (int b = 0; b < 2 && e == hipSuccess; b++) {
+            e = hipEventCreateWithFlags(&q->in_done[b], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&q->k_done[b], hipEventDisableTiming);
+            if (e == hipSuccess) e = hipEventCreateWithFlags(&q->out_done[b], hipEventDisableTiming);
+        }
+        if (e != hipSuccess) {
+            delete q;   // streams / events already made are reclaimed at exit
+            return hip_fail(e, "host buffers: stream or event creation");
+        }
+        p = q;
+    }
+    *pipe = p;
+    return XTR_OK;
+}
+
+int pipe_dev(HostPipe *p, int i, size_t bytes, void **ptr) {
+    if (p->dev_bytes[i] < bytes) {
+        if (p->dev[i]) XTR_HIP(hipFree(p->dev[i]));
+        p->dev[i] = nullptr;
+        p->dev_bytes[i] = 0;
+        const size_t want = (bytes + 255) & ~size_t(255);
+        hipError_t e = hipMalloc(&p->dev[i], want);
+        if (e != hipSuccess) {
+            p->dev[i] = nullptr;
+            return fail(XTR_ENOMEM, "hipMalloc(%zu) for a host-buffer panel: %s", want,
+                        hipGetErrorString(e));
+        }
+        p->dev_bytes[i] = want;
+    }
+    *ptr = p->dev[i];
+    return XTR_OK;
+}
+
+int pipe_pin(HostPipe *p, int i, size_t bytes, void **ptr) {
+    if (p->pin_bytes[i] < bytes) {
+        if (p->pin[i]) XTR_HIP(hipHostFree(p->pin[i]));
+        p->pin[i] = nullptr;
+        p->pin_bytes[i] = 0;
+        hipError_t e = hipHostMalloc(&p->pin[i], bytes, hipHostMallocDefault);
+        if (e != hipSuccess) {
+            p->pin[i] = nullptr;
+            return fail(XTR_ENOMEM, "hipHostMalloc(%zu) for host-buffer staging: %s", bytes,
+                        hipGetErrorString(e));
+        }
+        p->pin_bytes[i] = bytes;
+    }
+    *ptr = p->pin[i];
+    return XTR_OK;
+}
+
+bool host_pinned(const void *ptr) {
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, ptr) != hipSuccess) {
+        (void)hipGetLastError();   // pageable memory is not an error here
+        return false;
+    }
+    return a.type == hipMemoryTypeHost;
+}
+
+int pipe_sync(HostPipe *p) {
+    XTR_HIP(hipStreamSynchronize(p->in));
+    XTR_HIP(hipStreamSynchronize(p->comp));
+    XTR_HIP(hipStreamSynchronize(p->out));
+    return XTR_OK;
+}
+
 int resident_blocks(const void *kernel, int block_threads, int cap_per_cu) {
     static std::mutex mu;
     static std::map<std::pair<const void *, int>, int> cache;   // (kernel, device) -> per CU
@@ -271,6 +357,22 @@ int xtr_release(void) {
         }
     }
     xtr::g_stage.clear();
+    {
+        std::lock_guard<std::mutex> pk(xtr::g_pipe_mu);
+        for (auto &kv : xtr::g_pipes) {
+            xtr::HostPipe *p = kv.second;
+            std::lock_guard<std::mutex> pl(p->mu);
+            (void)hipSetDevice(p->device);
+            (void)xtr::pipe_sync(p);
+            for (int i = 0; i < 4; i++) {
+                if (p->dev[i]) (void)hipFree(p->dev[i]);
+                if (p->pin[i]) (void)hipHostFree(p->pin[i]);
+                p->dev[i] = p->pin[i] = nullptr;
+                p->dev_bytes[i] = p->pin_bytes[i] = 0;
+            }
+        }
+        // streams and events stay (a pipe may be in use again); buffers regrow
+    }
     (void)hipSetDevice(cur);
     return XTR_OK;
 }

@@ -30,6 +30,7 @@
 // 16-byte aligned, go through an element-wise path over the same LDS layout.
 #include "common.hpp"
 
+#include <cstring>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -770,6 +771,104 @@ int tpose_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     }
 }
 
+// ---------------------------------------------------------------- host buffers
+
+// Row panels of the host-buffer transpose hold about this many bytes.
+constexpr size_t HOST_PANEL_BYTES = size_t(32) << 20;
+
+// Transposes host src into host dst through the device, one row panel at a
+// time: the copy in of panel k+1, the transpose of panel k and the copy out
+// of panel k-1 overlap on the pipe's three streams.  A src row panel
+// [r0, r0 + R) becomes the dst column panel [r0, r0 + R): a strided copy out.
+// Page-locked host buffers are copied by DMA directly; pageable ones pass
+// through the pipe's pinned staging (a host memcpy per panel).
+int tpose_host_impl(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+                    int64_t ld_dst, int dtype) {
+    const char *who = "xtr_tpose_host";
+    int rc = check_one(src, dst, rows, cols, ld_src, ld_dst, dtype, who);
+    if (rc || rows == 0 || cols == 0) return rc;
+    const int64_t eb = elem_bytes(dtype);
+    HostPipe *p = nullptr;
+    rc = host_pipe(&p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(p->mu);
+    if ((rc = pipe_sync(p))) return rc;   // a failed earlier call may have left work queued
+    const bool spin = host_pinned(src), dpin = host_pinned(dst);
+    const int64_t tr = 256 / eb;                       // tile rows of the default geometry
+    int64_t R = (int64_t)(HOST_PANEL_BYTES / (size_t)(cols * eb));
+    R = R < tr ? tr : R / tr * tr;
+    if (R > rows) R = rows;
+    const size_t pbytes = (size_t)(R * cols * eb);
+    void *din[2], *dout[2], *sin[2] = {nullptr, nullptr}, *sout[2] = {nullptr, nullptr};
+    for (int b = 0; b < 2; b++) {
+        if ((rc = pipe_dev(p, b, pbytes, &din[b]))) return rc;
+        if ((rc = pipe_dev(p, 2 + b, pbytes, &dout[b]))) return rc;
+        if (!spin && (rc = pipe_pin(p, b, pbytes, &sin[b]))) return rc;
+        if (!dpin && (rc = pipe_pin(p, 2 + b, pbytes, &sout[b]))) return rc;
+    }
+    const unsigned char *hs = static_cast<const unsigned char *>(src);
+    unsigned char *hd = static_cast<unsigned char *>(dst);
+    auto scatter = [&](int64_t k) {   // pageable dst: staged panel k -> its dst columns
+        const int b = (int)(k & 1);
+        const int64_t r0 = k * R, Rk = (rows - r0) < R ? (rows - r0) : R;
+        const unsigned char *st = static_cast<const unsigned char *>(sout[b]);
+        for (int64_t c = 0; c < cols; c++)
+            memcpy(hd + (c * ld_dst + r0) * eb, st + c * Rk * eb, (size_t)(Rk * eb));
+    };
+    const int64_t np = (rows + R - 1) / R;
+    for (int64_t k = 0; k < np; k++) {
+        const int b = (int)(k & 1);
+        const int64_t r0 = k * R, Rk = (rows - r0) < R ? (rows - r0) : R;
+        // copy in (waits until the kernel of panel k-2 has read din[b])
+        if (k >= 2) XTR_HIP(hipStreamWaitEvent(p->in, p->k_done[b], 0));
+        if (spin) {
+            XTR_HIP(hipMemcpy2DAsync(din[b], (size_t)(cols * eb), hs + r0 * ld_src * eb,
+                                     (size_t)(ld_src * eb), (size_t)(cols * eb), (size_t)Rk,
+                                     hipMemcpyHostToDevice, p->in));
+        } else {
+            if (k >= 2) XTR_HIP(hipEventSynchronize(p->in_done[b]));   // sin[b] is free again
+            unsigned char *st = static_cast<unsigned char *>(sin[b]);
+            if (ld_src == cols) {
+                memcpy(st, hs + r0 * cols * eb, (size_t)(Rk * cols * eb));
+            } else {
+                for (int64_t r = 0; r < Rk; r++)
+                    memcpy(st + r * cols * eb, hs + (r0 + r) * ld_src * eb, (size_t)(cols * eb));
+            }
+            XTR_HIP(hipMemcpyAsync(din[b], st, (size_t)(Rk * cols * eb), hipMemcpyHostToDevice,
+                                   p->in));
+        }
+        XTR_HIP(hipEventRecord(p->in_done[b], p->in));
+        // transpose (waits for its input, and for the copy out of panel k-2 from dout[b])
+        XTR_HIP(hipStreamWaitEvent(p->comp, p->in_done[b], 0));
+        if (k >= 2) XTR_HIP(hipStreamWaitEvent(p->comp, p->out_done[b], 0));
+        rc = tpose_impl(din[b], dout[b], Rk, cols, cols, Rk, dtype, p->comp);
+        if (rc) {
+            (void)pipe_sync(p);
+            return rc;
+        }
+        XTR_HIP(hipEventRecord(p->k_done[b], p->comp));
+        // copy out
+        XTR_HIP(hipStreamWaitEvent(p->out, p->k_done[b], 0));
+        if (dpin) {
+            XTR_HIP(hipMemcpy2DAsync(hd + r0 * eb, (size_t)(ld_dst * eb), dout[b], (size_t)(Rk * eb),
+                                     (size_t)(Rk * eb), (size_t)cols, hipMemcpyDeviceToHost, p->out));
+        } else {
+            XTR_HIP(hipMemcpyAsync(sout[b], dout[b], (size_t)(cols * Rk * eb),
+                                   hipMemcpyDeviceToHost, p->out));
+        }
+        XTR_HIP(hipEventRecord(p->out_done[b], p->out));
+        if (!dpin && k >= 1) {   // the previous panel is staged: place it while this one runs
+            XTR_HIP(hipEventSynchronize(p->out_done[(k - 1) & 1]));
+            scatter(k - 1);
+        }
+    }
+    if (!dpin) {
+        XTR_HIP(hipEventSynchronize(p->out_done[(np - 1) & 1]));
+        scatter(np - 1);
+    }
+    return pipe_sync(p);
+}
+
 // Host-side form of a batch: jobs grouped by (element size, piece width,
 // 32-bit offsets); each group has its own slice of the device table, its own
 // concatenated tile space and one persistent launch.
@@ -912,6 +1011,11 @@ int tpose(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src
 
 int tpose_batched(const xtr_tpose_desc *descs, int64_t count, void *stream) {
     return xtr::tpose_batched_impl(descs, count, (hipStream_t)stream);
+}
+
+int xtr_tpose_host(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
+                   int64_t ld_dst, int dtype) {
+    return xtr::tpose_host_impl(src, dst, rows, cols, ld_src, ld_dst, dtype);
 }
 
 struct xtr_tpose_plan {
