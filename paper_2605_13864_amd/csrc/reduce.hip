@@ -28,11 +28,16 @@
 //   4. Workgroup level: one LDS slot per wave, a barrier, and the pairwise
 //      combine ((w0 + w1) + (w2 + w3)).
 //   5. Grid level: each chunk's pair becomes one fp64 partial (s + c, exact);
-//      partials are combined in fp64 by a radix-256 tree: the last workgroup
-//      of every group of 256 chunks (atomic ticket) sums the group with a
-//      fixed pairwise tree and passes the result one level up.  The order is
+//      partials are combined in fp64 by a radix-256 tree, each group of 256
+//      with a fixed pairwise tree, level by level.  Large single ranges store
+//      plain partials and small follow-up launches sum the levels; other
+//      ranges combine in-kernel: the last workgroup of every group (atomic
+//      ticket) sums it and passes the result one level up.  The order is
 //      fixed, so the result is a deterministic function of (data, n, dtype,
-//      alignment of ptr) -- the same alone, batched or as a segment.
+//      alignment of ptr) -- the same alone, batched, as a segment, or summed
+//      from host memory.
+//   6. Small segments (body within two vector rows of a chunk) are reduced by
+//      one wave that replays the chunk arithmetic of the whole workgroup.
 // The plain mode repeats the structure with uncompensated fp32 adds
 // everywhere (comparator).
 #include "common.hpp"

@@ -1,33 +1,37 @@
-// Out-of-place transpose for gfx950 (single and batched).
+// Out-of-place transpose for gfx950 (single, batched and host-buffer forms).
 //
 // What is computed: the sequential transpose of Listing 3.5,
 //     dst[c*ld_dst + r] = src[r*ld_src + c],  0 <= r < rows, 0 <= c < cols,
 // as a copy of element bits.
 //
 // How (tiled form of Listings 3.8 / 3.10): one workgroup of 256 threads moves
-// one TR x TC tile.  Phase 1 loads the tile from HBM with 16-byte vector loads
-// (16 lanes cover one 256-byte row segment, so every wave-level load is four
-// fully used 128-byte lines) and writes it to LDS.  A block barrier then hands
+// one TR x TC tile.  Phase 1 loads the tile from HBM in W-byte pieces (W = 16,
+// 8 or 4: the widest piece that divides both pointers and both row pitches),
+// 256 / W lanes per 256-byte row segment so that every wave-level load covers
+// whole cache lines, and writes the pieces to LDS.  A block barrier then hands
 // ownership of the LDS tile from the loading threads to the storing threads:
 // Section 3.3 places the barrier exactly where tile ownership changes.  Phase 2
-// reads a V x V element block per thread from LDS with 16-byte reads,
-// transposes it in registers, and writes V 16-byte vectors to V consecutive
-// dst rows, again 16 lanes per 256-byte row segment.
+// gives lane k of a dst row segment the piece k of that segment: it reads the
+// tile rows its piece covers from LDS with 16-byte reads, transposes them in
+// registers, and stores consecutive pieces across consecutive lanes.
 //
 // Differences from the paper's kernels (Listings 3.6 and 6.21), made for CDNA4:
 //  - the tile is 256 x 256 BYTES whatever the element size (fp32 64 x 64,
-//    bf16 128 x 128, fp8 256 x 256, fp64 32 x 32), so both HBM sides move
-//    whole 16-byte vectors and whole cache lines;
-//  - each thread moves V = 16/elem elements per vector and V vectors per phase
-//    (the paper's kernel moves 2 elements per thread, Section 7.2);
-//  - LDS 16-byte chunks are XOR-swizzled per row group so that both the row
-//    writes and the block reads hit distinct bank groups (the paper's 32 x 32
+//    bf16 128 x 128, fp8 256 x 256, fp64 32 x 32), or 512-byte row segments on
+//    one side (tuned), so both HBM sides move whole cache lines;
+//  - each lane moves W-byte pieces and transposes in registers (the paper's
+//    kernel moves 2 elements per thread, Section 7.2);
+//  - LDS 16-byte chunks are XOR-swizzled per row so that both the row writes
+//    and the transposed reads hit distinct bank groups (the paper's 32 x 32
 //    tile is unpadded);
 //  - tile coordinates come from one division per tile, not per element (the
 //    paper attributes its transpose gap to per-thread index arithmetic,
-//    Section 7.2 / Chapter 6).
-// Edge tiles, and matrices whose pointers or leading dimensions are not
-// 16-byte aligned, go through an element-wise path over the same LDS layout.
+//    Section 7.2 / Chapter 6);
+//  - the launch order is XCD-aware and banded, so tiles that share cache lines
+//    at their edges meet in one L2.
+// Tiles on the right or bottom edge mask whole pieces (elements only where an
+// edge cuts a piece); 1- and 2-byte matrices with odd pitches go element by
+// element over the same LDS layout.
 #include "common.hpp"
 
 #include <cstring>
