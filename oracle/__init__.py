@@ -76,6 +76,10 @@ class Oracle:
         lib.oracle_sum_segmented.restype = C.c_int
         lib.oracle_elem_bytes.argtypes = [C.c_int]
         lib.oracle_elem_bytes.restype = C.c_int
+        lib.oracle_scan_int.argtypes = [vp, i64, C.c_int, C.c_int, vp]
+        lib.oracle_scan_int.restype = C.c_int
+        lib.oracle_scan_float.argtypes = [vp, i64, C.c_int, C.c_int, vp]
+        lib.oracle_scan_float.restype = C.c_int
         self.lib = lib
         self.path = path
 
@@ -154,6 +158,21 @@ class Oracle:
             raise ValueError("oracle_sum_segmented: bad offsets")
         return out
 
+    def scan(self, bits: np.ndarray, dtype: str, exclusive: bool = False) -> np.ndarray:
+        """Inclusive (or exclusive) prefix sums: int64 for integer formats,
+        float64 for float formats."""
+        bits = np.ascontiguousarray(bits)
+        n = bits.size
+        if dtype in ("i32", "i64"):
+            out = np.empty(n, dtype=np.int64)
+            rc = self.lib.oracle_scan_int(_ptr(bits), n, CODES[dtype], int(exclusive), _ptr(out))
+        else:
+            out = np.empty(n, dtype=np.float64)
+            rc = self.lib.oracle_scan_float(_ptr(bits), n, CODES[dtype], int(exclusive), _ptr(out))
+        if rc:
+            raise ValueError(f"oracle scan: dtype {dtype}")
+        return out
+
 
 _default: Oracle | None = None
 
@@ -167,7 +186,7 @@ def get() -> Oracle:
 
 def __getattr__(name):  # module-level convenience: oracle.tpose(...), oracle.sum(...)
     if name in ("tpose", "tpose_batched", "sum_int", "sum_float", "sum", "sum_abs",
-                "sum_plain_f32", "decode", "sum_segmented"):
+                "sum_plain_f32", "decode", "sum_segmented", "scan"):
         return getattr(get(), name)
     raise AttributeError(name)
 

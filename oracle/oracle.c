@@ -31,6 +31,13 @@
  *   plain fp32  Listing 2.1 exactly as written: `float sum = 0; sum += arr[i]`.
  *               It is the uncompensated comparator, not a reference.
  *
+ *   prefix sum  the parallel prefix sum the conclusion names as the next case
+ *               study: the inclusive scan out[i] = A(0) + ... + A(i), or the
+ *               exclusive scan out[i] = A(0) + ... + A(i-1) (out[0] = 0), i.e.
+ *               reduce_sum of every prefix.  Same arithmetic as the sums:
+ *               int64 (modulo 2^64) for integers, a running fp64 Neumaier sum
+ *               of exact decodes for floats, each output rounded to fp64.
+ *
  * The element decoders are written from the format definitions (IEEE 754
  * binary16; bfloat16 = the top half of binary32; OCP 8-bit E4M3 "FN": bias 7,
  * no infinities, S.1111.111 is NaN, largest finite 448).
@@ -212,6 +219,58 @@ int oracle_sum_segmented(const void *src, const int64_t *offsets, int64_t nseg, 
             ((int64_t *)out)[i] = oracle_sum_int(p, hi - lo, dtype, NULL);
         else
             ((double *)out)[i] = oracle_sum_float(p, hi - lo, dtype);
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ prefix sums */
+
+/* Integer scan into int64 out[n] (modulo 2^64 for int64 inputs). */
+int oracle_scan_int(const void *src, int64_t n, int dtype, int exclusive, int64_t *out) {
+    if (dtype != OR_I32 && dtype != OR_I64) return -1;
+    uint64_t w = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const uint64_t x = dtype == OR_I32 ? (uint64_t)(int64_t)((const int32_t *)src)[i]
+                                           : (uint64_t)((const int64_t *)src)[i];
+        if (exclusive) {
+            memcpy(&out[i], &w, 8);
+            w += x;
+        } else {
+            w += x;
+            memcpy(&out[i], &w, 8);
+        }
+    }
+    return 0;
+}
+
+/* Float scan into double out[n]: each output is the compensated running sum of
+ * the exact decodes (Neumaier, fp64) rounded to fp64, with the IEEE rules of
+ * the exact prefix for non-finite values. */
+int oracle_scan_float(const void *src, int64_t n, int dtype, int exclusive, double *out) {
+    if (dtype != OR_F32 && dtype != OR_F16 && dtype != OR_BF16 && dtype != OR_F8E4M3) return -1;
+    double s = 0.0, c = 0.0;
+    int nan = 0, pinf = 0, ninf = 0;
+    for (int64_t i = 0; i < n; i++) {
+        double prefix;
+        if (exclusive) {
+            prefix = (nan || (pinf && ninf)) ? NAN : pinf ? INFINITY : ninf ? -INFINITY : s + c;
+            out[i] = prefix;
+        }
+        double x = oracle_decode(src, i, dtype);
+        if (isnan(x)) {
+            nan = 1;
+        } else if (isinf(x)) {
+            if (x > 0) pinf = 1; else ninf = 1;
+        } else {
+            double t = s + x;
+            if (fabs(s) >= fabs(x)) c += (s - t) + x;
+            else c += (x - t) + s;
+            s = t;
+        }
+        if (!exclusive) {
+            prefix = (nan || (pinf && ninf)) ? NAN : pinf ? INFINITY : ninf ? -INFINITY : s + c;
+            out[i] = prefix;
+        }
     }
     return 0;
 }

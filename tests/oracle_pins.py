@@ -277,9 +277,59 @@ def pin_segmented(o):
     assert list(o.sum_segmented(np.arange(5, dtype=np.int32), off2, "i32")) == [0, 3, 0, 7]
 
 
+# ------------------------------------------------------------------ prefix sums
+
+def pin_scan_int(o):
+    """Integer prefix sums: the iota closed form i(i+1)/2, numpy's int64 cumsum,
+    Python-integer brute force modulo 2^64, and exclusive = inclusive - x."""
+    for n in (0, 1, 2, 7, 1000):
+        a = np.arange(1, n + 1, dtype=np.int32)
+        inc = o.scan(a, "i32")
+        assert [int(v) for v in inc] == [i * (i + 1) // 2 for i in range(1, n + 1)]
+        exc = o.scan(a, "i32", exclusive=True)
+        assert [int(v) for v in exc] == [i * (i - 1) // 2 for i in range(1, n + 1)]
+    a = W.integers(50000, 71, -(1 << 30), 1 << 30, "i32")
+    inc = o.scan(a, "i32")
+    assert np.array_equal(inc, np.cumsum(a.astype(np.int64)))
+    assert np.array_equal(o.scan(a, "i32", exclusive=True), inc - a.astype(np.int64))
+    big = W.integers(3000, 72, -(1 << 62), 1 << 62, "i64")
+    run, want = 0, []
+    for v in big.tolist():
+        run += v
+        want.append((run + (1 << 63)) % (1 << 64) - (1 << 63))   # two's-complement wrap
+    assert [int(v) for v in o.scan(big, "i64")] == want
+
+
+def pin_scan_float(o):
+    """Float prefix sums: every prefix within 4 ulp of math.fsum of that prefix
+    (correctly rounded), the exclusive scan shifted by one with a leading 0,
+    the last inclusive prefix equal to the full fsum, and the IEEE rules."""
+    for dt, seed in (("f32", 73), ("bf16", 74), ("f8e4m3", 75)):
+        bits = W.signed_lognormal(700, seed, dt)[0] if dt != "f32" else W.normal(700, seed, "f32")
+        x = o.decode(bits, dt).tolist()
+        inc = o.scan(bits, dt)
+        exc = o.scan(bits, dt, exclusive=True)
+        for i in range(len(x)):
+            ref = math.fsum(x[:i + 1])
+            assert abs(inc[i] - ref) <= 4 * math.ulp(max(abs(ref), 1e-300)), (dt, i)
+        assert exc[0] == 0.0 and np.array_equal(exc[1:], inc[:-1])
+        assert inc[-1] == o.sum_float(bits, dt)
+    f = np.array([1.0, np.inf, 2.0, -np.inf, 3.0], dtype=np.float32)
+    got = o.scan(f, "f32")
+    assert got[0] == 1.0 and got[1] == np.inf and got[2] == np.inf and np.isnan(got[3:]).all()
+    gotx = o.scan(f, "f32", exclusive=True)
+    assert gotx[0] == 0.0 and gotx[1] == 1.0 and gotx[2] == np.inf and np.isnan(gotx[4])
+    g = np.array([1.0, np.nan, 2.0], dtype=np.float32)
+    assert o.scan(g, "f32")[0] == 1.0 and np.isnan(o.scan(g, "f32")[1:]).all()
+    # 1 + 1e30 - 1e30 + 1: the compensated running sum keeps both ones
+    c = np.array([1.0, 1e30, -1e30, 1.0], dtype=np.float32)
+    assert list(o.scan(c, "f32")) == [1.0, float(np.float32(1e30)) + 1.0, 1.0, 2.0]
+
+
 PINS_TPOSE = [pin_tpose_golden, pin_tpose_iota, pin_tpose_library, pin_tpose_involution_and_ld,
               pin_tpose_permutation, pin_tpose_bruteforce]
 PINS_INT = [pin_int_golden, pin_int_closed_forms, pin_int_bruteforce_shuffle, pin_int_wrap]
 PINS_FLOAT = [pin_decode_golden, pin_decode_all_codes, pin_float_golden, pin_float_fsum,
               pin_float_closed_forms, pin_float_nonfinite, pin_plain_f32, pin_segmented]
-ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT
+PINS_SCAN = [pin_scan_int, pin_scan_float]
+ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN

@@ -45,6 +45,12 @@ MUTANTS = [
      "double s = 0.0;\n    for (int64_t i = 0; i < n; i++) s += (double)", P.PINS_FLOAT),
     ("segment_bounds_shifted", "int64_t lo = offsets[i], hi = offsets[i + 1];",
      "int64_t lo = offsets[i], hi = offsets[i + 1] - (i > 0);", P.PINS_FLOAT),
+    ("scan_exclusive_includes_own_term", "        if (exclusive) {\n            memcpy(&out[i], &w, 8);\n            w += x;",
+     "        if (exclusive) {\n            w += x;\n            memcpy(&out[i], &w, 8);", P.PINS_SCAN),
+    ("scan_int32_sign_dropped", "(uint64_t)(int64_t)((const int32_t *)src)[i]",
+     "(uint64_t)(uint32_t)((const int32_t *)src)[i]", P.PINS_SCAN),
+    ("scan_float_no_compensation", "ninf ? -INFINITY : s + c;\n            out[i] = prefix;\n        }\n    }",
+     "ninf ? -INFINITY : s;\n            out[i] = prefix;\n        }\n    }", P.PINS_SCAN),
 ]
 
 
