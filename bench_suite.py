@@ -216,6 +216,26 @@ def piece_widths(xtr, torch, log):
     return res
 
 
+# ---------------------------------------------------------------- prefix sums
+
+def prefix_sums(xtr, torch, log, n=1 << 28):
+    """Inclusive prefix sums of 2^28 fp32 N(0,1) and int32 values (outputs fp64
+    / int64): algorithmic bytes = read n * elem + write n * 8."""
+    res = {}
+    gen = torch.Generator("cuda").manual_seed(21)
+    for dt in ("f32", "i32"):
+        x = (torch.randn(n, generator=gen, device="cuda") if dt == "f32" else
+             torch.randint(-1000, 1001, (n,), generator=gen, device="cuda", dtype=torch.int32))
+        out = torch.empty(n, dtype=torch.float64 if dt == "f32" else torch.int64, device="cuda")
+        sec, _ = _time_dev(torch, lambda: xtr.scan_sum(x, out), reps=10, warm=2)
+        nb = n * 4 + n * 8
+        res[f"scan_{dt}_2^28"] = {"gbs": round(nb / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
+        del x, out
+    torch.cuda.empty_cache()
+    log("suite prefix sums: " + ", ".join(f"{k} {v['gbs']} GB/s" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- host buffers
 
 def host_buffers(xtr, torch, log):
@@ -304,10 +324,10 @@ def paper_shapes(xtr, torch, log):
 
 
 def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "precision",
-                                   "host", "serving")):
+                                   "host", "scan", "serving")):
     out = {}
     for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
-                     ("host", host_buffers),
+                     ("host", host_buffers), ("scan", prefix_sums),
                      ("segmented", segmented), ("precision", precision)):
         if name in parts:
             t0 = time.time()

@@ -175,6 +175,25 @@ int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void 
                                int64_t count, int dtype, void *stream);
 
 /* ------------------------------------------------------------------------
+ * scan_sum -- prefix sums, the parallel prefix sum the thesis's conclusion
+ * names as the next case study: reduce_sum (Section 2.1) of every prefix.
+ *
+ *   inclusive (exclusive == 0): out[i] = src[0] + ... + src[i]
+ *   exclusive (exclusive != 0): out[i] = src[0] + ... + src[i-1], out[0] = 0
+ *
+ * out: device double[n] for F32/F16/BF16/F8E4M3, int64_t[n] for I32/I64
+ * (8-byte aligned; must not overlap src).  Integers: exact 64-bit sums
+ * (modulo 2^64 for I64).  Floats: exact decodes accumulated in fp64 in a
+ * fixed order (deterministic); every output is within about 300 * 2^-53 of
+ * the sum of magnitudes of its prefix from the exact prefix sum, and
+ * non-finite values follow the IEEE rules of the exact prefix (NaN -> NaN
+ * from there on; +inf with -inf -> NaN).  Three launches on `stream`
+ * (tile sums, their scan, the tile rescans); library workspace per stream.
+ * n == 0 is a no-op.  Errors: EINVAL, EDTYPE, EALIGN, EOVERLAP, ENOMEM, EHIP.
+ */
+int scan_sum(const void *src, int64_t n, void *out, int dtype, int exclusive, void *stream);
+
+/* ------------------------------------------------------------------------
  * Host buffers: the end-to-end form of the paper's host code (Listing 3.6:
  * copy in, kernel, copy out), for data that lives in host memory.
  *

@@ -77,6 +77,7 @@ _SIGS = {
     "xtr_tpose_host": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
                         C.c_int], C.c_int),
     "xtr_reduce_sum_host": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int], C.c_int),
+    "scan_sum": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "xtr_tpose_plan_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_destroy": ([C.c_void_p], C.c_int),
@@ -441,6 +442,22 @@ def reduce_sum_batched_scatter(srcs, outs, *, ns=None, dtype=None, stream=None):
                                         C.cast(optr, C.c_void_p), count, _code(dt),
                                         _stream(stream))
     _check(rc, "reduce_sum_batched_scatter")
+
+
+def scan_sum(src, out=None, *, n=None, dtype=None, exclusive=False, stream=None):
+    """Prefix sums of a contiguous tensor: float64 output for float formats,
+    int64 for int32/int64; exclusive=True shifts by one (out[0] = 0)."""
+    import torch
+    lib = load()
+    dt = dtype or dtype_of(src)
+    n = src.numel() if n is None else n
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64 if dt in FLOAT_SUM else torch.int64,
+                          device=src.device)
+    rc = lib.scan_sum(C.c_void_p(src.data_ptr()), n, C.c_void_p(out.data_ptr()), _code(dt),
+                      int(bool(exclusive)), _stream(stream))
+    _check(rc, "scan_sum")
+    return out
 
 
 def _host_ptr(a):

@@ -45,7 +45,8 @@ inline bool is_int_sum_dtype(int d) { return d == XTR_I32 || d == XTR_I64; }
 //   WS_TABLE:  job/descriptor tables uploaded by the batched entry points.
 // Returns XTR_OK and sets *ptr, or an error code.  Growing a buffer waits for
 // the stream (the old buffer may still be in use by enqueued work).
-enum { WS_REDUCE = 0, WS_TABLE = 1, WS_KINDS = 2 };
+//   WS_SCAN:   tile sums / offsets of the prefix sums (written before read).
+enum { WS_REDUCE = 0, WS_TABLE = 1, WS_SCAN = 2, WS_KINDS = 3 };
 int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr, size_t *actual = nullptr);
 
 // Asynchronous host -> device copy of `bytes` from pageable `host` memory:
