@@ -14,6 +14,9 @@ It wraps ``oracle.c`` (plain single-threaded C, built with gcc) through ctypes:
 * ``decode(bits, dtype)``       exact fp64 value of every element.
 * ``sum_segmented(...)``        the sum above per CSR segment.
 * ``tpose_batched(jobs)``       the transpose above per job.
+* ``scan(bits, dtype, excl)``   inclusive / exclusive prefix sums, same arithmetic as the sums.
+* ``histogram_int(...)``        counts in ``nbins`` bins of ``width`` from ``lo`` (exact).
+* ``histogram_float(...)``      counts in ``nbins`` equal bins of [lo, hi), fp64 bin rule.
 
 ``Oracle(path)`` loads any build of ``oracle.c`` (the mutation tests load
 deliberately broken copies to show that the pins catch them).
@@ -33,6 +36,7 @@ LIB = os.path.join(HERE, "liboracle.so")
 
 # oracle-local dtype codes (mirror the enum in oracle.c, not the product's)
 CODES = {"f32": 0, "f16": 1, "bf16": 2, "f8e4m3": 3, "i32": 4, "i64": 5}
+HCODES = {"i32": 4, "i64": 5, "u8": 7, "u16": 8}       # integer histogram inputs
 FLOATS = ("f32", "f16", "bf16", "f8e4m3")
 INTS = ("i32", "i64")
 
@@ -80,6 +84,10 @@ class Oracle:
         lib.oracle_scan_int.restype = C.c_int
         lib.oracle_scan_float.argtypes = [vp, i64, C.c_int, C.c_int, vp]
         lib.oracle_scan_float.restype = C.c_int
+        lib.oracle_histogram_int.argtypes = [vp, i64, C.c_int, i64, i64, i64, vp]
+        lib.oracle_histogram_int.restype = C.c_int
+        lib.oracle_histogram_float.argtypes = [vp, i64, C.c_int, C.c_double, C.c_double, i64, vp]
+        lib.oracle_histogram_float.restype = C.c_int
         self.lib = lib
         self.path = path
 
@@ -173,6 +181,24 @@ class Oracle:
             raise ValueError(f"oracle scan: dtype {dtype}")
         return out
 
+    def histogram_int(self, bits: np.ndarray, dtype: str, lo: int, width: int,
+                      nbins: int) -> np.ndarray:
+        bits = np.ascontiguousarray(bits)
+        out = np.empty(nbins, dtype=np.int64)
+        if self.lib.oracle_histogram_int(_ptr(bits), bits.size, HCODES[dtype], lo, width, nbins,
+                                         _ptr(out)):
+            raise ValueError("oracle_histogram_int: bad arguments")
+        return out
+
+    def histogram_float(self, bits: np.ndarray, dtype: str, lo: float, hi: float,
+                        nbins: int) -> np.ndarray:
+        bits = np.ascontiguousarray(bits)
+        out = np.empty(nbins, dtype=np.int64)
+        if self.lib.oracle_histogram_float(_ptr(bits), bits.size, CODES[dtype], lo, hi, nbins,
+                                           _ptr(out)):
+            raise ValueError("oracle_histogram_float: bad arguments")
+        return out
+
 
 _default: Oracle | None = None
 
@@ -186,7 +212,8 @@ def get() -> Oracle:
 
 def __getattr__(name):  # module-level convenience: oracle.tpose(...), oracle.sum(...)
     if name in ("tpose", "tpose_batched", "sum_int", "sum_float", "sum", "sum_abs",
-                "sum_plain_f32", "decode", "sum_segmented", "scan"):
+                "sum_plain_f32", "decode", "sum_segmented", "scan", "histogram_int",
+                "histogram_float"):
         return getattr(get(), name)
     raise AttributeError(name)
 

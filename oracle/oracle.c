@@ -38,6 +38,14 @@
  *               int64 (modulo 2^64) for integers, a running fp64 Neumaier sum
  *               of exact decodes for floats, each output rounded to fp64.
  *
+ *   histogram   the other case study the conclusion names: counts of the
+ *               elements in equal bins.  Integers: bin b holds
+ *               lo + b*width <= x < lo + (b+1)*width, b < nbins (exact).
+ *               Floats: x decoded exactly; bin floor((x - lo) * s) with
+ *               s = nbins / (hi - lo), both evaluated in fp64 with round to
+ *               nearest, capped at nbins - 1; x outside [lo, hi) and NaN are
+ *               not counted.
+ *
  * The element decoders are written from the format definitions (IEEE 754
  * binary16; bfloat16 = the top half of binary32; OCP 8-bit E4M3 "FN": bias 7,
  * no infinities, S.1111.111 is NaN, largest finite 448).
@@ -51,7 +59,8 @@
 #include <stdlib.h>
 
 /* Oracle-local element format codes (kept independent of the product's). */
-enum { OR_F32 = 0, OR_F16 = 1, OR_BF16 = 2, OR_F8E4M3 = 3, OR_I32 = 4, OR_I64 = 5 };
+enum { OR_F32 = 0, OR_F16 = 1, OR_BF16 = 2, OR_F8E4M3 = 3, OR_I32 = 4, OR_I64 = 5, OR_U8 = 7,
+       OR_U16 = 8 };
 
 int oracle_elem_bytes(int dtype) {
     switch (dtype) {
@@ -61,6 +70,8 @@ int oracle_elem_bytes(int dtype) {
     case OR_F8E4M3: return 1;
     case OR_I32: return 4;
     case OR_I64: return 8;
+    case OR_U8: return 1;
+    case OR_U16: return 2;
     default: return 0;
     }
 }
@@ -271,6 +282,53 @@ int oracle_scan_float(const void *src, int64_t n, int dtype, int exclusive, doub
             prefix = (nan || (pinf && ninf)) ? NAN : pinf ? INFINITY : ninf ? -INFINITY : s + c;
             out[i] = prefix;
         }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ histograms */
+
+static int int_elem(const void *src, int64_t i, int dtype, __int128 *x) {
+    switch (dtype) {
+    case OR_I32: *x = ((const int32_t *)src)[i]; return 0;
+    case OR_I64: *x = ((const int64_t *)src)[i]; return 0;
+    case OR_U8: *x = ((const uint8_t *)src)[i]; return 0;
+    case OR_U16: *x = ((const uint16_t *)src)[i]; return 0;
+    default: return -1;
+    }
+}
+
+/* Integer histogram: counts[b] = #{i : lo + b*width <= x_i < lo + (b+1)*width}. */
+int oracle_histogram_int(const void *src, int64_t n, int dtype, int64_t lo, int64_t width,
+                         int64_t nbins, int64_t *counts) {
+    if (width < 1 || nbins < 0) return -1;
+    for (int64_t b = 0; b < nbins; b++) counts[b] = 0;
+    const __int128 span = (__int128)width * nbins;
+    for (int64_t i = 0; i < n; i++) {
+        __int128 x;
+        if (int_elem(src, i, dtype, &x)) return -1;
+        __int128 d = x - lo;
+        if (d < 0 || d >= span) continue;
+        counts[(int64_t)(d / width)] += 1;
+    }
+    return 0;
+}
+
+/* Float histogram over [lo, hi): bin floor((x - lo) * (nbins / (hi - lo))) in
+ * fp64, capped at nbins - 1; NaN and x outside [lo, hi) are not counted. */
+int oracle_histogram_float(const void *src, int64_t n, int dtype, double lo, double hi,
+                           int64_t nbins, int64_t *counts) {
+    if (dtype != OR_F32 && dtype != OR_F16 && dtype != OR_BF16 && dtype != OR_F8E4M3) return -1;
+    if (!(hi > lo) || nbins < 1) return -1;
+    for (int64_t b = 0; b < nbins; b++) counts[b] = 0;
+    const double scale = (double)nbins / (hi - lo);
+    for (int64_t i = 0; i < n; i++) {
+        const double x = oracle_decode(src, i, dtype);
+        if (!(x >= lo && x < hi)) continue;             /* NaN fails both */
+        double t = (x - lo) * scale;
+        int64_t b = (int64_t)floor(t);
+        if (b > nbins - 1) b = nbins - 1;
+        counts[b] += 1;
     }
     return 0;
 }

@@ -326,10 +326,68 @@ def pin_scan_float(o):
     assert list(o.scan(c, "f32")) == [1.0, float(np.float32(1e30)) + 1.0, 1.0, 2.0]
 
 
+# ------------------------------------------------------------------ histograms
+
+def pin_histogram_int(o):
+    """Integer bins against numpy.histogram on exact integer edges, brute force
+    on small inputs, and the total = the number of in-range elements."""
+    a = W.integers(100000, 81, -5000, 5000, "i32")
+    for lo, width, nb in ((-5000, 10, 1000), (-1234, 7, 300), (0, 1, 4096), (-6000, 100, 150)):
+        got = o.histogram_int(a, "i32", lo, width, nb)
+        hi = lo + nb * width                         # numpy closes the last bin: drop x == hi
+        want, _ = np.histogram(a[a != hi].astype(np.float64), bins=nb, range=(lo, hi))
+        assert np.array_equal(got, want), (lo, width, nb)
+        inr = int(((a >= lo) & (a < lo + nb * width)).sum())
+        assert got.sum() == inr
+    b = np.array([0, 1, 2, 3, 255, 7, 8, 9], dtype=np.uint8)
+    got = o.histogram_int(b, "u8", 2, 3, 3)           # bins [2,5) [5,8) [8,11)
+    assert list(got) == [2, 1, 2]
+    big = np.array([-(1 << 62), 1 << 62, 5, 6], dtype=np.int64)
+    assert list(o.histogram_int(big, "i64", 5, 1, 2)) == [1, 1]
+
+
+def _check_vs_numpy(got, xd, lo, hi, nb):
+    """``got`` against numpy.histogram over the same fp64 values.  numpy closes
+    its last bin, so x == hi is dropped first.  With dyadic edges both rules
+    are exact and must agree bin for bin; otherwise numpy places an element
+    against rounded linspace edges, so the two may differ only for elements
+    within rounding of an interior edge."""
+    xd = xd[np.isfinite(xd) & (xd != hi)]
+    want, edges = np.histogram(xd, bins=nb, range=(lo, hi))
+    width = hi - lo
+    if (nb & (nb - 1)) == 0 and math.frexp(width)[0] == 0.5 and (lo / (width / nb)).is_integer():
+        assert np.array_equal(got, want), (lo, hi, nb)
+        return
+    inner = edges[1:-1]
+    k = np.clip(np.searchsorted(inner, xd), 1, max(len(inner), 1)) if len(inner) else None
+    near = 0
+    if len(inner):
+        d = np.minimum(np.abs(xd - inner[k - 1]), np.abs(xd - inner[np.minimum(k, len(inner) - 1)]))
+        near = int((d <= 1e-12 * np.maximum(1.0, np.abs(xd))).sum())
+    assert got.sum() == want.sum() and np.abs(got - want).sum() <= 2 * near, (lo, hi, nb)
+
+
+def pin_histogram_float(o):
+    """Float bins against numpy.histogram (its uniform-bin rule, in fp64), the
+    half-open range (lo counted, hi not), NaN and infinities not counted."""
+    x = W.normal(200000, 82, "f32")
+    xd = x.astype(np.float64)
+    for lo, hi, nb in ((-4.0, 4.0, 256), (-1.0, 2.5, 1000), (0.0, 1.0, 7), (-0.5, 3.0, 1)):
+        _check_vs_numpy(o.histogram_float(x, "f32", lo, hi, nb), xd, lo, hi, nb)
+    e = np.array([0.0, 1.0, 0.5, np.nan, np.inf, -np.inf, 0.999999, -1e-30], dtype=np.float32)
+    got = o.histogram_float(e, "f32", 0.0, 1.0, 2)
+    assert list(got) == [1, 2], got                  # 0.0 -> bin 0; 0.5, 0.999999 -> bin 1
+    bits, _ = W.signed_lognormal(50000, 83, "bf16")
+    vals = o.decode(bits, "bf16")
+    _check_vs_numpy(o.histogram_float(bits, "bf16", -10.0, 10.0, 64), vals, -10.0, 10.0, 64)
+    _check_vs_numpy(o.histogram_float(bits, "bf16", -8.0, 8.0, 64), vals, -8.0, 8.0, 64)
+
+
 PINS_TPOSE = [pin_tpose_golden, pin_tpose_iota, pin_tpose_library, pin_tpose_involution_and_ld,
               pin_tpose_permutation, pin_tpose_bruteforce]
 PINS_INT = [pin_int_golden, pin_int_closed_forms, pin_int_bruteforce_shuffle, pin_int_wrap]
 PINS_FLOAT = [pin_decode_golden, pin_decode_all_codes, pin_float_golden, pin_float_fsum,
               pin_float_closed_forms, pin_float_nonfinite, pin_plain_f32, pin_segmented]
 PINS_SCAN = [pin_scan_int, pin_scan_float]
-ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN
+PINS_HIST = [pin_histogram_int, pin_histogram_float]
+ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN + PINS_HIST

@@ -51,6 +51,14 @@ MUTANTS = [
      "(uint64_t)(uint32_t)((const int32_t *)src)[i]", P.PINS_SCAN),
     ("scan_float_no_compensation", "ninf ? -INFINITY : s + c;\n            out[i] = prefix;\n        }\n    }",
      "ninf ? -INFINITY : s;\n            out[i] = prefix;\n        }\n    }", P.PINS_SCAN),
+    ("hist_int_hi_included", "if (d < 0 || d >= span) continue;", "if (d < 0 || d > span) continue; if (d == span) d = span - 1;",
+     P.PINS_HIST),
+    ("hist_int_bin_rounds", "counts[(int64_t)(d / width)] += 1;",
+     "counts[(int64_t)((d + width / 2) / width) % nbins] += 1;", P.PINS_HIST),
+    ("hist_float_lo_excluded", "if (!(x >= lo && x < hi)) continue;",
+     "if (!(x > lo && x < hi)) continue;", P.PINS_HIST),
+    ("hist_float_scale_off", "const double scale = (double)nbins / (hi - lo);",
+     "const double scale = (double)(nbins - 1) / (hi - lo);", P.PINS_HIST),
 ]
 
 
