@@ -166,7 +166,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--suite", choices=["step", "full"], default="step")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,serving",
+    ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -236,6 +236,38 @@ def prefix_sums(xtr, torch, log, n=1 << 28):
     return res
 
 
+def histograms(xtr, torch, log, n=1 << 28):
+    """Histograms (algorithmic bytes = the input read once; the counts are a
+    few KiB): 2^28 fp32 N(0,1) values in 1024 bins over [-4, 4); 2^30 uint8
+    values, uniform, in 256 bins; 2^28 int32 values, uniform in [0, 2^20), in
+    4096 bins of width 256; and the constant fp32 input (every element in one
+    bin: one LDS atomic per 16-byte vector, all lanes of a wave on one
+    counter)."""
+    res = {}
+    gen = torch.Generator("cuda").manual_seed(23)
+    cases = (
+        ("f32_normal_1024", lambda: torch.randn(n, generator=gen, device="cuda"),
+         lambda x: xtr.histogram_float(x, -4.0, 4.0, 1024)),
+        ("u8_uniform_256", lambda: torch.randint(0, 256, (4 * n,), generator=gen, device="cuda",
+                                                 dtype=torch.uint8),
+         lambda x: xtr.histogram_int(x, 0, 1, 256)),
+        ("i32_uniform_4096", lambda: torch.randint(0, 1 << 20, (n,), generator=gen,
+                                                   device="cuda", dtype=torch.int32),
+         lambda x: xtr.histogram_int(x, 0, 256, 4096)),
+        ("f32_constant_1024", lambda: torch.full((n,), 0.5, device="cuda"),
+         lambda x: xtr.histogram_float(x, -4.0, 4.0, 1024)),
+    )
+    for name, make, call in cases:
+        x = make()
+        sec, _ = _time_dev(torch, lambda: call(x), reps=10, warm=2)
+        nb = x.numel() * x.element_size()
+        res[name] = {"gbs": round(nb / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
+        del x
+    torch.cuda.empty_cache()
+    log("suite histograms: " + ", ".join(f"{k} {v['gbs']} GB/s" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- host buffers
 
 def host_buffers(xtr, torch, log):
@@ -324,10 +356,10 @@ def paper_shapes(xtr, torch, log):
 
 
 def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "precision",
-                                   "host", "scan", "serving")):
+                                   "host", "scan", "hist", "serving")):
     out = {}
     for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
-                     ("host", host_buffers), ("scan", prefix_sums),
+                     ("host", host_buffers), ("scan", prefix_sums), ("hist", histograms),
                      ("segmented", segmented), ("precision", precision)):
         if name in parts:
             t0 = time.time()

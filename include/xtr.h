@@ -195,6 +195,37 @@ int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void 
 int scan_sum(const void *src, int64_t n, void *out, int dtype, int exclusive, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Histograms: the third case study the thesis's conclusion names (after the
+ * reduction and the prefix sum).  The thesis's system has no atomics
+ * (Section 1.2); these kernels use them.
+ *
+ * counts: device int64_t[nbins] (8-byte aligned; must not overlap src),
+ * fully overwritten with exact counts (deterministic).  src: device array of
+ * n elements, aligned to its element size.  1 <= nbins <= XTR_HIST_MAX_BINS.
+ * Up to 16384 bins the elements are counted in per-workgroup LDS histograms
+ * whose rows are summed by a second launch (library workspace per stream);
+ * more bins are counted with 64-bit device atomics into counts (zero-filled
+ * first).  n == 0 zero-fills counts.  Asynchronous on `stream`.
+ * Errors: EINVAL (n < 0, nbins or width out of range, a bad float range,
+ * null pointer), EDTYPE, EALIGN, EOVERLAP, ENOMEM, EHIP.
+ */
+#define XTR_HIST_MAX_BINS ((int64_t)1 << 28)
+
+/* Integer bins: counts[b] = number of x with lo + b*width <= x < lo + (b+1)*width
+ * (exact; elements outside [lo, lo + nbins*width) are not counted).
+ * dtype: I32, I64, U8 or U16.  width >= 1. */
+int histogram_int(const void *src, int64_t n, int dtype, int64_t lo, int64_t width,
+                  int64_t nbins, int64_t *counts, void *stream);
+
+/* Float bins over [lo, hi): x is decoded exactly to fp64 and counted in bin
+ * floor((x - lo) * s), s = nbins / (hi - lo), capped at nbins - 1, with every
+ * operation an fp64 operation rounded to nearest.  x < lo, x >= hi and NaN are
+ * not counted.  lo, hi, hi - lo and s must be finite, lo < hi.
+ * dtype: F32, F16, BF16 or F8E4M3. */
+int histogram_float(const void *src, int64_t n, int dtype, double lo, double hi,
+                    int64_t nbins, int64_t *counts, void *stream);
+
+/* ------------------------------------------------------------------------
  * Host buffers: the end-to-end form of the paper's host code (Listing 3.6:
  * copy in, kernel, copy out), for data that lives in host memory.
  *

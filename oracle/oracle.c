@@ -319,9 +319,10 @@ int oracle_histogram_int(const void *src, int64_t n, int dtype, int64_t lo, int6
 int oracle_histogram_float(const void *src, int64_t n, int dtype, double lo, double hi,
                            int64_t nbins, int64_t *counts) {
     if (dtype != OR_F32 && dtype != OR_F16 && dtype != OR_BF16 && dtype != OR_F8E4M3) return -1;
-    if (!(hi > lo) || nbins < 1) return -1;
-    for (int64_t b = 0; b < nbins; b++) counts[b] = 0;
+    if (!(hi > lo) || !isfinite(lo) || !isfinite(hi) || nbins < 1) return -1;
     const double scale = (double)nbins / (hi - lo);
+    if (!isfinite(hi - lo) || !isfinite(scale)) return -1;   /* the bin rule needs both finite */
+    for (int64_t b = 0; b < nbins; b++) counts[b] = 0;
     for (int64_t i = 0; i < n; i++) {
         const double x = oracle_decode(src, i, dtype);
         if (!(x >= lo && x < hi)) continue;             /* NaN fails both */

@@ -78,6 +78,10 @@ _SIGS = {
                         C.c_int], C.c_int),
     "xtr_reduce_sum_host": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int], C.c_int),
     "scan_sum": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "histogram_int": ([C.c_void_p, C.c_int64, C.c_int, C.c_int64, C.c_int64, C.c_int64,
+                       C.c_void_p, C.c_void_p], C.c_int),
+    "histogram_float": ([C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_int64,
+                         C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_destroy": ([C.c_void_p], C.c_int),
@@ -458,6 +462,47 @@ def scan_sum(src, out=None, *, n=None, dtype=None, exclusive=False, stream=None)
                       int(bool(exclusive)), _stream(stream))
     _check(rc, "scan_sum")
     return out
+
+
+def _hist_dtype(src, dtype):
+    import torch
+    if dtype is None and src.dtype in (torch.int8, torch.int16):
+        raise TypeError("int8/int16 tensors have no signed histogram format; pass dtype='u8' or "
+                        "'u16' to count their raw bits as unsigned")
+    return dtype or dtype_of(src)
+
+
+def histogram_int(src, lo: int, width: int, nbins: int, counts=None, *, n=None, dtype=None,
+                  stream=None):
+    """Exact integer histogram: counts[b] = #{x : lo + b*width <= x < lo + (b+1)*width}
+    over an int32 / int64 / uint8 / uint16 tensor; returns int64[nbins]."""
+    import torch
+    lib = load()
+    dt = _hist_dtype(src, dtype)
+    n = src.numel() if n is None else n
+    if counts is None:
+        counts = torch.empty(nbins, dtype=torch.int64, device=src.device)
+    rc = lib.histogram_int(C.c_void_p(src.data_ptr()), n, _code(dt), int(lo), int(width),
+                           int(nbins), C.c_void_p(counts.data_ptr()), _stream(stream))
+    _check(rc, "histogram_int")
+    return counts
+
+
+def histogram_float(src, lo: float, hi: float, nbins: int, counts=None, *, n=None, dtype=None,
+                    stream=None):
+    """Histogram of a float tensor over [lo, hi) in nbins equal bins (bin
+    floor((x - lo) * nbins / (hi - lo)) in fp64, capped at nbins - 1; NaN and
+    values outside [lo, hi) are not counted); returns int64[nbins]."""
+    import torch
+    lib = load()
+    dt = _hist_dtype(src, dtype)
+    n = src.numel() if n is None else n
+    if counts is None:
+        counts = torch.empty(nbins, dtype=torch.int64, device=src.device)
+    rc = lib.histogram_float(C.c_void_p(src.data_ptr()), n, _code(dt), float(lo), float(hi),
+                             int(nbins), C.c_void_p(counts.data_ptr()), _stream(stream))
+    _check(rc, "histogram_float")
+    return counts
 
 
 def _host_ptr(a):

@@ -46,7 +46,8 @@ inline bool is_int_sum_dtype(int d) { return d == XTR_I32 || d == XTR_I64; }
 // Returns XTR_OK and sets *ptr, or an error code.  Growing a buffer waits for
 // the stream (the old buffer may still be in use by enqueued work).
 //   WS_SCAN:   tile sums / offsets of the prefix sums (written before read).
-enum { WS_REDUCE = 0, WS_TABLE = 1, WS_SCAN = 2, WS_KINDS = 3 };
+//   WS_HIST:   per-workgroup partial histograms (written before read).
+enum { WS_REDUCE = 0, WS_TABLE = 1, WS_SCAN = 2, WS_HIST = 3, WS_KINDS = 4 };
 int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr, size_t *actual = nullptr);
 
 // Asynchronous host -> device copy of `bytes` from pageable `host` memory:

@@ -133,3 +133,47 @@ def test_segmented_and_batched_validation(lib):
     assert lib.reduce_sum_batched(C.cast(ptrs, C.c_void_p), C.cast(ns, C.c_void_p), 2,
                                   C.c_void_p(FAKE + 8192), 0, None) == -4
     assert b"job 1" in lib.xtr_last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, 10, 0, 0, 1, 16, FAKE + 4096), -2),           # f32 is not an integer format
+    ((FAKE, 10, 6, 0, 1, 16, FAKE + 4096), -2),           # nor f64
+    ((FAKE, -1, 4, 0, 1, 16, FAKE + 4096), -1),           # negative n
+    ((FAKE, 10, 4, 0, 0, 16, FAKE + 4096), -1),           # width 0
+    ((FAKE, 10, 4, 0, 1, 0, FAKE + 4096), -1),            # no bins
+    ((FAKE, 10, 4, 0, 1, (1 << 28) + 1, FAKE + 4096), -1),  # too many bins
+    ((FAKE, 10, 4, 0, 1, 16, 0), -1),                     # null counts
+    ((0, 10, 4, 0, 1, 16, FAKE + 4096), -1),              # null src
+    ((FAKE + 2, 10, 4, 0, 1, 16, FAKE + 4096), -4),       # misaligned int32 src
+    ((FAKE, 10, 4, 0, 1, 16, FAKE + 4100), -4),           # misaligned counts
+    ((FAKE, 10, 4, 0, 1, 16, FAKE + 8), -3),              # counts overlap src
+])
+def test_histogram_int_rejects(lib, args, code):
+    src, n, dt, lo, width, nb, counts = args
+    assert lib.histogram_int(C.c_void_p(src), n, dt, lo, width, nb, C.c_void_p(counts),
+                             None) == code
+    assert lib.xtr_last_error()
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, 10, 4, 0.0, 1.0, 16, FAKE + 4096), -2),               # i32 is not a float format
+    ((FAKE, 10, 0, 1.0, 1.0, 16, FAKE + 4096), -1),               # empty range
+    ((FAKE, 10, 0, 2.0, 1.0, 16, FAKE + 4096), -1),               # lo > hi
+    ((FAKE, 10, 0, float("nan"), 1.0, 16, FAKE + 4096), -1),      # NaN bound
+    ((FAKE, 10, 0, float("-inf"), 1.0, 16, FAKE + 4096), -1),     # infinite bound
+    ((FAKE, 10, 0, -1.7e308, 1.7e308, 16, FAKE + 4096), -1),      # hi - lo overflows
+    ((FAKE, 10, 0, 0.0, 5e-324, 16, FAKE + 4096), -1),            # nbins / (hi - lo) overflows
+    ((FAKE, 10, 0, 0.0, 1.0, 0, FAKE + 4096), -1),                # no bins
+    ((FAKE + 1, 10, 0, 0.0, 1.0, 16, FAKE + 4096), -4),           # misaligned fp32 src
+])
+def test_histogram_float_rejects(lib, args, code):
+    src, n, dt, lo, hi, nb, counts = args
+    assert lib.histogram_float(C.c_void_p(src), n, dt, lo, hi, nb, C.c_void_p(counts),
+                               None) == code
+    assert lib.xtr_last_error()
+
+
+def test_histogram_rejects_int8_without_dtype():
+    import torch
+    with pytest.raises(TypeError):
+        X.histogram_int(torch.zeros(4, dtype=torch.int8), 0, 1, 4)
