@@ -240,9 +240,8 @@ def histograms(xtr, torch, log, n=1 << 28):
     """Histograms (algorithmic bytes = the input read once; the counts are a
     few KiB): 2^28 fp32 N(0,1) values in 1024 bins over [-4, 4); 2^30 uint8
     values, uniform, in 256 bins; 2^28 int32 values, uniform in [0, 2^20), in
-    4096 bins of width 256; and the constant fp32 input (every element in one
-    bin: one LDS atomic per 16-byte vector, all lanes of a wave on one
-    counter)."""
+    4096 bins of width 256; 2^29 bf16 and 2^30 fp8 N(0,1) values in 256 bins;
+    and constant inputs (every element in one bin)."""
     res = {}
     gen = torch.Generator("cuda").manual_seed(23)
     cases = (
@@ -256,6 +255,13 @@ def histograms(xtr, torch, log, n=1 << 28):
          lambda x: xtr.histogram_int(x, 0, 256, 4096)),
         ("f32_constant_1024", lambda: torch.full((n,), 0.5, device="cuda"),
          lambda x: xtr.histogram_float(x, -4.0, 4.0, 1024)),
+        ("bf16_normal_256", lambda: torch.randn(2 * n, generator=gen, device="cuda",
+                                                dtype=torch.bfloat16),
+         lambda x: xtr.histogram_float(x, -4.0, 4.0, 256)),
+        ("f8e4m3_normal_256", lambda: torch.randn(4 * n, generator=gen, device="cuda").to(
+            torch.float8_e4m3fn), lambda x: xtr.histogram_float(x, -4.0, 4.0, 256)),
+        ("u8_constant_256", lambda: torch.full((4 * n,), 7, device="cuda", dtype=torch.uint8),
+         lambda x: xtr.histogram_int(x, 0, 1, 256)),
     )
     for name, make, call in cases:
         x = make()

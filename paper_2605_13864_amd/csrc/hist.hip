@@ -37,12 +37,15 @@ namespace {
 
 constexpr int HNT = 1024;                    // threads per workgroup (16 waves)
 constexpr int HUNROLL = 4;                   // 16-byte vectors in flight per thread
-constexpr int64_t LDS_BINS = 16384;          // 64 KiB of 32-bit counters
+constexpr int64_t LDS_WORDS = 16384;         // 64 KiB of 32-bit LDS counters per workgroup
 constexpr int64_t WG_MAX_ELEMS = (int64_t)1 << 31;
 constexpr int MERGE_NT = 1024;               // merge: 16 waves x 64 bins
 
 // How an integer offset d = x - lo in [0, span) becomes its bin d / width.
-enum { BIN_FLOAT = 0, BIN_SHIFT = 1, BIN_MAGIC = 2, BIN_DIV = 3 };
+// The *32 forms serve inputs of at most 32 bits with lo in the int32 range and
+// span <= 2^32: x and lo are compared and subtracted as 32-bit values, biased
+// by 2^31 so that unsigned order is signed order.
+enum { BIN_FLOAT = 0, BIN_SHIFT = 1, BIN_MAGIC = 2, BIN_DIV = 3, BIN_SHIFT32 = 4, BIN_MAGIC32 = 5 };
 
 typedef uint32_t hu32x4 __attribute__((ext_vector_type(4)));
 
@@ -56,7 +59,10 @@ struct HistArgs {
     uint64_t span_m1;      // min(width * nbins, 2^64) - 1
     uint64_t width;
     uint64_t magic;        // ceil(2^64 / width)      (BIN_MAGIC)
-    int shift;             // log2(width)             (BIN_SHIFT)
+    int shift;             // log2(width)             (BIN_SHIFT, BIN_SHIFT32)
+    uint32_t lo32;         // lo ^ 2^31, order-preserving 32-bit form  (BIN_*32)
+    uint32_t span_m1_32;   // width * nbins - 1                        (BIN_*32)
+    int rs;                // log2 of the LDS copies per bin
     // float rule
     double lo_f, hi_f, scale;
 };
@@ -87,6 +93,38 @@ template <int DT> __device__ __forceinline__ int64_t idecode(uint64_t r) {
     else return (int64_t)(r & 0xffffu);
 }
 
+// The bin of the element with raw bits r when it is counted, else nbins (a
+// spare bin that collects the elements outside the range and is never
+// reported).  Only the 32-bit and float rules have this form; it lets the
+// branch-free loop add 1 for every element.
+template <int DT, int MODE>
+__device__ __forceinline__ uint32_t bin_or_spare(uint64_t r, const HistArgs &a) {
+    const uint32_t nb = (uint32_t)a.nbins;
+    if constexpr (MODE == BIN_FLOAT) {
+        const double x = fdecode<DT>((uint32_t)r);
+        const bool ok = x >= a.lo_f && x < a.hi_f;                     // NaN fails both
+        const double t = (x - a.lo_f) * a.scale;
+        // t >= 0 when ok, so truncation is the floor
+        const uint32_t b = (uint32_t)(int)t;
+        return ok ? (b < nb - 1 ? b : nb - 1) : nb;
+    } else {
+        static_assert(MODE == BIN_SHIFT32 || MODE == BIN_MAGIC32, "32-bit integer rules only");
+        const uint32_t ux = (uint32_t)(int32_t)idecode<DT>(r) ^ 0x80000000u;
+        uint32_t d;
+        const bool below = __builtin_sub_overflow(ux, a.lo32, &d);     // x < lo
+        const bool ok = !below && d <= a.span_m1_32;
+        uint32_t q;
+        if constexpr (MODE == BIN_SHIFT32) {
+            q = d >> a.shift;
+        } else {
+            const uint64_t p0 = (uint64_t)d * (uint32_t)a.magic;       // as in BIN_MAGIC
+            const uint64_t p1 = (uint64_t)d * (uint32_t)(a.magic >> 32);
+            q = (uint32_t)((p1 + (p0 >> 32)) >> 32);
+        }
+        return ok ? q : nb;
+    }
+}
+
 // The bin of the element with raw bits r, or -1 when it is not counted.
 template <int DT, int MODE>
 __device__ __forceinline__ int bin_of(uint64_t r, const HistArgs &a) {
@@ -96,6 +134,18 @@ __device__ __forceinline__ int bin_of(uint64_t r, const HistArgs &a) {
         const double t = (x - a.lo_f) * a.scale;
         const int b = (int)floor(t);
         return b < (int)a.nbins - 1 ? b : (int)a.nbins - 1;
+    } else if constexpr (MODE == BIN_SHIFT32 || MODE == BIN_MAGIC32) {
+        const uint32_t ux = (uint32_t)(int32_t)idecode<DT>(r) ^ 0x80000000u;
+        uint32_t d;
+        if (__builtin_sub_overflow(ux, a.lo32, &d)) return -1;    // x < lo
+        if (d > a.span_m1_32) return -1;
+        if constexpr (MODE == BIN_SHIFT32) {
+            return (int)(d >> a.shift);
+        } else {
+            const uint64_t p0 = (uint64_t)d * (uint32_t)a.magic;   // as in BIN_MAGIC
+            const uint64_t p1 = (uint64_t)d * (uint32_t)(a.magic >> 32);
+            return (int)((p1 + (p0 >> 32)) >> 32);
+        }
     } else {
         const int64_t x = idecode<DT>(r);
         if (x < a.lo_i) return -1;
@@ -117,38 +167,59 @@ __device__ __forceinline__ int bin_of(uint64_t r, const HistArgs &a) {
     }
 }
 
+// Where the LDS counters live: R = 2^rs copies of the histogram, interleaved
+// bin-major (counter (b, c) at word b * R + c); thread t adds to copy t % R.
+// With R = 32 the 32 lanes an LDS pass serves hit 32 different banks whatever
+// their bins, and no two of them share a counter.
 template <bool GLOBAL> __device__ __forceinline__ void add_run(uint32_t *h, uint64_t *g, int b,
-                                                               uint32_t c) {
+                                                               uint32_t c, const HistArgs &a,
+                                                               uint32_t lr) {
     if constexpr (GLOBAL)
         __hip_atomic_fetch_add(g + b, (uint64_t)c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     else
-        __hip_atomic_fetch_add(h + b, c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_add(h + (((uint32_t)b << a.rs) | lr), c, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Bins the V elements of one 16-byte vector, one atomic add per run of equal bins.
-template <int DT, int MODE, bool GLOBAL>
+template <int EB> __device__ __forceinline__ uint64_t raw_of(const uint32_t (&w)[4], int i) {
+    if constexpr (EB == 8) return (uint64_t)w[2 * i] | ((uint64_t)w[2 * i + 1] << 32);
+    else if constexpr (EB == 4) return w[i];
+    else if constexpr (EB == 2) return (w[i >> 1] >> (16 * (i & 1))) & 0xffffu;
+    else return (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
+}
+
+// Bins the V elements of one 16-byte vector.  RUNS: one atomic add per run of
+// equal bins (a constant or sorted input costs one add per vector, not V).
+// Without RUNS (32 LDS copies, where lanes never share a counter): one add of
+// 1 per element, with no branch: an element that is not counted goes to the
+// spare bin nbins.
+template <int DT, int MODE, bool GLOBAL, bool RUNS>
 __device__ __forceinline__ void count_vec(const hu32x4 &v, const HistArgs &a, uint32_t *h,
-                                          uint64_t *g) {
+                                          uint64_t *g, uint32_t lr) {
     constexpr int EB = HistT<DT>::EB, V = 16 / EB;
     const uint32_t w[4] = {v[0], v[1], v[2], v[3]};
+    if constexpr (!RUNS) {
+#pragma unroll
+        for (int i = 0; i < V; i++) {
+            const uint32_t b = bin_or_spare<DT, MODE>(raw_of<EB>(w, i), a);
+            __hip_atomic_fetch_add(h + ((b << 5) | lr), 1u, __ATOMIC_RELAXED,   // R = 32 copies
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+        return;
+    }
     int cur = -1;
     uint32_t cnt = 0;
 #pragma unroll
     for (int i = 0; i < V; i++) {
-        uint64_t r;
-        if constexpr (EB == 8) r = (uint64_t)w[2 * i] | ((uint64_t)w[2 * i + 1] << 32);
-        else if constexpr (EB == 4) r = w[i];
-        else if constexpr (EB == 2) r = (w[i >> 1] >> (16 * (i & 1))) & 0xffffu;
-        else r = (w[i >> 2] >> (8 * (i & 3))) & 0xffu;
-        const int b = bin_of<DT, MODE>(r, a);
+        const int b = bin_of<DT, MODE>(raw_of<EB>(w, i), a);
         if (b != cur) {
-            if (cur >= 0) add_run<GLOBAL>(h, g, cur, cnt);
+            if (cur >= 0) add_run<GLOBAL>(h, g, cur, cnt, a, lr);
             cur = b;
             cnt = 0;
         }
         cnt++;
     }
-    if (cur >= 0) add_run<GLOBAL>(h, g, cur, cnt);
+    if (cur >= 0) add_run<GLOBAL>(h, g, cur, cnt, a, lr);
 }
 
 template <int DT> __device__ __forceinline__ uint64_t raw_at(const unsigned char *p) {
@@ -161,14 +232,16 @@ template <int DT> __device__ __forceinline__ uint64_t raw_at(const unsigned char
 
 // Streams the input; GLOBAL = false: LDS histogram, then row blockIdx.x of part;
 // GLOBAL = true: 64-bit atomics straight into counts (zero-filled before).
-template <int DT, int MODE, bool GLOBAL>
+template <int DT, int MODE, bool GLOBAL, bool RUNS>
 __global__ __launch_bounds__(HNT) void k_hist(const unsigned char *__restrict__ src, HistArgs a,
                                              uint32_t *__restrict__ part,
                                              uint64_t *__restrict__ counts) {
     constexpr int EB = HistT<DT>::EB, V = 16 / EB;
-    extern __shared__ uint32_t h[];
+    // static, so that LDS addresses need no base (two workgroups per CU fit)
+    __shared__ uint32_t h[GLOBAL ? 1 : LDS_WORDS];
+    const uint32_t lr = threadIdx.x & ((1u << a.rs) - 1);
     if constexpr (!GLOBAL) {
-        for (int j = threadIdx.x; j < (int)a.nbins; j += HNT) h[j] = 0;
+        for (int j = threadIdx.x; j < ((int)a.nbins + (RUNS ? 0 : 1)) << a.rs; j += HNT) h[j] = 0;
         __syncthreads();
     }
     const hu32x4 *vs = reinterpret_cast<const hu32x4 *>(src + a.head * EB);
@@ -179,11 +252,11 @@ __global__ __launch_bounds__(HNT) void k_hist(const unsigned char *__restrict__ 
 #pragma unroll
         for (int k = 0; k < HUNROLL; k++) v[k] = __builtin_nontemporal_load(vs + i + k * stride);
 #pragma unroll
-        for (int k = 0; k < HUNROLL; k++) count_vec<DT, MODE, GLOBAL>(v[k], a, h, counts);
+        for (int k = 0; k < HUNROLL; k++) count_vec<DT, MODE, GLOBAL, RUNS>(v[k], a, h, counts, lr);
     }
     for (; i < a.nvec; i += stride) {
         const hu32x4 v = __builtin_nontemporal_load(vs + i);
-        count_vec<DT, MODE, GLOBAL>(v, a, h, counts);
+        count_vec<DT, MODE, GLOBAL, RUNS>(v, a, h, counts, lr);
     }
     // the < V elements before the first 16-byte boundary and the < V after the
     // last whole vector
@@ -193,13 +266,18 @@ __global__ __launch_bounds__(HNT) void k_hist(const unsigned char *__restrict__ 
         const bool in = t < V ? e < a.head : e < a.n;
         if (in) {
             const int b = bin_of<DT, MODE>(raw_at<DT>(src + e * EB), a);
-            if (b >= 0) add_run<GLOBAL>(h, counts, b, 1u);
+            if (b >= 0) add_run<GLOBAL>(h, counts, b, 1u, a, lr);
         }
     }
     if constexpr (!GLOBAL) {
         __syncthreads();
         uint32_t *row = part + (int64_t)blockIdx.x * a.nbins;
-        for (int j = threadIdx.x; j < (int)a.nbins; j += HNT) row[j] = h[j];
+        const int R = 1 << a.rs;
+        for (int j = threadIdx.x; j < (int)a.nbins; j += HNT) {
+            uint32_t t = 0;
+            for (int c = 0; c < R; c++) t += h[(j << a.rs) + ((c + j) & (R - 1))];   // rotated: no bank conflicts
+            row[j] = t;
+        }
     }
 }
 
@@ -245,22 +323,32 @@ int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_
     const unsigned char *s = static_cast<const unsigned char *>(src);
     uint64_t *c64 = reinterpret_cast<uint64_t *>(counts);
     const int64_t want = (a.nvec + (int64_t)HNT * HUNROLL - 1) / ((int64_t)HNT * HUNROLL);
-    if (a.nbins > LDS_BINS) {
+    if (a.nbins > LDS_WORDS) {
         int rc = zero_fill(counts, (size_t)a.nbins * 8, st);
         if (rc) return rc;
-        int64_t G = resident_blocks((const void *)k_hist<DT, MODE, true>, HNT);
+        a.rs = 0;
+        int64_t G = resident_blocks((const void *)k_hist<DT, MODE, true, true>, HNT);
         if (G > want) G = want;
         if (G < 1) G = 1;
-        hipLaunchKernelGGL((k_hist<DT, MODE, true>), dim3((unsigned)G), dim3(HNT), 0, st, s, a,
-                           (uint32_t *)nullptr, c64);
+        hipLaunchKernelGGL((k_hist<DT, MODE, true, true>), dim3((unsigned)G), dim3(HNT), 0, st, s,
+                           a, (uint32_t *)nullptr, c64);
         XTR_HIP(hipGetLastError());
         return XTR_OK;
     }
-    const size_t lds = (size_t)a.nbins * 4;
+    // as many copies per bin (up to 32) as the LDS budget holds; the
+    // branch-free loop needs 32 copies of nbins + 1 bins (the spare one)
+    constexpr bool flat = MODE == BIN_FLOAT || MODE == BIN_SHIFT32 || MODE == BIN_MAGIC32;
+    const bool runs = !flat || ((a.nbins + 1) << 5) > LDS_WORDS;
+    a.rs = 5;
+    if (runs) {
+        a.rs = 0;
+        while (a.rs < 5 && (a.nbins << (a.rs + 1)) <= LDS_WORDS) a.rs++;
+    }
+    const void *kern = runs ? (const void *)k_hist<DT, MODE, false, true>
+                            : (const void *)k_hist<DT, MODE, false, !flat>;
     // at most 2 workgroups per CU: more only lengthens the partial table
     int occ = 0;
-    XTR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(
-        &occ, (const void *)k_hist<DT, MODE, false>, HNT, lds));
+    XTR_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kern, HNT, 0));
     if (occ < 1) occ = 1;
     if (occ > 2) occ = 2;
     int64_t G = (int64_t)occ * cu_count();
@@ -273,8 +361,12 @@ int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_
     int rc = workspace(WS_HIST, st, (size_t)G * (size_t)a.nbins * 4, &ws);
     if (rc) return rc;
     uint32_t *part = static_cast<uint32_t *>(ws);
-    hipLaunchKernelGGL((k_hist<DT, MODE, false>), dim3((unsigned)G), dim3(HNT), lds, st, s, a,
-                       part, (uint64_t *)nullptr);
+    if (runs)
+        hipLaunchKernelGGL((k_hist<DT, MODE, false, true>), dim3((unsigned)G), dim3(HNT), 0, st,
+                           s, a, part, (uint64_t *)nullptr);
+    else
+        hipLaunchKernelGGL((k_hist<DT, MODE, false, !flat>), dim3((unsigned)G), dim3(HNT), 0, st,
+                           s, a, part, (uint64_t *)nullptr);
     hipLaunchKernelGGL(k_hist_merge, dim3((unsigned)((a.nbins + 63) / 64)), dim3(MERGE_NT), 0, st,
                        part, (int)G, a.nbins, counts);
     XTR_HIP(hipGetLastError());
@@ -309,6 +401,16 @@ int dispatch_int(const void *src, int dtype, const HistArgs &a, int64_t *counts,
     }
 }
 
+template <int MODE>
+int dispatch_int32(const void *src, int dtype, const HistArgs &a, int64_t *counts,
+                   hipStream_t st) {
+    switch (dtype) {
+    case XTR_I32: return launch_hist<XTR_I32, MODE>(src, a, counts, st);
+    case XTR_U8: return launch_hist<XTR_U8, MODE>(src, a, counts, st);
+    default: return launch_hist<XTR_U16, MODE>(src, a, counts, st);
+    }
+}
+
 int histogram_int_impl(const void *src, int64_t n, int dtype, int64_t lo, int64_t width,
                        int64_t nbins, int64_t *counts, hipStream_t st) {
     const char *who = "histogram_int";
@@ -325,15 +427,19 @@ int histogram_int_impl(const void *src, int64_t n, int dtype, int64_t lo, int64_
     a.width = (uint64_t)width;
     const unsigned __int128 span = (unsigned __int128)(uint64_t)width * (uint64_t)nbins;
     a.span_m1 = span > ((unsigned __int128)1 << 64) ? ~(uint64_t)0 : (uint64_t)(span - 1);
-    if ((a.width & (a.width - 1)) == 0) {
-        a.shift = __builtin_ctzll(a.width);
-        return dispatch_int<BIN_SHIFT>(src, dtype, a, counts, st);
+    const bool pow2 = (a.width & (a.width - 1)) == 0;
+    const bool small = span <= ((unsigned __int128)1 << 32);
+    if (pow2) a.shift = __builtin_ctzll(a.width);
+    // c = ceil(2^64 / width) = floor((2^64 - 1) / width) + 1 (width is not a power of two)
+    else if (small) a.magic = ~(uint64_t)0 / a.width + 1;
+    if (dtype != XTR_I64 && small && lo >= INT32_MIN && lo <= INT32_MAX) {
+        a.lo32 = (uint32_t)(int32_t)lo ^ 0x80000000u;
+        a.span_m1_32 = (uint32_t)a.span_m1;
+        return pow2 ? dispatch_int32<BIN_SHIFT32>(src, dtype, a, counts, st)
+                    : dispatch_int32<BIN_MAGIC32>(src, dtype, a, counts, st);
     }
-    if (span <= ((unsigned __int128)1 << 32)) {
-        // c = ceil(2^64 / width) = floor((2^64 - 1) / width) + 1 (width is not a power of two)
-        a.magic = ~(uint64_t)0 / a.width + 1;
-        return dispatch_int<BIN_MAGIC>(src, dtype, a, counts, st);
-    }
+    if (pow2) return dispatch_int<BIN_SHIFT>(src, dtype, a, counts, st);
+    if (small) return dispatch_int<BIN_MAGIC>(src, dtype, a, counts, st);
     return dispatch_int<BIN_DIV>(src, dtype, a, counts, st);
 }
 
