@@ -17,6 +17,8 @@ It wraps ``oracle.c`` (plain single-threaded C, built with gcc) through ctypes:
 * ``scan(bits, dtype, excl)``   inclusive / exclusive prefix sums, same arithmetic as the sums.
 * ``histogram_int(...)``        counts in ``nbins`` bins of ``width`` from ``lo`` (exact).
 * ``histogram_float(...)``      counts in ``nbins`` equal bins of [lo, hi), fp64 bin rule.
+* ``matmul(a, b, dtype)``       fp64 C = A @ B (exact products, compensated sums in k order).
+* ``matmul_entries(...)``       sampled entries of the same product.
 
 ``Oracle(path)`` loads any build of ``oracle.c`` (the mutation tests load
 deliberately broken copies to show that the pins catch them).
@@ -88,6 +90,11 @@ class Oracle:
         lib.oracle_histogram_int.restype = C.c_int
         lib.oracle_histogram_float.argtypes = [vp, i64, C.c_int, C.c_double, C.c_double, i64, vp]
         lib.oracle_histogram_float.restype = C.c_int
+        lib.oracle_matmul.argtypes = [vp, vp, vp, i64, i64, i64, i64, i64, i64, C.c_int, C.c_int]
+        lib.oracle_matmul.restype = C.c_int
+        lib.oracle_matmul_entries.argtypes = [vp, vp, i64, i64, i64, i64, i64, C.c_int, C.c_int,
+                                              i64, vp, vp, vp]
+        lib.oracle_matmul_entries.restype = C.c_int
         self.lib = lib
         self.path = path
 
@@ -199,6 +206,44 @@ class Oracle:
             raise ValueError("oracle_histogram_float: bad arguments")
         return out
 
+    # ------------------------------------------------------------ matmul
+    def matmul(self, a: np.ndarray, b: np.ndarray, dtype: str, trans_b: bool = False,
+               M=None, N=None, K=None, lda=None, ldb=None) -> np.ndarray:
+        """fp64 C = A @ B (or A @ B^T with trans_b, B given as N x K) over the
+        raw-bit 2-D arrays a and b of format dtype."""
+        a = np.ascontiguousarray(a)
+        b = np.ascontiguousarray(b)
+        M = a.shape[0] if M is None else M
+        K = a.shape[1] if K is None else K
+        N = (b.shape[0] if trans_b else b.shape[1]) if N is None else N
+        lda = a.shape[1] if lda is None else lda
+        ldb = b.shape[1] if ldb is None else ldb
+        out = np.empty((M, N), dtype=np.float64)
+        if self.lib.oracle_matmul(_ptr(a), _ptr(b), _ptr(out), M, N, K, lda, ldb, N,
+                                  int(bool(trans_b)), CODES[dtype]):
+            raise ValueError("oracle_matmul: bad arguments")
+        return out
+
+    def matmul_entries(self, a: np.ndarray, b: np.ndarray, dtype: str, rows, cols,
+                       trans_b: bool = False, M=None, N=None, K=None, lda=None,
+                       ldb=None) -> np.ndarray:
+        """The entries C[rows[t]][cols[t]] of the product above."""
+        a = np.ascontiguousarray(a)
+        b = np.ascontiguousarray(b)
+        M = a.shape[0] if M is None else M
+        K = a.shape[1] if K is None else K
+        N = (b.shape[0] if trans_b else b.shape[1]) if N is None else N
+        lda = a.shape[1] if lda is None else lda
+        ldb = b.shape[1] if ldb is None else ldb
+        rows = np.ascontiguousarray(rows, dtype=np.int64)
+        cols = np.ascontiguousarray(cols, dtype=np.int64)
+        out = np.empty(rows.size, dtype=np.float64)
+        if self.lib.oracle_matmul_entries(_ptr(a), _ptr(b), M, N, K, lda, ldb,
+                                          int(bool(trans_b)), CODES[dtype], rows.size,
+                                          _ptr(rows), _ptr(cols), _ptr(out)):
+            raise ValueError("oracle_matmul_entries: bad arguments")
+        return out
+
 
 _default: Oracle | None = None
 
@@ -213,7 +258,7 @@ def get() -> Oracle:
 def __getattr__(name):  # module-level convenience: oracle.tpose(...), oracle.sum(...)
     if name in ("tpose", "tpose_batched", "sum_int", "sum_float", "sum", "sum_abs",
                 "sum_plain_f32", "decode", "sum_segmented", "scan", "histogram_int",
-                "histogram_float"):
+                "histogram_float", "matmul", "matmul_entries"):
         return getattr(get(), name)
     raise AttributeError(name)
 

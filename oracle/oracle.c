@@ -46,6 +46,15 @@
  *               nearest, capped at nbins - 1; x outside [lo, hi) and NaN are
  *               not counted.
  *
+ *   matmul      the matrix multiplication case study the conclusion says was
+ *               started: C[i][j] = sum over k of A[i][k] * B[k][j] for row-major
+ *               A (M x K, leading dimension lda) and B (K x N, ldb; or, with
+ *               trans_b, B stored as its N x K transpose).  Every element is
+ *               decoded exactly; each product is exact in fp64 (at most 24-bit
+ *               significands); the K products are summed in k order with
+ *               Neumaier's update, non-finite products by the IEEE rules of the
+ *               exact sum.
+ *
  * The element decoders are written from the format definitions (IEEE 754
  * binary16; bfloat16 = the top half of binary32; OCP 8-bit E4M3 "FN": bias 7,
  * no infinities, S.1111.111 is NaN, largest finite 448).
@@ -330,6 +339,59 @@ int oracle_histogram_float(const void *src, int64_t n, int dtype, double lo, dou
         int64_t b = (int64_t)floor(t);
         if (b > nbins - 1) b = nbins - 1;
         counts[b] += 1;
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------ matmul */
+
+/* One entry C[i][j] = sum_k A[i][k] * B[k][j]: exact products, Neumaier sum in k order. */
+static double mm_entry(const void *a, const void *b, int64_t K, int64_t lda, int64_t ldb,
+                       int trans_b, int dtype, int64_t i, int64_t j) {
+    double s = 0.0, c = 0.0;
+    int nan = 0, pinf = 0, ninf = 0;
+    for (int64_t k = 0; k < K; k++) {
+        const double x = oracle_decode(a, i * lda + k, dtype);
+        const double y = oracle_decode(b, trans_b ? j * ldb + k : k * ldb + j, dtype);
+        const double p = x * y;
+        if (isnan(p)) {
+            nan = 1;
+        } else if (isinf(p)) {
+            if (p > 0) pinf = 1; else ninf = 1;
+        } else {
+            const double t = s + p;
+            if (fabs(s) >= fabs(p)) c += (s - t) + p;
+            else c += (p - t) + s;
+            s = t;
+        }
+    }
+    return (nan || (pinf && ninf)) ? NAN : pinf ? INFINITY : ninf ? -INFINITY : s + c;
+}
+
+static int mm_dtype_ok(int dtype) {
+    return dtype == OR_F32 || dtype == OR_F16 || dtype == OR_BF16 || dtype == OR_F8E4M3;
+}
+
+/* c[i*ldc + j] = C[i][j] for the whole M x N product. */
+int oracle_matmul(const void *a, const void *b, double *c, int64_t M, int64_t N, int64_t K,
+                  int64_t lda, int64_t ldb, int64_t ldc, int trans_b, int dtype) {
+    if (!mm_dtype_ok(dtype) || M < 0 || N < 0 || K < 0 || lda < K || ldc < N ||
+        ldb < (trans_b ? K : N))
+        return -1;
+    for (int64_t i = 0; i < M; i++)
+        for (int64_t j = 0; j < N; j++)
+            c[i * ldc + j] = mm_entry(a, b, K, lda, ldb, trans_b, dtype, i, j);
+    return 0;
+}
+
+/* out[t] = C[rows[t]][cols[t]] for t < count (sampled entries of a large product). */
+int oracle_matmul_entries(const void *a, const void *b, int64_t M, int64_t N, int64_t K,
+                          int64_t lda, int64_t ldb, int trans_b, int dtype, int64_t count,
+                          const int64_t *rows, const int64_t *cols, double *out) {
+    if (!mm_dtype_ok(dtype) || lda < K || ldb < (trans_b ? K : N)) return -1;
+    for (int64_t t = 0; t < count; t++) {
+        if (rows[t] < 0 || rows[t] >= M || cols[t] < 0 || cols[t] >= N) return -1;
+        out[t] = mm_entry(a, b, K, lda, ldb, trans_b, dtype, rows[t], cols[t]);
     }
     return 0;
 }

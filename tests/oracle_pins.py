@@ -389,5 +389,93 @@ PINS_INT = [pin_int_golden, pin_int_closed_forms, pin_int_bruteforce_shuffle, pi
 PINS_FLOAT = [pin_decode_golden, pin_decode_all_codes, pin_float_golden, pin_float_fsum,
               pin_float_closed_forms, pin_float_nonfinite, pin_plain_f32, pin_segmented]
 PINS_SCAN = [pin_scan_int, pin_scan_float]
+# ------------------------------------------------------------------ matmul
+
+def _bf16_values(bits):
+    """Values of bf16 bits by the format definition (the top half of binary32),
+    with numpy only: independent of the oracle's decoder."""
+    return (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def pin_matmul_exact_small(o):
+    """Against exact rational arithmetic (Python fractions) on small random
+    bf16 and fp16 matrices, both layouts of B: within one rounding of the exact
+    product sum."""
+    from fractions import Fraction
+    for dt, M, N, K, seed in (("bf16", 5, 7, 13, 90), ("f16", 6, 3, 17, 91), ("bf16", 1, 1, 40, 92)):
+        a = W.to_bits(np.random.default_rng(seed).standard_normal((M, K)) * 3, dt)
+        b = W.to_bits(np.random.default_rng(seed + 1).standard_normal((K, N)) * 3, dt)
+        av = _bf16_values(a) if dt == "bf16" else a.view(np.float16).astype(np.float64)
+        bv = _bf16_values(b) if dt == "bf16" else b.view(np.float16).astype(np.float64)
+        got = o.matmul(a, b, dt)
+        got_t = o.matmul(a, np.ascontiguousarray(b.T), dt, trans_b=True)
+        assert np.array_equal(got, got_t)
+        for i in range(M):
+            for j in range(N):
+                ex = sum(Fraction(float(av[i, k])) * Fraction(float(bv[k, j])) for k in range(K))
+                assert abs(Fraction(got[i, j]) - ex) <= abs(ex) * Fraction(1, 2 ** 52), (dt, i, j)
+
+
+def pin_matmul_integers(o):
+    """Integer-valued bf16 matrices: every product and sum is exact, so the
+    result equals numpy's int64 matrix product exactly."""
+    rng = np.random.default_rng(93)
+    ai = rng.integers(-16, 17, (33, 70))
+    bi = rng.integers(-16, 17, (70, 21))
+    a = W.to_bits(ai.astype(np.float64), "bf16")
+    b = W.to_bits(bi.astype(np.float64), "bf16")
+    assert np.array_equal(o.matmul(a, b, "bf16"), (ai @ bi).astype(np.float64))
+
+
+def pin_matmul_closed_forms(o):
+    """A[i][k] = i, B[k][j] = j + 1: C[i][j] = i * K * (j + 1).  Identity:
+    A @ I = A.  Cancellation: 2^100 * 1 + 1 * 1 + (-2^100) * 1 = 1, which a
+    plain fp64 sum gets wrong (0)."""
+    M, N, K = 9, 11, 24
+    a = W.to_bits(np.repeat(np.arange(M, dtype=np.float64)[:, None], K, axis=1), "bf16")
+    b = W.to_bits(np.repeat(np.arange(1, N + 1, dtype=np.float64)[None, :], K, axis=0), "bf16")
+    want = np.arange(M)[:, None] * K * np.arange(1, N + 1)[None, :]
+    assert np.array_equal(o.matmul(a, b, "bf16"), want.astype(np.float64))
+    x = W.to_bits(np.random.default_rng(94).standard_normal((6, 8)), "bf16")
+    eye = W.to_bits(np.eye(8), "bf16")
+    assert np.array_equal(o.matmul(x, eye, "bf16"), _bf16_values(x))
+    ca = W.to_bits(np.array([[2.0 ** 100, 1.0, -2.0 ** 100]]), "bf16")
+    cb = W.to_bits(np.ones((3, 1)), "bf16")
+    assert o.matmul(ca, cb, "bf16")[0, 0] == 1.0
+
+
+def pin_matmul_leading_dims_and_entries(o):
+    """Padded leading dimensions give the packed result; sampled entries equal
+    the full product's; B^T storage equals B storage."""
+    rng = np.random.default_rng(95)
+    M, N, K = 13, 10, 29
+    a = W.to_bits(rng.standard_normal((M, K)), "bf16")
+    b = W.to_bits(rng.standard_normal((K, N)), "bf16")
+    full = o.matmul(a, b, "bf16")
+    ap = np.zeros((M, K + 5), np.uint16)
+    ap[:, :K] = a
+    ap[:, K:] = 0x7FC0                                  # NaN padding must never be read
+    bp = np.full((K, N + 3), 0x7FC0, np.uint16)
+    bp[:, :N] = b
+    assert np.array_equal(o.matmul(ap, bp, "bf16", M=M, N=N, K=K, lda=K + 5, ldb=N + 3), full)
+    bt = np.full((N, K + 2), 0x7FC0, np.uint16)
+    bt[:, :K] = b.T
+    assert np.array_equal(o.matmul(a, bt, "bf16", trans_b=True, N=N, ldb=K + 2), full)
+    r = rng.integers(0, M, 20)
+    c = rng.integers(0, N, 20)
+    assert np.array_equal(o.matmul_entries(a, b, "bf16", r, c), full[r, c])
+
+
+def pin_matmul_nonfinite(o):
+    """inf * 0 is NaN; inf + -inf is NaN; one infinite product gives inf."""
+    inf = np.inf
+    a = W.to_bits(np.array([[inf, 1.0], [inf, 1.0], [inf, -inf]]), "f32")
+    b = W.to_bits(np.array([[0.0, 2.0], [1.0, 1.0]]), "f32")
+    got = o.matmul(a, b, "f32")
+    assert np.isnan(got[0, 0]) and got[0, 1] == inf and np.isnan(got[2, 1])
+
+
 PINS_HIST = [pin_histogram_int, pin_histogram_float]
-ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN + PINS_HIST
+PINS_MM = [pin_matmul_exact_small, pin_matmul_integers, pin_matmul_closed_forms,
+           pin_matmul_leading_dims_and_entries, pin_matmul_nonfinite]
+ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN + PINS_HIST + PINS_MM

@@ -59,6 +59,16 @@ MUTANTS = [
      "if (!(x > lo && x < hi)) continue;", P.PINS_HIST),
     ("hist_float_scale_off", "const double scale = (double)nbins / (hi - lo);",
      "const double scale = (double)(nbins - 1) / (hi - lo);", P.PINS_HIST),
+    ("mm_b_transposed", "trans_b ? j * ldb + k : k * ldb + j", "trans_b ? k * ldb + j : j * ldb + k",
+     P.PINS_MM),
+    ("mm_last_k_dropped", "for (int64_t k = 0; k < K; k++) {\n        const double x",
+     "for (int64_t k = 0; k < K - 1; k++) {\n        const double x", P.PINS_MM),
+    ("mm_lda_ignored", "oracle_decode(a, i * lda + k, dtype)", "oracle_decode(a, i * K + k, dtype)",
+     P.PINS_MM),
+    ("mm_uncompensated", "ninf ? -INFINITY : s + c;\n}\n\nstatic int mm_dtype_ok",
+     "ninf ? -INFINITY : s;\n}\n\nstatic int mm_dtype_ok", P.PINS_MM),
+    ("mm_inf_times_zero", "if (isnan(p)) {\n            nan = 1;\n        } else if (isinf(p)) {\n            if (p > 0) pinf = 1; else ninf = 1;\n        } else {\n            const double t",
+     "if (isnan(p)) {\n            (void)p;\n        } else if (isinf(p)) {\n            if (p > 0) pinf = 1; else ninf = 1;\n        } else {\n            const double t", P.PINS_MM),
 ]
 
 
