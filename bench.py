@@ -36,10 +36,17 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# What decides the kernels of the step and their launches: their sources and
+# the tuned launch settings.  Counter summaries are valid for this hash only.
+STEP_SOURCES = ("paper_2605_13864_amd/csrc/common.hpp", "paper_2605_13864_amd/csrc/runtime.hip",
+                "paper_2605_13864_amd/csrc/tpose.hip", "paper_2605_13864_amd/csrc/reduce.hip",
+                "paper_2605_13864_amd/tuned/gfx950.json")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
-    for f in sorted(os.listdir(os.path.join(ROOT, "paper_2605_13864_amd", "csrc"))):
-        with open(os.path.join(ROOT, "paper_2605_13864_amd", "csrc", f), "rb") as fh:
+    for f in STEP_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
             h.update(f.encode() + fh.read())
     return h.hexdigest()[:16]
 
@@ -166,7 +173,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--suite", choices=["step", "full"], default="step")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,serving",
+    ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,matmul,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
     if args.gpus != 1:
