@@ -274,6 +274,33 @@ def histograms(xtr, torch, log, n=1 << 28):
     return res
 
 
+def matmuls(xtr, torch, log):
+    """Matrix products on the matrix cores, TFLOP/s = 2 M N K / time: bf16 and
+    fp16 8192^3 with B given transposed (one launch) and row-major (transpose
+    into the workspace first), bf16 4096^3; torch.matmul (the vendor BLAS)
+    on the same operands for context (fp32 output from bf16 inputs is not a
+    torch op: it writes bf16)."""
+    res = {}
+    gen = torch.Generator("cuda").manual_seed(25)
+    for n, dt, tdt in ((8192, "bf16", torch.bfloat16), (8192, "f16", torch.float16),
+                       (4096, "bf16", torch.bfloat16)):
+        a = torch.randn((n, n), generator=gen, device="cuda").to(tdt)
+        b = torch.randn((n, n), generator=gen, device="cuda").to(tdt)
+        c = torch.empty((n, n), device="cuda")
+        flop = 2.0 * n ** 3
+        for tb in (True, False):
+            sec, _ = _time_dev(torch, lambda: xtr.matmul(a, b, c, trans_b=tb), reps=10, warm=2)
+            res[f"{dt}_{n}_{'nt' if tb else 'nn'}"] = {"tflops": round(flop / sec / 1e12, 1),
+                                                      "us": round(sec * 1e6, 1)}
+        sec, _ = _time_dev(torch, lambda: torch.matmul(a, b), reps=10, warm=2)
+        res[f"{dt}_{n}_torch_nn"] = {"tflops": round(flop / sec / 1e12, 1),
+                                     "us": round(sec * 1e6, 1)}
+        del a, b, c
+    torch.cuda.empty_cache()
+    log("suite matmul: " + ", ".join(f"{k} {v['tflops']} TFLOP/s" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- host buffers
 
 def host_buffers(xtr, torch, log):
@@ -362,10 +389,11 @@ def paper_shapes(xtr, torch, log):
 
 
 def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "precision",
-                                   "host", "scan", "hist", "serving")):
+                                   "host", "scan", "hist", "matmul", "serving")):
     out = {}
     for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
                      ("host", host_buffers), ("scan", prefix_sums), ("hist", histograms),
+                     ("matmul", matmuls),
                      ("segmented", segmented), ("precision", precision)):
         if name in parts:
             t0 = time.time()

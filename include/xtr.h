@@ -226,6 +226,29 @@ int histogram_float(const void *src, int64_t n, int dtype, double lo, double hi,
                     int64_t nbins, int64_t *counts, void *stream);
 
 /* ------------------------------------------------------------------------
+ * matmul -- matrix multiplication on the matrix cores, the case study the
+ * thesis's conclusion says was started (Chapter 9):
+ *
+ *   C[i][j] = sum over k of A[i][k] * B[k][j],   0 <= i < M, 0 <= j < N
+ *
+ * a: device, row-major M x K (leading dimension lda >= K).
+ * b: device, row-major K x N (ldb >= N); with trans_b != 0, B is given as its
+ *    N x K transpose, row-major (ldb >= K).
+ * c: device float[M x N], row-major (ldc >= N), fully overwritten; must not
+ *    overlap a or b.
+ * dtype: BF16 or F16 (both operands).  Products are exact in fp32 and are
+ * summed in fp32 by the matrix cores in k order, so |C - exact| <=
+ * K * 2^-24 * sum_k |A[i][k] B[k][j]|.  K == 0 gives C = 0; M == 0 or N == 0
+ * is a no-op.  With trans_b == 0 the library first transposes B into its
+ * workspace (per stream) with tpose(); with trans_b != 0 the product runs in
+ * one launch.  Asynchronous on `stream`.
+ * Errors: EINVAL, EDTYPE, EALIGN (a, b not 2-byte or c not 4-byte aligned),
+ * EOVERLAP, ENOMEM, EHIP.
+ */
+int matmul(const void *a, const void *b, float *c, int64_t M, int64_t N, int64_t K,
+           int64_t lda, int64_t ldb, int64_t ldc, int trans_b, int dtype, void *stream);
+
+/* ------------------------------------------------------------------------
  * Host buffers: the end-to-end form of the paper's host code (Listing 3.6:
  * copy in, kernel, copy out), for data that lives in host memory.
  *

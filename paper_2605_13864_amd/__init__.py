@@ -82,6 +82,8 @@ _SIGS = {
                        C.c_void_p, C.c_void_p], C.c_int),
     "histogram_float": ([C.c_void_p, C.c_int64, C.c_int, C.c_double, C.c_double, C.c_int64,
                          C.c_void_p, C.c_void_p], C.c_int),
+    "matmul": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_int64, C.c_int64,
+                C.c_int64, C.c_int64, C.c_int, C.c_int, C.c_void_p], C.c_int),
     "xtr_tpose_plan_create": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
     "xtr_tpose_plan_destroy": ([C.c_void_p], C.c_int),
@@ -503,6 +505,33 @@ def histogram_float(src, lo: float, hi: float, nbins: int, counts=None, *, n=Non
                              int(nbins), C.c_void_p(counts.data_ptr()), _stream(stream))
     _check(rc, "histogram_float")
     return counts
+
+
+def matmul(a, b, c=None, *, trans_b=False, M=None, N=None, K=None, lda=None, ldb=None,
+           ldc=None, dtype=None, stream=None):
+    """C (float32, M x N) = A @ B on the matrix cores, for bf16 or fp16 2-D
+    tensors A (M x K) and B (K x N; with trans_b, B given as N x K).  Strides
+    come from the tensors (rows must be contiguous) unless given."""
+    import torch
+    lib = load()
+    dt = dtype or dtype_of(a)
+    M = a.shape[0] if M is None else M
+    K = a.shape[1] if K is None else K
+    N = (b.shape[0] if trans_b else b.shape[1]) if N is None else N
+    if lda is None:
+        assert a.stride(-1) == 1, "rows of A must be contiguous"
+        lda = a.stride(0) if a.dim() == 2 else K
+    if ldb is None:
+        assert b.stride(-1) == 1, "rows of B must be contiguous"
+        ldb = b.stride(0) if b.dim() == 2 else (K if trans_b else N)
+    if c is None:
+        c = torch.empty((M, N), dtype=torch.float32, device=a.device)
+    if ldc is None:
+        ldc = c.stride(0) if c.dim() == 2 else N
+    rc = lib.matmul(C.c_void_p(a.data_ptr()), C.c_void_p(b.data_ptr()), C.c_void_p(c.data_ptr()),
+                    M, N, K, lda, ldb, ldc, int(bool(trans_b)), _code(dt), _stream(stream))
+    _check(rc, "matmul")
+    return c
 
 
 def _host_ptr(a):

@@ -47,7 +47,8 @@ inline bool is_int_sum_dtype(int d) { return d == XTR_I32 || d == XTR_I64; }
 // the stream (the old buffer may still be in use by enqueued work).
 //   WS_SCAN:   tile sums / offsets of the prefix sums (written before read).
 //   WS_HIST:   per-workgroup partial histograms (written before read).
-enum { WS_REDUCE = 0, WS_TABLE = 1, WS_SCAN = 2, WS_HIST = 3, WS_KINDS = 4 };
+//   WS_MM:     the transposed B operand of a matrix product (written before read).
+enum { WS_REDUCE = 0, WS_TABLE = 1, WS_SCAN = 2, WS_HIST = 3, WS_MM = 4, WS_KINDS = 5 };
 int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr, size_t *actual = nullptr);
 
 // Asynchronous host -> device copy of `bytes` from pageable `host` memory:

@@ -1,0 +1,245 @@
+// Matrix multiplication for gfx950 on the matrix cores (MFMA): the case study
+// the thesis's conclusion says was started (its CPU transformations done, no
+// GPU code yet).  The thesis's system has no tensor-core instructions
+// (Section 1.2); this is the first path here that uses them.
+//
+// What is computed: C[i][j] = sum over k of A[i][k] * B[k][j], C in fp32
+// (M x N, leading dimension ldc), A row-major M x K (lda), B row-major K x N
+// (ldb) or, with trans_b, given as its N x K transpose Bt (ldb).  Inputs are
+// bf16 or fp16; every product is exact in fp32 and the products are summed in
+// fp32 by the matrix cores (32x32x16 MFMA blocks, in k order).
+//
+// How:
+//   * The kernel multiplies A by Bt: both operands are k-contiguous, so every
+//     lane's MFMA fragment (8 consecutive k of one row) is one 16-byte LDS
+//     read.  A row-major B is first transposed into a workspace with the
+//     library's own transpose (the thesis's other case study).
+//   * A workgroup of 256 threads (4 waves, 2 x 2) owns a 128 x 128 tile of C;
+//     a wave owns 64 x 64 = 2 x 2 MFMA blocks of 32 x 32, 64 fp32
+//     accumulators per lane.  K advances in blocks of 64: each thread loads
+//     four 16-byte chunks of A and four of Bt for the next block into
+//     registers while the matrix cores work on the current one from LDS, then
+//     stores them into the other of two LDS buffers (one barrier per block).
+//   * LDS rows are padded to 144 bytes, so the 16-byte fragment reads of 16
+//     lanes (16 rows, same column) fall on 16 disjoint groups of 4 banks.
+//   * Tiles are numbered so that the workgroups one XCD runs (the hardware
+//     deals workgroups to the 8 XCDs in turn) are neighbours in groups of 8
+//     tile rows, sharing operand tiles in that XCD's L2.
+#include "common.hpp"
+
+namespace xtr {
+namespace {
+
+constexpr int MM_NT = 256;          // threads per workgroup
+constexpr int BM = 128, BN = 128;   // workgroup tile of C
+constexpr int BK = 64;              // k per LDS block
+constexpr int LROW = BK + 8;        // LDS row in elements (144 bytes)
+constexpr int GROUP_M = 8;          // tile rows per group of the tile order
+constexpr int NXCD = 8;
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef uint32_t mu32x4 __attribute__((ext_vector_type(4)));
+
+template <int DT> __device__ __forceinline__ f32x16 mfma(const mu32x4 &a, const mu32x4 &b,
+                                                         const f32x16 &c) {
+    if constexpr (DT == XTR_BF16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                       __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                      __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
+
+// Chunk q (0..3) of this thread in a 128 x 64 operand block: row = c / 8,
+// 8-element column chunk = c % 8, c = t + 256 q.
+// VEC: rows are 16-byte aligned and K % 8 == 0, so a chunk is one 16-byte load
+// (all or nothing); otherwise element by element.  Out-of-range elements are 0.
+template <bool VEC>
+__device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64_t ld,
+                                           int64_t rows_left, int64_t k0, int64_t K, int t,
+                                           mu32x4 (&r)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int c = t + MM_NT * q;
+        const int row = c >> 3;
+        const int64_t k = k0 + (c & 7) * 8;
+        if constexpr (VEC) {
+            r[q] = mu32x4{0, 0, 0, 0};
+            if (row < rows_left && k < K)
+                r[q] = *reinterpret_cast<const mu32x4 *>(p + (int64_t)row * ld + k);
+        } else {
+            uint32_t w[4] = {0, 0, 0, 0};
+            if (row < rows_left) {
+                const uint16_t *s = p + (int64_t)row * ld;
+#pragma unroll
+                for (int e = 0; e < 8; e++)
+                    if (k + e < K) w[e >> 1] |= (uint32_t)s[k + e] << (16 * (e & 1));
+            }
+            r[q] = mu32x4{w[0], w[1], w[2], w[3]};
+        }
+    }
+}
+
+__device__ __forceinline__ void store_block(uint16_t *lds, int t, const mu32x4 (&r)[4]) {
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int c = t + MM_NT * q;
+        *reinterpret_cast<mu32x4 *>(lds + (c >> 3) * LROW + (c & 7) * 8) = r[q];
+    }
+}
+
+// The tile (tm, tn) workgroup b computes.
+__device__ __forceinline__ void tile_of(int64_t b, int64_t nb, int64_t tiles_m, int64_t tiles_n,
+                                        int64_t &tm, int64_t &tn) {
+    // workgroups b, b + 8, b + 16, ... run on one XCD: give them consecutive ids
+    int64_t id = b;
+    if (nb % NXCD == 0) id = (b % NXCD) * (nb / NXCD) + b / NXCD;
+    // groups of GROUP_M tile rows, column-major inside a group
+    const int64_t per_group = (int64_t)GROUP_M * tiles_n;
+    const int64_t g = id / per_group;
+    const int64_t first = g * GROUP_M;
+    const int64_t gm = (tiles_m - first) < GROUP_M ? (tiles_m - first) : GROUP_M;
+    const int64_t in = id - g * per_group;
+    tm = first + in % gm;
+    tn = in / gm;
+}
+
+template <int DT, bool VEC>
+__global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A,
+                                                  const uint16_t *__restrict__ Bt,
+                                                  float *__restrict__ C, int64_t M, int64_t N,
+                                                  int64_t K, int64_t lda, int64_t ldb,
+                                                  int64_t ldc, int64_t tiles_m, int64_t tiles_n) {
+    __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * LROW];
+    __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * LROW];
+    const int t = threadIdx.x, l = t & 63, w = t >> 6;
+    const int wr = w >> 1, wc = w & 1;
+    int64_t tm, tn;
+    tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const uint16_t *pa = A + m0 * lda;
+    const uint16_t *pb = Bt + n0 * ldb;
+    const int64_t ma = M - m0, nbl = N - n0;
+
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) acc[i][j] = f32x16{};
+
+    const int64_t nk = (K + BK - 1) / BK;
+    mu32x4 ra[4], rb[4];
+    if (nk > 0) {
+        load_block<VEC>(pa, lda, ma, 0, K, t, ra);
+        load_block<VEC>(pb, ldb, nbl, 0, K, t, rb);
+        store_block(sa[0], t, ra);
+        store_block(sb[0], t, rb);
+    }
+    __syncthreads();
+    // lane l's fragment: row l % 32 of a 32-row block, k chunk l / 32 of a 16-k step
+    const int fr = l & 31, fk = (l >> 5) * 8;
+    for (int64_t kb = 0; kb < nk; kb++) {
+        const int cur = kb & 1;
+        const bool more = kb + 1 < nk;
+        if (more) {
+            load_block<VEC>(pa, lda, ma, (kb + 1) * BK, K, t, ra);
+            load_block<VEC>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb);
+        }
+        const uint16_t *la = sa[cur] + (wr * 64 + fr) * LROW + fk;
+        const uint16_t *lb = sb[cur] + (wc * 64 + fr) * LROW + fk;
+#pragma unroll
+        for (int ks = 0; ks < BK / 16; ks++) {
+            mu32x4 fa[2], fb[2];
+#pragma unroll
+            for (int i = 0; i < 2; i++) {
+                fa[i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * LROW + ks * 16);
+                fb[i] = *reinterpret_cast<const mu32x4 *>(lb + i * 32 * LROW + ks * 16);
+            }
+#pragma unroll
+            for (int i = 0; i < 2; i++)
+#pragma unroll
+                for (int j = 0; j < 2; j++) acc[i][j] = mfma<DT>(fa[i], fb[j], acc[i][j]);
+        }
+        if (more) {
+            store_block(sa[cur ^ 1], t, ra);
+            store_block(sb[cur ^ 1], t, rb);
+        }
+        __syncthreads();
+    }
+    // accumulator v of block (i, j): row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
+#pragma unroll
+    for (int i = 0; i < 2; i++)
+#pragma unroll
+        for (int j = 0; j < 2; j++) {
+            const int64_t col = n0 + wc * 64 + j * 32 + (l & 31);
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int64_t row = m0 + wr * 64 + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+                if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
+            }
+        }
+}
+
+int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, int64_t K,
+                int64_t lda, int64_t ldb, int64_t ldc, int trans_b, int dtype, hipStream_t st) {
+    const char *who = "matmul";
+    if (dtype != XTR_BF16 && dtype != XTR_F16)
+        return fail(XTR_EDTYPE, "%s: dtype %d is not bf16 or fp16", who, dtype);
+    if (M < 0 || N < 0 || K < 0) return fail(XTR_EINVAL, "%s: negative size", who);
+    if (lda < K || ldc < N || ldb < (trans_b ? K : N))
+        return fail(XTR_EINVAL, "%s: leading dimension smaller than its row", who);
+    if (M == 0 || N == 0) return XTR_OK;
+    if (!c || (K > 0 && (!a || !b))) return fail(XTR_EINVAL, "%s: null pointer", who);
+    if ((uintptr_t)a % 2 || (uintptr_t)b % 2 || (uintptr_t)c % 4)
+        return fail(XTR_EALIGN, "%s: pointer not aligned to its element", who);
+    const uintptr_t c0 = (uintptr_t)c, c1 = c0 + (uintptr_t)((M - 1) * ldc + N) * 4;
+    if (K > 0) {
+        const uintptr_t a0 = (uintptr_t)a, a1 = a0 + (uintptr_t)((M - 1) * lda + K) * 2;
+        const int64_t brows = trans_b ? N : K, bcols = trans_b ? K : N;
+        const uintptr_t b0 = (uintptr_t)b, b1 = b0 + (uintptr_t)((brows - 1) * ldb + bcols) * 2;
+        if ((a0 < c1 && c0 < a1) || (b0 < c1 && c0 < b1))
+            return fail(XTR_EOVERLAP, "%s: C overlaps an operand", who);
+    }
+    const uint16_t *bt = static_cast<const uint16_t *>(b);
+    int64_t ldbt = ldb;
+    if (!trans_b && K > 0) {
+        // Bt = B^T (N x K) in the workspace, rows padded to 8 elements
+        ldbt = (K + 7) / 8 * 8;
+        void *ws = nullptr;
+        int rc = workspace(WS_MM, st, (size_t)N * (size_t)ldbt * 2, &ws);
+        if (rc) return rc;
+        rc = tpose(b, ws, K, N, ldb, ldbt, dtype, st);
+        if (rc) return rc;
+        bt = static_cast<const uint16_t *>(ws);
+    }
+    const bool vec = K % 8 == 0 && lda % 8 == 0 && ldbt % 8 == 0 && (uintptr_t)a % 16 == 0 &&
+                     (uintptr_t)bt % 16 == 0;
+    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    const int64_t nb = tiles_m * tiles_n;
+    if (nb > 0x7fffffff) return fail(XTR_EINVAL, "%s: too many tiles", who);
+    const uint16_t *pa = static_cast<const uint16_t *>(a);
+#define XTR_MM(D, V)                                                                          \
+    hipLaunchKernelGGL((k_matmul<D, V>), dim3((unsigned)nb), dim3(MM_NT), 0, st, pa, bt, c, M, N, \
+                       K, lda, ldbt, ldc, tiles_m, tiles_n)
+    if (dtype == XTR_BF16) {
+        if (vec) XTR_MM(XTR_BF16, true);
+        else XTR_MM(XTR_BF16, false);
+    } else {
+        if (vec) XTR_MM(XTR_F16, true);
+        else XTR_MM(XTR_F16, false);
+    }
+#undef XTR_MM
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+}  // namespace
+}  // namespace xtr
+
+extern "C" int matmul(const void *a, const void *b, float *c, int64_t M, int64_t N, int64_t K,
+                      int64_t lda, int64_t ldb, int64_t ldc, int trans_b, int dtype,
+                      void *stream) {
+    return xtr::matmul_impl(a, b, c, M, N, K, lda, ldb, ldc, trans_b, dtype, (hipStream_t)stream);
+}

@@ -177,3 +177,26 @@ def test_histogram_rejects_int8_without_dtype():
     import torch
     with pytest.raises(TypeError):
         X.histogram_int(torch.zeros(4, dtype=torch.int8), 0, 1, 4)
+
+
+@pytest.mark.parametrize("args,code", [
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31), 4, 4, 4, 4, 4, 4, 0, 0), -2),   # f32 operands
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31), -1, 4, 4, 4, 4, 4, 0, 2), -1),  # negative M
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31), 4, 4, 8, 7, 4, 4, 0, 2), -1),   # lda < K
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31), 4, 4, 8, 8, 4, 4, 1, 2), -1),   # ldb < K (Bt)
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31), 4, 6, 8, 8, 6, 5, 0, 2), -1),   # ldc < N
+    ((0, FAKE + (1 << 30), FAKE + (1 << 31), 4, 4, 4, 4, 4, 4, 0, 2), -1),      # null a
+    ((FAKE + 1, FAKE + (1 << 30), FAKE + (1 << 31), 4, 4, 4, 4, 4, 4, 0, 2), -4),  # odd a
+    ((FAKE, FAKE + (1 << 30), FAKE + (1 << 31) + 2, 4, 4, 4, 4, 4, 4, 0, 2), -4),  # c not 4-aligned
+    ((FAKE, FAKE + (1 << 30), FAKE + 8, 4, 4, 4, 4, 4, 4, 0, 2), -3),           # c overlaps a
+])
+def test_matmul_rejects(lib, args, code):
+    a, b, c, M, N, K, lda, ldb, ldc, tb, dt = args
+    assert lib.matmul(C.c_void_p(a), C.c_void_p(b), C.c_void_p(c), M, N, K, lda, ldb, ldc, tb, dt,
+                      None) == code
+    assert lib.xtr_last_error()
+
+
+def test_matmul_empty_is_noop(lib):
+    assert lib.matmul(None, None, C.c_void_p(FAKE), 0, 4, 4, 4, 4, 4, 0, 2, None) == 0
+    assert lib.matmul(None, None, C.c_void_p(FAKE), 4, 0, 4, 4, 4, 4, 0, 2, None) == 0
