@@ -31,7 +31,6 @@ namespace xtr {
 namespace {
 
 constexpr int MM_NT = 256;          // threads per workgroup
-constexpr int BM = 128, BN = 128;   // workgroup tile of C
 constexpr int BK = 64;              // k per LDS block
 constexpr int LROW = BK + 8;        // LDS row in elements (144 bytes)
 constexpr int GROUP_M = 8;          // tile rows per group of the tile order
@@ -52,24 +51,29 @@ template <int DT> __device__ __forceinline__ f32x16 mfma(const mu32x4 &a, const 
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-// Chunk q (0..3) of this thread in a 128 x 64 operand block: row = c / 8,
+// Chunk q (0..Q-1) of this thread in a (32 Q) x 64 operand block: row = c / 8,
 // 8-element column chunk = c % 8, c = t + 256 q.
 // VEC: rows are 16-byte aligned and K % 8 == 0, so a chunk is one 16-byte load
 // (all or nothing); otherwise element by element.  Out-of-range elements are 0.
-template <bool VEC>
+template <bool VEC, int Q>
 __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64_t ld,
                                            int64_t rows_left, int64_t k0, int64_t K, int t,
-                                           mu32x4 (&r)[4]) {
+                                           mu32x4 (&r)[Q], bool (&in)[Q]) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < Q; q++) {
         const int c = t + MM_NT * q;
         const int row = c >> 3;
         const int64_t k = k0 + (c & 7) * 8;
         if constexpr (VEC) {
-            r[q] = mu32x4{0, 0, 0, 0};
-            if (row < rows_left && k < K)
-                r[q] = *reinterpret_cast<const mu32x4 *>(p + (int64_t)row * ld + k);
+            // branch-free: always load from a clamped, valid address, then zero
+            // what lies outside the operand (rows_left >= 1, K >= 8 here)
+            // (the zeroing waits for the store, so that the loads overlap the MFMAs)
+            in[q] = row < rows_left && k < K;
+            const int64_t rr = row < rows_left ? row : rows_left - 1;
+            const int64_t kk = k < K ? k : K - 8;
+            r[q] = *reinterpret_cast<const mu32x4 *>(p + rr * ld + kk);
         } else {
+            in[q] = true;
             uint32_t w[4] = {0, 0, 0, 0};
             if (row < rows_left) {
                 const uint16_t *s = p + (int64_t)row * ld;
@@ -82,11 +86,14 @@ __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64
     }
 }
 
-__device__ __forceinline__ void store_block(uint16_t *lds, int t, const mu32x4 (&r)[4]) {
+template <int Q>
+__device__ __forceinline__ void store_block(uint16_t *lds, int t, const mu32x4 (&r)[Q],
+                                            const bool (&in)[Q]) {
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
+    for (int q = 0; q < Q; q++) {
         const int c = t + MM_NT * q;
-        *reinterpret_cast<mu32x4 *>(lds + (c >> 3) * LROW + (c & 7) * 8) = r[q];
+        *reinterpret_cast<mu32x4 *>(lds + (c >> 3) * LROW + (c & 7) * 8) =
+            in[q] ? r[q] : mu32x4{0, 0, 0, 0};
     }
 }
 
@@ -106,12 +113,15 @@ __device__ __forceinline__ void tile_of(int64_t b, int64_t nb, int64_t tiles_m, 
     tn = in / gm;
 }
 
-template <int DT, bool VEC>
+// One workgroup: 2 x 2 waves, each owning TM x TN MFMA blocks of 32 x 32, so
+// the workgroup tile is BM x BN = 64 TM x 64 TN.
+template <int DT, bool VEC, int TM, int TN>
 __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A,
                                                   const uint16_t *__restrict__ Bt,
                                                   float *__restrict__ C, int64_t M, int64_t N,
                                                   int64_t K, int64_t lda, int64_t ldb,
                                                   int64_t ldc, int64_t tiles_m, int64_t tiles_n) {
+    constexpr int BM = 64 * TM, BN = 64 * TN, QA = BM / 32, QB = BN / 32;
     __shared__ __attribute__((aligned(16))) uint16_t sa[2][BM * LROW];
     __shared__ __attribute__((aligned(16))) uint16_t sb[2][BN * LROW];
     const int t = threadIdx.x, l = t & 63, w = t >> 6;
@@ -123,19 +133,20 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
     const uint16_t *pb = Bt + n0 * ldb;
     const int64_t ma = M - m0, nbl = N - n0;
 
-    f32x16 acc[2][2];
+    f32x16 acc[TM][TN];
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < TM; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) acc[i][j] = f32x16{};
+        for (int j = 0; j < TN; j++) acc[i][j] = f32x16{};
 
     const int64_t nk = (K + BK - 1) / BK;
-    mu32x4 ra[4], rb[4];
+    mu32x4 ra[QA], rb[QB];
+    bool ia[QA], ib[QB];
     if (nk > 0) {
-        load_block<VEC>(pa, lda, ma, 0, K, t, ra);
-        load_block<VEC>(pb, ldb, nbl, 0, K, t, rb);
-        store_block(sa[0], t, ra);
-        store_block(sb[0], t, rb);
+        load_block<VEC, QA>(pa, lda, ma, 0, K, t, ra, ia);
+        load_block<VEC, QB>(pb, ldb, nbl, 0, K, t, rb, ib);
+        store_block<QA>(sa[0], t, ra, ia);
+        store_block<QB>(sb[0], t, rb, ib);
     }
     __syncthreads();
     // lane l's fragment: row l % 32 of a 32-row block, k chunk l / 32 of a 16-k step
@@ -144,39 +155,53 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
         const int cur = kb & 1;
         const bool more = kb + 1 < nk;
         if (more) {
-            load_block<VEC>(pa, lda, ma, (kb + 1) * BK, K, t, ra);
-            load_block<VEC>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb);
+            load_block<VEC, QA>(pa, lda, ma, (kb + 1) * BK, K, t, ra, ia);
+            load_block<VEC, QB>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb, ib);
         }
-        const uint16_t *la = sa[cur] + (wr * 64 + fr) * LROW + fk;
-        const uint16_t *lb = sb[cur] + (wc * 64 + fr) * LROW + fk;
+        const uint16_t *la = sa[cur] + (wr * 32 * TM + fr) * LROW + fk;
+        const uint16_t *lb = sb[cur] + (wc * 32 * TN + fr) * LROW + fk;
+        // fragments of step ks + 1 are read while the MFMAs of step ks run; the
+        // next block's LDS stores go to the other buffer (last read before the
+        // previous barrier) half way through
+        mu32x4 fa[2][TM], fb[2][TN];
+#pragma unroll
+        for (int i = 0; i < TM; i++) fa[0][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * LROW);
+#pragma unroll
+        for (int j = 0; j < TN; j++) fb[0][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * LROW);
 #pragma unroll
         for (int ks = 0; ks < BK / 16; ks++) {
-            mu32x4 fa[2], fb[2];
+            const int c = ks & 1;
+            if (ks + 1 < BK / 16) {
 #pragma unroll
-            for (int i = 0; i < 2; i++) {
-                fa[i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * LROW + ks * 16);
-                fb[i] = *reinterpret_cast<const mu32x4 *>(lb + i * 32 * LROW + ks * 16);
+                for (int i = 0; i < TM; i++)
+                    fa[c ^ 1][i] =
+                        *reinterpret_cast<const mu32x4 *>(la + i * 32 * LROW + (ks + 1) * 16);
+#pragma unroll
+                for (int j = 0; j < TN; j++)
+                    fb[c ^ 1][j] =
+                        *reinterpret_cast<const mu32x4 *>(lb + j * 32 * LROW + (ks + 1) * 16);
             }
 #pragma unroll
-            for (int i = 0; i < 2; i++)
+            for (int i = 0; i < TM; i++)
 #pragma unroll
-                for (int j = 0; j < 2; j++) acc[i][j] = mfma<DT>(fa[i], fb[j], acc[i][j]);
-        }
-        if (more) {
-            store_block(sa[cur ^ 1], t, ra);
-            store_block(sb[cur ^ 1], t, rb);
+                for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[c][i], fb[c][j], acc[i][j]);
+            if (ks == 1 && more) {
+                store_block<QA>(sa[cur ^ 1], t, ra, ia);
+                store_block<QB>(sb[cur ^ 1], t, rb, ib);
+            }
         }
         __syncthreads();
     }
     // accumulator v of block (i, j): row 8 (v / 4) + 4 (l / 32) + v % 4, column l % 32
 #pragma unroll
-    for (int i = 0; i < 2; i++)
+    for (int i = 0; i < TM; i++)
 #pragma unroll
-        for (int j = 0; j < 2; j++) {
-            const int64_t col = n0 + wc * 64 + j * 32 + (l & 31);
+        for (int j = 0; j < TN; j++) {
+            const int64_t col = n0 + wc * 32 * TN + j * 32 + (l & 31);
 #pragma unroll
             for (int v = 0; v < 16; v++) {
-                const int64_t row = m0 + wr * 64 + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+                const int64_t row =
+                    m0 + wr * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
                 if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
             }
         }
@@ -216,19 +241,26 @@ int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, in
     }
     const bool vec = K % 8 == 0 && lda % 8 == 0 && ldbt % 8 == 0 && (uintptr_t)a % 16 == 0 &&
                      (uintptr_t)bt % 16 == 0;
-    const int64_t tiles_m = (M + BM - 1) / BM, tiles_n = (N + BN - 1) / BN;
+    // 256 x 256 tiles (a wave owns 128 x 128: half the LDS reads per MFMA) once
+    // they fill the GPU; 128 x 128 otherwise
+    const int64_t big_tiles = ((M + 255) / 256) * ((N + 255) / 256);
+    const bool big = vec && big_tiles >= cu_count();
+    const int64_t bm = big ? 256 : 128;
+    const int64_t tiles_m = (M + bm - 1) / bm, tiles_n = (N + bm - 1) / bm;
     const int64_t nb = tiles_m * tiles_n;
     if (nb > 0x7fffffff) return fail(XTR_EINVAL, "%s: too many tiles", who);
     const uint16_t *pa = static_cast<const uint16_t *>(a);
-#define XTR_MM(D, V)                                                                          \
-    hipLaunchKernelGGL((k_matmul<D, V>), dim3((unsigned)nb), dim3(MM_NT), 0, st, pa, bt, c, M, N, \
-                       K, lda, ldbt, ldc, tiles_m, tiles_n)
+#define XTR_MM(D, V, T)                                                                       \
+    hipLaunchKernelGGL((k_matmul<D, V, T, T>), dim3((unsigned)nb), dim3(MM_NT), 0, st, pa, bt, c, \
+                       M, N, K, lda, ldbt, ldc, tiles_m, tiles_n)
     if (dtype == XTR_BF16) {
-        if (vec) XTR_MM(XTR_BF16, true);
-        else XTR_MM(XTR_BF16, false);
+        if (big) XTR_MM(XTR_BF16, true, 4);
+        else if (vec) XTR_MM(XTR_BF16, true, 2);
+        else XTR_MM(XTR_BF16, false, 2);
     } else {
-        if (vec) XTR_MM(XTR_F16, true);
-        else XTR_MM(XTR_F16, false);
+        if (big) XTR_MM(XTR_F16, true, 4);
+        else if (vec) XTR_MM(XTR_F16, true, 2);
+        else XTR_MM(XTR_F16, false, 2);
     }
 #undef XTR_MM
     XTR_HIP(hipGetLastError());

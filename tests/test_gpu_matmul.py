@@ -103,6 +103,27 @@ def test_nan_propagates(xtr, orc):
 
 
 @pytest.mark.parametrize("trans_b", [False, True])
+def test_large_tiles_ragged(xtr, orc, trans_b):
+    """A product big enough for the 256 x 256 workgroup tiles, with M, N and K
+    not multiples of the tile: 3000 sampled entries, every edge row and column
+    among them, against the oracle."""
+    M, N, K = 4100, 4000, 200
+    a, b = operands(M, N, K, "bf16", 845, trans_b)
+    got = gpu_mm(xtr, a, b, "bf16", trans_b)
+    rng = np.random.default_rng(846)
+    edge_r = np.concatenate([np.arange(M - 4, M), np.arange(4096 - 2, 4096 + 2)])
+    edge_c = np.concatenate([np.arange(N - 4, N), np.arange(3840 - 2, 3840 + 2)])
+    rows = np.concatenate([rng.integers(0, M, 2000), np.repeat(edge_r, 64),
+                           rng.integers(0, M, edge_c.size * 64)])
+    cols = np.concatenate([rng.integers(0, N, 2000), rng.integers(0, N, edge_r.size * 64),
+                           np.repeat(edge_c, 64)])
+    ref = orc.matmul_entries(a, b, "bf16", rows, cols, trans_b=trans_b)
+    absref = orc.matmul_entries(a & SIGN, b & SIGN, "bf16", rows, cols, trans_b=trans_b)
+    err = np.abs(got[rows, cols].astype(np.float64) - ref)
+    assert (err <= K * 2.0 ** -24 * absref + 1e-30).all(), err.max()
+
+
+@pytest.mark.parametrize("trans_b", [False, True])
 def test_full_size_sampled(xtr, orc, trans_b):
     """8192 x 8192 x 8192 bf16 (the benchmark's product): 256 sampled entries
     against the oracle, one by one."""
