@@ -51,6 +51,10 @@ template <int DT> __device__ __forceinline__ f32x16 mfma(const mu32x4 &a, const 
                                                       __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
+// 16 zero bytes: the source of every operand chunk outside the matrix, so that
+// edge chunks need no select after their load (which would wait for it).
+__device__ __attribute__((aligned(16))) uint32_t g_mm_zero[4];
+
 // Chunk q (0..Q-1) of this thread in a (32 Q) x 64 operand block: row = c / 8,
 // 8-element column chunk = c % 8, c = t + 256 q.
 // VEC: rows are 16-byte aligned and K % 8 == 0, so a chunk is one 16-byte load
@@ -65,13 +69,12 @@ __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64
         const int row = c >> 3;
         const int64_t k = k0 + (c & 7) * 8;
         if constexpr (VEC) {
-            // branch-free: always load from a clamped, valid address, then zero
-            // what lies outside the operand (rows_left >= 1, K >= 8 here)
-            // (the zeroing waits for the store, so that the loads overlap the MFMAs)
-            in[q] = row < rows_left && k < K;
-            const int64_t rr = row < rows_left ? row : rows_left - 1;
-            const int64_t kk = k < K ? k : K - 8;
-            r[q] = *reinterpret_cast<const mu32x4 *>(p + rr * ld + kk);
+            // branch-free: a chunk outside the operand loads the zero chunk
+            in[q] = true;
+            const bool ok = row < rows_left && k < K;
+            const mu32x4 *src = ok ? reinterpret_cast<const mu32x4 *>(p + (int64_t)row * ld + k)
+                                   : reinterpret_cast<const mu32x4 *>(g_mm_zero);
+            r[q] = *src;
         } else {
             in[q] = true;
             uint32_t w[4] = {0, 0, 0, 0};
@@ -153,16 +156,16 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
     const int fr = l & 31, fk = (l >> 5) * 8;
     for (int64_t kb = 0; kb < nk; kb++) {
         const int cur = kb & 1;
-        const bool more = kb + 1 < nk;
-        if (more) {
-            load_block<VEC, QA>(pa, lda, ma, (kb + 1) * BK, K, t, ra, ia);
-            load_block<VEC, QB>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb, ib);
-        }
+        // The body is one basic block (the last block's loads of the block
+        // after it read clamped, valid addresses and land in the unused buffer),
+        // so the schedule below can interleave it.
+        load_block<VEC, QA>(pa, lda, ma, (kb + 1) * BK, K, t, ra, ia);
+        load_block<VEC, QB>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb, ib);
         const uint16_t *la = sa[cur] + (wr * 32 * TM + fr) * LROW + fk;
         const uint16_t *lb = sb[cur] + (wc * 32 * TN + fr) * LROW + fk;
         // fragments of step ks + 1 are read while the MFMAs of step ks run; the
         // next block's LDS stores go to the other buffer (last read before the
-        // previous barrier) half way through
+        // previous barrier) in the second half
         mu32x4 fa[2][TM], fb[2][TN];
 #pragma unroll
         for (int i = 0; i < TM; i++) fa[0][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * LROW);
@@ -185,9 +188,38 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
             for (int i = 0; i < TM; i++)
 #pragma unroll
                 for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[c][i], fb[c][j], acc[i][j]);
-            if (ks == 1 && more) {
-                store_block<QA>(sa[cur ^ 1], t, ra, ia);
-                store_block<QB>(sb[cur ^ 1], t, rb, ib);
+            if (ks == 2) store_block<QA>(sa[cur ^ 1], t, ra, ia);
+            if (ks == 3) store_block<QB>(sb[cur ^ 1], t, rb, ib);
+        }
+        if constexpr (TM == 4 && TN == 4 && QA == 8 && QB == 8) {
+            // order: step 0's fragments; step 0's MFMAs with the 16 global loads
+            // and step 1's fragments; step 1 with step 2's fragments; steps 2
+            // and 3 with the 16 LDS stores (and step 3's fragments)
+            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+            }
+#pragma unroll
+            for (int q = 0; q < 8; q++) {
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
+                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             }
         }
         __syncthreads();
