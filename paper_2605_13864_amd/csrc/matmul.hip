@@ -239,6 +239,165 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
         }
 }
 
+typedef __attribute__((address_space(3))) void lds_void;
+typedef __attribute__((address_space(1))) void global_void;
+
+// The large-tile kernel with direct global -> LDS loads: each load instruction
+// moves 64 lanes x 16 bytes from global memory straight into 1 KiB of LDS (8
+// rows of the 128-byte k block), with no register staging and no LDS store
+// instructions.  Rows are not padded; instead chunk c of row r sits in slot
+// c ^ (r % 8), so the 8 lanes an LDS pass serves (8 consecutive rows, one
+// chunk) hit 8 different 16-byte bank groups.  Lane i of a load instruction
+// fills slot i % 8 of row i / 8 and therefore fetches chunk (i % 8) ^ (i / 8).
+// One k block of the direct kernel: the MFMAs on buffers (xa, xb) while the
+// next block's loads fill (ya, yb).  Distinct LDS arrays per buffer let the
+// compiler see that the reads of one buffer do not wait for the loads into the
+// other.
+template <int DT, int TM, int TN>
+__device__ __forceinline__ void direct_block(
+    f32x16 (&acc)[TM][TN], const uint16_t *xa, const uint16_t *xb, uint16_t *ya, uint16_t *yb,
+    const uint16_t *pa, const uint16_t *pb, int64_t lda, int64_t ldb, int64_t ma, int64_t nbl,
+    int64_t knext, int64_t K, int w, int lrow, int lchunk, int wr, int wc, int fr, int fh, int sw) {
+    // the next block (knext >= K: only zero chunks)
+    const int64_t k = knext + lchunk * 8;
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        const int row = w * 64 + q * 8 + lrow;
+        const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
+                                             : (const void *)g_mm_zero;
+        __builtin_amdgcn_global_load_lds((global_void *)ga, (lds_void *)(ya + (w * 64 + q * 8) * BK),
+                                         16, 0, 0);
+        const void *gb = (row < nbl && k < K) ? (const void *)(pb + (int64_t)row * ldb + k)
+                                              : (const void *)g_mm_zero;
+        __builtin_amdgcn_global_load_lds((global_void *)gb, (lds_void *)(yb + (w * 64 + q * 8) * BK),
+                                         16, 0, 0);
+    }
+    const uint16_t *la = xa + (wr * 32 * TM + fr) * BK;
+    const uint16_t *lb = xb + (wc * 32 * TN + fr) * BK;
+    mu32x4 fa[2][TM], fb[2][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+        fa[0][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * BK + ((fh ^ sw) << 3));
+#pragma unroll
+    for (int j = 0; j < TN; j++)
+        fb[0][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * BK + ((fh ^ sw) << 3));
+#pragma unroll
+    for (int ks = 0; ks < BK / 16; ks++) {
+        const int c = ks & 1;
+        if (ks + 1 < BK / 16) {
+            const int slot = ((2 * (ks + 1) + fh) ^ sw) << 3;
+#pragma unroll
+            for (int i = 0; i < TM; i++)
+                fa[c ^ 1][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * BK + slot);
+#pragma unroll
+            for (int j = 0; j < TN; j++)
+                fb[c ^ 1][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * BK + slot);
+        }
+#pragma unroll
+        for (int i = 0; i < TM; i++)
+#pragma unroll
+            for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[c][i], fb[c][j], acc[i][j]);
+    }
+    // order: step 0's fragments; step 0's MFMAs with the 16 loads and step 1's
+    // fragments; steps 1 and 2 with the fragments of the step after; step 3
+    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+#pragma unroll
+    for (int q = 0; q < 8; q++) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+#pragma unroll
+    for (int r = 0; r < 2; r++)
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+        }
+    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads are in LDS
+    __syncthreads();
+}
+
+// The large-tile kernel with direct global -> LDS loads: each load instruction
+// moves 64 lanes x 16 bytes from global memory straight into 1 KiB of LDS (8
+// rows of the 128-byte k block), with no register staging and no LDS store
+// instructions.  Rows are not padded; instead chunk c of row r sits in slot
+// c ^ (r % 8), so the 8 lanes an LDS pass serves (8 consecutive rows, one
+// chunk) hit 8 different 16-byte bank groups.  Lane i of a load instruction
+// fills slot i % 8 of row i / 8 and therefore fetches chunk (i % 8) ^ (i / 8).
+template <int DT>
+__global__ __launch_bounds__(MM_NT) void k_matmul_direct(const uint16_t *__restrict__ A,
+                                                         const uint16_t *__restrict__ Bt,
+                                                         float *__restrict__ C, int64_t M,
+                                                         int64_t N, int64_t K, int64_t lda,
+                                                         int64_t ldb, int64_t ldc,
+                                                         int64_t tiles_m, int64_t tiles_n) {
+    constexpr int TM = 4, TN = 4, BM = 256, BN = 256;
+    __shared__ __attribute__((aligned(1024))) uint16_t sa0[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb0[BN * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sa1[BM * BK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb1[BN * BK];
+    const int t = threadIdx.x, l = t & 63;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wr = w >> 1, wc = w & 1;
+    int64_t tm, tn;
+    tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
+    const int64_t m0 = tm * BM, n0 = tn * BN;
+    const uint16_t *pa = A + m0 * lda;
+    const uint16_t *pb = Bt + n0 * ldb;
+    const int64_t ma = M - m0, nbl = N - n0;
+
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) acc[i][j] = f32x16{};
+
+    // this lane's part of the wave's 8 load instructions per operand: rows
+    // w * 64 + 8 q + l / 8, chunk (l % 8) ^ (l / 8)
+    const int lrow = l >> 3, lchunk = (l & 7) ^ (l >> 3);
+    const int fr = l & 31, fh = l >> 5, sw = fr & 7;
+    const int64_t nk = (K + BK - 1) / BK;
+    {   // block 0 into buffer 0
+        const int64_t k = lchunk * 8;
+#pragma unroll
+        for (int q = 0; q < 8; q++) {
+            const int row = w * 64 + q * 8 + lrow;
+            const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
+                                                 : (const void *)g_mm_zero;
+            __builtin_amdgcn_global_load_lds((global_void *)ga,
+                                             (lds_void *)(sa0 + (w * 64 + q * 8) * BK), 16, 0, 0);
+            const void *gb = (row < nbl && k < K) ? (const void *)(pb + (int64_t)row * ldb + k)
+                                                  : (const void *)g_mm_zero;
+            __builtin_amdgcn_global_load_lds((global_void *)gb,
+                                             (lds_void *)(sb0 + (w * 64 + q * 8) * BK), 16, 0, 0);
+        }
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+    }
+    for (int64_t kb = 0; kb < nk; kb += 2) {
+        direct_block<DT, TM, TN>(acc, sa0, sb0, sa1, sb1, pa, pb, lda, ldb, ma, nbl,
+                                 (kb + 1) * BK, K, w, lrow, lchunk, wr, wc, fr, fh, sw);
+        if (kb + 1 < nk)
+            direct_block<DT, TM, TN>(acc, sa1, sb1, sa0, sb0, pa, pb, lda, ldb, ma, nbl,
+                                     (kb + 2) * BK, K, w, lrow, lchunk, wr, wc, fr, fh, sw);
+    }
+#pragma unroll
+    for (int i = 0; i < TM; i++)
+#pragma unroll
+        for (int j = 0; j < TN; j++) {
+            const int64_t col = n0 + wc * 32 * TN + j * 32 + (l & 31);
+#pragma unroll
+            for (int v = 0; v < 16; v++) {
+                const int64_t row =
+                    m0 + wr * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+                if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
+            }
+        }
+}
+
 int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, int64_t K,
                 int64_t lda, int64_t ldb, int64_t ldc, int trans_b, int dtype, hipStream_t st) {
     const char *who = "matmul";
@@ -285,7 +444,14 @@ int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, in
 #define XTR_MM(D, V, T)                                                                       \
     hipLaunchKernelGGL((k_matmul<D, V, T, T>), dim3((unsigned)nb), dim3(MM_NT), 0, st, pa, bt, c, \
                        M, N, K, lda, ldbt, ldc, tiles_m, tiles_n)
-    if (dtype == XTR_BF16) {
+    if (big) {
+        if (dtype == XTR_BF16)
+            hipLaunchKernelGGL((k_matmul_direct<XTR_BF16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
+                               pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
+        else
+            hipLaunchKernelGGL((k_matmul_direct<XTR_F16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
+                               pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
+    } else if (dtype == XTR_BF16) {
         if (big) XTR_MM(XTR_BF16, true, 4);
         else if (vec) XTR_MM(XTR_BF16, true, 2);
         else XTR_MM(XTR_BF16, false, 2);
