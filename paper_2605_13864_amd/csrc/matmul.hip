@@ -246,9 +246,11 @@ typedef __attribute__((address_space(1))) void global_void;
 // moves 64 lanes x 16 bytes from global memory straight into 1 KiB of LDS (8
 // rows of the 128-byte k block), with no register staging and no LDS store
 // instructions.  Rows are not padded; instead chunk c of row r sits in slot
-// c ^ (r % 8), so the 8 lanes an LDS pass serves (8 consecutive rows, one
-// chunk) hit 8 different 16-byte bank groups.  Lane i of a load instruction
-// fills slot i % 8 of row i / 8 and therefore fetches chunk (i % 8) ^ (i / 8).
+// c ^ ((r / 2) % 8).  Two 128-byte rows span the 64 banks, so the 16 lanes an
+// LDS pass serves (16 consecutive rows, one chunk) hit 16 different 16-byte
+// bank groups: even rows the first 8, odd rows the other 8, and within each
+// parity 8 different slots.  Lane i of a load instruction fills slot i % 8 of
+// row i / 8 of its 8-row group and fetches the chunk that belongs there.
 // One k block of the direct kernel: the MFMAs on buffers (xa, xb) while the
 // next block's loads fill (ya, yb).  Distinct LDS arrays per buffer let the
 // compiler see that the reads of one buffer do not wait for the loads into the
@@ -259,9 +261,9 @@ __device__ __forceinline__ void direct_block(
     const uint16_t *pa, const uint16_t *pb, int64_t lda, int64_t ldb, int64_t ma, int64_t nbl,
     int64_t knext, int64_t K, int w, int lrow, int lchunk, int wr, int wc, int fr, int fh, int sw) {
     // the next block (knext >= K: only zero chunks)
-    const int64_t k = knext + lchunk * 8;
 #pragma unroll
     for (int q = 0; q < 8; q++) {
+        const int64_t k = knext + (lchunk ^ ((q & 1) << 2)) * 8;
         const int row = w * 64 + q * 8 + lrow;
         const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
                                              : (const void *)g_mm_zero;
@@ -324,9 +326,11 @@ __device__ __forceinline__ void direct_block(
 // moves 64 lanes x 16 bytes from global memory straight into 1 KiB of LDS (8
 // rows of the 128-byte k block), with no register staging and no LDS store
 // instructions.  Rows are not padded; instead chunk c of row r sits in slot
-// c ^ (r % 8), so the 8 lanes an LDS pass serves (8 consecutive rows, one
-// chunk) hit 8 different 16-byte bank groups.  Lane i of a load instruction
-// fills slot i % 8 of row i / 8 and therefore fetches chunk (i % 8) ^ (i / 8).
+// c ^ ((r / 2) % 8).  Two 128-byte rows span the 64 banks, so the 16 lanes an
+// LDS pass serves (16 consecutive rows, one chunk) hit 16 different 16-byte
+// bank groups: even rows the first 8, odd rows the other 8, and within each
+// parity 8 different slots.  Lane i of a load instruction fills slot i % 8 of
+// row i / 8 of its 8-row group and fetches the chunk that belongs there.
 template <int DT>
 __global__ __launch_bounds__(MM_NT) void k_matmul_direct(const uint16_t *__restrict__ A,
                                                          const uint16_t *__restrict__ Bt,
@@ -355,15 +359,16 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_direct(const uint16_t *__restr
 #pragma unroll
         for (int j = 0; j < TN; j++) acc[i][j] = f32x16{};
 
-    // this lane's part of the wave's 8 load instructions per operand: rows
-    // w * 64 + 8 q + l / 8, chunk (l % 8) ^ (l / 8)
-    const int lrow = l >> 3, lchunk = (l & 7) ^ (l >> 3);
-    const int fr = l & 31, fh = l >> 5, sw = fr & 7;
+    // this lane's part of the wave's 8 load instructions per operand: row
+    // r = w * 64 + 8 q + l / 8, slot l % 8, chunk (l % 8) ^ ((r / 2) % 8), and
+    // (r / 2) % 8 = 4 (q % 2) + (l / 8) / 2
+    const int lrow = l >> 3, lchunk = (l & 7) ^ (lrow >> 1);
+    const int fr = l & 31, fh = l >> 5, sw = (fr >> 1) & 7;
     const int64_t nk = (K + BK - 1) / BK;
     {   // block 0 into buffer 0
-        const int64_t k = lchunk * 8;
 #pragma unroll
         for (int q = 0; q < 8; q++) {
+            const int64_t k = (lchunk ^ ((q & 1) << 2)) * 8;
             const int row = w * 64 + q * 8 + lrow;
             const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
                                                  : (const void *)g_mm_zero;
