@@ -10,18 +10,23 @@
 // fp32 by the matrix cores (32x32x16 MFMA blocks, in k order).
 //
 // How:
-//   * The kernel multiplies A by Bt: both operands are k-contiguous, so every
+//   * The kernels multiply A by Bt: both operands are k-contiguous, so every
 //     lane's MFMA fragment (8 consecutive k of one row) is one 16-byte LDS
 //     read.  A row-major B is first transposed into a workspace with the
 //     library's own transpose (the thesis's other case study).
-//   * A workgroup of 256 threads (4 waves, 2 x 2) owns a 128 x 128 tile of C;
-//     a wave owns 64 x 64 = 2 x 2 MFMA blocks of 32 x 32, 64 fp32
-//     accumulators per lane.  K advances in blocks of 64: each thread loads
-//     four 16-byte chunks of A and four of Bt for the next block into
-//     registers while the matrix cores work on the current one from LDS, then
-//     stores them into the other of two LDS buffers (one barrier per block).
-//   * LDS rows are padded to 144 bytes, so the 16-byte fragment reads of 16
-//     lanes (16 rows, same column) fall on 16 disjoint groups of 4 banks.
+//   * Products whose 256 x 256 tiles fill the GPU (k_matmul_deep): a
+//     workgroup of 256 threads (4 waves, 2 x 2) owns a 256 x 256 tile of C, a
+//     wave 128 x 128 = 4 x 4 MFMA blocks of 32 x 32 (256 fp32 accumulators per
+//     lane, in AGPRs).  Operands go straight from global memory into LDS (no
+//     staging registers) through four stages of k blocks of 32, three blocks
+//     ahead of the MFMAs; an explicit schedule interleaves the MFMAs with the
+//     loads and the fragment reads.
+//   * Smaller products and operands whose rows are not 16-byte aligned
+//     (k_matmul): 128 x 128 tiles, a wave 64 x 64; k blocks of 64 staged
+//     through registers into two LDS buffers whose rows are padded to 144
+//     bytes, so the 16-byte fragment reads of 16 lanes hit 16 bank groups.
+//   * Operand chunks outside the matrices are read from a zero chunk, so no
+//     load is predicated and no select waits for a load.
 //   * Tiles are numbered so that the workgroups one XCD runs (the hardware
 //     deals workgroups to the 8 XCDs in turn) are neighbours in groups of 8
 //     tile rows, sharing operand tiles in that XCD's L2.
@@ -62,7 +67,7 @@ __device__ __attribute__((aligned(16))) uint32_t g_mm_zero[4];
 template <bool VEC, int Q>
 __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64_t ld,
                                            int64_t rows_left, int64_t k0, int64_t K, int t,
-                                           mu32x4 (&r)[Q], bool (&in)[Q]) {
+                                           mu32x4 (&r)[Q]) {
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int c = t + MM_NT * q;
@@ -70,13 +75,11 @@ __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64
         const int64_t k = k0 + (c & 7) * 8;
         if constexpr (VEC) {
             // branch-free: a chunk outside the operand loads the zero chunk
-            in[q] = true;
             const bool ok = row < rows_left && k < K;
             const mu32x4 *src = ok ? reinterpret_cast<const mu32x4 *>(p + (int64_t)row * ld + k)
                                    : reinterpret_cast<const mu32x4 *>(g_mm_zero);
             r[q] = *src;
         } else {
-            in[q] = true;
             uint32_t w[4] = {0, 0, 0, 0};
             if (row < rows_left) {
                 const uint16_t *s = p + (int64_t)row * ld;
@@ -90,13 +93,11 @@ __device__ __forceinline__ void load_block(const uint16_t *__restrict__ p, int64
 }
 
 template <int Q>
-__device__ __forceinline__ void store_block(uint16_t *lds, int t, const mu32x4 (&r)[Q],
-                                            const bool (&in)[Q]) {
+__device__ __forceinline__ void store_block(uint16_t *lds, int t, const mu32x4 (&r)[Q]) {
 #pragma unroll
     for (int q = 0; q < Q; q++) {
         const int c = t + MM_NT * q;
-        *reinterpret_cast<mu32x4 *>(lds + (c >> 3) * LROW + (c & 7) * 8) =
-            in[q] ? r[q] : mu32x4{0, 0, 0, 0};
+        *reinterpret_cast<mu32x4 *>(lds + (c >> 3) * LROW + (c & 7) * 8) = r[q];
     }
 }
 
@@ -144,23 +145,21 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
 
     const int64_t nk = (K + BK - 1) / BK;
     mu32x4 ra[QA], rb[QB];
-    bool ia[QA], ib[QB];
     if (nk > 0) {
-        load_block<VEC, QA>(pa, lda, ma, 0, K, t, ra, ia);
-        load_block<VEC, QB>(pb, ldb, nbl, 0, K, t, rb, ib);
-        store_block<QA>(sa[0], t, ra, ia);
-        store_block<QB>(sb[0], t, rb, ib);
+        load_block<VEC, QA>(pa, lda, ma, 0, K, t, ra);
+        load_block<VEC, QB>(pb, ldb, nbl, 0, K, t, rb);
+        store_block<QA>(sa[0], t, ra);
+        store_block<QB>(sb[0], t, rb);
     }
     __syncthreads();
     // lane l's fragment: row l % 32 of a 32-row block, k chunk l / 32 of a 16-k step
     const int fr = l & 31, fk = (l >> 5) * 8;
     for (int64_t kb = 0; kb < nk; kb++) {
         const int cur = kb & 1;
-        // The body is one basic block (the last block's loads of the block
-        // after it read clamped, valid addresses and land in the unused buffer),
-        // so the schedule below can interleave it.
-        load_block<VEC, QA>(pa, lda, ma, (kb + 1) * BK, K, t, ra, ia);
-        load_block<VEC, QB>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb, ib);
+        // the block after this one (past the end: zero chunks, into the
+        // buffer nobody reads any more)
+        load_block<VEC, QA>(pa, lda, ma, (kb + 1) * BK, K, t, ra);
+        load_block<VEC, QB>(pb, ldb, nbl, (kb + 1) * BK, K, t, rb);
         const uint16_t *la = sa[cur] + (wr * 32 * TM + fr) * LROW + fk;
         const uint16_t *lb = sb[cur] + (wc * 32 * TN + fr) * LROW + fk;
         // fragments of step ks + 1 are read while the MFMAs of step ks run; the
@@ -188,39 +187,8 @@ __global__ __launch_bounds__(MM_NT) void k_matmul(const uint16_t *__restrict__ A
             for (int i = 0; i < TM; i++)
 #pragma unroll
                 for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[c][i], fb[c][j], acc[i][j]);
-            if (ks == 2) store_block<QA>(sa[cur ^ 1], t, ra, ia);
-            if (ks == 3) store_block<QB>(sb[cur ^ 1], t, rb, ib);
-        }
-        if constexpr (TM == 4 && TN == 4 && QA == 8 && QB == 8) {
-            // order: step 0's fragments; step 0's MFMAs with the 16 global loads
-            // and step 1's fragments; step 1 with step 2's fragments; steps 2
-            // and 3 with the 16 LDS stores (and step 3's fragments)
-            __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-            }
-#pragma unroll
-            for (int q = 0; q < 8; q++) {
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x200, 1, 0);
-                __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-            }
+            if (ks == 2) store_block<QA>(sa[cur ^ 1], t, ra);
+            if (ks == 3) store_block<QB>(sb[cur ^ 1], t, rb);
         }
         __syncthreads();
     }
@@ -251,98 +219,99 @@ typedef __attribute__((address_space(1))) void global_void;
 // bank groups: even rows the first 8, odd rows the other 8, and within each
 // parity 8 different slots.  Lane i of a load instruction fills slot i % 8 of
 // row i / 8 of its 8-row group and fetches the chunk that belongs there.
-// One k block of the direct kernel: the MFMAs on buffers (xa, xb) while the
-// next block's loads fill (ya, yb).  Distinct LDS arrays per buffer let the
-// compiler see that the reads of one buffer do not wait for the loads into the
-// other.
-template <int DT, int TM, int TN>
-__device__ __forceinline__ void direct_block(
-    f32x16 (&acc)[TM][TN], const uint16_t *xa, const uint16_t *xb, uint16_t *ya, uint16_t *yb,
-    const uint16_t *pa, const uint16_t *pb, int64_t lda, int64_t ldb, int64_t ma, int64_t nbl,
-    int64_t knext, int64_t K, int w, int lrow, int lchunk, int wr, int wc, int fr, int fh, int sw) {
-    // the next block (knext >= K: only zero chunks)
+// ---------------------------------------------------------------- deep pipeline
+// The large-tile kernel with four LDS stages of k blocks of 32: the loads of
+// block kb + 3 are issued while block kb is multiplied, so each load has three
+// blocks of MFMA work (about 3000 cycles) to arrive, against one in the
+// two-stage form.  A stage holds 256 rows x 64 bytes per operand; chunk c of
+// row r sits in slot c ^ ((r / 4) % 4), so the 16 lanes of an LDS pass (16
+// consecutive rows, one chunk) hit 16 different 16-byte bank groups.
+constexpr int DBK = 32;
+
+template <int DT>
+__device__ __forceinline__ void deep_issue(const uint16_t *pa, const uint16_t *pb, int64_t lda,
+                                           int64_t ldb, int64_t ma, int64_t nbl, int64_t kb,
+                                           int64_t K, int w, int lrow, int lchunk, uint16_t *ya,
+                                           uint16_t *yb) {
+    const int64_t k = kb * DBK + lchunk * 8;
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
-        const int64_t k = knext + (lchunk ^ ((q & 1) << 2)) * 8;
-        const int row = w * 64 + q * 8 + lrow;
+    for (int q = 0; q < 4; q++) {
+        const int g = w * 4 + q;                  // 16-row group of this load instruction
+        const int row = g * 16 + lrow;
         const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
                                              : (const void *)g_mm_zero;
-        __builtin_amdgcn_global_load_lds((global_void *)ga, (lds_void *)(ya + (w * 64 + q * 8) * BK),
-                                         16, 0, 0);
+        __builtin_amdgcn_global_load_lds((global_void *)ga, (lds_void *)(ya + g * 16 * DBK), 16,
+                                         0, 0);
         const void *gb = (row < nbl && k < K) ? (const void *)(pb + (int64_t)row * ldb + k)
                                               : (const void *)g_mm_zero;
-        __builtin_amdgcn_global_load_lds((global_void *)gb, (lds_void *)(yb + (w * 64 + q * 8) * BK),
-                                         16, 0, 0);
+        __builtin_amdgcn_global_load_lds((global_void *)gb, (lds_void *)(yb + g * 16 * DBK), 16,
+                                         0, 0);
     }
-    const uint16_t *la = xa + (wr * 32 * TM + fr) * BK;
-    const uint16_t *lb = xb + (wc * 32 * TN + fr) * BK;
-    mu32x4 fa[2][TM], fb[2][TN];
+}
+
+// One step: wait for block kb (this wave's loads of the two blocks after it may
+// still fly), barrier, issue block kb + 3 into the stage block kb - 1 used,
+// multiply block kb.
+template <int DT>
+__device__ __forceinline__ void deep_step(f32x16 (&acc)[4][4], const uint16_t *xa,
+                                          const uint16_t *xb, uint16_t *ya, uint16_t *yb,
+                                          const uint16_t *pa, const uint16_t *pb, int64_t lda,
+                                          int64_t ldb, int64_t ma, int64_t nbl, int64_t kb,
+                                          int64_t K, int w, int lrow, int lchunk, int wr, int wc,
+                                          int fr, int fh, int sw) {
+    // this wave's loads of block kb are in LDS (those of kb + 1 and kb + 2 may
+    // still fly); the barrier then makes every wave's block kb visible.  Written
+    // as one statement: a plain __syncthreads() would wait for every load.
+    asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
+    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, kb + 3, K, w, lrow, lchunk, ya, yb);
+    const uint16_t *la = xa + (wr * 128 + fr) * DBK;
+    const uint16_t *lb = xb + (wc * 128 + fr) * DBK;
+    mu32x4 fa[2][4], fb[2][4];
 #pragma unroll
-    for (int i = 0; i < TM; i++)
-        fa[0][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * BK + ((fh ^ sw) << 3));
+    for (int ks = 0; ks < 2; ks++) {
+        const int slot = ((2 * ks + fh) ^ sw) << 3;
 #pragma unroll
-    for (int j = 0; j < TN; j++)
-        fb[0][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * BK + ((fh ^ sw) << 3));
+        for (int i = 0; i < 4; i++)
+            fa[ks][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * DBK + slot);
 #pragma unroll
-    for (int ks = 0; ks < BK / 16; ks++) {
-        const int c = ks & 1;
-        if (ks + 1 < BK / 16) {
-            const int slot = ((2 * (ks + 1) + fh) ^ sw) << 3;
-#pragma unroll
-            for (int i = 0; i < TM; i++)
-                fa[c ^ 1][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * BK + slot);
-#pragma unroll
-            for (int j = 0; j < TN; j++)
-                fb[c ^ 1][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * BK + slot);
-        }
-#pragma unroll
-        for (int i = 0; i < TM; i++)
-#pragma unroll
-            for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[c][i], fb[c][j], acc[i][j]);
+        for (int j = 0; j < 4; j++)
+            fb[ks][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * DBK + slot);
     }
-    // order: step 0's fragments; step 0's MFMAs with the 16 loads and step 1's
-    // fragments; steps 1 and 2 with the fragments of the step after; step 3
+#pragma unroll
+    for (int ks = 0; ks < 2; ks++)
+#pragma unroll
+        for (int i = 0; i < 4; i++)
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[i][j] = mfma<DT>(fa[ks][i], fb[ks][j], acc[i][j]);
+    // order: step 0's fragments; its MFMAs with the 8 loads and step 1's
+    // fragments; step 1's MFMAs
     __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
 #pragma unroll
     for (int q = 0; q < 8; q++) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
-        __builtin_amdgcn_sched_group_barrier(0x020, 2, 0);
+        __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-#pragma unroll
-    for (int r = 0; r < 2; r++)
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            __builtin_amdgcn_sched_group_barrier(0x008, 2, 0);
-            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
-        }
     __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
-    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's loads are in LDS
-    __syncthreads();
 }
 
-// The large-tile kernel with direct global -> LDS loads: each load instruction
-// moves 64 lanes x 16 bytes from global memory straight into 1 KiB of LDS (8
-// rows of the 128-byte k block), with no register staging and no LDS store
-// instructions.  Rows are not padded; instead chunk c of row r sits in slot
-// c ^ ((r / 2) % 8).  Two 128-byte rows span the 64 banks, so the 16 lanes an
-// LDS pass serves (16 consecutive rows, one chunk) hit 16 different 16-byte
-// bank groups: even rows the first 8, odd rows the other 8, and within each
-// parity 8 different slots.  Lane i of a load instruction fills slot i % 8 of
-// row i / 8 of its 8-row group and fetches the chunk that belongs there.
 template <int DT>
-__global__ __launch_bounds__(MM_NT) void k_matmul_direct(const uint16_t *__restrict__ A,
-                                                         const uint16_t *__restrict__ Bt,
-                                                         float *__restrict__ C, int64_t M,
-                                                         int64_t N, int64_t K, int64_t lda,
-                                                         int64_t ldb, int64_t ldc,
-                                                         int64_t tiles_m, int64_t tiles_n) {
-    constexpr int TM = 4, TN = 4, BM = 256, BN = 256;
-    __shared__ __attribute__((aligned(1024))) uint16_t sa0[BM * BK];
-    __shared__ __attribute__((aligned(1024))) uint16_t sb0[BN * BK];
-    __shared__ __attribute__((aligned(1024))) uint16_t sa1[BM * BK];
-    __shared__ __attribute__((aligned(1024))) uint16_t sb1[BN * BK];
+__global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restrict__ A,
+                                                       const uint16_t *__restrict__ Bt,
+                                                       float *__restrict__ C, int64_t M, int64_t N,
+                                                       int64_t K, int64_t lda, int64_t ldb,
+                                                       int64_t ldc, int64_t tiles_m,
+                                                       int64_t tiles_n) {
+    constexpr int BM = 256, BN = 256;
+    __shared__ __attribute__((aligned(1024))) uint16_t sa0[BM * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb0[BN * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sa1[BM * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb1[BN * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sa2[BM * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb2[BN * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sa3[BM * DBK];
+    __shared__ __attribute__((aligned(1024))) uint16_t sb3[BN * DBK];
     const int t = threadIdx.x, l = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wr = w >> 1, wc = w & 1;
@@ -353,51 +322,40 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_direct(const uint16_t *__restr
     const uint16_t *pb = Bt + n0 * ldb;
     const int64_t ma = M - m0, nbl = N - n0;
 
-    f32x16 acc[TM][TN];
+    f32x16 acc[4][4];
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < TN; j++) acc[i][j] = f32x16{};
+        for (int j = 0; j < 4; j++) acc[i][j] = f32x16{};
 
-    // this lane's part of the wave's 8 load instructions per operand: row
-    // r = w * 64 + 8 q + l / 8, slot l % 8, chunk (l % 8) ^ ((r / 2) % 8), and
-    // (r / 2) % 8 = 4 (q % 2) + (l / 8) / 2
-    const int lrow = l >> 3, lchunk = (l & 7) ^ (lrow >> 1);
-    const int fr = l & 31, fh = l >> 5, sw = (fr >> 1) & 7;
-    const int64_t nk = (K + BK - 1) / BK;
-    {   // block 0 into buffer 0
-#pragma unroll
-        for (int q = 0; q < 8; q++) {
-            const int64_t k = (lchunk ^ ((q & 1) << 2)) * 8;
-            const int row = w * 64 + q * 8 + lrow;
-            const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
-                                                 : (const void *)g_mm_zero;
-            __builtin_amdgcn_global_load_lds((global_void *)ga,
-                                             (lds_void *)(sa0 + (w * 64 + q * 8) * BK), 16, 0, 0);
-            const void *gb = (row < nbl && k < K) ? (const void *)(pb + (int64_t)row * ldb + k)
-                                                  : (const void *)g_mm_zero;
-            __builtin_amdgcn_global_load_lds((global_void *)gb,
-                                             (lds_void *)(sb0 + (w * 64 + q * 8) * BK), 16, 0, 0);
-        }
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
+    // load lane l: row l / 4 of its 16-row group, slot l % 4, chunk
+    // (l % 4) ^ ((row / 4) % 4) = (l % 4) ^ (l / 16)
+    const int lrow = l >> 2, lchunk = (l & 3) ^ (l >> 4);
+    // fragment lane l: row l % 32 of a 32-row block, chunk 2 ks + l / 32
+    const int fr = l & 31, fh = l >> 5, sw = (fr >> 2) & 3;
+    const int64_t nk = (K + DBK - 1) / DBK;
+    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 0, K, w, lrow, lchunk, sa0, sb0);
+    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 1, K, w, lrow, lchunk, sa1, sb1);
+    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 2, K, w, lrow, lchunk, sa2, sb2);
+#define XTR_DS(X, Y, KB)                                                                      \
+    deep_step<DT>(acc, sa##X, sb##X, sa##Y, sb##Y, pa, pb, lda, ldb, ma, nbl, KB, K, w, lrow,   \
+                  lchunk, wr, wc, fr, fh, sw)
+    for (int64_t kb = 0; kb < nk; kb += 4) {
+        XTR_DS(0, 3, kb);
+        if (kb + 1 < nk) XTR_DS(1, 0, kb + 1);
+        if (kb + 2 < nk) XTR_DS(2, 1, kb + 2);
+        if (kb + 3 < nk) XTR_DS(3, 2, kb + 3);
     }
-    for (int64_t kb = 0; kb < nk; kb += 2) {
-        direct_block<DT, TM, TN>(acc, sa0, sb0, sa1, sb1, pa, pb, lda, ldb, ma, nbl,
-                                 (kb + 1) * BK, K, w, lrow, lchunk, wr, wc, fr, fh, sw);
-        if (kb + 1 < nk)
-            direct_block<DT, TM, TN>(acc, sa1, sb1, sa0, sb0, pa, pb, lda, ldb, ma, nbl,
-                                     (kb + 2) * BK, K, w, lrow, lchunk, wr, wc, fr, fh, sw);
-    }
+#undef XTR_DS
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // no load may outlive the workgroup's LDS
 #pragma unroll
-    for (int i = 0; i < TM; i++)
+    for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < TN; j++) {
-            const int64_t col = n0 + wc * 32 * TN + j * 32 + (l & 31);
+        for (int j = 0; j < 4; j++) {
+            const int64_t col = n0 + wc * 128 + j * 32 + (l & 31);
 #pragma unroll
             for (int v = 0; v < 16; v++) {
-                const int64_t row =
-                    m0 + wr * 32 * TM + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
+                const int64_t row = m0 + wr * 128 + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
                 if (row < M && col < N) C[row * ldc + col] = acc[i][j][v];
             }
         }
@@ -451,18 +409,16 @@ int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, in
                        M, N, K, lda, ldbt, ldc, tiles_m, tiles_n)
     if (big) {
         if (dtype == XTR_BF16)
-            hipLaunchKernelGGL((k_matmul_direct<XTR_BF16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
+            hipLaunchKernelGGL((k_matmul_deep<XTR_BF16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
                                pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
         else
-            hipLaunchKernelGGL((k_matmul_direct<XTR_F16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
+            hipLaunchKernelGGL((k_matmul_deep<XTR_F16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
                                pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
     } else if (dtype == XTR_BF16) {
-        if (big) XTR_MM(XTR_BF16, true, 4);
-        else if (vec) XTR_MM(XTR_BF16, true, 2);
+        if (vec) XTR_MM(XTR_BF16, true, 2);
         else XTR_MM(XTR_BF16, false, 2);
     } else {
-        if (big) XTR_MM(XTR_F16, true, 4);
-        else if (vec) XTR_MM(XTR_F16, true, 2);
+        if (vec) XTR_MM(XTR_F16, true, 2);
         else XTR_MM(XTR_F16, false, 2);
     }
 #undef XTR_MM
