@@ -187,6 +187,7 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 // two that divides both base pointers and both row pitches (in bytes).  A
 // 16-byte vector is split into 16 / W pieces on the store side.
 template <int W> struct PieceT;
+template <> struct PieceT<1> { using T = uint32_t; };   // 4-byte pieces at any alignment
 template <> struct PieceT<4> { using T = uint32_t; };
 template <> struct PieceT<8> { using T = u32x2; };
 template <> struct PieceT<16> { using T = u32x4; };
@@ -232,6 +233,34 @@ __device__ __forceinline__ void piece_transpose(const uint4 *a, typename PieceT<
     }
 }
 
+// Rows of 1- and 2-byte elements whose addresses are not 4-byte aligned
+// (odd pitches): a wave moves one 256-byte row segment as 64 4-byte pieces,
+// each built from aligned dwords.  Reading, lane k loads the aligned dword that
+// holds the first byte of its piece and funnel-shifts it with its right
+// neighbour's (lane 63 loads that one itself; it still holds a byte of the
+// segment, so it lies on a page the segment touches).  Writing, lane k stores
+// the aligned dword that ends inside its piece, funnel-shifted from its left
+// neighbour's piece and its own; the segment's partial first and last dwords
+// are written byte by byte, so no byte outside the segment is touched.
+__device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t bytes) {
+    return __builtin_amdgcn_alignbyte(hi, lo, bytes);   // (hi:lo) >> 8 * bytes
+}
+
+template <bool NT>
+__device__ __forceinline__ void st_funnel(unsigned char *pp, uint32_t piece, int k) {
+    const uint32_t md = (uint32_t)(uintptr_t)pp & 3;     // the same in every lane
+    const uint32_t prev = (uint32_t)__shfl_up((int)piece, 1, 64);
+    if (md == 0) {
+        stw<4, NT>(pp, piece);
+        return;
+    }
+    if (k > 0) stw<4, NT>(pp - md, funnel(piece, prev, 4 - md));
+    else
+        for (uint32_t b = 0; b < 4 - md; b++) pp[b] = (unsigned char)(piece >> (8 * b));
+    if (k == 63)
+        for (uint32_t b = 4 - md; b < 4; b++) pp[b] = (unsigned char)(piece >> (8 * b));
+}
+
 // ---------------------------------------------------------------- one tile
 
 // Moves the TR x TC tile at (R0, C0).  Interior tiles run without any bounds
@@ -247,11 +276,15 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     using PT = typename PieceT<W>::T;
     // per-lane part of an address: 32 bits when the host guarantees it fits
     using LaneOff = typename std::conditional<OFF32, uint32_t, int64_t>::type;
+    // W = 1: 4-byte pieces of rows at any alignment (interior tiles only)
+    constexpr bool UA = W == 1;
+    constexpr int WP = UA ? 4 : W;      // piece bytes
+    static_assert(!UA || (SC == 16 && DC == 16 && EB <= 2), "unaligned rows: default tiles");
     constexpr int V = G::V;
-    constexpr int P = 16 * SC / W;      // pieces per src row segment
+    constexpr int P = 16 * SC / WP;     // pieces per src row segment
     constexpr int RP = NT / P;          // tile rows per pass of the workgroup
     constexpr int PASSES = G::TR / RP;
-    constexpr int EPW = W / EB;         // elements per piece
+    constexpr int EPW = WP / EB;        // elements per piece
     static_assert(RP >= 1 && PASSES >= 1 && G::TR % RP == 0, "phase-1 lane layout");
     const int t = threadIdx.x;
     const bool full = (R0 + G::TR <= rows) && (C0 + G::TC <= cols);
@@ -265,9 +298,27 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         const int k = t % P, r0 = t / P;
         const int64_t ldsrc = ld_src * EB;
         const unsigned char *tb = src + (R0 * ld_src + C0) * EB;           // uniform
-        const LaneOff lane = (LaneOff)r0 * (LaneOff)ldsrc + (LaneOff)(k * W);
-        const int inner = (k * W) & 15, chunk = (k * W) >> 4;
-        if (full) {
+        const LaneOff lane = (LaneOff)r0 * (LaneOff)ldsrc + (LaneOff)(k * WP);
+        const int inner = (k * WP) & 15, chunk = (k * WP) >> 4;
+        if constexpr (UA) {
+            // aligned dwords first (all in flight), then the funnel shifts
+            uint32_t d[PASSES], x[PASSES], m[PASSES];
+#pragma unroll
+            for (int p = 0; p < PASSES; p++) {
+                const unsigned char *pp = (tb + (int64_t)(RP * p) * ldsrc) + lane;
+                m[p] = (uint32_t)(uintptr_t)pp & 3;
+                d[p] = ldw<4, NTL>(pp - m[p]);
+                x[p] = (k == P - 1 && m[p] != 0) ? ldw<4, NTL>(pp - m[p] + 4) : 0u;
+            }
+#pragma unroll
+            for (int p = 0; p < PASSES; p++) {
+                uint32_t nxt = (uint32_t)__shfl_down((int)d[p], 1, 64);
+                if (k == P - 1) nxt = x[p];
+                const int row = r0 + RP * p;
+                *reinterpret_cast<uint32_t *>(ldsb + (row * SC + swz<EB>(row, chunk)) * 16 + inner) =
+                    funnel(nxt, d[p], m[p]);
+            }
+        } else if (full) {
             // all loads first (PASSES pieces in flight per lane), then the LDS writes
             PT v[PASSES];
 #pragma unroll
@@ -309,14 +360,14 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     // from LDS and transposes them in registers into V pieces, one per dst
     // row of the chunk.  With W = 16 this is the V x V block transpose.
     {
-        constexpr int P2 = 16 * DC / W;              // pieces per dst row segment
+        constexpr int P2 = 16 * DC / WP;             // pieces per dst row segment
         constexpr int RP2 = NT / P2;                 // column chunks per pass
         constexpr int CPT = SC / RP2;                // 16-byte column chunks per lane
         static_assert(RP2 >= 1 && CPT >= 1 && SC % RP2 == 0, "phase-2 lane layout");
         const int k = t % P2, g = t / P2;
         const int64_t lddst = ld_dst * EB;
         unsigned char *tb = dst + (C0 * ld_dst + R0) * EB;                  // uniform
-        const LaneOff lane = (LaneOff)(g * V) * (LaneOff)lddst + (LaneOff)(k * W);
+        const LaneOff lane = (LaneOff)(g * V) * (LaneOff)lddst + (LaneOff)(k * WP);
         const int64_t rk = R0 + (int64_t)k * EPW;    // first src row of the piece
 #pragma unroll
         for (int cc = 0; cc < CPT; cc++) {
@@ -328,9 +379,12 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                 a[e] = lds[row * SC + swz<EB>(row, m)];
             }
             PT o[V];
-            piece_transpose<EB, W>(a, o);
+            piece_transpose<EB, WP>(a, o);
             unsigned char *cb = tb + (int64_t)(RP2 * cc * V) * lddst;       // uniform
-            if (full) {
+            if constexpr (UA) {
+#pragma unroll
+                for (int i = 0; i < V; i++) st_funnel<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k);
+            } else if (full) {
 #pragma unroll
                 for (int i = 0; i < V; i++) stw<W, NTS>((cb + (int64_t)i * lddst) + lane, o[i]);
             } else {
@@ -393,8 +447,15 @@ __device__ __forceinline__ void tile_any(const unsigned char *src, unsigned char
                                          int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                          int64_t C0, uint4 *lds) {
     if constexpr (W == 0) {
+        // rows not 4-byte aligned: interior tiles in funnel-shifted 4-byte
+        // pieces, edge tiles element by element
         static_assert(SC == 16 && DC == 16, "element-wise tiles use the default geometry");
-        do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+        using G = Geo<EB>;
+        if (R0 + G::TR <= rows && C0 + G::TC <= cols)
+            do_tile<EB, 1, NTL, NTS, OFF32, 16, 16>(src, dst, rows, cols, ld_src, ld_dst, R0, C0,
+                                                     lds);
+        else
+            do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
     } else {
         do_tile<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
     }

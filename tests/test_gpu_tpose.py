@@ -92,6 +92,25 @@ def test_every_piece_width(xtr, orc, eb, w):
         run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=40 + i)
 
 
+@pytest.mark.parametrize("eb", [1, 2])
+def test_unaligned_rows(xtr, orc, eb):
+    """Rows that are not 4-byte aligned (odd pitches, odd pointer offsets):
+    interior tiles move funnel-shifted 4-byte pieces built from aligned
+    dwords, edge tiles go element by element.  Every dst byte is compared,
+    padding and canaries included, so a store outside a row segment shows;
+    every src and dst misalignment occurs among the rows."""
+    T = TILE[eb]
+    if eb == 1:
+        cases = [(1, 0, 0, 0), (0, 1, 0, 0), (3, 5, 1, 2), (2, 2, 3, 1), (1, 3, 2, 3),
+                 (0, 0, 1, 3), (0, 0, 2, 0)]
+    else:
+        cases = [(1, 0, 0, 0), (0, 1, 0, 0), (3, 5, 1, 1), (2, 1, 1, 0), (0, 0, 1, 1)]
+    for i, (pad_s, pad_d, off_s, off_d) in enumerate(cases):
+        for j, (r, c) in enumerate([(3 * T + 5, 2 * T + 7), (4 * T, 4 * T)]):
+            run_tpose(xtr, orc, r, c, eb, pad_s=pad_s, pad_d=pad_d, off_s=off_s, off_d=off_d,
+                      seed=200 + 10 * i + j)
+
+
 @pytest.mark.parametrize("eb", [2, 4, 8])
 @pytest.mark.parametrize("tile", [1, 2])
 def test_tile_geometries(xtr, orc, eb, tile):
