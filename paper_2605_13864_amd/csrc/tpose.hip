@@ -245,20 +245,68 @@ __device__ __forceinline__ void piece_transpose(const uint4 *a, typename PieceT<
 __device__ __forceinline__ uint32_t funnel(uint32_t hi, uint32_t lo, uint32_t bytes) {
     return __builtin_amdgcn_alignbyte(hi, lo, bytes);   // (hi:lo) >> 8 * bytes
 }
-
+// Lane k receives lane k - 1's value (lane 0: 0), and lane k + 1's (lane 63:
+// 0): whole-wave DPP shifts, no LDS traffic.
+__device__ __forceinline__ uint32_t from_left(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x138, 0xf, 0xf, false);  // wave_shr:1
+}
+__device__ __forceinline__ uint32_t from_right(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x130, 0xf, 0xf, false);  // wave_shl:1
+}
 template <bool NT>
 __device__ __forceinline__ void st_funnel(unsigned char *pp, uint32_t piece, int k) {
     const uint32_t md = (uint32_t)(uintptr_t)pp & 3;     // the same in every lane
-    const uint32_t prev = (uint32_t)__shfl_up((int)piece, 1, 64);
+    const uint32_t prev = from_left(piece);
     if (md == 0) {
         stw<4, NT>(pp, piece);
         return;
     }
     if (k > 0) stw<4, NT>(pp - md, funnel(piece, prev, 4 - md));
-    else
-        for (uint32_t b = 0; b < 4 - md; b++) pp[b] = (unsigned char)(piece >> (8 * b));
+    // The partial dwords: lane 0 writes bytes [0, 4 - md) of its piece (they
+    // end on a dword edge), lane 63 bytes [4 - md, 4) (they start on one).
+    // Each writes at most one naturally aligned 16-bit half and one byte, and
+    // the two lanes share the store instructions.
+    if (k == 0 || k == 63) {
+        const uint32_t b0 = k == 0 ? 0u : 4 - md, n = k == 0 ? 4 - md : md;
+        unsigned char *q = pp + b0;
+        const uint32_t v = piece >> (8 * b0);
+        const bool odd = ((uintptr_t)q & 1) != 0;
+        const bool has_b = odd || (n & 1);          // the byte: at q if q is odd,
+        const uint32_t bo = odd ? 0u : n - 1;       // else the last of an odd count
+        const uint32_t so = odd ? 1u : 0u;          // the half: after an odd q, else first
+        if (n > 1) *reinterpret_cast<uint16_t *>(q + so) = (uint16_t)(v >> (8 * so));
+        if (has_b) q[bo] = (unsigned char)(v >> (8 * bo));
+    }
+}
+
+// The same on an edge tile: only logical bytes [0, vb) of the segment exist.
+// Whole dwords inside them as above; a dword the end cuts, and the head when
+// it is cut, byte by byte.
+template <bool NT>
+__device__ __forceinline__ void st_funnel_edge(unsigned char *pp, uint32_t piece, int k, int vb) {
+    const int md = (int)((uintptr_t)pp & 3);
+    const uint32_t prev = from_left(piece);
+    if (md == 0) {
+        if (4 * k + 4 <= vb) stw<4, NT>(pp, piece);
+        else
+            for (int b = 0; b < 4; b++)
+                if (4 * k + b < vb) pp[b] = (unsigned char)(piece >> (8 * b));
+        return;
+    }
+    if (k > 0) {
+        const int lo = 4 * k - md;                      // logical byte at pp - md
+        const uint32_t v = funnel(piece, prev, 4 - md);
+        if (lo + 4 <= vb) stw<4, NT>(pp - md, v);
+        else
+            for (int b = 0; b < 4; b++)
+                if (lo + b < vb) pp[b - md] = (unsigned char)(v >> (8 * b));
+    } else {
+        for (int b = 0; b < 4 - md; b++)
+            if (b < vb) pp[b] = (unsigned char)(piece >> (8 * b));
+    }
     if (k == 63)
-        for (uint32_t b = 4 - md; b < 4; b++) pp[b] = (unsigned char)(piece >> (8 * b));
+        for (int b = 4 - md; b < 4; b++)
+            if (4 * k + b < vb) pp[b] = (unsigned char)(piece >> (8 * b));
 }
 
 // ---------------------------------------------------------------- one tile
@@ -301,22 +349,53 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         const LaneOff lane = (LaneOff)r0 * (LaneOff)ldsrc + (LaneOff)(k * WP);
         const int inner = (k * WP) & 15, chunk = (k * WP) >> 4;
         if constexpr (UA) {
-            // aligned dwords first (all in flight), then the funnel shifts
-            uint32_t d[PASSES], x[PASSES], m[PASSES];
+            // In batches of PB passes: the aligned dwords first (all in flight),
+            // then the funnel shifts and the LDS writes.  On an edge tile only
+            // bytes [0, vb) of a row exist: a lane whose piece they cut reads its
+            // bytes one by one (and shifts by 0), and a lane whose right
+            // neighbour does so loads that neighbour's dword itself.
+            constexpr int PB = PASSES < 16 ? PASSES : 16;
+            const int vb = full ? 256 : (int)(cols - C0 < G::TC ? (cols - C0) * EB : 256);
+            const bool whole = 4 * k + 4 <= vb, cut = !whole && 4 * k < vb;
+            const bool own_next = k == P - 1 || 4 * k + 8 > vb;
+            for (int p0 = 0; p0 < PASSES; p0 += PB) {
+                uint32_t d[PB], x[PB];
+                if (full) {
 #pragma unroll
-            for (int p = 0; p < PASSES; p++) {
-                const unsigned char *pp = (tb + (int64_t)(RP * p) * ldsrc) + lane;
-                m[p] = (uint32_t)(uintptr_t)pp & 3;
-                d[p] = ldw<4, NTL>(pp - m[p]);
-                x[p] = (k == P - 1 && m[p] != 0) ? ldw<4, NTL>(pp - m[p] + 4) : 0u;
-            }
+                    for (int j = 0; j < PB; j++) {
+                        const unsigned char *pp = (tb + (int64_t)(RP * (p0 + j)) * ldsrc) + lane;
+                        const uint32_t m = (uint32_t)(uintptr_t)pp & 3;
+                        d[j] = ldw<4, NTL>(pp - m);
+                        x[j] = (k == P - 1 && m != 0) ? ldw<4, NTL>(pp - m + 4) : 0u;
+                    }
+                } else {
 #pragma unroll
-            for (int p = 0; p < PASSES; p++) {
-                uint32_t nxt = (uint32_t)__shfl_down((int)d[p], 1, 64);
-                if (k == P - 1) nxt = x[p];
-                const int row = r0 + RP * p;
-                *reinterpret_cast<uint32_t *>(ldsb + (row * SC + swz<EB>(row, chunk)) * 16 + inner) =
-                    funnel(nxt, d[p], m[p]);
+                    for (int j = 0; j < PB; j++) {
+                        const unsigned char *pp = (tb + (int64_t)(RP * (p0 + j)) * ldsrc) + lane;
+                        const uint32_t m = (uint32_t)(uintptr_t)pp & 3;
+                        const bool rowok = R0 + r0 + RP * (p0 + j) < rows;
+                        d[j] = 0u;
+                        x[j] = 0u;
+                        if (rowok && whole) {
+                            d[j] = ldw<4, NTL>(pp - m);
+                            if (own_next && m != 0) x[j] = ldw<4, NTL>(pp - m + 4);
+                        } else if (rowok && cut) {
+                            for (int b = 0; b < 4; b++)
+                                if (4 * k + b < vb) d[j] |= (uint32_t)pp[b] << (8 * b);
+                        }
+                    }
+                }
+#pragma unroll
+                for (int j = 0; j < PB; j++) {
+                    const int row = r0 + RP * (p0 + j);
+                    const unsigned char *pp = (tb + (int64_t)(RP * (p0 + j)) * ldsrc) + lane;
+                    const uint32_t m = cut ? 0u : (uint32_t)(uintptr_t)pp & 3;
+                    uint32_t nxt = from_right(d[j]);
+                    if (own_next) nxt = x[j];
+                    if (full || (R0 + row < rows && 4 * k < vb))
+                        *reinterpret_cast<uint32_t *>(ldsb + (row * SC + swz<EB>(row, chunk)) * 16 +
+                                                      inner) = funnel(nxt, d[j], m);
+                }
             }
         } else if (full) {
             // all loads first (PASSES pieces in flight per lane), then the LDS writes
@@ -382,8 +461,17 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
             piece_transpose<EB, WP>(a, o);
             unsigned char *cb = tb + (int64_t)(RP2 * cc * V) * lddst;       // uniform
             if constexpr (UA) {
+                if (full) {
 #pragma unroll
-                for (int i = 0; i < V; i++) st_funnel<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k);
+                    for (int i = 0; i < V; i++)
+                        st_funnel<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k);
+                } else {
+                    const int vb = (int)(rows - R0 < G::TR ? (rows - R0) * EB : 256);
+#pragma unroll
+                    for (int i = 0; i < V; i++)
+                        if (C0 + m * V + i < cols)
+                            st_funnel_edge<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k, vb);
+                }
             } else if (full) {
 #pragma unroll
                 for (int i = 0; i < V; i++) stw<W, NTS>((cb + (int64_t)i * lddst) + lane, o[i]);
@@ -408,38 +496,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     }
 }
 
-// Element-wise form of the same tile for 1- and 2-byte elements whose
-// pointers or pitches are not 4-byte aligned (coalesced, one element per
-// lane per access, same LDS layout).
-template <int EB>
-__device__ __forceinline__ void do_tile_elem(const unsigned char *__restrict__ src,
-                                             unsigned char *__restrict__ dst, int64_t rows,
-                                             int64_t cols, int64_t ld_src, int64_t ld_dst,
-                                             int64_t R0, int64_t C0, uint4 *lds) {
-    using G = Geo<EB>;
-    using T = typename Elem<EB>::T;
-    constexpr int V = G::V;
-    const int t = threadIdx.x;
-    const unsigned char *sb = src + (R0 * ld_src + C0) * EB;
-    for (int e = t; e < G::TR * G::TC; e += NT) {
-        const int r = e / G::TC, c = e % G::TC;
-        if (R0 + r < rows && C0 + c < cols) {
-            T val = *reinterpret_cast<const T *>(sb + ((int64_t)r * ld_src + c) * EB);
-            reinterpret_cast<T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V] = val;
-        }
-    }
-    __syncthreads();
-    unsigned char *db = dst + (C0 * ld_dst + R0) * EB;
-    for (int e = t; e < G::TR * G::TC; e += NT) {
-        const int c = e / G::TR, r = e % G::TR;   // dst row c of the tile, dst col r
-        if (R0 + r < rows && C0 + c < cols) {
-            T val = reinterpret_cast<const T *>(&lds[r * 16 + swz<EB>(r, c / V)])[c % V];
-            *reinterpret_cast<T *>(db + ((int64_t)c * ld_dst + r) * EB) = val;
-        }
-    }
-}
-
-// W = 0 selects the element-wise form.  OFF32: every per-lane offset inside a
+// W = 0 selects the form for rows that are not 4-byte aligned.  OFF32: every per-lane offset inside a
 // tile fits in 32 bits (the host checks the pitches), so addresses are a
 // uniform 64-bit tile base plus a 32-bit lane offset.
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
@@ -447,15 +504,9 @@ __device__ __forceinline__ void tile_any(const unsigned char *src, unsigned char
                                          int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                          int64_t C0, uint4 *lds) {
     if constexpr (W == 0) {
-        // rows not 4-byte aligned: interior tiles in funnel-shifted 4-byte
-        // pieces, edge tiles element by element
-        static_assert(SC == 16 && DC == 16, "element-wise tiles use the default geometry");
-        using G = Geo<EB>;
-        if (R0 + G::TR <= rows && C0 + G::TC <= cols)
-            do_tile<EB, 1, NTL, NTS, OFF32, 16, 16>(src, dst, rows, cols, ld_src, ld_dst, R0, C0,
-                                                     lds);
-        else
-            do_tile_elem<EB>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+        // rows not 4-byte aligned: funnel-shifted 4-byte pieces
+        static_assert(SC == 16 && DC == 16, "unaligned rows use the default geometry");
+        do_tile<EB, 1, NTL, NTS, OFF32, 16, 16>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
     } else {
         do_tile<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
     }
@@ -493,7 +544,7 @@ struct Job {
     int64_t rows, cols, ld_src, ld_dst;
     int64_t tiles_c;
     int64_t tile_base;   // first global tile id of this job
-    int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = element-wise
+    int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = rows not 4-byte aligned
 };
 
 // Job of linear tile L within a group: the last j with bases[j] <= L
@@ -612,7 +663,8 @@ bool off32_rt(int eb, int64_t ld_src, int64_t ld_dst) {
 }
 
 // Widest piece (16, 8 or 4 bytes, and >= the element) that divides both base
-// pointers and both row pitches; 0 = element-wise (1- or 2-byte elements only).
+// pointers and both row pitches; 0 = none (1- or 2-byte elements only): rows
+// not 4-byte aligned, moved as funnel-shifted 4-byte pieces.
 int piece_width(const void *src, const void *dst, int64_t ld_src, int64_t ld_dst, int eb) {
     const uint64_t a = (uint64_t)(uintptr_t)src | (uint64_t)(uintptr_t)dst |
                        (uint64_t)(ld_src * eb) | (uint64_t)(ld_dst * eb);
