@@ -30,8 +30,10 @@
 //  - the launch order is XCD-aware and banded, so tiles that share cache lines
 //    at their edges meet in one L2.
 // Tiles on the right or bottom edge mask whole pieces (elements only where an
-// edge cuts a piece); 1- and 2-byte matrices with odd pitches go element by
-// element over the same LDS layout.
+// edge cuts a piece).  1- and 2-byte matrices whose rows are not 4-byte
+// aligned (odd pitches or offsets) move 4-byte pieces too: each is built from
+// aligned dwords by a funnel shift with the neighbouring lane's, over the
+// same LDS layout.
 #include "common.hpp"
 
 #include <cstring>
