@@ -187,9 +187,11 @@ int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void 
  * fixed order (deterministic); every output is within about 300 * 2^-53 of
  * the sum of magnitudes of its prefix from the exact prefix sum, and
  * non-finite values follow the IEEE rules of the exact prefix (NaN -> NaN
- * from there on; +inf with -inf -> NaN).  Four launches on `stream` (tile
- * sums, two levels of their scan, the tile rescans); library workspace per
- * stream.
+ * from there on; +inf with -inf -> NaN).  Floats: four launches on `stream`
+ * (tile sums, two levels of their scan, the tile rescans).  Integers with a
+ * 16-byte aligned src: two (a fill of the tile flags, then one pass whose
+ * workgroups look back over the totals their predecessors publish).  Library
+ * workspace per stream.
  * n == 0 is a no-op.  Errors: EINVAL, EDTYPE, EALIGN, EOVERLAP, ENOMEM, EHIP.
  */
 int scan_sum(const void *src, int64_t n, void *out, int dtype, int exclusive, void *stream);

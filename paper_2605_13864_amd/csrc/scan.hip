@@ -20,6 +20,9 @@
 //      (shuffles), plus the carry of the rows before and the tile's offset;
 //      the outputs of a row go out through LDS as whole-line stores.
 // The input is read twice and the 8-byte outputs written once.
+// Integer scans of 16-byte aligned inputs take one pass instead (k_scan_lookback,
+// below): integer sums do not depend on their order, so a tile may add up the
+// totals its predecessors publish in whatever state it finds them.
 #include "common.hpp"
 
 #pragma clang fp contract(off)
@@ -223,11 +226,67 @@ __global__ void __launch_bounds__(OFF_NT) k_scan_offsets(T *__restrict__ v, int6
     }
 }
 
+// Rescans one row of a wave tile (lane l holds elements x[0..V-1] at
+// rb + l V + i) on top of `carry`, writes the outputs through the wave's LDS
+// slice `sw` as 16-byte pieces that consecutive lanes place side by side
+// (whole lines per instruction, streamed past the caches: every output is
+// written once), and returns the row total.
+template <int DT, bool EXCL, bool OUTV>
+__device__ __forceinline__ typename ScanT<DT>::T apply_row(const typename ScanT<DT>::T *x,
+                                                           typename ScanT<DT>::T carry,
+                                                           typename ScanT<DT>::T *sw, int l,
+                                                           int64_t rb, int64_t n,
+                                                           typename ScanT<DT>::T *out) {
+    using T = typename ScanT<DT>::T;
+    constexpr int V = svec<DT>();
+    constexpr int ROW = 64 * V;
+    T p[V];
+    p[0] = x[0];
+#pragma unroll
+    for (int i = 1; i < V; i++) p[i] = p[i - 1] + x[i];
+    // exclusive scan of the lane totals over the wave (Hillis-Steele)
+    T inc = p[V - 1];
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const T o = shfl_up64(inc, d);
+        if (l >= d) inc = inc + o;
+    }
+    T ex = shfl_up64(inc, 1);
+    if (l == 0) ex = T(0);
+    const T rowbase = carry + ex;
+    const T rowtot = shfl64(inc, 63);
+#pragma unroll
+    for (int i = 0; i < V; i++) {
+        T y;
+        if constexpr (EXCL) y = (i == 0) ? rowbase : rowbase + p[i - 1];
+        else y = rowbase + p[i];
+        sw[l * V + i] = y;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (OUTV && rb + ROW <= n) {
+#pragma unroll
+        for (int q = 0; q < V / 2; q++) {            // 16 bytes = 2 outputs per lane
+            const int j = (q * 64 + l) * 2;
+            const uint64_t a = __builtin_bit_cast(uint64_t, sw[j]);
+            const uint64_t b = __builtin_bit_cast(uint64_t, sw[j + 1]);
+            typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+            const u32x4 w = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32)};
+            __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(out + rb + j));
+        }
+    } else {
+        for (int j = l; j < ROW; j += 64)
+            if (rb + j < n) out[rb + j] = sw[j];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();   // the slice is rewritten by the next row
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return rowtot;
+}
+
 // Pass 3: every tile rescanned row by row, plus its offset (the block
-// offset plus the tile's offset inside its block).  Each wave stages a row of
-// outputs in its own LDS slice, so the stores of a row are 16-byte pieces
-// that consecutive lanes place side by side (whole lines per instruction),
-// streamed past the caches (every output is written once).
+// offset plus the tile's offset inside its block).
 template <int DT, bool VEC, bool EXCL, bool OUTV>
 __global__ void __launch_bounds__(SNT) k_scan_apply(const unsigned char *__restrict__ src, int64_t n,
                                                     int64_t ntiles,
@@ -254,58 +313,190 @@ __global__ void __launch_bounds__(SNT) k_scan_apply(const unsigned char *__restr
         for (int k = 0; k < RG; k++) {
             const int64_t rb = base + (int64_t)(r0 + k) * ROW;   // first element of the row
             if (rb >= n) break;                                   // uniform
-            T x[V], p[V];
+            T x[V];
             g.row(src, n, base, l, r0, k, x);
-            p[0] = x[0];
-#pragma unroll
-            for (int i = 1; i < V; i++) p[i] = p[i - 1] + x[i];
-            // exclusive scan of the lane totals over the wave (Hillis-Steele)
-            T inc = p[V - 1];
-#pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const T o = shfl_up64(inc, d);
-                if (l >= d) inc = inc + o;
-            }
-            T ex = shfl_up64(inc, 1);
-            if (l == 0) ex = T(0);
-            const T rowbase = carry + ex;
-            const T rowtot = shfl64(inc, 63);
-#pragma unroll
-            for (int i = 0; i < V; i++) {
-                T y;
-                if constexpr (EXCL) y = (i == 0) ? rowbase : rowbase + p[i - 1];
-                else y = rowbase + p[i];
-                sw[l * V + i] = y;
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            if (OUTV && rb + ROW <= n) {
-#pragma unroll
-                for (int q = 0; q < V / 2; q++) {            // 16 bytes = 2 outputs per lane
-                    const int j = (q * 64 + l) * 2;
-                    const uint64_t a = __builtin_bit_cast(uint64_t, sw[j]);
-                    const uint64_t b = __builtin_bit_cast(uint64_t, sw[j + 1]);
-                    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
-                    const u32x4 w = {(uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b,
-                                     (uint32_t)(b >> 32)};
-                    __builtin_nontemporal_store(w, reinterpret_cast<u32x4 *>(out + rb + j));
-                }
-            } else {
-                for (int j = l; j < ROW; j += 64)
-                    if (rb + j < n) out[rb + j] = sw[j];
-            }
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();   // the slice is rewritten by the next row
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            carry = carry + rowtot;
+            carry = carry + apply_row<DT, EXCL, OUTV>(x, carry, sw, l, rb, n, out);
         }
     }
+}
+
+// ---------------------------------------------------------------- one pass
+// Integer scans (exact, so any order of additions gives the same result) in
+// one pass over the input with a decoupled look-back (Merrill and Garland,
+// "Single-pass Parallel Prefix Scan with Decoupled Look-back", 2016): a
+// workgroup takes the next tile of 4 wave tiles from a ticket counter, keeps
+// its input in registers, publishes the tile's total (flag 1), finds the sum
+// of all earlier tiles from their published totals and inclusive prefixes
+// (64 predecessors per step, one per lane), publishes its own inclusive
+// prefix (flag 2), and only then rescans and writes its elements.  A
+// workgroup waits only on tiles whose tickets were taken earlier, i.e. by
+// workgroups already running, so every wait ends.  Floats keep the
+// three-pass form: their fixed summation order is part of the result.
+constexpr int LB_WAVES = SNT / 64;
+constexpr uint32_t LB_SPIN_LIMIT = 1u << 18;     // a bound on every wait (never reached)
+
+template <int DT> constexpr int64_t lb_tile_elems() { return LB_WAVES * tile_elems<DT>(); }
+
+// Publication without cache-wide fences: the totals, prefixes and flags are
+// written and read only with device-scope relaxed atomics, which go past the
+// XCD-private L2s to the coherent level.  A writer waits until its value store
+// has completed (s_waitcnt vmcnt(0)) before it stores the flag, and a reader
+// loads a value only after it has seen the flag, so a flag is never seen
+// before its value.  (Release/acquire fences would write back and invalidate
+// the whole L2 of the XCD on every publication.)
+__device__ __forceinline__ uint32_t lb_flag(const uint32_t *f) {
+    return __hip_atomic_load(f, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ uint64_t lb_value(const uint64_t *v) {
+    return __hip_atomic_load(v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void lb_publish(uint64_t *v, uint64_t x, uint32_t *f, uint32_t state) {
+    __hip_atomic_store(v, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __hip_atomic_store(f, state, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+template <int DT, bool EXCL, bool OUTV>
+__global__ void __launch_bounds__(SNT) k_scan_lookback(const unsigned char *__restrict__ src,
+                                                       int64_t n, int64_t ntiles,
+                                                       uint32_t *__restrict__ ticket,
+                                                       uint32_t *__restrict__ flag,
+                                                       uint64_t *__restrict__ agg,
+                                                       uint64_t *__restrict__ incl,
+                                                       uint64_t *__restrict__ out) {
+    using T = uint64_t;
+    constexpr int V = svec<DT>(), EB = ScanT<DT>::EB;
+    constexpr int ROW = 64 * V;
+    __shared__ T stage[LB_WAVES][ROW];
+    __shared__ T wsum[LB_WAVES];
+    __shared__ T sh_excl;
+    __shared__ uint32_t sh_tile;
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (threadIdx.x == 0) sh_tile = __hip_atomic_fetch_add(ticket, 1u, __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int64_t tile = sh_tile;
+    if (tile >= ntiles) return;                      // (the grid has exactly ntiles workgroups)
+    const int64_t base = tile * lb_tile_elems<DT>() + (int64_t)w * tile_elems<DT>();
+    // this wave's 16 rows, all in flight, kept for the rescan
+    su32x4 raw[SROWS];
+#pragma unroll
+    for (int r = 0; r < SROWS; r++) {
+        const int64_t e0 = base + (int64_t)r * ROW + (int64_t)l * V;
+        raw[r] = su32x4{0, 0, 0, 0};
+        if (e0 + V <= n)
+            raw[r] = __builtin_nontemporal_load(reinterpret_cast<const su32x4 *>(src + e0 * EB));
+        else
+            for (int i = 0; i < V; i++)
+                if (e0 + i < n) {
+                    const T v = sdecode_at<DT>(src + (e0 + i) * EB);
+                    if constexpr (EB == 4) raw[r][i] = (uint32_t)v;
+                    else { raw[r][2 * i] = (uint32_t)v; raw[r][2 * i + 1] = (uint32_t)(v >> 32); }
+                }
+    }
+    T acc = 0;
+#pragma unroll
+    for (int r = 0; r < SROWS; r++) {
+        const uint4 v = make_uint4(raw[r].x, raw[r].y, raw[r].z, raw[r].w);
+#pragma unroll
+        for (int i = 0; i < V; i++) acc += sdecode<DT>(v, i);
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) acc += shfl_xor64(acc, m);
+    if (l == 0) wsum[w] = acc;
+    __syncthreads();
+    if (w == 0) {
+        T tot = 0;
+#pragma unroll
+        for (int k = 0; k < LB_WAVES; k++) tot += wsum[k];
+        // publish the tile total (its inclusive prefix at once for tile 0)
+        if (l == 0) {
+            if (tile == 0) lb_publish(incl, tot, flag, 2u);
+            else lb_publish(agg + tile, tot, flag + tile, 1u);
+        }
+        // look back: lane i examines tile j - i
+        T excl = 0;
+        int64_t j = tile - 1;
+        uint32_t spins = 0;
+        while (j >= 0) {
+            const int64_t jj = j - l;
+            const uint32_t f = jj >= 0 ? lb_flag(flag + jj) : 2u;   // before tile 0: prefix 0
+            const uint64_t has_incl = __ballot(f == 2u);
+            const uint64_t none = __ballot(f == 0u);
+            const int s = has_incl ? __builtin_ctzll(has_incl) : 64;   // nearest inclusive prefix
+            const uint64_t before = s == 64 ? ~0ull : ((1ull << s) - 1);
+            if ((none & before) && ++spins < LB_SPIN_LIMIT) continue;  // a nearer tile not ready
+            T v = 0;
+            if (jj >= 0 && l < s) v = lb_value(agg + jj);
+            else if (jj >= 0 && l == s) v = lb_value(incl + jj);
+#pragma unroll
+            for (int m = 1; m < 64; m <<= 1) v += shfl_xor64(v, m);
+            excl += v;
+            if (s < 64) break;
+            j -= 64;
+        }
+        if (l == 0) {
+            if (tile > 0) lb_publish(incl + tile, excl + tot, flag + tile, 2u);
+            sh_excl = excl;
+        }
+    }
+    __syncthreads();
+    // rescan this wave's rows on top of the tile's prefix and the waves before
+    T carry = sh_excl;
+    for (int k = 0; k < w; k++) carry += wsum[k];
+    T *sw = stage[w];
+#pragma unroll
+    for (int r = 0; r < SROWS; r++) {
+        const int64_t rb = base + (int64_t)r * ROW;
+        if (rb >= n) break;                                    // uniform
+        const uint4 v = make_uint4(raw[r].x, raw[r].y, raw[r].z, raw[r].w);
+        T x[V];
+#pragma unroll
+        for (int i = 0; i < V; i++) x[i] = sdecode<DT>(v, i);
+        carry += apply_row<DT, EXCL, OUTV>(x, carry, sw, l, rb, n, out);
+    }
+}
+
+template <int DT>
+int launch_lookback(const void *src, int64_t n, void *out, bool excl, hipStream_t st) {
+    const int64_t ntiles = (n + lb_tile_elems<DT>() - 1) / lb_tile_elems<DT>();
+    if (ntiles > 0x7fffffff) return fail(XTR_EINVAL, "scan_sum: input too large");
+    // ticket and flags (zeroed by a fill kernel every call), totals, prefixes
+    const size_t fbytes = ((size_t)(ntiles + 1) * 4 + 255) / 256 * 256;
+    const size_t vbytes = (size_t)ntiles * 8;
+    void *ws = nullptr;
+    int rc = workspace(WS_SCAN, st, fbytes + 2 * vbytes, &ws);
+    if (rc) return rc;
+    unsigned char *wb = static_cast<unsigned char *>(ws);
+    uint32_t *ticket = reinterpret_cast<uint32_t *>(wb);
+    uint32_t *flag = ticket + 1;
+    uint64_t *agg = reinterpret_cast<uint64_t *>(wb + fbytes);
+    uint64_t *incl = reinterpret_cast<uint64_t *>(wb + fbytes + vbytes);
+    rc = zero_fill(wb, fbytes, st);
+    if (rc) return rc;
+    const unsigned char *s = static_cast<const unsigned char *>(src);
+    uint64_t *o = static_cast<uint64_t *>(out);
+    const bool outv = ((uintptr_t)out % 16) == 0;
+#define XTR_LB(EE, OO)                                                                        \
+    hipLaunchKernelGGL((k_scan_lookback<DT, EE, OO>), dim3((unsigned)ntiles), dim3(SNT), 0, st, s, \
+                       n, ntiles, ticket, flag, agg, incl, o)
+    if (outv) {
+        if (excl) XTR_LB(true, true);
+        else XTR_LB(false, true);
+    } else {
+        if (excl) XTR_LB(true, false);
+        else XTR_LB(false, false);
+    }
+#undef XTR_LB
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
 }
 
 template <int DT>
 int launch_scan(const void *src, int64_t n, void *out, bool excl, hipStream_t st) {
     using T = typename ScanT<DT>::T;
+    if constexpr (DT == XTR_I32 || DT == XTR_I64)
+        if ((uintptr_t)src % 16 == 0) return launch_lookback<DT>(src, n, out, excl, st);
     const int64_t ntiles = (n + tile_elems<DT>() - 1) / tile_elems<DT>();
     const int64_t nblk = (ntiles + OFF_NT - 1) / OFF_NT;
     const size_t sums_bytes = ((size_t)ntiles * sizeof(T) + 255) / 256 * 256;

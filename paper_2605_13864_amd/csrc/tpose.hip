@@ -351,6 +351,8 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         const LaneOff lane = (LaneOff)r0 * (LaneOff)ldsrc + (LaneOff)(k * WP);
         const int inner = (k * WP) & 15, chunk = (k * WP) >> 4;
         if constexpr (UA) {
+            // Cached accesses whatever the settings: neighbouring lanes and tiles
+            // read and write the same dwords and lines.
             // In batches of PB passes: the aligned dwords first (all in flight),
             // then the funnel shifts and the LDS writes.  On an edge tile only
             // bytes [0, vb) of a row exist: a lane whose piece they cut reads its
@@ -367,8 +369,8 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                     for (int j = 0; j < PB; j++) {
                         const unsigned char *pp = (tb + (int64_t)(RP * (p0 + j)) * ldsrc) + lane;
                         const uint32_t m = (uint32_t)(uintptr_t)pp & 3;
-                        d[j] = ldw<4, NTL>(pp - m);
-                        x[j] = (k == P - 1 && m != 0) ? ldw<4, NTL>(pp - m + 4) : 0u;
+                        d[j] = ldw<4, false>(pp - m);
+                        x[j] = (k == P - 1 && m != 0) ? ldw<4, false>(pp - m + 4) : 0u;
                     }
                 } else {
 #pragma unroll
@@ -379,8 +381,8 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                         d[j] = 0u;
                         x[j] = 0u;
                         if (rowok && whole) {
-                            d[j] = ldw<4, NTL>(pp - m);
-                            if (own_next && m != 0) x[j] = ldw<4, NTL>(pp - m + 4);
+                            d[j] = ldw<4, false>(pp - m);
+                            if (own_next && m != 0) x[j] = ldw<4, false>(pp - m + 4);
                         } else if (rowok && cut) {
                             for (int b = 0; b < 4; b++)
                                 if (4 * k + b < vb) d[j] |= (uint32_t)pp[b] << (8 * b);
@@ -466,13 +468,13 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                 if (full) {
 #pragma unroll
                     for (int i = 0; i < V; i++)
-                        st_funnel<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k);
+                        st_funnel<false>((cb + (int64_t)i * lddst) + lane, o[i], k);
                 } else {
                     const int vb = (int)(rows - R0 < G::TR ? (rows - R0) * EB : 256);
 #pragma unroll
                     for (int i = 0; i < V; i++)
                         if (C0 + m * V + i < cols)
-                            st_funnel_edge<NTS>((cb + (int64_t)i * lddst) + lane, o[i], k, vb);
+                            st_funnel_edge<false>((cb + (int64_t)i * lddst) + lane, o[i], k, vb);
                 }
             } else if (full) {
 #pragma unroll

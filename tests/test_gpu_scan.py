@@ -103,3 +103,38 @@ def test_scan_empty_and_errors(xtr):
         xtr.scan_sum(a, a)                                   # out overlaps src
     with pytest.raises(xtr.XtrError):
         xtr.scan_sum(a, dtype="u8")                          # not summable
+
+
+@pytest.mark.parametrize("dt", ["i32", "i64"])
+@pytest.mark.parametrize("exclusive", [False, True])
+def test_int_single_pass_many_tiles(xtr, orc, dt, exclusive):
+    """Integer scans run in one pass with a look-back over the published tile
+    totals: enough tiles that a look-back spans several 64-tile windows, a
+    ragged last tile, bit-exact, and the same bits on a second call (the
+    ticket and flags start from zero every call)."""
+    lb_tile = 4 * TILE[dt]
+    n = 300 * lb_tile + 77
+    bits = data(dt, n, 620)
+    a = gpu_scan(xtr, bits, dt, exclusive)
+    check_scan(orc, a, bits, dt, exclusive, (dt, n))
+    b = gpu_scan(xtr, bits, dt, exclusive)
+    assert np.array_equal(a, b)
+
+
+def test_int_single_pass_unaligned_output(xtr, orc):
+    """Outputs that do not start on 16 bytes (element stores) over many tiles."""
+    import torch
+    n = 70 * 4 * TILE["i32"] + 5
+    bits = data("i32", n, 630)
+    t = to_dev(bits)
+    out = torch.empty(n + 1, dtype=torch.int64, device="cuda")
+    xtr.scan_sum(t, out[1:], dtype="i32")
+    check_scan(orc, out[1:].cpu().numpy(), bits, "i32", False, "unaligned out")
+
+
+def test_int_single_pass_large(xtr, orc):
+    """2^26 + 12345 int32 values (4097 tiles of the one-pass form)."""
+    n = (1 << 26) + 12345
+    bits = data("i32", n, 640)
+    got = gpu_scan(xtr, bits, "i32", False)
+    check_scan(orc, got, bits, "i32", False, "large i32")
