@@ -26,6 +26,8 @@
 //      and writes counts.
 // More bins than one LDS histogram holds take the global path: counts is
 // zero-filled and every run is added with a 64-bit device-scope atomic.
+// fp8 inputs are counted per code (256 bins of the byte values), and the 256
+// code counts are then added to the bins of their values.
 #include "common.hpp"
 
 #include <math.h>
@@ -312,8 +314,11 @@ __global__ __launch_bounds__(MERGE_NT) void k_hist_merge(const uint32_t *__restr
     }
 }
 
+// counts == nullptr: the counts go to the first nbins * 8 bytes of the
+// workspace (returned in *ws_counts), ahead of the partial table.
 template <int DT, int MODE>
-int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_t st) {
+int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_t st,
+                int64_t **ws_counts = nullptr) {
     constexpr int EB = HistT<DT>::EB, V = 16 / EB;
     HistArgs a = a0;
     const uintptr_t p = (uintptr_t)src;
@@ -323,6 +328,7 @@ int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_
     const unsigned char *s = static_cast<const unsigned char *>(src);
     uint64_t *c64 = reinterpret_cast<uint64_t *>(counts);
     const int64_t want = (a.nvec + (int64_t)HNT * HUNROLL - 1) / ((int64_t)HNT * HUNROLL);
+    if (!counts && a.nbins > LDS_WORDS) return fail(XTR_EINVAL, "histogram: internal bins");
     if (a.nbins > LDS_WORDS) {
         int rc = zero_fill(counts, (size_t)a.nbins * 8, st);
         if (rc) return rc;
@@ -358,9 +364,14 @@ int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_
     if (G < 1) G = 1;
     if (G > 0x7fffffff) return fail(XTR_EINVAL, "histogram: input too large");
     void *ws = nullptr;
-    int rc = workspace(WS_HIST, st, (size_t)G * (size_t)a.nbins * 4, &ws);
+    const size_t reserve = counts ? 0 : ((size_t)a.nbins * 8 + 255) / 256 * 256;
+    int rc = workspace(WS_HIST, st, reserve + (size_t)G * (size_t)a.nbins * 4, &ws);
     if (rc) return rc;
-    uint32_t *part = static_cast<uint32_t *>(ws);
+    uint32_t *part = reinterpret_cast<uint32_t *>(static_cast<unsigned char *>(ws) + reserve);
+    if (!counts) {
+        counts = static_cast<int64_t *>(ws);
+        *ws_counts = counts;
+    }
     if (runs)
         hipLaunchKernelGGL((k_hist<DT, MODE, false, true>), dim3((unsigned)G), dim3(HNT), 0, st,
                            s, a, part, (uint64_t *)nullptr);
@@ -369,6 +380,39 @@ int launch_hist(const void *src, const HistArgs &a0, int64_t *counts, hipStream_
                            s, a, part, (uint64_t *)nullptr);
     hipLaunchKernelGGL(k_hist_merge, dim3((unsigned)((a.nbins + 63) / 64)), dim3(MERGE_NT), 0, st,
                        part, (int)G, a.nbins, counts);
+    XTR_HIP(hipGetLastError());
+    return XTR_OK;
+}
+
+// fp8 histograms through their 256 codes: the counts of every code (the fast
+// one-byte histogram), then one thread per code adds its count to the bin the
+// float rule gives the code's value (the same bin_of as the direct form).
+__global__ __launch_bounds__(256) void k_hist_codes(const int64_t *__restrict__ codes, HistArgs a,
+                                                    uint64_t *__restrict__ counts) {
+    const uint32_t c = threadIdx.x;
+    const int b = bin_of<XTR_F8E4M3, BIN_FLOAT>(c, a);
+    if (b >= 0 && codes[c] != 0)
+        __hip_atomic_fetch_add(counts + b, (uint64_t)codes[c], __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+}
+
+int hist_fp8_by_codes(const void *src, const HistArgs &a, int64_t *counts, hipStream_t st) {
+    HistArgs ac{};
+    ac.n = a.n;
+    ac.nbins = 256;
+    ac.lo_i = 0;
+    ac.width = 1;
+    ac.shift = 0;
+    ac.lo32 = 0x80000000u;          // lo = 0, biased
+    ac.span_m1 = 255;
+    ac.span_m1_32 = 255;
+    int64_t *codes = nullptr;
+    int rc = launch_hist<XTR_U8, BIN_SHIFT32>(src, ac, nullptr, st, &codes);
+    if (rc) return rc;
+    rc = zero_fill(counts, (size_t)a.nbins * 8, st);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_hist_codes, dim3(1), dim3(256), 0, st, codes, a,
+                       reinterpret_cast<uint64_t *>(counts));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
@@ -466,7 +510,7 @@ int histogram_float_impl(const void *src, int64_t n, int dtype, double lo, doubl
     case XTR_F32: return launch_hist<XTR_F32, BIN_FLOAT>(src, a, counts, st);
     case XTR_F16: return launch_hist<XTR_F16, BIN_FLOAT>(src, a, counts, st);
     case XTR_BF16: return launch_hist<XTR_BF16, BIN_FLOAT>(src, a, counts, st);
-    default: return launch_hist<XTR_F8E4M3, BIN_FLOAT>(src, a, counts, st);
+    default: return hist_fp8_by_codes(src, a, counts, st);
     }
 }
 
