@@ -15,9 +15,9 @@
 //     read.  A row-major B is first transposed into a workspace with the
 //     library's own transpose (the thesis's other case study).
 //   * Products whose 256 x 256 tiles fill the GPU (k_matmul_deep): a
-//     workgroup of 256 threads (4 waves, 2 x 2) owns a 256 x 256 tile of C, a
-//     wave 128 x 128 = 4 x 4 MFMA blocks of 32 x 32 (256 fp32 accumulators per
-//     lane, in AGPRs).  Operands go straight from global memory into LDS (no
+//     workgroup of 512 threads (8 waves, 2 x 4, two per SIMD) owns a 256 x 256
+//     tile of C, a wave 128 x 64 = 4 x 2 MFMA blocks of 32 x 32 (128 fp32
+//     accumulators per lane).  Operands go straight from global memory into LDS (no
 //     staging registers) through four stages of k blocks of 32, three blocks
 //     ahead of the MFMAs; an explicit schedule interleaves the MFMAs with the
 //     loads and the fragment reads.
@@ -227,16 +227,25 @@ typedef __attribute__((address_space(1))) void global_void;
 // row r sits in slot c ^ ((r / 4) % 4), so the 16 lanes of an LDS pass (16
 // consecutive rows, one chunk) hit 16 different 16-byte bank groups.
 constexpr int DBK = 32;
+constexpr int MM_DEEP_WAVES = 8;
 
-template <int DT>
+// NW = 8 waves per workgroup: 2 x 4 waves of 128 x 64, two per SIMD, so one
+// wave's MFMAs cover the other's waits (6% faster at 8192^3 than 2 x 2 waves
+// of 128 x 128, one per SIMD, despite 1.5x the LDS fragment reads); WC waves
+// along N, TN MFMA blocks of 32 columns per wave.
+template <int NW> struct DeepGeo {
+    static constexpr int WC = NW / 2, TN = 8 / WC, QPW = 16 / NW;
+};
+
+template <int DT, int NW>
 __device__ __forceinline__ void deep_issue(const uint16_t *pa, const uint16_t *pb, int64_t lda,
                                            int64_t ldb, int64_t ma, int64_t nbl, int64_t kb,
                                            int64_t K, int w, int lrow, int lchunk, uint16_t *ya,
                                            uint16_t *yb) {
     const int64_t k = kb * DBK + lchunk * 8;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int g = w * 4 + q;                  // 16-row group of this load instruction
+    for (int q = 0; q < DeepGeo<NW>::QPW; q++) {
+        const int g = w * DeepGeo<NW>::QPW + q;   // 16-row group of this load instruction
         const int row = g * 16 + lrow;
         const void *ga = (row < ma && k < K) ? (const void *)(pa + (int64_t)row * lda + k)
                                              : (const void *)g_mm_zero;
@@ -252,21 +261,23 @@ __device__ __forceinline__ void deep_issue(const uint16_t *pa, const uint16_t *p
 // One step: wait for block kb (this wave's loads of the two blocks after it may
 // still fly), barrier, issue block kb + 3 into the stage block kb - 1 used,
 // multiply block kb.
-template <int DT>
-__device__ __forceinline__ void deep_step(f32x16 (&acc)[4][4], const uint16_t *xa,
+template <int DT, int NW>
+__device__ __forceinline__ void deep_step(f32x16 (&acc)[4][DeepGeo<NW>::TN], const uint16_t *xa,
                                           const uint16_t *xb, uint16_t *ya, uint16_t *yb,
                                           const uint16_t *pa, const uint16_t *pb, int64_t lda,
                                           int64_t ldb, int64_t ma, int64_t nbl, int64_t kb,
                                           int64_t K, int w, int lrow, int lchunk, int wr, int wc,
                                           int fr, int fh, int sw) {
+    constexpr int TN = DeepGeo<NW>::TN;
     // this wave's loads of block kb are in LDS (those of kb + 1 and kb + 2 may
     // still fly); the barrier then makes every wave's block kb visible.  Written
     // as one statement: a plain __syncthreads() would wait for every load.
-    asm volatile("s_waitcnt vmcnt(16)\n\ts_barrier" ::: "memory");
-    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, kb + 3, K, w, lrow, lchunk, ya, yb);
+    static_assert(NW == 8, "the wait count and the schedule below are for 8 waves");
+    asm volatile("s_waitcnt vmcnt(8)\n\ts_barrier" ::: "memory");
+    deep_issue<DT, NW>(pa, pb, lda, ldb, ma, nbl, kb + 3, K, w, lrow, lchunk, ya, yb);
     const uint16_t *la = xa + (wr * 128 + fr) * DBK;
-    const uint16_t *lb = xb + (wc * 128 + fr) * DBK;
-    mu32x4 fa[2][4], fb[2][4];
+    const uint16_t *lb = xb + (wc * 32 * TN + fr) * DBK;
+    mu32x4 fa[2][4], fb[2][TN];
 #pragma unroll
     for (int ks = 0; ks < 2; ks++) {
         const int slot = ((2 * ks + fh) ^ sw) << 3;
@@ -274,7 +285,7 @@ __device__ __forceinline__ void deep_step(f32x16 (&acc)[4][4], const uint16_t *x
         for (int i = 0; i < 4; i++)
             fa[ks][i] = *reinterpret_cast<const mu32x4 *>(la + i * 32 * DBK + slot);
 #pragma unroll
-        for (int j = 0; j < 4; j++)
+        for (int j = 0; j < TN; j++)
             fb[ks][j] = *reinterpret_cast<const mu32x4 *>(lb + j * 32 * DBK + slot);
     }
 #pragma unroll
@@ -282,28 +293,29 @@ __device__ __forceinline__ void deep_step(f32x16 (&acc)[4][4], const uint16_t *x
 #pragma unroll
         for (int i = 0; i < 4; i++)
 #pragma unroll
-            for (int j = 0; j < 4; j++) acc[i][j] = mfma<DT>(fa[ks][i], fb[ks][j], acc[i][j]);
-    // order: step 0's fragments; its MFMAs with the 8 loads and step 1's
+            for (int j = 0; j < TN; j++) acc[i][j] = mfma<DT>(fa[ks][i], fb[ks][j], acc[i][j]);
+    // order: step 0's fragments; its MFMAs with the loads and step 1's
     // fragments; step 1's MFMAs
-    __builtin_amdgcn_sched_group_barrier(0x100, 8, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 6, 0);
 #pragma unroll
-    for (int q = 0; q < 8; q++) {
+    for (int q = 0; q < 4; q++) {
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x020, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
         __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 16, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
 }
 
-template <int DT>
-__global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restrict__ A,
-                                                       const uint16_t *__restrict__ Bt,
-                                                       float *__restrict__ C, int64_t M, int64_t N,
-                                                       int64_t K, int64_t lda, int64_t ldb,
-                                                       int64_t ldc, int64_t tiles_m,
-                                                       int64_t tiles_n) {
-    constexpr int BM = 256, BN = 256;
+template <int DT, int NW>
+__global__ __launch_bounds__(64 * NW) void k_matmul_deep(const uint16_t *__restrict__ A,
+                                                         const uint16_t *__restrict__ Bt,
+                                                         float *__restrict__ C, int64_t M,
+                                                         int64_t N, int64_t K, int64_t lda,
+                                                         int64_t ldb, int64_t ldc,
+                                                         int64_t tiles_m, int64_t tiles_n) {
+    constexpr int BM = 256, BN = 256, WC = DeepGeo<NW>::WC, TN = DeepGeo<NW>::TN;
     __shared__ __attribute__((aligned(1024))) uint16_t sa0[BM * DBK];
     __shared__ __attribute__((aligned(1024))) uint16_t sb0[BN * DBK];
     __shared__ __attribute__((aligned(1024))) uint16_t sa1[BM * DBK];
@@ -314,7 +326,7 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restric
     __shared__ __attribute__((aligned(1024))) uint16_t sb3[BN * DBK];
     const int t = threadIdx.x, l = t & 63;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wr = w >> 1, wc = w & 1;
+    const int wr = w / WC, wc = w % WC;
     int64_t tm, tn;
     tile_of(blockIdx.x, gridDim.x, tiles_m, tiles_n, tm, tn);
     const int64_t m0 = tm * BM, n0 = tn * BN;
@@ -322,11 +334,11 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restric
     const uint16_t *pb = Bt + n0 * ldb;
     const int64_t ma = M - m0, nbl = N - n0;
 
-    f32x16 acc[4][4];
+    f32x16 acc[4][TN];
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = f32x16{};
+        for (int j = 0; j < TN; j++) acc[i][j] = f32x16{};
 
     // load lane l: row l / 4 of its 16-row group, slot l % 4, chunk
     // (l % 4) ^ ((row / 4) % 4) = (l % 4) ^ (l / 16)
@@ -334,12 +346,12 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restric
     // fragment lane l: row l % 32 of a 32-row block, chunk 2 ks + l / 32
     const int fr = l & 31, fh = l >> 5, sw = (fr >> 2) & 3;
     const int64_t nk = (K + DBK - 1) / DBK;
-    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 0, K, w, lrow, lchunk, sa0, sb0);
-    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 1, K, w, lrow, lchunk, sa1, sb1);
-    deep_issue<DT>(pa, pb, lda, ldb, ma, nbl, 2, K, w, lrow, lchunk, sa2, sb2);
+    deep_issue<DT, NW>(pa, pb, lda, ldb, ma, nbl, 0, K, w, lrow, lchunk, sa0, sb0);
+    deep_issue<DT, NW>(pa, pb, lda, ldb, ma, nbl, 1, K, w, lrow, lchunk, sa1, sb1);
+    deep_issue<DT, NW>(pa, pb, lda, ldb, ma, nbl, 2, K, w, lrow, lchunk, sa2, sb2);
 #define XTR_DS(X, Y, KB)                                                                      \
-    deep_step<DT>(acc, sa##X, sb##X, sa##Y, sb##Y, pa, pb, lda, ldb, ma, nbl, KB, K, w, lrow,   \
-                  lchunk, wr, wc, fr, fh, sw)
+    deep_step<DT, NW>(acc, sa##X, sb##X, sa##Y, sb##Y, pa, pb, lda, ldb, ma, nbl, KB, K, w,     \
+                      lrow, lchunk, wr, wc, fr, fh, sw)
     for (int64_t kb = 0; kb < nk; kb += 4) {
         XTR_DS(0, 3, kb);
         if (kb + 1 < nk) XTR_DS(1, 0, kb + 1);
@@ -351,8 +363,8 @@ __global__ __launch_bounds__(MM_NT) void k_matmul_deep(const uint16_t *__restric
 #pragma unroll
     for (int i = 0; i < 4; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) {
-            const int64_t col = n0 + wc * 128 + j * 32 + (l & 31);
+        for (int j = 0; j < TN; j++) {
+            const int64_t col = n0 + wc * 32 * TN + j * 32 + (l & 31);
 #pragma unroll
             for (int v = 0; v < 16; v++) {
                 const int64_t row = m0 + wr * 128 + i * 32 + 8 * (v >> 2) + 4 * (l >> 5) + (v & 3);
@@ -408,12 +420,13 @@ int matmul_impl(const void *a, const void *b, float *c, int64_t M, int64_t N, in
     hipLaunchKernelGGL((k_matmul<D, V, T, T>), dim3((unsigned)nb), dim3(MM_NT), 0, st, pa, bt, c, \
                        M, N, K, lda, ldbt, ldc, tiles_m, tiles_n)
     if (big) {
+        constexpr int NW = MM_DEEP_WAVES;
         if (dtype == XTR_BF16)
-            hipLaunchKernelGGL((k_matmul_deep<XTR_BF16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
-                               pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
+            hipLaunchKernelGGL((k_matmul_deep<XTR_BF16, NW>), dim3((unsigned)nb), dim3(64 * NW), 0,
+                               st, pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
         else
-            hipLaunchKernelGGL((k_matmul_deep<XTR_F16>), dim3((unsigned)nb), dim3(MM_NT), 0, st,
-                               pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
+            hipLaunchKernelGGL((k_matmul_deep<XTR_F16, NW>), dim3((unsigned)nb), dim3(64 * NW), 0,
+                               st, pa, bt, c, M, N, K, lda, ldbt, ldc, tiles_m, tiles_n);
     } else if (dtype == XTR_BF16) {
         if (vec) XTR_MM(XTR_BF16, true, 2);
         else XTR_MM(XTR_BF16, false, 2);
