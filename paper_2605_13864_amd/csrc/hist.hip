@@ -15,13 +15,17 @@
 //
 // How (two launches):
 //   1. k_hist: G workgroups of 1024 threads stream the input as 16-byte
-//      vectors (grid-stride, four vectors in flight per thread).  Each thread
-//      bins the V elements of a vector and adds runs of equal bins to a
-//      histogram of 32-bit counters in the workgroup's LDS (one atomic add
-//      per run: a sorted or constant input costs one add per vector, not V).
-//      At the end the workgroup writes its histogram to row g of a partial
-//      table in the workspace.  G keeps every workgroup under 2^31 elements,
-//      so the 32-bit counters cannot overflow.
+//      vectors (grid-stride, four vectors in flight per thread) and count in
+//      32-bit counters in the workgroup's LDS.  Up to 511 bins there are 32
+//      copies of the histogram, interleaved bin-major, and thread t adds 1 to
+//      copy t % 32 for every element, without a branch (elements outside the
+//      range go to a spare bin): the 32 lanes of an LDS pass never share a
+//      bank or a counter, whatever the data.  With more bins the copies
+//      shrink to what 64 KiB holds and each thread adds runs of equal bins
+//      within its vector (one atomic add per run).  At the end the workgroup
+//      folds its copies into row g of a partial table in the workspace.  G
+//      keeps every workgroup under 2^31 elements, so the 32-bit counters
+//      cannot overflow.
 //   2. k_hist_merge: one workgroup per 64 bins sums the G rows in 64 bits
 //      and writes counts.
 // More bins than one LDS histogram holds take the global path: counts is
