@@ -28,7 +28,7 @@
 //   * Operand chunks outside the matrices are read from a zero chunk, so no
 //     load is predicated and no select waits for a load.
 //   * Tiles are numbered so that the workgroups one XCD runs (the hardware
-//     deals workgroups to the 8 XCDs in turn) are neighbours in groups of 8
+//     deals workgroups to the 8 XCDs in turn) are neighbours in groups of 4
 //     tile rows, sharing operand tiles in that XCD's L2.
 #include "common.hpp"
 
@@ -38,7 +38,7 @@ namespace {
 constexpr int MM_NT = 256;          // threads per workgroup
 constexpr int BK = 64;              // k per LDS block
 constexpr int LROW = BK + 8;        // LDS row in elements (144 bytes)
-constexpr int GROUP_M = 8;          // tile rows per group of the tile order
+constexpr int GROUP_M = 4;          // tile rows per group of the tile order
 constexpr int NXCD = 8;
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
