@@ -80,3 +80,53 @@ def test_sum_plan_runs_and_replays(xtr):
     assert torch.equal(p2.run().cpu(), xtr.reduce_sum_batched(ints, dtype="i32").cpu())
     plan.close()
     p2.close()
+
+
+def test_scan_histogram_matmul_replay(xtr, orc):
+    """Prefix sums (one-pass integer and three-pass float), histograms (LDS,
+    fp8-by-code and global-atomic forms) and matrix products (both layouts of
+    B) captured in one graph: their flags, counters and partial tables are
+    cleared by fill kernels inside the graph, so every replay, with other
+    library work and synchronisations between replays, equals the eager
+    result."""
+    import torch
+    n = 3 * 16384 * 4 + 11
+    xi = to_dev(W.integers(n, 900, -1000, 1000, "i32"))
+    xf = to_dev(W.normal(n, 901, "f32"))
+    x8 = to_dev(W.signed_lognormal(n, 902, "f8e4m3", sigma=1.0)[0])
+    a = torch.randn((300, 200), device="cuda").to(torch.bfloat16)
+    b = torch.randn((200, 260), device="cuda").to(torch.bfloat16)
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    outs = {}
+
+    def work():
+        outs["si"] = xtr.scan_sum(xi, outs.get("si"), dtype="i32")
+        outs["sf"] = xtr.scan_sum(xf, outs.get("sf"), dtype="f32", exclusive=True)
+        outs["hf"] = xtr.histogram_float(xf, -3.0, 3.0, 700, outs.get("hf"))
+        outs["h8"] = xtr.histogram_float(x8, -2.0, 2.0, 64, outs.get("h8"), dtype="f8e4m3")
+        outs["hg"] = xtr.histogram_int(xi, -1000, 1, 20001, outs.get("hg"))
+        outs["mn"] = xtr.matmul(a, b, outs.get("mn"))
+        outs["mt"] = xtr.matmul(a, b.t().contiguous(), outs.get("mt"), trans_b=True)
+
+    with torch.cuda.stream(s):
+        work()                                        # grows the stream's workspaces
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in outs.items()}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            work()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for v in outs.values():
+            v.fill_(7)                                # eager work between replays
+        xtr.scan_sum(xi, dtype="i32")                 # other library calls in between
+        xtr.histogram_int(xi, 0, 3, 100)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for k in outs:
+            assert torch.equal(outs[k], eager[k]), (k, rep)
+    want = orc.scan(xi.cpu().numpy(), "i32")
+    assert np.array_equal(eager["si"].cpu().numpy(), want)
