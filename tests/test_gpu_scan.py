@@ -105,13 +105,13 @@ def test_scan_empty_and_errors(xtr):
         xtr.scan_sum(a, dtype="u8")                          # not summable
 
 
-@pytest.mark.parametrize("dt", ["i32", "i64"])
+@pytest.mark.parametrize("dt", ["i32", "i64", "f32", "bf16", "f8e4m3"])
 @pytest.mark.parametrize("exclusive", [False, True])
-def test_int_single_pass_many_tiles(xtr, orc, dt, exclusive):
-    """Integer scans run in one pass with a look-back over the published tile
-    totals: enough tiles that a look-back spans several 64-tile windows, a
-    ragged last tile, bit-exact, and the same bits on a second call (the
-    ticket and flags start from zero every call)."""
+def test_many_tiles(xtr, orc, dt, exclusive):
+    """Hundreds of 64 KiB tiles with a ragged last one: integers run in one
+    pass with a look-back spanning several 64-tile windows (bit-exact),
+    floats in three passes (within the bar); the same bits on a second call
+    (the look-back's ticket and flags start from zero every call)."""
     lb_tile = 4 * TILE[dt]
     n = 300 * lb_tile + 77
     bits = data(dt, n, 620)
@@ -138,3 +138,17 @@ def test_int_single_pass_large(xtr, orc):
     bits = data("i32", n, 640)
     got = gpu_scan(xtr, bits, "i32", False)
     check_scan(orc, got, bits, "i32", False, "large i32")
+
+
+def test_nonfinite_across_tiles(xtr, orc):
+    """+inf in one 64 KiB tile, -inf in a later one: the prefixes are finite
+    before, +inf between, NaN after, across the tile offsets."""
+    lb_tile = 4 * TILE["f32"]
+    n = 9 * lb_tile + 5
+    x = W.normal(n, 650, "f32")
+    x[2 * lb_tile + 17] = np.inf
+    x[5 * lb_tile + 3] = -np.inf
+    got = gpu_scan(xtr, x, "f32", False)
+    check_scan(orc, got, x, "f32", False, "nonfinite tiles")
+    a, b = 2 * lb_tile + 17, 5 * lb_tile + 3
+    assert np.isfinite(got[:a]).all() and (got[a:b] == np.inf).all() and np.isnan(got[b:]).all()
