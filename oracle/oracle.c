@@ -28,8 +28,14 @@
  *               semantics of the exact sum (any NaN -> NaN; +inf with -inf ->
  *               NaN; otherwise the infinity).
  *
- *   plain fp32  Listing 2.1 exactly as written: `float sum = 0; sum += arr[i]`.
- *               It is the uncompensated comparator, not a reference.
+ *   plain fp32  the reduce of Listing 2.1 as specified there: a single fp32
+ *               accumulator, one rounding per element, elements taken in index
+ *               order.  It is the uncompensated comparator, not a reference.
+ *
+ *   sum of |x|  sum over i of |A(i)|, decoded exactly and summed like the float
+ *               sum above (the magnitude sum that scales the float error bounds
+ *               and the condition number sum|x| / |sum x|).  Any NaN gives NaN,
+ *               any infinity gives +inf.
  *
  *   prefix sum  the parallel prefix sum the conclusion names as the next case
  *               study: the inclusive scan out[i] = A(0) + ... + A(i), or the
@@ -203,20 +209,27 @@ double oracle_sum_float(const void *src, int64_t n, int dtype) {
     return s + c;
 }
 
-/* Sum of magnitudes in fp64 (for the condition number sum|x| / |sum x|). */
+/* Sum of magnitudes: |x| decoded exactly, fp64 Neumaier sum (both operands
+ * are >= 0, so the larger one is the one with the larger value).  A NaN gives
+ * NaN, an infinity +inf (the exact sum of the magnitudes). */
 double oracle_sum_abs(const void *src, int64_t n, int dtype) {
     double s = 0.0, c = 0.0;
+    int nan = 0, inf = 0;
     for (int64_t i = 0; i < n; i++) {
         double x = fabs(oracle_decode(src, i, dtype));
+        if (isnan(x)) { nan = 1; continue; }
+        if (isinf(x)) { inf = 1; continue; }
         double t = s + x;
         if (s >= x) c += (s - t) + x;
         else c += (x - t) + s;
         s = t;
     }
+    if (nan) return NAN;
+    if (inf) return INFINITY;
     return s + c;
 }
 
-/* Listing 2.1 as written: a float accumulator, one rounding per element. */
+/* The comparator: one fp32 accumulator, one rounding per element (Listing 2.1). */
 float oracle_sum_plain_f32(const void *src, int64_t n, int dtype) {
     float s = 0.0f;
     for (int64_t i = 0; i < n; i++) s += (float)oracle_decode(src, i, dtype);

@@ -277,6 +277,52 @@ def pin_segmented(o):
     assert list(o.sum_segmented(np.arange(5, dtype=np.int32), off2, "i32")) == [0, 3, 0, 7]
 
 
+def pin_sum_abs(o):
+    """The sum of magnitudes (the scale of every float error bound): against
+    math.fsum of |x| (correctly rounded, magnitudes taken with numpy, not the
+    oracle) per format; closed forms on mixed signs (the integers -k..k give
+    k(k + 1); +-2^-j for j < 41 give 2 - 2^-40); the triangle inequality
+    sum|x| >= |sum x|, with equality on non-negative data; the IEEE rules
+    (an infinity of either sign gives +inf, NaN gives NaN); n = 0 gives 0."""
+    cases = [("f32", W.normal(1 << 15, 201, "f32")),
+             ("bf16", W.signed_lognormal(1 << 14, 202, "bf16")[0]),
+             ("f16", W.signed_lognormal(1 << 14, 203, "f16")[0]),
+             ("f8e4m3", W.signed_lognormal(1 << 14, 204, "f8e4m3")[0])]
+    for dt, bits in cases:
+        if dt == "f32":
+            mags = np.abs(bits.astype(np.float64))
+        elif dt == "bf16":
+            mags = np.abs(_bf16_values(bits))
+        elif dt == "f16":
+            mags = np.abs(bits.view(np.float16).astype(np.float64))
+        else:
+            import torch
+            mags = np.abs(torch.from_numpy(bits).view(torch.float8_e4m3fn).to(torch.float64).numpy())
+        exact = math.fsum(mags.tolist())
+        got = o.sum_abs(bits, dt)
+        assert abs(got - exact) <= 4 * math.ulp(exact), (dt, got, exact)
+        assert got >= abs(o.sum_float(bits, dt))
+    k = 3000
+    ints = np.arange(-k, k + 1, dtype=np.float32)
+    np.random.default_rng(205).shuffle(ints)
+    assert o.sum_abs(ints, "f32") == float(k * (k + 1))
+    assert o.sum_float(ints, "f32") == 0.0
+    geo = np.array([(-1) ** j * 2.0 ** -j for j in range(41)], dtype=np.float32)
+    assert o.sum_abs(geo, "f32") == 2.0 - 2.0 ** -40
+    # magnitudes an uncompensated fp64 sum drops: 2^60 followed by 1000 ones of
+    # either sign; the exact 2^60 + 1000 rounds to the fp64 value 2^60 + 1024
+    wide = np.array([-2.0 ** 60] + [(-1.0) ** j for j in range(1000)], dtype=np.float32)
+    assert o.sum_abs(wide, "f32") == float(2 ** 60 + 1000)
+    pos = W.uniform(5000, 206, "f32", 0.0, 1.0)
+    assert o.sum_abs(pos, "f32") == o.sum_float(pos, "f32")
+    inf, nan = np.float32(np.inf), np.float32(np.nan)
+    assert o.sum_abs(np.array([1, -inf, 2], np.float32), "f32") == math.inf
+    assert o.sum_abs(np.array([inf, -inf], np.float32), "f32") == math.inf
+    assert math.isnan(o.sum_abs(np.array([1, nan, -inf], np.float32), "f32"))
+    assert o.sum_abs(np.zeros(0, np.float32), "f32") == 0.0
+    assert o.sum_abs(np.array([0xB8], np.uint8), "f8e4m3") == 1.0      # fp8 -1.0
+
+
 # ------------------------------------------------------------------ prefix sums
 
 def pin_scan_int(o):
@@ -346,6 +392,34 @@ def pin_histogram_int(o):
     assert list(o.histogram_int(big, "i64", 5, 1, 2)) == [1, 1]
 
 
+def pin_histogram_u16(o):
+    """The uint16 branch: every one of the 65536 codes once, in width-1 bins
+    (each bin holds exactly its code) and in bins that start above 2^15 (the
+    codes must read as unsigned); random data against numpy.bincount of the
+    bin index computed with Python integers; brute force on a small input."""
+    codes = np.arange(1 << 16, dtype=np.uint16)
+    np.random.default_rng(207).shuffle(codes)
+    assert np.array_equal(o.histogram_int(codes, "u16", 0, 1, 1 << 16), np.ones(1 << 16, np.int64))
+    got = o.histogram_int(codes, "u16", 40000, 1000, 30)      # [40000, 70000): 25536 codes
+    want = [1000] * 25 + [536] + [0] * 4
+    assert list(got) == want, got
+    assert list(o.histogram_int(codes, "u16", -5, 16, 4)) == [11, 16, 16, 16]
+    x = W.integers(200000, 208, 0, 65535, "i32").astype(np.uint16)
+    for lo, width, nb in ((0, 256, 256), (-300, 7, 10000), (32000, 3, 500)):
+        d = x.astype(np.int64) - lo
+        keep = (d >= 0) & (d < width * nb)
+        want = np.bincount((d[keep] // width).astype(np.int64), minlength=nb)
+        assert np.array_equal(o.histogram_int(x, "u16", lo, width, nb), want), (lo, width, nb)
+    small = np.array([65535, 0, 32768, 32767, 65534, 1], dtype=np.uint16)
+    want = [0, 0, 0]
+    for v in small.tolist():                       # brute force, Python integers
+        d = v - 32767
+        if 0 <= d < 3 * 16384:
+            want[d // 16384] += 1
+    assert want == [2, 1, 1]
+    assert list(o.histogram_int(small, "u16", 32767, 16384, 3)) == want
+
+
 def _check_vs_numpy(got, xd, lo, hi, nb):
     """``got`` against numpy.histogram over the same fp64 values.  numpy closes
     its last bin, so x == hi is dropped first.  With dyadic edges both rules
@@ -388,6 +462,7 @@ PINS_TPOSE = [pin_tpose_golden, pin_tpose_iota, pin_tpose_library, pin_tpose_inv
 PINS_INT = [pin_int_golden, pin_int_closed_forms, pin_int_bruteforce_shuffle, pin_int_wrap]
 PINS_FLOAT = [pin_decode_golden, pin_decode_all_codes, pin_float_golden, pin_float_fsum,
               pin_float_closed_forms, pin_float_nonfinite, pin_plain_f32, pin_segmented]
+PINS_ABS = [pin_sum_abs]
 PINS_SCAN = [pin_scan_int, pin_scan_float]
 # ------------------------------------------------------------------ matmul
 
@@ -475,7 +550,7 @@ def pin_matmul_nonfinite(o):
     assert np.isnan(got[0, 0]) and got[0, 1] == inf and np.isnan(got[2, 1])
 
 
-PINS_HIST = [pin_histogram_int, pin_histogram_float]
+PINS_HIST = [pin_histogram_int, pin_histogram_u16, pin_histogram_float]
 PINS_MM = [pin_matmul_exact_small, pin_matmul_integers, pin_matmul_closed_forms,
            pin_matmul_leading_dims_and_entries, pin_matmul_nonfinite]
-ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_SCAN + PINS_HIST + PINS_MM
+ALL_PINS = PINS_TPOSE + PINS_INT + PINS_FLOAT + PINS_ABS + PINS_SCAN + PINS_HIST + PINS_MM

@@ -51,6 +51,15 @@ MUTANTS = [
      "(uint64_t)(uint32_t)((const int32_t *)src)[i]", P.PINS_SCAN),
     ("scan_float_no_compensation", "ninf ? -INFINITY : s + c;\n            out[i] = prefix;\n        }\n    }",
      "ninf ? -INFINITY : s;\n            out[i] = prefix;\n        }\n    }", P.PINS_SCAN),
+    ("abs_sign_kept", "double x = fabs(oracle_decode(src, i, dtype));",
+     "double x = oracle_decode(src, i, dtype);", P.PINS_ABS),
+    ("abs_no_compensation", "if (inf) return INFINITY;\n    return s + c;",
+     "if (inf) return INFINITY;\n    return s;", P.PINS_ABS),
+    ("abs_inf_gives_nan", "if (isinf(x)) { inf = 1; continue; }", "(void)inf;", P.PINS_ABS),
+    ("abs_comparison_flipped", "if (s >= x) c += (s - t) + x;", "if (s < x) c += (s - t) + x;",
+     P.PINS_ABS),
+    ("hist_u16_read_signed", "case OR_U16: *x = ((const uint16_t *)src)[i]; return 0;",
+     "case OR_U16: *x = ((const int16_t *)src)[i]; return 0;", P.PINS_HIST),
     ("hist_int_hi_included", "if (d < 0 || d >= span) continue;", "if (d < 0 || d > span) continue; if (d == span) d = span - 1;",
      P.PINS_HIST),
     ("hist_int_bin_rounds", "counts[(int64_t)(d / width)] += 1;",
