@@ -151,7 +151,7 @@ def segmented(xtr, torch, log, total=1 << 27, nseg=100000):
     ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, "f32"), dtype=torch.uint8,
                      device="cuda")
     out = torch.empty(nseg, dtype=torch.float64, device="cuda")
-    fn = lambda: xtr.reduce_sum_segmented_ws(x, doff, total, ws, out, dtype="f32")
+    fn = lambda: xtr.reduce_sum_segmented_ws(x, doff, ws, out, dtype="f32")
     sec, wall = _time_dev(torch, fn, reps=10)
     res["segmented_ws"] = {"gbs": round(nbytes / sec / 1e9, 1), "us": round(sec * 1e6, 1)}
     g = _graph(torch, fn)

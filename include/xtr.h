@@ -24,7 +24,16 @@
  *   - The caller owns every data buffer; the library never frees them.
  *     The library owns its internal workspace (per device and stream, grown
  *     on demand and kept until xtr_release or process exit) and its pinned
- *     host staging for descriptor tables.
+ *     host staging for descriptor tables.  A grown workspace replaces the old
+ *     buffer without freeing it (queued work or a captured graph may still
+ *     use it); replaced buffers are freed by xtr_release.
+ *   - Graphs: calls that use the library workspace can be captured once the
+ *     workspace is large enough (it cannot grow during capture: ENOMEM).  A
+ *     captured graph keeps the workspace address it saw, so its replays share
+ *     that buffer with eager calls on the capture stream: replay it on that
+ *     stream (or order the streams), and keep the graph's replays from
+ *     overlapping each other.  The *_ws entry points and the batch plans take
+ *     caller-owned state instead.
  *   - Return value: XTR_OK (0) or a negative XTR_E* code.  On a validation
  *     error (EINVAL, EDTYPE, EOVERLAP, EALIGN) nothing has been enqueued.
  *     EHIP means a HIP call failed (message in xtr_last_error()).  No C++
@@ -155,12 +164,27 @@ int reduce_sum_segmented(const void *src, const int64_t *offsets, int64_t nseg,
  * total_elems elements in all (total_elems = offsets[nseg] - offsets[0]). */
 size_t xtr_segmented_workspace_bytes(int64_t nseg, int64_t total_elems, int dtype);
 
-/* reduce_sum_segmented with the element total given by the caller and a
- * caller-owned workspace (zeroed before first use; left reusable, as for
- * reduce_sum_ws). */
-int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg,
-                            int64_t total_elems, void *out, int dtype, void *ws,
-                            size_t ws_bytes, void *stream);
+/* reduce_sum_segmented with a caller-owned device workspace `ws` of
+ * `ws_bytes` bytes (zeroed before first use; left reusable, as for
+ * reduce_sum_ws), fully asynchronous: nothing is read back.  The chunk space
+ * is as large as the workspace holds; ws_bytes >=
+ * xtr_segmented_workspace_bytes(nseg, offsets[nseg] - offsets[0], dtype)
+ * holds every table whose lengths sum to that total.  A table that needs
+ * more chunk space than the workspace holds is treated like an invalid table
+ * (every output NaN for float dtypes, 0 for integer dtypes), which is
+ * detected on the device.
+ * Errors: as reduce_sum_segmented, plus EBUDGET when the workspace cannot
+ * hold nseg + 1 chunks. */
+int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg, void *out,
+                            int dtype, void *ws, size_t ws_bytes, void *stream);
+
+/* The same with the element total (offsets[nseg] - offsets[0]) given by the
+ * caller: the chunk space is sized from it, and EBUDGET is returned when the
+ * workspace is smaller than xtr_segmented_workspace_bytes(nseg, total_elems,
+ * dtype). */
+int reduce_sum_segmented_ws_total(const void *src, const int64_t *offsets, int64_t nseg,
+                                  int64_t total_elems, void *out, int dtype, void *ws,
+                                  size_t ws_bytes, void *stream);
 
 /* Sums of `count` independent arrays: srcs (host array of device pointers),
  * ns (host array of lengths), out device double[count] / int64_t[count]. */
@@ -195,6 +219,16 @@ int reduce_sum_batched_scatter(const void *const *srcs, const int64_t *ns, void 
  * n == 0 is a no-op.  Errors: EINVAL, EDTYPE, EALIGN, EOVERLAP, ENOMEM, EHIP.
  */
 int scan_sum(const void *src, int64_t n, void *out, int dtype, int exclusive, void *stream);
+
+/* Bound on each wait of the one-pass integer scan: a workgroup that has polled
+ * a window of 64 predecessor tiles `polls` times while a nearer one has still
+ * published nothing stops waiting and sums that tile's elements itself (the
+ * decoupled look-back's waits end anyway, since a tile waits only on tiles
+ * taken earlier; the bound only caps how long).  Results never depend on it:
+ * integer sums are exact in any order.  Process-wide; applies to launches
+ * issued after the call.  Default 2^18; 0 or 1 computes at once.  Returns the
+ * previous bound. */
+uint32_t xtr_scan_lookback_bound(uint32_t polls);
 
 /* ------------------------------------------------------------------------
  * Histograms: the third case study the thesis's conclusion names (after the

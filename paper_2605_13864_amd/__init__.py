@@ -67,8 +67,11 @@ _SIGS = {
     "reduce_sum_segmented": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                               C.c_void_p], C.c_int),
     "xtr_segmented_workspace_bytes": ([C.c_int64, C.c_int64, C.c_int], C.c_size_t),
-    "reduce_sum_segmented_ws": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
-                                 C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "reduce_sum_segmented_ws": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
+                                 C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "reduce_sum_segmented_ws_total": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_int64, C.c_void_p,
+                                       C.c_int, C.c_void_p, C.c_size_t, C.c_void_p], C.c_int),
+    "xtr_scan_lookback_bound": ([C.c_uint32], C.c_uint32),
     "reduce_sum_batched": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                             C.c_void_p], C.c_int),
     "reduce_sum_batched_scatter": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_int,
@@ -358,20 +361,37 @@ def segmented_workspace_bytes(nseg: int, total: int, dtype) -> int:
     return int(load().xtr_segmented_workspace_bytes(nseg, total, _code(dtype)))
 
 
-def reduce_sum_segmented_ws(src, offsets, total: int, ws, out=None, *, dtype=None, stream=None):
-    """Segmented sums with the element total given (no host read-back) and a
-    caller-owned zero-initialised workspace."""
+def reduce_sum_segmented_ws(src, offsets, ws, out=None, *, total=None, dtype=None,
+                            stream=None):
+    """Segmented sums with a caller-owned zero-initialised workspace, fully
+    asynchronous.  Without ``total`` the chunk space is what the workspace
+    holds (reduce_sum_segmented_ws); with it, it is sized from the element
+    total (reduce_sum_segmented_ws_total)."""
     lib = load()
     dt = dtype or dtype_of(src)
     nseg = offsets.numel() - 1
     if out is None:
         out = _sum_out(dt, src.device, nseg)
-    rc = lib.reduce_sum_segmented_ws(C.c_void_p(src.data_ptr()), C.c_void_p(offsets.data_ptr()),
-                                     nseg, total, C.c_void_p(out.data_ptr()), _code(dt),
-                                     C.c_void_p(ws.data_ptr()), ws.numel() * ws.element_size(),
-                                     _stream(stream))
-    _check(rc, "reduce_sum_segmented_ws")
+    wsb = ws.numel() * ws.element_size()
+    if total is None:
+        rc = lib.reduce_sum_segmented_ws(C.c_void_p(src.data_ptr()),
+                                         C.c_void_p(offsets.data_ptr()), nseg,
+                                         C.c_void_p(out.data_ptr()), _code(dt),
+                                         C.c_void_p(ws.data_ptr()), wsb, _stream(stream))
+        _check(rc, "reduce_sum_segmented_ws")
+    else:
+        rc = lib.reduce_sum_segmented_ws_total(C.c_void_p(src.data_ptr()),
+                                               C.c_void_p(offsets.data_ptr()), nseg, total,
+                                               C.c_void_p(out.data_ptr()), _code(dt),
+                                               C.c_void_p(ws.data_ptr()), wsb, _stream(stream))
+        _check(rc, "reduce_sum_segmented_ws_total")
     return out
+
+
+def scan_lookback_bound(polls: int) -> int:
+    """Sets the bound on each look-back wait of the one-pass integer scan
+    (results never depend on it); returns the previous bound."""
+    return int(load().xtr_scan_lookback_bound(polls))
 
 
 def reduce_sum_batched(srcs, out=None, *, ns=None, dtype=None, stream=None):

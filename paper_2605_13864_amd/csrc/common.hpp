@@ -43,8 +43,9 @@ inline bool is_int_sum_dtype(int d) { return d == XTR_I32 || d == XTR_I64; }
 //   WS_REDUCE: zero-filled when (re)allocated; the reduction kernels leave it
 //              zeroed again when they finish (counters, partials).
 //   WS_TABLE:  job/descriptor tables uploaded by the batched entry points.
-// Returns XTR_OK and sets *ptr, or an error code.  Growing a buffer waits for
-// the stream (the old buffer may still be in use by enqueued work).
+// Returns XTR_OK and sets *ptr, or an error code.  Growing a buffer retires
+// the old one without freeing it (enqueued work or a captured graph may still
+// use it); retired buffers are freed by xtr_release.
 //   WS_SCAN:   tile sums / offsets of the prefix sums (written before read).
 //   WS_HIST:   per-workgroup partial histograms (written before read).
 //   WS_MM:     the transposed B operand of a matrix product (written before read).

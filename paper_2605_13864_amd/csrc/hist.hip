@@ -480,7 +480,10 @@ int histogram_int_impl(const void *src, int64_t n, int dtype, int64_t lo, int64_
     if (pow2) a.shift = __builtin_ctzll(a.width);
     // c = ceil(2^64 / width) = floor((2^64 - 1) / width) + 1 (width is not a power of two)
     else if (small) a.magic = ~(uint64_t)0 / a.width + 1;
-    if (dtype != XTR_I64 && small && lo >= INT32_MIN && lo <= INT32_MAX) {
+    // The 32-bit rules need every shift below 32: width = 2^32 (one bin
+    // spanning the whole 32-bit range) takes the 64-bit shift rule.
+    const bool rule32_ok = !(pow2 && a.shift >= 32);
+    if (dtype != XTR_I64 && small && rule32_ok && lo >= INT32_MIN && lo <= INT32_MAX) {
         a.lo32 = (uint32_t)(int32_t)lo ^ 0x80000000u;
         a.span_m1_32 = (uint32_t)a.span_m1;
         return pow2 ? dispatch_int32<BIN_SHIFT32>(src, dtype, a, counts, st)

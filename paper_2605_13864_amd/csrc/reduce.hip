@@ -1242,6 +1242,33 @@ size_t seg_ws_bytes(int64_t nseg, int64_t total_elems, int dtype) {
     return ws_size_for(cap, seg_layout(nseg, cap, mode_for(dtype, false)).total);
 }
 
+// Largest chunk space a caller workspace of ws_bytes holds for nseg segments
+// (at least nseg + 1 slots), or -1 when it holds less.
+int64_t seg_cap_of(size_t ws_bytes, int64_t nseg, int mode) {
+    auto fits = [&](int64_t cap) { return ws_fits(ws_bytes, cap, seg_layout(nseg, cap, mode).total); };
+    constexpr int64_t LIM = 0x7fffffffLL;
+    int64_t lo = nseg + 1;
+    if (lo > LIM || !fits(lo)) return -1;
+    int64_t top;                       // the first doubling that does not fit
+    for (;;) {
+        const int64_t nxt = 2 * lo > LIM ? LIM : 2 * lo;
+        if (nxt == lo) return lo;      // LIM fits
+        if (!fits(nxt)) {
+            top = nxt;
+            break;
+        }
+        lo = nxt;
+    }
+    while (top - lo > 1) {             // fits(lo), !fits(top)
+        const int64_t mid = lo + (top - lo) / 2;
+        if (fits(mid)) lo = mid;
+        else top = mid;
+    }
+    return lo;
+}
+
+// total_elems >= 0: the chunk space is sized from it; -1: offsets[nseg] is
+// read back; -2: the chunk space is what the caller workspace holds.
 int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, void *out,
                        int dtype, void *ws, size_t ws_bytes, int64_t total_elems,
                        hipStream_t st) {
@@ -1254,19 +1281,27 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     if (!src) return fail(XTR_EINVAL, "%s: null src", who);
     if ((uintptr_t)offsets % 8) return fail(XTR_EALIGN, "%s: offsets misaligned", who);
     if (nseg > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: too many segments", who);
-    if (total_elems < 0) {   // read offsets[nseg] back to size the chunk space
-        XTR_HIP(hipMemcpyAsync(&total_elems, offsets + nseg, 8, hipMemcpyDeviceToHost, st));
-        XTR_HIP(hipStreamSynchronize(st));
-        if (total_elems < 0) return fail(XTR_EINVAL, "%s: offsets[nseg] < 0", who);
-    }
     const int mode = mode_for(dtype, false);
     const int eb = elem_bytes(dtype);
     const int64_t ch = chunk_elems_rt(dtype);
-    // Each segment has max(1, ceil(body / ch)) chunks, body <= its length, and
-    // lengths (after clamping decreasing pairs to 0) sum to at most offsets[nseg]
-    // minus offsets[0]; so nseg + ceil(total / ch) bounds the chunk space.
-    const int64_t cap = nseg + (total_elems + ch - 1) / ch;
-    if (cap > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: chunk space too large", who);
+    int64_t cap;
+    if (total_elems == -2) {   // as much chunk space as the caller's workspace holds
+        cap = seg_cap_of(ws_bytes, nseg, mode);
+        if (cap < 0)
+            return fail(XTR_EBUDGET, "%s: workspace %zu bytes holds fewer than nseg + 1 chunks",
+                        who, ws_bytes);
+    } else {
+        if (total_elems < 0) {   // read offsets[nseg] back to size the chunk space
+            XTR_HIP(hipMemcpyAsync(&total_elems, offsets + nseg, 8, hipMemcpyDeviceToHost, st));
+            XTR_HIP(hipStreamSynchronize(st));
+            if (total_elems < 0) return fail(XTR_EINVAL, "%s: offsets[nseg] < 0", who);
+        }
+        // Each segment has max(1, ceil(body / ch)) chunks, body <= its length, and
+        // lengths (after clamping decreasing pairs to 0) sum to at most offsets[nseg]
+        // minus offsets[0]; so nseg + ceil(total / ch) bounds the chunk space.
+        cap = nseg + (total_elems + ch - 1) / ch;
+        if (cap > 0x7fffffffLL) return fail(XTR_EINVAL, "%s: chunk space too large", who);
+    }
     const SegLayout L = seg_layout(nseg, cap, mode);
     WsView v;
     rc = get_ws(ws, ws_bytes, cap, L.total, st, who, &v);
@@ -1434,11 +1469,18 @@ int reduce_sum_segmented(const void *src, const int64_t *offsets, int64_t nseg, 
                                    (hipStream_t)stream);
 }
 
-int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg,
-                            int64_t total_elems, void *out, int dtype, void *ws, size_t ws_bytes,
-                            void *stream) {
+int reduce_sum_segmented_ws(const void *src, const int64_t *offsets, int64_t nseg, void *out,
+                            int dtype, void *ws, size_t ws_bytes, void *stream) {
     if (!ws) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws: null workspace");
-    if (total_elems < 0) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws: total < 0");
+    return xtr::sum_segmented_impl(src, offsets, nseg, out, dtype, ws, ws_bytes, -2,
+                                   (hipStream_t)stream);
+}
+
+int reduce_sum_segmented_ws_total(const void *src, const int64_t *offsets, int64_t nseg,
+                                  int64_t total_elems, void *out, int dtype, void *ws,
+                                  size_t ws_bytes, void *stream) {
+    if (!ws) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws_total: null workspace");
+    if (total_elems < 0) return xtr::fail(XTR_EINVAL, "reduce_sum_segmented_ws_total: total < 0");
     return xtr::sum_segmented_impl(src, offsets, nseg, out, dtype, ws, ws_bytes, total_elems,
                                    (hipStream_t)stream);
 }

@@ -10,6 +10,7 @@
 #include <new>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 namespace xtr {
 
@@ -102,6 +103,13 @@ struct Key {
 };
 std::mutex g_mu;
 std::map<Key, Buf> g_ws;
+// Buffers replaced by a larger one.  They are kept until xtr_release: a graph
+// captured while one of them was current still holds its address.
+struct Retired {
+    int dev;
+    void *ptr;
+};
+std::vector<Retired> g_retired;
 
 // pinned host staging ring for upload(): RING slots per (device, stream), each
 // guarded by the event recorded after the copy that last read it
@@ -131,8 +139,9 @@ int workspace(int kind, hipStream_t stream, size_t bytes, void **ptr, size_t *ac
         return fail(XTR_ENOMEM, "workspace must grow to %zu bytes while the stream is being "
                     "captured; use the *_ws entry points with a caller-owned workspace", bytes);
     if (b.ptr) {
-        XTR_HIP(hipStreamSynchronize(stream));   // old buffer may be in use by queued work
-        XTR_HIP(hipFree(b.ptr));
+        // The old buffer may be in use by queued work, or be held by a graph
+        // captured earlier: it is retired, not freed, until xtr_release.
+        g_retired.push_back(Retired{dev, b.ptr});
         b.ptr = nullptr;
         b.bytes = 0;
     }
@@ -346,6 +355,11 @@ int xtr_release(void) {
         }
     }
     xtr::g_ws.clear();
+    for (const auto &r : xtr::g_retired) {
+        (void)hipSetDevice(r.dev);
+        (void)hipFree(r.ptr);
+    }
+    xtr::g_retired.clear();
     for (auto &kv : xtr::g_stage) {
         (void)hipSetDevice(kv.first.dev);
         for (int i = 0; i < xtr::RING; i++) {

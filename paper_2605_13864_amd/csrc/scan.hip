@@ -330,12 +330,39 @@ __global__ void __launch_bounds__(SNT) k_scan_apply(const unsigned char *__restr
 // (64 predecessors per step, one per lane), publishes its own inclusive
 // prefix (flag 2), and only then rescans and writes its elements.  A
 // workgroup waits only on tiles whose tickets were taken earlier, i.e. by
-// workgroups already running, so every wait ends.  Floats keep the
-// three-pass form: their fixed summation order is part of the result.
+// workgroups already running, so every wait ends.  Each wait is bounded all
+// the same: once a window of 64 predecessors has been polled `spin_limit`
+// times while a nearer tile in it has still published nothing, the waiting
+// wave computes that tile's total from the input itself (a tile's total is a
+// function of its elements alone, and integer sums are exact, so the result
+// is the same bit for bit).  Floats keep the three-pass form: their fixed
+// summation order is part of the result.
 constexpr int LB_WAVES = SNT / 64;
-constexpr uint32_t LB_SPIN_LIMIT = 1u << 18;     // a bound on every wait (never reached)
+constexpr uint32_t LB_SPIN_DEFAULT = 1u << 18;   // polls per window before computing
 
 template <int DT> constexpr int64_t lb_tile_elems() { return LB_WAVES * tile_elems<DT>(); }
+
+// Total of look-back tile `tile` (every element in range: it precedes another
+// tile), summed by one wave; every lane returns it.
+template <int DT> __device__ __noinline__ uint64_t lb_tile_total(const unsigned char *src, int64_t n,
+                                                                int64_t tile) {
+    constexpr int V = svec<DT>(), EB = ScanT<DT>::EB;
+    const int l = threadIdx.x & 63;
+    uint64_t acc = 0;
+    for (int w = 0; w < LB_WAVES; w++) {
+        const int64_t base = tile * lb_tile_elems<DT>() + (int64_t)w * tile_elems<DT>();
+#pragma unroll 4
+        for (int r = 0; r < SROWS; r++) {
+            const int64_t e0 = base + (int64_t)r * 64 * V + (int64_t)l * V;
+#pragma unroll
+            for (int i = 0; i < V; i++)
+                if (e0 + i < n) acc += sdecode_at<DT>(src + (e0 + i) * EB);
+        }
+    }
+#pragma unroll
+    for (int m = 1; m < 64; m <<= 1) acc += shfl_xor64(acc, m);
+    return acc;
+}
 
 // Publication without cache-wide fences: the totals, prefixes and flags are
 // written and read only with device-scope relaxed atomics, which go past the
@@ -363,7 +390,8 @@ __global__ void __launch_bounds__(SNT) k_scan_lookback(const unsigned char *__re
                                                        uint32_t *__restrict__ flag,
                                                        uint64_t *__restrict__ agg,
                                                        uint64_t *__restrict__ incl,
-                                                       uint64_t *__restrict__ out) {
+                                                       uint64_t *__restrict__ out,
+                                                       uint32_t spin_limit) {
     using T = uint64_t;
     constexpr int V = svec<DT>(), EB = ScanT<DT>::EB;
     constexpr int ROW = 64 * V;
@@ -417,7 +445,7 @@ __global__ void __launch_bounds__(SNT) k_scan_lookback(const unsigned char *__re
         // look back: lane i examines tile j - i
         T excl = 0;
         int64_t j = tile - 1;
-        uint32_t spins = 0;
+        uint32_t spins = 0;                          // polls of the current window
         while (j >= 0) {
             const int64_t jj = j - l;
             const uint32_t f = jj >= 0 ? lb_flag(flag + jj) : 2u;   // before tile 0: prefix 0
@@ -425,15 +453,23 @@ __global__ void __launch_bounds__(SNT) k_scan_lookback(const unsigned char *__re
             const uint64_t none = __ballot(f == 0u);
             const int s = has_incl ? __builtin_ctzll(has_incl) : 64;   // nearest inclusive prefix
             const uint64_t before = s == 64 ? ~0ull : ((1ull << s) - 1);
-            if ((none & before) && ++spins < LB_SPIN_LIMIT) continue;  // a nearer tile not ready
+            uint64_t silent = none & before;         // nearer tiles that published nothing
+            if (silent && ++spins < spin_limit) continue;
             T v = 0;
-            if (jj >= 0 && l < s) v = lb_value(agg + jj);
+            if (jj >= 0 && l < s && !((silent >> l) & 1)) v = lb_value(agg + jj);
             else if (jj >= 0 && l == s) v = lb_value(incl + jj);
+            while (silent) {                         // bound reached: sum those tiles here
+                const int i = __builtin_ctzll(silent);
+                silent &= silent - 1;
+                const T tot = lb_tile_total<DT>(src, n, j - i);
+                if (l == i) v = tot;
+            }
 #pragma unroll
             for (int m = 1; m < 64; m <<= 1) v += shfl_xor64(v, m);
             excl += v;
             if (s < 64) break;
             j -= 64;
+            spins = 0;
         }
         if (l == 0) {
             if (tile > 0) lb_publish(incl + tile, excl + tot, flag + tile, 2u);
@@ -457,6 +493,8 @@ __global__ void __launch_bounds__(SNT) k_scan_lookback(const unsigned char *__re
     }
 }
 
+uint32_t g_lb_spin = LB_SPIN_DEFAULT;
+
 template <int DT>
 int launch_lookback(const void *src, int64_t n, void *out, bool excl, hipStream_t st) {
     const int64_t ntiles = (n + lb_tile_elems<DT>() - 1) / lb_tile_elems<DT>();
@@ -477,9 +515,10 @@ int launch_lookback(const void *src, int64_t n, void *out, bool excl, hipStream_
     const unsigned char *s = static_cast<const unsigned char *>(src);
     uint64_t *o = static_cast<uint64_t *>(out);
     const bool outv = ((uintptr_t)out % 16) == 0;
+    const uint32_t spin = __atomic_load_n(&g_lb_spin, __ATOMIC_RELAXED);
 #define XTR_LB(EE, OO)                                                                        \
     hipLaunchKernelGGL((k_scan_lookback<DT, EE, OO>), dim3((unsigned)ntiles), dim3(SNT), 0, st, s, \
-                       n, ntiles, ticket, flag, agg, incl, o)
+                       n, ntiles, ticket, flag, agg, incl, o, spin)
     if (outv) {
         if (excl) XTR_LB(true, true);
         else XTR_LB(false, true);
@@ -565,4 +604,9 @@ int scan_impl(const void *src, int64_t n, void *out, int dtype, int exclusive, h
 extern "C" int scan_sum(const void *src, int64_t n, void *out, int dtype, int exclusive,
                         void *stream) {
     return xtr::scan_impl(src, n, out, dtype, exclusive, (hipStream_t)stream);
+}
+
+extern "C" uint32_t xtr_scan_lookback_bound(uint32_t polls) {
+    uint32_t old = __atomic_exchange_n(&xtr::g_lb_spin, polls, __ATOMIC_RELAXED);
+    return old;
 }

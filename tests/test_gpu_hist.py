@@ -117,6 +117,20 @@ def test_int_extremes(xtr, orc):
 
 
 @pytest.mark.parametrize("dt", ["i32", "u8", "u16"])
+def test_one_bin_of_width_2_32(xtr, orc, dt):
+    """width = 2^32 with one bin spans the whole 32-bit range from lo: the
+    bin index is a shift by 32, which the 32-bit rules cannot take (it goes to
+    the 64-bit shift rule).  Regression test: every element in range counts."""
+    vlo, vhi = {"i32": (-(1 << 31), (1 << 31) - 1), "u8": (0, 255), "u16": (0, 65535)}[dt]
+    a = W.integers(100_003, 760, vlo, vhi, dt)
+    for lo in (-(1 << 31), 0, -5, vlo + 1):
+        got = gpu_hist_int(xtr, a, dt, lo, 1 << 32, 1)
+        want = orc.histogram_int(a, dt, lo, 1 << 32, 1)
+        assert np.array_equal(got, want), (dt, lo, got, want)
+    assert gpu_hist_int(xtr, a, dt, -(1 << 31), 1 << 32, 1)[0] == a.size
+
+
+@pytest.mark.parametrize("dt", ["i32", "u8", "u16"])
 def test_int_unaligned_start(xtr, orc, dt):
     vhi = {"i32": 5000, "u8": 255, "u16": 65535}[dt]
     a = W.integers(40_000, 750, 0, vhi, dt)

@@ -130,3 +130,52 @@ def test_scan_histogram_matmul_replay(xtr, orc):
             assert torch.equal(outs[k], eager[k]), (k, rep)
     want = orc.scan(xi.cpu().numpy(), "i32")
     assert np.array_equal(eager["si"].cpu().numpy(), want)
+
+
+def test_replay_after_workspace_growth(xtr, orc):
+    """A graph captured from calls that use the library workspace keeps the
+    buffer it saw; a later, larger eager call on the same stream grows (and
+    replaces) the workspace.  The old buffer must stay valid: every replay
+    after the growth still equals the eager result."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    n = 5 * 16384 + 3
+    xi = to_dev(W.integers(n, 910, -1000, 1000, "i32"))
+    xf = to_dev(W.normal(n, 911, "f32"))
+    outs = {}
+
+    def work():
+        outs["r"] = xtr.reduce_sum(xf, outs.get("r"), dtype="f32")
+        outs["si"] = xtr.scan_sum(xi, outs.get("si"), dtype="i32")
+        outs["h"] = xtr.histogram_int(xi, -1000, 4, 501, outs.get("h"))
+
+    with torch.cuda.stream(s):
+        work()
+    torch.cuda.synchronize()
+    eager = {k: v.clone() for k, v in outs.items()}
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            work()
+    torch.cuda.synchronize()
+    big = 64 << 20
+    bi = to_dev(W.integers(big, 912, -1000, 1000, "i32"))
+    bf = to_dev(W.normal(big, 913, "f32"))
+    for rep in range(3):
+        with torch.cuda.stream(s):                    # grows every workspace of the stream
+            r = xtr.reduce_sum(bf[:big // (3 - rep)], dtype="f32")
+            sc = xtr.scan_sum(bi[:big // (3 - rep)], dtype="i32")
+            hh = xtr.histogram_int(bi[:big // (3 - rep)], -1000, 4, 501)
+        torch.cuda.synchronize()
+        for v in outs.values():
+            v.fill_(7)
+        torch.cuda.synchronize()
+        with torch.cuda.stream(s):
+            g.replay()
+        torch.cuda.synchronize()
+        for k in outs:
+            assert torch.equal(outs[k], eager[k]), (k, rep)
+        del r, sc, hh
+    want = orc.scan(xi.cpu().numpy(), "i32")
+    assert np.array_equal(eager["si"].cpu().numpy(), want)

@@ -280,10 +280,22 @@ def test_segmented_ws_and_invalid_table(xtr):
     d, doff = to_dev(bits), to_dev(off)
     nb = xtr.segmented_workspace_bytes(500, 100000, "f32")
     ws = torch.zeros(nb, dtype=torch.uint8, device="cuda")
-    a = xtr.reduce_sum_segmented_ws(d, doff, 100000, ws, dtype="f32").cpu()
-    b = xtr.reduce_sum_segmented_ws(d, doff, 100000, ws, dtype="f32").cpu()   # reused workspace
+    a = xtr.reduce_sum_segmented_ws(d, doff, ws, total=100000, dtype="f32").cpu()
+    b = xtr.reduce_sum_segmented_ws(d, doff, ws, total=100000, dtype="f32").cpu()   # reused
     c = xtr.reduce_sum_segmented(d, doff, dtype="f32").cpu()
-    assert torch.equal(a, b) and torch.equal(a, c)
+    e = xtr.reduce_sum_segmented_ws(d, doff, ws, dtype="f32").cpu()   # chunk space from ws
+    big = torch.zeros(4 * nb, dtype=torch.uint8, device="cuda")
+    f = xtr.reduce_sum_segmented_ws(d, doff, big, dtype="f32").cpu()
+    assert torch.equal(a, b) and torch.equal(a, c) and torch.equal(a, e) and torch.equal(a, f)
+    # a workspace too small for the table's chunk space: every output NaN, and
+    # the workspace stays usable
+    off_long = np.array([0, 100000], dtype=np.int64)      # one segment of 13 chunks
+    small_ws = torch.zeros(3072, dtype=torch.uint8, device="cuda")   # holds 10 chunk slots
+    g = xtr.reduce_sum_segmented_ws(d, to_dev(off_long), small_ws, dtype="f32").cpu()
+    assert torch.isnan(g).all()
+    h = xtr.reduce_sum_segmented_ws(d[:10], to_dev(np.array([0, 10], np.int64)), small_ws,
+                                    dtype="f32").cpu()
+    assert h[0].item() == xtr.reduce_sum(d[:10], dtype="f32").item()
     bad = off.copy()
     bad[10], bad[11] = bad[11], bad[10] - 1        # a decreasing pair
     out = xtr.reduce_sum_segmented(d, to_dev(bad), dtype="f32").cpu()

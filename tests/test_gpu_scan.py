@@ -152,3 +152,21 @@ def test_nonfinite_across_tiles(xtr, orc):
     check_scan(orc, got, x, "f32", False, "nonfinite tiles")
     a, b = 2 * lb_tile + 17, 5 * lb_tile + 3
     assert np.isfinite(got[:a]).all() and (got[a:b] == np.inf).all() and np.isnan(got[b:]).all()
+
+
+@pytest.mark.parametrize("dt", ["i32", "i64"])
+def test_lookback_bound_reached(xtr, orc, dt):
+    """The one-pass integer scan with its wait bound forced to 0 polls: every
+    workgroup that finds a nearer predecessor silent sums that tile's elements
+    itself instead of waiting.  The results must not change (integer sums are
+    exact in any order); the kernels exit normally."""
+    t = TILE[dt] * 4                                   # elements of a look-back tile
+    old = xtr.scan_lookback_bound(0)
+    try:
+        for k, n in enumerate([5, t - 1, t + 1, 700 * t + 13]):
+            bits = data(dt, n, 1300 + k)
+            for excl in (False, True):
+                got = gpu_scan(xtr, bits, dt, excl)
+                check_scan(orc, got, bits, dt, excl, (dt, n, excl))
+    finally:
+        assert xtr.scan_lookback_bound(old) == 0
