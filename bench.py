@@ -12,8 +12,20 @@ Each kernel is also timed alone with HIP events on the stream it runs on, and
 the dominant one is reported against the HBM roofline.  The CPU oracle is
 timed on a bounded 1/16 sample of the same workload.
 
-`--suite full` adds the batched (one launch per batch vs one per job),
-segmented, precision and serving measurements under "suite".
+Besides the step, the default run measures the rest of the metric:
+  * "batched": the 4096-job fp32 transpose batch (sides uniform in
+    [16, 2048]) and the 100k-segment fp32 sum (2^27 values), each as one
+    batched call against one launch per job, in GB/s of algorithmic bytes;
+  * "serving": the request loop on its Poisson mix (20k jobs/s) for a few
+    seconds, continuous batching against one launch per job: p50 / p99
+    latency and aggregate GB/s;
+  * "cpu_baseline": the CPU oracle on one thread, and the same plain loops on
+    every host core (OpenMP), with the host's core count and CPU model.
+Per-kernel times are reported as medians and means of per-launch HIP events.
+
+`--suite full` adds the precision sweep, paper shapes, piece widths, host
+buffers, prefix sums, histograms, matrix products and the serving sweep under
+"suite".
 
 Prints ONE JSON line on stdout; progress goes to stderr.
 """
@@ -133,37 +145,168 @@ def copy_ceiling(xtr, torch, nbytes=1 << 30, reps=20):
     return res
 
 
+def host_info():
+    """Core count and CPU model of the host the run is on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model,
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None}
+
+
 def cpu_baseline():
     """The oracle, as it stands, on a 1/16 sample of the step's workload
-    (single thread)."""
-    import numpy as np
+    (single thread), and the same plain loops on every host core (OpenMP, the
+    partials-then-combine pattern of Listing 2.2)."""
     import oracle
     import workloads as W
     o = oracle.get()
-    parts = []
+    b = oracle.omp()
     a = W.matrix(4096, 4096, 2, "f32")
-    parts.append(("tpose f32 4096x4096", 2 * a.nbytes, lambda: o.tpose(a)))
-    b = W.matrix(3072, 5000, 3, "bf16")
-    parts.append(("tpose bf16 3072x5000", 2 * b.nbytes, lambda: o.tpose(b)))
+    bb = W.matrix(3072, 5000, 3, "bf16")
     c = W.normal(1 << 24, 4, "f32")
-    parts.append(("sum f32 2^24", c.nbytes, lambda: o.sum_float(c, "f32")))
     d = W.integers(1 << 24, 5, -(1 << 40), 1 << 40, "i64")
-    parts.append(("sum i64 2^24", d.nbytes, lambda: o.sum_int(d, "i64")))
-    total_b, total_t = 0, 0.0
-    reps = 0
-    t_start = time.time()
-    while reps < 1 or (time.time() - t_start < 8.0 and reps < 20):
-        for _, nb, fn in parts:
-            t0 = time.perf_counter()
-            fn()
-            total_t += time.perf_counter() - t0
-            total_b += nb
-        reps += 1
-    _ = np
-    return {"value": round(total_b / total_t / 1e9, 3), "unit": "GB/s", "cores": 1,
-            "kind": "oracle",
-            "sample": f"1/16 of the step ({', '.join(p[0] for p in parts)}), "
-                      f"{reps} repetition(s), {total_t:.1f}s of CPU time, single thread"}
+    names = ("tpose f32 4096x4096", "tpose bf16 3072x5000", "sum f32 2^24", "sum i64 2^24")
+    nbytes = (2 * a.nbytes, 2 * bb.nbytes, c.nbytes, d.nbytes)
+
+    def measure(fns, budget_s):
+        total_b, total_t, reps = 0, 0.0, 0
+        t_start = time.time()
+        while reps < 1 or (time.time() - t_start < budget_s and reps < 20):
+            for nb, fn in zip(nbytes, fns):
+                t0 = time.perf_counter()
+                fn()
+                total_t += time.perf_counter() - t0
+                total_b += nb
+            reps += 1
+        return total_b / total_t / 1e9, reps, total_t
+
+    v1, r1, t1 = measure((lambda: o.tpose(a), lambda: o.tpose(bb), lambda: o.sum_float(c, "f32"),
+                          lambda: o.sum_int(d, "i64")), 8.0)
+    vp, rp, tp = measure((lambda: b.tpose(a), lambda: b.tpose(bb),
+                          lambda: b.sum_float(c, "f32"), lambda: b.sum_int(d, "i64")), 4.0)
+    info = host_info()
+    return {"value": round(v1, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": f"1/16 of the step ({', '.join(names)}), {r1} repetition(s), "
+                      f"{t1:.1f}s of CPU time, single thread",
+            "all_cores": {"value": round(vp, 3), "unit": "GB/s", "cores": b.threads(),
+                          "kind": "oracle loops, OpenMP (Listing 2.2 partials pattern)",
+                          "sample": f"the same 1/16 sample, {rp} repetition(s), {tp:.1f}s wall"},
+            **info}
+
+
+def _ev_ms(torch, fn, reps, warm=1):
+    """Per-repetition device time (ms) of fn on the current stream: list."""
+    for _ in range(warm):
+        fn()
+    torch.cuda.synchronize()
+    out = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record()
+        fn()
+        e.record()
+        torch.cuda.synchronize()
+        out.append(s.elapsed_time(e))
+    return out
+
+
+def _median(v):
+    v = sorted(v)
+    n = len(v)
+    return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
+
+
+def batched_vs_per_job(xtr, torch):
+    """The batched configuration: 4096 fp32 transposes with sides uniform in
+    [16, 2048] (seed 9) as one tpose_batched call against one tpose launch per
+    job; 2^27 fp32 values in 100k lognormal(6, 1.5) segments (seeds 10, 11) as
+    one segmented call against one reduce_sum launch per segment.  Values are
+    drawn on the device with a seeded generator (a copy's or a sum's speed
+    does not depend on them)."""
+    import workloads as W
+    res = {}
+    shapes = W.batched_shapes(4096, 9)
+    gen = torch.Generator("cuda").manual_seed(9)
+    jobs, nbytes = [], 0
+    for r, c in shapes:
+        jobs.append((torch.rand((r, c), generator=gen, device="cuda") * 2 - 1,
+                     torch.empty((c, r), device="cuda")))
+        nbytes += 2 * r * c * 4
+    bt = _ev_ms(torch, lambda: xtr.tpose_batched(jobs), reps=5)
+
+    def per_job():
+        for s_, d_ in jobs:
+            xtr.tpose(s_, d_, dtype="f32")
+    pj = _ev_ms(torch, per_job, reps=2)
+    ok = all(torch.equal(jobs[k][1], jobs[k][0].t()) for k in (0, 2047, 4095))
+    res["tpose_4096_jobs_f32"] = {
+        "bytes": nbytes, "batched_ms": round(_median(bt), 3),
+        "batched_gbs": round(nbytes / _median(bt) / 1e6, 1),
+        "per_job_ms": round(_median(pj), 3), "per_job_gbs": round(nbytes / _median(pj) / 1e6, 1),
+        "speedup": round(_median(pj) / _median(bt), 2), "spot_check_ok": ok}
+    del jobs
+    torch.cuda.empty_cache()
+    total, nseg = 1 << 27, 100000
+    off = W.segment_offsets(total, nseg, 11)
+    x = torch.randn(total, generator=torch.Generator("cuda").manual_seed(10), device="cuda")
+    doff = torch.from_numpy(off).cuda()
+    ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, "f32"), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    sg = _ev_ms(torch, lambda: xtr.reduce_sum_segmented_ws(x, doff, ws, out, dtype="f32"), reps=10)
+    views = [x[off[i]:off[i + 1]] for i in range(nseg)]
+    per = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    outs = [per[i:i + 1].view(()) for i in range(nseg)]
+
+    def per_seg():
+        for v, o_ in zip(views, outs):
+            xtr.reduce_sum(v, o_, dtype="f32")
+    ps = _ev_ms(torch, per_seg, reps=1)
+    nb = total * 4
+    res["segmented_100k_f32"] = {
+        "bytes": nb, "batched_us": round(_median(sg) * 1e3, 1),
+        "batched_gbs": round(nb / _median(sg) / 1e6, 1),
+        "per_job_us": round(_median(ps) * 1e3, 1), "per_job_gbs": round(nb / _median(ps) / 1e6, 1),
+        "speedup": round(_median(ps) / _median(sg), 1),
+        "bit_identical_to_alone": bool(torch.equal(per, out))}
+    del x, ws, views, outs
+    torch.cuda.empty_cache()
+    return res
+
+
+def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12):
+    """The serving workload for a few seconds: Poisson arrivals at `rate`
+    jobs/s of the configured mix, continuous batching against one launch per
+    job on the same GPU."""
+    import workloads as W
+    from paper_2605_13864_amd import serve
+    count = int(seconds * rate)
+    jobs = W.serving_jobs(count, seed, rate=rate)
+    pool = serve.InputPool(torch, jobs)
+    outs = serve.OutputBuffers(torch, jobs)
+    warm = [j for j in W.serving_jobs(2000, seed + 1000, rate=rate)
+            if serve.InputPool.key(j) in pool.t]
+    serve.run(xtr, torch, warm, pool=pool, outs=outs)
+    serve.run(xtr, torch, warm, batching=False, pool=pool, outs=outs)
+    keys = ("jobs", "p50_ms", "p99_ms", "mean_ms", "throughput_gbs", "achieved_jobs_per_s",
+            "launches", "batches", "mean_jobs_per_batch", "max_inflight_gib")
+    res = {"rate_jobs_per_s": rate, "seconds": seconds,
+           "offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1)}
+    for name, b in (("batched", True), ("per_job", False)):
+        st = serve.run(xtr, torch, jobs, batching=b, pool=pool, outs=outs)
+        res[name] = {k: st[k] for k in keys}
+    res["batched_p99_below_per_job"] = res["batched"]["p99_ms"] < res["per_job"]["p99_ms"]
+    del pool, outs
+    torch.cuda.empty_cache()
+    return res
 
 
 def main():
@@ -173,6 +316,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--suite", choices=["step", "full"], default="step")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip batched vs per-job")
+    ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
     ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,matmul,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
@@ -213,11 +358,16 @@ def main():
     torch.cuda.synchronize()
     per = []
     for i, (name, nbytes, _) in enumerate(step.kernels):
-        us = sum(evs[k][i][0].elapsed_time(evs[k][i][1]) for k in range(args.steps)) / args.steps * 1e3
+        each = [evs[k][i][0].elapsed_time(evs[k][i][1]) * 1e3 for k in range(args.steps)]
+        us = sum(each) / len(each)
+        med = _median(each)
         gbs = nbytes / (us * 1e-6) / 1e9
-        per.append({"kernel": name, "bytes": nbytes, "avg_us": round(us, 2), "gbs": round(gbs, 1),
+        per.append({"kernel": name, "bytes": nbytes, "avg_us": round(us, 2),
+                    "median_us": round(med, 2), "gbs": round(gbs, 1),
+                    "median_gbs": round(nbytes / (med * 1e-6) / 1e9, 1),
                     "frac": round(gbs / HBM_PEAK_GBS, 4)})
-        log(f"bench: {name:28s} {us:9.2f} us  {gbs:8.1f} GB/s  {gbs / HBM_PEAK_GBS:6.1%} of peak")
+        log(f"bench: {name:28s} {us:9.2f} us (median {med:9.2f})  {gbs:8.1f} GB/s  "
+            f"{gbs / HBM_PEAK_GBS:6.1%} of peak")
     dom = max(per, key=lambda p: p["avg_us"])
     value = step.bytes / (ms_per_step * 1e-3) / 1e9
     copy = copy_ceiling(xtr, torch)
@@ -243,10 +393,25 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": {"bound": "hbm", "kernel": dom["kernel"], "achieved": dom["gbs"],
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": dom["frac"],
-                     "traffic": tr},
+                     "traffic": tr, "median_achieved": dom["median_gbs"]},
         "kernels": per,
         "copy_gbs": copy,
     }
+    if not args.no_batched:
+        t0 = time.time()
+        out["batched"] = batched_vs_per_job(xtr, torch)
+        b = out["batched"]
+        log(f"bench: batched 4096 transposes {b['tpose_4096_jobs_f32']['batched_gbs']} GB/s vs "
+            f"per-job {b['tpose_4096_jobs_f32']['per_job_gbs']}; segmented 100k "
+            f"{b['segmented_100k_f32']['batched_gbs']} GB/s vs per-job "
+            f"{b['segmented_100k_f32']['per_job_gbs']} ({time.time() - t0:.1f}s)")
+    if not args.no_serving:
+        t0 = time.time()
+        out["serving"] = serving(xtr, torch)
+        v = out["serving"]
+        log(f"bench: serving 20k jobs/s: batched p50 {v['batched']['p50_ms']} p99 "
+            f"{v['batched']['p99_ms']} ms {v['batched']['throughput_gbs']} GB/s; per-job p50 "
+            f"{v['per_job']['p50_ms']} p99 {v['per_job']['p99_ms']} ms ({time.time() - t0:.1f}s)")
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline()

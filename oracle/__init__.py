@@ -35,6 +35,8 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+OMP_SRC = os.path.join(HERE, "oracle_omp.c")        # all-cores baseline (bench cpu leg)
+OMP_LIB = os.path.join(HERE, "liboracle_omp.so")
 
 # oracle-local dtype codes (mirror the enum in oracle.c, not the product's)
 CODES = {"f32": 0, "f16": 1, "bf16": 2, "f8e4m3": 3, "i32": 4, "i64": 5}
@@ -50,6 +52,12 @@ def build(src: str = SRC, out: str = LIB, extra=()) -> str:
            "-fno-fast-math", *extra, "-o", out, src, "-lm"]
     subprocess.run(cmd, check=True)
     return out
+
+
+def build_omp(src: str = OMP_SRC, out: str = OMP_LIB) -> str:
+    """Compile the OpenMP build of the same plain loops (the all-cores CPU
+    baseline of the benchmark)."""
+    return build(src, out, extra=("-fopenmp",))
 
 
 def _stale(lib: str, src: str) -> bool:
@@ -245,7 +253,56 @@ class Oracle:
         return out
 
 
+class OmpBaseline:
+    """The plain loops of the oracle on every host core (OpenMP, the
+    tile-partials-then-serial-combine pattern of Listing 2.2): the benchmark's
+    all-cores CPU baseline.  Transposes and integer sums equal the oracle bit
+    for bit; float sums are associated per tile of 128 elements."""
+
+    def __init__(self, path: str = OMP_LIB):
+        if path == OMP_LIB and _stale(OMP_LIB, OMP_SRC):
+            build_omp()
+        lib = C.CDLL(path)
+        i64, vp = C.c_int64, C.c_void_p
+        lib.omp_threads.argtypes = []
+        lib.omp_threads.restype = C.c_int
+        lib.omp_tpose.argtypes = [vp, vp, i64, i64, i64, i64, C.c_int]
+        lib.omp_tpose.restype = C.c_int
+        lib.omp_sum_int.argtypes = [vp, i64, C.c_int]
+        lib.omp_sum_int.restype = C.c_int64
+        lib.omp_sum_float.argtypes = [vp, i64, C.c_int]
+        lib.omp_sum_float.restype = C.c_double
+        self.lib = lib
+
+    def threads(self) -> int:
+        return int(self.lib.omp_threads())
+
+    def tpose(self, src: np.ndarray) -> np.ndarray:
+        src = np.ascontiguousarray(src)
+        rows, cols = src.shape
+        dst = np.empty((cols, rows), dtype=src.dtype)
+        if self.lib.omp_tpose(_ptr(src), _ptr(dst), rows, cols, cols, rows, src.itemsize):
+            raise ValueError("omp_tpose: invalid arguments")
+        return dst
+
+    def sum_int(self, bits: np.ndarray, dtype: str) -> int:
+        bits = np.ascontiguousarray(bits)
+        return int(self.lib.omp_sum_int(_ptr(bits), bits.size, CODES[dtype]))
+
+    def sum_float(self, bits: np.ndarray, dtype: str) -> float:
+        bits = np.ascontiguousarray(bits)
+        return float(self.lib.omp_sum_float(_ptr(bits), bits.size, CODES[dtype]))
+
+
 _default: Oracle | None = None
+_omp: OmpBaseline | None = None
+
+
+def omp() -> OmpBaseline:
+    global _omp
+    if _omp is None:
+        _omp = OmpBaseline()
+    return _omp
 
 
 def get() -> Oracle:
@@ -265,4 +322,5 @@ def __getattr__(name):  # module-level convenience: oracle.tpose(...), oracle.su
 
 if __name__ == "__main__":
     build()
-    print(LIB, file=sys.stderr)
+    build_omp()
+    print(LIB, OMP_LIB, file=sys.stderr)
