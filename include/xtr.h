@@ -126,6 +126,22 @@ size_t xtr_reduce_workspace_bytes(int64_t n, int dtype);
 int reduce_sum_ws(const void *src, int64_t n, void *out, int dtype,
                   void *ws, size_t ws_bytes, void *stream);
 
+/* reduce_sum for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, result and errors as reduce_sum (bit for bit), but the call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine):
+ * its workspace is a fixed device array of XTR_NOALLOC_SCRATCH_BYTES that
+ * the library holds on every GPU it runs on until the process ends (its
+ * address is looked up once per device).  n is limited to what that array
+ * holds: 209715 chunks, i.e. about 1.7e9 fp32 or int32, 3.4e9 bf16 or fp16,
+ * 6.9e9 fp8 and 8.6e8 int64 elements; larger n returns XTR_EBUDGET with
+ * nothing enqueued.  Every call
+ * on one GPU shares that GPU's array, whatever the stream: calls that overlap
+ * in time on one GPU race (serialize them on one stream or with events).
+ * The call clears what must start at zero with a fill kernel on `stream`. */
+#define XTR_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+int reduce_sum_noalloc(const void *src, int64_t n, void *out, int dtype, void *stream);
+
 /* ------------------------------------------------------------------------
  * Batched and segmented forms (one persistent launch per batch).
  */

@@ -63,6 +63,7 @@ _SIGS = {
     "xtr_reduce_workspace_bytes": ([C.c_int64, C.c_int], C.c_size_t),
     "reduce_sum_ws": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t,
                        C.c_void_p], C.c_int),
+    "reduce_sum_noalloc": ([C.c_void_p, C.c_int64, C.c_void_p, C.c_int, C.c_void_p], C.c_int),
     "tpose_batched": ([C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
     "reduce_sum_segmented": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p, C.c_int,
                               C.c_void_p], C.c_int),

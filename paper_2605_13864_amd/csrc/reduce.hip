@@ -1331,6 +1331,55 @@ int sum_one_impl(const void *src, int64_t n, void *out, int dtype, bool plain, v
     return sum_one(src, n, out, dtype, plain, ws, ws_bytes, st, who);
 }
 
+// ---------------------------------------------------------------- no allocation
+
+// The workspace of reduce_sum_noalloc: a fixed device array, one copy per GPU,
+// held until the process ends.  Host code never passes the array's name to a
+// kernel (on the host it is only a stand-in for the symbol): it passes the
+// device address hipGetSymbolAddress returns for the current device.
+__device__ __align__(256) unsigned char scratch[XTR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of the current device's copy of `scratch`, looked up once
+// per device (with that device current).
+int scratch_ptr(void **p, const char *who) {
+    int dev = 0;
+    XTR_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) return fail(XTR_EINVAL, "%s: device %d out of range", who, dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *q = nullptr;
+        hipError_t e = hipGetSymbolAddress(&q, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(scratch)");
+        if (!q) return fail(XTR_EHIP, "%s: hipGetSymbolAddress(scratch) gave a null address", who);
+        g_scratch_ptr[dev] = q;
+    }
+    *p = g_scratch_ptr[dev];
+    return XTR_OK;
+}
+
+int sum_noalloc(const void *src, int64_t n, void *out, int dtype, hipStream_t st) {
+    const char *who = "reduce_sum_noalloc";
+    int rc = check_sum_args(src, n, out, dtype, false, who);
+    if (rc) return rc;
+    const int mode = mode_for(dtype, false);
+    const Range rg = host_range(src, n, dtype, out);
+    if (!ws_fits(XTR_NOALLOC_SCRATCH_BYTES, rg.nchunks, parts_bytes(rg.nchunks, mode)))
+        return fail(XTR_EBUDGET, "%s: n = %lld needs %zu bytes of scratch, more than the "
+                    "fixed %zu", who, (long long)n, ws_size_for(rg.nchunks, parts_bytes(rg.nchunks, mode)),
+                    (size_t)XTR_NOALLOC_SCRATCH_BYTES);
+    void *p = nullptr;
+    if ((rc = scratch_ptr(&p, who))) return rc;
+    // The array keeps the previous call's contents: clear the tickets this call
+    // may use (a fill kernel; the partial arrays are written before they are read).
+    const WsView v = split_ws(p, XTR_NOALLOC_SCRATCH_BYTES);
+    if ((rc = zero_fill(v.tickets, (size_t)rg.nchunks * MAXLEV * 4, st))) return rc;
+    return sum_one(src, n, out, dtype, false, p, XTR_NOALLOC_SCRATCH_BYTES, st, who);
+}
+
 }  // namespace xtr
 
 extern "C" {
@@ -1437,6 +1486,10 @@ int reduce_sum_plain_f32(const void *src, int64_t n, float *out, int dtype, void
 
 size_t xtr_reduce_workspace_bytes(int64_t n, int dtype) {
     return xtr::reduce_ws_bytes(n, dtype, false);
+}
+
+int reduce_sum_noalloc(const void *src, int64_t n, void *out, int dtype, void *stream) {
+    return xtr::sum_noalloc(src, n, out, dtype, (hipStream_t)stream);
 }
 
 int reduce_sum_ws(const void *src, int64_t n, void *out, int dtype, void *ws, size_t ws_bytes,
