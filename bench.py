@@ -51,7 +51,9 @@ def log(*a):
 # What decides the kernels of the step and their launches: their sources and
 # the tuned launch settings.  Counter summaries are valid for this hash only.
 STEP_SOURCES = ("paper_2605_13864_amd/csrc/common.hpp", "paper_2605_13864_amd/csrc/runtime.hip",
-                "paper_2605_13864_amd/csrc/tpose.hip", "paper_2605_13864_amd/csrc/reduce.hip",
+                "paper_2605_13864_amd/csrc/tile_map.h", "paper_2605_13864_amd/csrc/tpose_dev.hpp",
+                "paper_2605_13864_amd/csrc/tpose.hip", "paper_2605_13864_amd/csrc/tpose_s2.hip",
+                "paper_2605_13864_amd/csrc/tpose_s4.hip", "paper_2605_13864_amd/csrc/reduce.hip",
                 "paper_2605_13864_amd/tuned/gfx950.json")
 
 
@@ -224,7 +226,7 @@ def _median(v):
     return v[n // 2] if n % 2 else 0.5 * (v[n // 2 - 1] + v[n // 2])
 
 
-def batched_vs_per_job(xtr, torch):
+def batched_vs_per_job(xtr, torch, per_job=True):
     """The batched configuration: 4096 fp32 transposes with sides uniform in
     [16, 2048] (seed 9) as one tpose_batched call against one tpose launch per
     job; 2^27 fp32 values in 100k lognormal(6, 1.5) segments (seeds 10, 11) as
@@ -240,18 +242,26 @@ def batched_vs_per_job(xtr, torch):
         jobs.append((torch.rand((r, c), generator=gen, device="cuda") * 2 - 1,
                      torch.empty((c, r), device="cuda")))
         nbytes += 2 * r * c * 4
+    # one call: host-side validation and grouping, table upload, launches
+    # (the events also see the device idle while the host prepares the batch)
     bt = _ev_ms(torch, lambda: xtr.tpose_batched(jobs), reps=5)
+    plan = xtr.TposePlan(jobs)     # the same batch validated and uploaded once
+    bp = _ev_ms(torch, plan.run, reps=5)
+    plan.close()
 
-    def per_job():
+    def per_job_loop():
         for s_, d_ in jobs:
             xtr.tpose(s_, d_, dtype="f32")
-    pj = _ev_ms(torch, per_job, reps=2)
+    pj = _ev_ms(torch, per_job_loop, reps=2) if per_job else [float("nan")]
     ok = all(torch.equal(jobs[k][1], jobs[k][0].t()) for k in (0, 2047, 4095))
     res["tpose_4096_jobs_f32"] = {
-        "bytes": nbytes, "batched_ms": round(_median(bt), 3),
-        "batched_gbs": round(nbytes / _median(bt) / 1e6, 1),
+        "bytes": nbytes,
+        "batched_ms": round(_median(bp), 3), "batched_gbs": round(nbytes / _median(bp) / 1e6, 1),
+        "batched_call_ms": round(_median(bt), 3),
+        "batched_call_gbs": round(nbytes / _median(bt) / 1e6, 1),
         "per_job_ms": round(_median(pj), 3), "per_job_gbs": round(nbytes / _median(pj) / 1e6, 1),
-        "speedup": round(_median(pj) / _median(bt), 2), "spot_check_ok": ok}
+        "speedup_call_vs_per_job": round(_median(pj) / _median(bt), 2),
+        "spot_check_ok": ok}
     del jobs
     torch.cuda.empty_cache()
     total, nseg = 1 << 27, 100000
@@ -269,14 +279,14 @@ def batched_vs_per_job(xtr, torch):
     def per_seg():
         for v, o_ in zip(views, outs):
             xtr.reduce_sum(v, o_, dtype="f32")
-    ps = _ev_ms(torch, per_seg, reps=1)
+    ps = _ev_ms(torch, per_seg, reps=1) if per_job else [float("nan")]
     nb = total * 4
     res["segmented_100k_f32"] = {
         "bytes": nb, "batched_us": round(_median(sg) * 1e3, 1),
         "batched_gbs": round(nb / _median(sg) / 1e6, 1),
         "per_job_us": round(_median(ps) * 1e3, 1), "per_job_gbs": round(nb / _median(ps) / 1e6, 1),
         "speedup": round(_median(ps) / _median(sg), 1),
-        "bit_identical_to_alone": bool(torch.equal(per, out))}
+        "bit_identical_to_alone": bool(torch.equal(per, out)) if per_job else None}
     del x, ws, views, outs
     torch.cuda.empty_cache()
     return res
@@ -294,14 +304,14 @@ def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12):
     outs = serve.OutputBuffers(torch, jobs)
     warm = [j for j in W.serving_jobs(2000, seed + 1000, rate=rate)
             if serve.InputPool.key(j) in pool.t]
-    serve.run(xtr, torch, warm, pool=pool, outs=outs)
-    serve.run(xtr, torch, warm, batching=False, pool=pool, outs=outs)
+    serve.run_native(xtr, torch, warm, pool=pool, outs=outs)
+    serve.run_native(xtr, torch, warm, batching=False, pool=pool, outs=outs)
     keys = ("jobs", "p50_ms", "p99_ms", "mean_ms", "throughput_gbs", "achieved_jobs_per_s",
             "launches", "batches", "mean_jobs_per_batch", "max_inflight_gib")
-    res = {"rate_jobs_per_s": rate, "seconds": seconds,
+    res = {"rate_jobs_per_s": rate, "seconds": seconds, "loop": "native (xtr_server)",
            "offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1)}
     for name, b in (("batched", True), ("per_job", False)):
-        st = serve.run(xtr, torch, jobs, batching=b, pool=pool, outs=outs)
+        st = serve.run_native(xtr, torch, jobs, batching=b, pool=pool, outs=outs)
         res[name] = {k: st[k] for k in keys}
     res["batched_p99_below_per_job"] = res["batched"]["p99_ms"] < res["per_job"]["p99_ms"]
     del pool, outs
@@ -318,6 +328,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip batched vs per-job")
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
+    ap.add_argument("--no-per-job", action="store_true",
+                    help="batched section without the one-launch-per-job loops (profiling)")
     ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,matmul,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
@@ -399,9 +411,10 @@ def main():
     }
     if not args.no_batched:
         t0 = time.time()
-        out["batched"] = batched_vs_per_job(xtr, torch)
+        out["batched"] = batched_vs_per_job(xtr, torch, per_job=not args.no_per_job)
         b = out["batched"]
-        log(f"bench: batched 4096 transposes {b['tpose_4096_jobs_f32']['batched_gbs']} GB/s vs "
+        log(f"bench: batched 4096 transposes {b['tpose_4096_jobs_f32']['batched_gbs']} GB/s "
+            f"(one call incl. upload {b['tpose_4096_jobs_f32']['batched_call_gbs']}) vs "
             f"per-job {b['tpose_4096_jobs_f32']['per_job_gbs']}; segmented 100k "
             f"{b['segmented_100k_f32']['batched_gbs']} GB/s vs per-job "
             f"{b['segmented_100k_f32']['per_job_gbs']} ({time.time() - t0:.1f}s)")

@@ -357,6 +357,71 @@ int xtr_sum_plan_run(const xtr_sum_plan *plan, void *stream);
 int xtr_sum_plan_destroy(xtr_sum_plan *plan);
 
 /* ------------------------------------------------------------------------
+ * Serving: a request loop with continuous batching (the serving workload;
+ * the paper has no serving).  A server owns a thread and `nstreams` streams
+ * of default priority on the device current at creation.  Each job names a
+ * device-resident input and output the caller owns (they must stay valid and
+ * the input ready until the job completes); the loop allocates nothing per
+ * job.  A job becomes visible to the loop at its arrival time; the loop
+ * admits arrived jobs in FIFO order while the in-flight bytes (input + output
+ * of every admitted, unfinished job) stay within budget_bytes, and launches
+ * the jobs admitted in one pass as units on the next stream, each unit with
+ * a completion event: with batching, jobs under small_job_bytes share one
+ * unit per kind (one tpose_batched / reduce_sum_batched_scatter launch per
+ * element size or dtype) and larger jobs are units of their own unless jobs
+ * are left waiting; without batching, one launch per job.  Results are the
+ * entry points' own (tpose, reduce_sum), bit for bit whatever the mix.
+ */
+typedef struct {
+    int32_t kind;        /* 0: transpose (tpose of a contiguous rows x cols matrix),
+                            1: sum (reduce_sum of n elements)                       */
+    int32_t dtype;
+    const void *src;     /* device input                                            */
+    void *dst;           /* device output: cols x rows matrix, or the sum's result  */
+    int64_t rows, cols;  /* transpose                                               */
+    int64_t n;           /* sum                                                     */
+    int64_t arrival_ns;  /* arrival on xtr_server_clock_ns(); < 0: at submission.
+                            Arrivals are non-decreasing in submission order (a time
+                            before the previous job's is raised to it).             */
+} xtr_job;
+
+typedef struct {
+    int32_t nstreams;         /* 1..8                                              */
+    int32_t batching;         /* 1: continuous batching; 0: one launch per job     */
+    int64_t budget_bytes;     /* HBM budget of the in-flight jobs                  */
+    int64_t small_job_bytes;  /* jobs below this share launch units                */
+    int64_t _reserved[4];
+} xtr_server_config;
+
+typedef struct {
+    int64_t submitted, completed, failed, launches, units, max_inflight_bytes;
+    int64_t _reserved[4];
+} xtr_server_stats;
+
+typedef struct xtr_server xtr_server;
+
+/* The loop's clock: steady host time in nanoseconds. */
+int64_t xtr_server_clock_ns(void);
+/* Starts a server on the current device.  Errors: EINVAL, ENOMEM, EHIP. */
+int xtr_server_create(const xtr_server_config *cfg, xtr_server **srv);
+/* Hands jobs[0..count) (host array, copied) to the loop; *first_id (may be
+ * NULL) receives the id of jobs[0], ids being consecutive in submission
+ * order.  Validated first: EINVAL / EDTYPE for a bad job, EBUDGET for a job
+ * larger than the budget; then nothing is submitted. */
+int xtr_server_submit(xtr_server *srv, const xtr_job *jobs, int64_t count, int64_t *first_id);
+/* Waits until every submitted job has completed (timeout_ms < 0: no limit).
+ * EHIP if some job's launch failed (its completion time is -2). */
+int xtr_server_drain(xtr_server *srv, int64_t timeout_ms);
+/* Arrival and completion times (ns, server clock; completion -1 while
+ * pending, -2 if its launch failed) of jobs [first, first + count); either
+ * output array may be NULL. */
+int xtr_server_times(xtr_server *srv, int64_t first, int64_t count, int64_t *arrival_ns,
+                     int64_t *done_ns);
+int xtr_server_get_stats(xtr_server *srv, xtr_server_stats *stats);
+/* Completes every submitted job, then stops the loop and frees the server. */
+int xtr_server_destroy(xtr_server *srv);
+
+/* ------------------------------------------------------------------------
  * Launch configuration (the autotuner's interface).  The settings change how
  * the work is scheduled, never the result: transposes are bit copies, and
  * the reduction's chunking and combine order do not depend on them.

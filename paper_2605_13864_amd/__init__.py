@@ -46,6 +46,23 @@ class ReduceConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("_reserved", C.c_int32 * 6)]
 
 
+class Job(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("src", C.c_void_p),
+                ("dst", C.c_void_p), ("rows", C.c_int64), ("cols", C.c_int64), ("n", C.c_int64),
+                ("arrival_ns", C.c_int64)]
+
+
+class ServerConfig(C.Structure):
+    _fields_ = [("nstreams", C.c_int32), ("batching", C.c_int32), ("budget_bytes", C.c_int64),
+                ("small_job_bytes", C.c_int64), ("_reserved", C.c_int64 * 4)]
+
+
+class ServerStats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
+                ("launches", C.c_int64), ("units", C.c_int64), ("max_inflight_bytes", C.c_int64),
+                ("_reserved", C.c_int64 * 4)]
+
+
 class TposeDesc(C.Structure):
     _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("rows", C.c_int64),
                 ("cols", C.c_int64), ("ld_src", C.c_int64), ("ld_dst", C.c_int64),
@@ -99,6 +116,13 @@ _SIGS = {
     "xtr_tpose_set_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_reduce_get_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_reduce_set_config": ([C.c_int, C.c_void_p], C.c_int),
+    "xtr_server_clock_ns": ([], C.c_int64),
+    "xtr_server_create": ([C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_server_submit": ([C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p], C.c_int),
+    "xtr_server_drain": ([C.c_void_p, C.c_int64], C.c_int),
+    "xtr_server_times": ([C.c_void_p, C.c_int64, C.c_int64, C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_server_get_stats": ([C.c_void_p, C.c_void_p], C.c_int),
+    "xtr_server_destroy": ([C.c_void_p], C.c_int),
     "xtr_last_error": ([], C.c_char_p),
     "xtr_elem_bytes": ([C.c_int], C.c_int),
     "xtr_version": ([], C.c_int),
@@ -387,6 +411,63 @@ def reduce_sum_segmented_ws(src, offsets, ws, out=None, *, total=None, dtype=Non
                                                C.c_void_p(ws.data_ptr()), wsb, _stream(stream))
         _check(rc, "reduce_sum_segmented_ws_total")
     return out
+
+
+class Server:
+    """The native request loop (xtr_server_*): submit jobs on device-resident
+    tensors, drain, read arrival / completion times (ns, server clock)."""
+
+    def __init__(self, *, nstreams=4, batching=True, budget=64 << 30, small_job_bytes=4 << 20):
+        lib = load()
+        cfg = ServerConfig(nstreams, int(bool(batching)), int(budget), int(small_job_bytes))
+        h = C.c_void_p()
+        _check(lib.xtr_server_create(C.byref(cfg), C.byref(h)), "xtr_server_create")
+        self._h = h
+        self.count = 0
+
+    @staticmethod
+    def clock_ns() -> int:
+        return int(load().xtr_server_clock_ns())
+
+    def submit(self, jobs) -> int:
+        """jobs: a ctypes array of Job (or a list of Job); returns the first id."""
+        if not isinstance(jobs, C.Array):
+            arr = (Job * len(jobs))(*jobs)
+        else:
+            arr = jobs
+        first = C.c_int64(0)
+        _check(_lib.xtr_server_submit(self._h, C.cast(arr, C.c_void_p), len(arr), C.byref(first)),
+               "xtr_server_submit")
+        self.count += len(arr)
+        return first.value
+
+    def drain(self, timeout_ms: int = -1):
+        _check(_lib.xtr_server_drain(self._h, int(timeout_ms)), "xtr_server_drain")
+
+    def times(self, first: int = 0, count: int | None = None):
+        import numpy as np
+        count = self.count - first if count is None else count
+        arr = np.empty(count, dtype=np.int64)
+        done = np.empty(count, dtype=np.int64)
+        _check(_lib.xtr_server_times(self._h, first, count, arr.ctypes.data_as(C.c_void_p),
+                                     done.ctypes.data_as(C.c_void_p)), "xtr_server_times")
+        return arr, done
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(_lib.xtr_server_get_stats(self._h, C.byref(st)), "xtr_server_get_stats")
+        return {k: getattr(st, k) for k, _ in ServerStats._fields_ if k != "_reserved"}
+
+    def close(self):
+        if self._h:
+            _lib.xtr_server_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def scan_lookback_bound(polls: int) -> int:

@@ -54,9 +54,11 @@ def compile_one(src: str, extra=()) -> str:
     return obj
 
 
-def build(jobs: int = 4, save_temps: str | None = None) -> str:
+def build(jobs: int = 8, save_temps: str | None = None) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    # longest compiles first (the transpose units), so the pool stays busy
+    srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")), key=lambda f: -os.path.getsize(f))
+    srcs.sort(key=lambda f: not os.path.basename(f).startswith("tpose_"))
     extra = []
     if save_temps:
         os.makedirs(save_temps, exist_ok=True)
@@ -81,7 +83,7 @@ def build(jobs: int = 4, save_temps: str | None = None) -> str:
 
 if __name__ == "__main__":
     ap = argparse.ArgumentParser()
-    ap.add_argument("--jobs", type=int, default=4)
+    ap.add_argument("--jobs", type=int, default=8)
     ap.add_argument("--save-temps", default=None)
     a = ap.parse_args()
     print(build(a.jobs, a.save_temps))

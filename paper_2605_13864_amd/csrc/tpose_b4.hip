@@ -1,0 +1,16 @@
+// Transpose kernels of 4-byte elements, batched launches (the kernel templates
+// are in tpose_dev.hpp; one element size and form per translation unit, so
+// the instantiations compile in parallel).
+#include "tpose_dev.hpp"
+
+namespace xtr {
+namespace tpk {
+
+void launch_group_e4(int w, bool off32, bool lines, bool wide, int64_t grid, hipStream_t st,
+                       const Job *jobs, const int64_t *bases, int nj, int64_t ntiles,
+                       const JobPack *pk) {
+    launch_batched<4>(w, off32, lines, wide, grid, st, jobs, bases, nj, ntiles, pk);
+}
+
+}  // namespace tpk
+}  // namespace xtr

@@ -29,6 +29,12 @@ unit and launch, with its own event (the comparison).
 The policy (`Scheduler`) is separate from the device (`GpuExecutor`), so the
 admission and batching rules are tested on the CPU with a fake clock and a
 fake executor.
+
+`run_native` serves the same jobs with the library's native loop
+(`xtr_server_*`: the same policy in C++, csrc/serve_policy.h, on a server
+thread, so no Python runs between an arrival and its launch); `run` is this
+module's Python loop with the same policy plus per-class output slots.  The
+benchmark uses the native loop.
 """
 from __future__ import annotations
 
@@ -320,6 +326,76 @@ def run(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=No
     return stats
 
 
+def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=None,
+               outs=None, keep_results=False, lead_s=0.005, log=None):
+    """Serve `jobs` with the native request loop (xtr_server_*, the same
+    policy as Scheduler, in a server thread of the library): the whole arrival
+    schedule is handed over at once and each job becomes visible to the loop
+    at its arrival time, so no host-side submission cost enters the
+    latencies.  With keep_results every job gets an output of its own (else
+    the jobs of a class take that class's output slots in turn: the timing
+    does not depend on the values).  Returns stats like run()."""
+    pool = pool or InputPool(torch, jobs)
+    arr = (xtr.Job * len(jobs))()
+    keep = []
+    nxt = {}
+    if not keep_results:
+        outs = outs or OutputBuffers(torch, jobs)
+    for i, j in enumerate(jobs):
+        x = pool.get(j)
+        c = job_class(j)
+        if keep_results:
+            if j.kind == "tpose":
+                o = torch.empty((j.cols, j.rows), dtype=x.dtype, device="cuda")
+            else:
+                o = torch.empty((), dtype=torch.float64 if j.dtype == "f32" else torch.int64,
+                                device="cuda")
+            keep.append(o)
+        else:
+            s = nxt.get(c, 0)
+            nxt[c] = (s + 1) % outs.counts[c]
+            o = outs.out(c, s)
+        a = arr[i]
+        a.kind = 0 if j.kind == "tpose" else 1
+        a.dtype = xtr.CODES[j.dtype]
+        a.src = x.data_ptr()
+        a.dst = o.data_ptr()
+        a.rows, a.cols, a.n = j.rows, j.cols, j.n
+    torch.cuda.synchronize()                     # inputs and outputs exist before serving
+    srv = xtr.Server(nstreams=nstreams, batching=batching, budget=budget)
+    t0 = xtr.Server.clock_ns() + int(lead_s * 1e9)
+    for i, j in enumerate(jobs):
+        arr[i].arrival_ns = t0 + int(round(j.arrival_s * 1e9))
+    srv.submit(arr)
+    srv.drain()
+    arrival, done = srv.times()
+    st = srv.stats()
+    srv.close()
+    lat = (done - arrival) * 1e-9
+    tot_bytes = sum(j.nbytes for j in jobs)
+    span = (done.max() - arrival.min()) * 1e-9
+    stats = {
+        "jobs": len(jobs), "batching": batching, "streams": nstreams, "loop": "native",
+        "budget_gib": budget / 2 ** 30, "max_inflight_gib": round(st["max_inflight_bytes"] / 2 ** 30, 3),
+        "max_inflight_bytes": int(st["max_inflight_bytes"]),
+        "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 4),
+        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 4),
+        "mean_ms": round(float(np.mean(lat)) * 1e3, 4),
+        "max_ms": round(float(np.max(lat)) * 1e3, 4),
+        "throughput_gbs": round(tot_bytes / span / 1e9, 1),
+        "offered_jobs_per_s": round(len(jobs) / max(jobs[-1].arrival_s - jobs[0].arrival_s, 1e-12), 1),
+        "achieved_jobs_per_s": round(len(jobs) / span, 1),
+        "launches": st["launches"], "batches": st["units"],
+        "mean_jobs_per_batch": round(len(jobs) / max(st["units"], 1), 2),
+    }
+    if log:
+        log(f"serve (native) batching={batching}: p50 {stats['p50_ms']} ms p99 {stats['p99_ms']} ms, "
+            f"{stats['throughput_gbs']} GB/s, {stats['launches']} launches in {stats['batches']} units")
+    if keep_results:
+        stats["results"] = {i: keep[i] for i in range(len(jobs))}
+    return stats
+
+
 def bench(xtr, torch, log, count=200000, seed=12, rate=20000.0,
           sweep=((60000.0, 120000), (200000.0, 100000))):
     """The serving workload: a Poisson stream (mean 20k jobs/s) of mixed jobs,
@@ -333,15 +409,18 @@ def bench(xtr, torch, log, count=200000, seed=12, rate=20000.0,
     warm = [j for j in W.serving_jobs(3000, seed + 1000, rate=rate) if InputPool.key(j) in pool.t]
     run(xtr, torch, warm, pool=pool, outs=outs)
     run(xtr, torch, warm, batching=False, pool=pool, outs=outs)
+    run_native(xtr, torch, warm, pool=pool, outs=outs)
     out = {"offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1), "rate_jobs_per_s": rate}
-    out["batched"] = run(xtr, torch, jobs, batching=True, pool=pool, outs=outs, log=log)
-    out["per_job"] = run(xtr, torch, jobs, batching=False, pool=pool, outs=outs, log=log)
+    out["batched"] = run_native(xtr, torch, jobs, batching=True, pool=pool, outs=outs, log=log)
+    out["per_job"] = run_native(xtr, torch, jobs, batching=False, pool=pool, outs=outs, log=log)
+    out["python_loop_batched"] = run(xtr, torch, jobs[:40000], batching=True, pool=pool, outs=outs,
+                                     log=log)
     out["sweep"] = []
     for r, c in sweep:
         js = [j for j in W.serving_jobs(c, seed + int(r), rate=r) if InputPool.key(j) in pool.t]
         ent = {"rate_jobs_per_s": r, "offered_gbs": round(W.mean_job_bytes() * r / 1e9, 1)}
         for name, b in (("batched", True), ("per_job", False)):
-            st = run(xtr, torch, js, batching=b, pool=pool, outs=outs, log=log)
+            st = run_native(xtr, torch, js, batching=b, pool=pool, outs=outs, log=log)
             ent[name] = {k: st[k] for k in ("jobs", "p50_ms", "p99_ms", "throughput_gbs",
                                             "achieved_jobs_per_s", "launches", "batches")}
         out["sweep"].append(ent)

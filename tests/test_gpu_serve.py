@@ -43,3 +43,51 @@ def test_results_same_alone_and_in_mix(xtr, orc, batching):
                     assert got.item() == orc.sum_int(h, "i32")[0]
                 else:
                     check_float_sum(got.item(), orc.sum_float(h, "f32"), orc.sum_abs(h, "f32"), i)
+
+
+@pytest.mark.parametrize("batching", [True, False])
+def test_native_loop_same_alone_and_in_mix(xtr, orc, batching):
+    """The native request loop (xtr_server_*): every job's result in the mix
+    equals the job run alone, bit for bit; the in-flight bytes stay within a
+    tight budget; every job completes after it arrives."""
+    import torch
+    from paper_2605_13864_amd import serve
+    jobs = W.serving_jobs(800, 22, rate=20000.0, tpose_k=(5, 10), sum_k=(10, 20))
+    budget = 64 << 20
+    st = serve.run_native(xtr, torch, jobs, batching=batching, budget=budget, keep_results=True)
+    assert 0 < st["max_inflight_bytes"] <= budget
+    assert st["p50_ms"] > 0 and st["max_ms"] < 5000
+    pool = serve.InputPool(torch, jobs)
+    for i, j in enumerate(jobs):
+        x = pool.get(j)
+        got = st["results"][i]
+        if j.kind == "tpose":
+            alone = xtr.tpose(x)
+            a = got.view(torch.int16) if x.dtype == torch.bfloat16 else got.view(torch.int32)
+            b = alone.view(torch.int16) if x.dtype == torch.bfloat16 else alone.view(torch.int32)
+            assert torch.equal(a, b), i
+        else:
+            alone = xtr.reduce_sum(x)
+            assert got.item() == alone.item(), (i, got.item(), alone.item())
+            if i % 20 == 0 and j.dtype == "i32":
+                assert got.item() == orc.sum_int(x.cpu().numpy(), "i32")[0]
+
+
+def test_native_loop_validation(xtr):
+    """Submission refuses bad jobs before anything is queued: an unknown kind,
+    a dtype the sums do not take, a job larger than the budget."""
+    import torch
+    x = torch.zeros(64, dtype=torch.float32, device="cuda")
+    o = torch.zeros((), dtype=torch.float64, device="cuda")
+    srv = xtr.Server(budget=1 << 20)
+    bad = [xtr.Job(7, 0, x.data_ptr(), o.data_ptr(), 0, 0, 64, -1),
+           xtr.Job(1, xtr.CODES["u8"], x.data_ptr(), o.data_ptr(), 0, 0, 64, -1),
+           xtr.Job(1, 0, x.data_ptr(), o.data_ptr(), 0, 0, 1 << 20, -1)]
+    for j, code in zip(bad, (-1, -2, -7)):
+        with pytest.raises(xtr.XtrError) as e:
+            srv.submit([j])
+        assert e.value.code == code
+    srv.submit([xtr.Job(1, 0, x.data_ptr(), o.data_ptr(), 0, 0, 64, -1)])
+    srv.drain(10000)
+    assert srv.stats()["completed"] == 1 and o.item() == 0.0
+    srv.close()

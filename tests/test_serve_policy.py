@@ -127,3 +127,21 @@ def test_per_job_units_each_have_their_own_completion():
     sch, ex, _ = simulate(jobs, 1 << 40, slots_for(jobs, 64), batching=False, dt=1e-4)
     assert all(len(ix) == 1 for ix, _ in ex.launched)
     assert sch.batches == len(jobs) == sch.launches
+
+
+def test_native_policy_host_check(tmp_path):
+    """The native loop's policy (csrc/serve_policy.h) under a fake clock and
+    executor (tests/native/serve_policy_check.cpp): budget, FIFO admission,
+    completion, the batching rule, failed launches."""
+    import os
+    import shutil
+    import subprocess
+    if shutil.which("g++") is None:
+        import pytest
+        pytest.skip("needs g++")
+    here = os.path.dirname(os.path.abspath(__file__))
+    exe = os.path.join(tmp_path, "serve_policy_check")
+    subprocess.run(["g++", "-std=c++17", "-O2", "-o", exe,
+                    os.path.join(here, "native", "serve_policy_check.cpp")], check=True)
+    r = subprocess.run([exe], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0 and "serving policy ok" in r.stdout, r.stdout
