@@ -136,6 +136,43 @@ def batched_tpose(xtr, torch, log, count=4096, seed=9):
     return res
 
 
+def batched_probe(xtr, torch, log, seed=9):
+    """Where batched transposes lose: the same 4096-job fp32 batch (plan,
+    device time) against batches that differ in one respect each -- sides
+    rounded up to multiples of 32 (every row on cache lines, 16-byte pieces),
+    4096 equal 1024^2 and 1023^2 jobs (no size spread; aligned / not), 16
+    jobs of 8192^2 (few large jobs) -- and a single 16383^2 transpose."""
+    import workloads as W
+    res = {}
+    shapes = W.batched_shapes(4096, seed)
+    cases = {"config": shapes,
+             "rounded_32": [((r + 31) // 32 * 32, (c + 31) // 32 * 32) for r, c in shapes],
+             "equal_1024": [(1024, 1024)] * 4096, "equal_1023": [(1023, 1023)] * 4096,
+             "large_8192": [(8192, 8192)] * 16}
+    gen = torch.Generator("cuda").manual_seed(seed)
+    for name, shp in cases.items():
+        jobs, nb = [], 0
+        for r, c in shp:
+            jobs.append((torch.rand((r, c), generator=gen, device="cuda"),
+                         torch.empty((c, r), device="cuda")))
+            nb += 2 * r * c * 4
+        plan = xtr.TposePlan(jobs)
+        sec, _ = _time_dev(torch, plan.run, reps=5, warm=1)
+        plan.close()
+        res[name] = {"gbs": round(nb / sec / 1e9, 1), "ms": round(sec * 1e3, 3),
+                     "bytes": nb, "jobs": len(shp)}
+        del jobs
+        torch.cuda.empty_cache()
+    x = torch.rand((16383, 16383), generator=gen, device="cuda")
+    y = torch.empty((16383, 16383), device="cuda")
+    sec, _ = _time_dev(torch, lambda: xtr.tpose(x, y, dtype="f32"), reps=10, warm=2)
+    res["single_16383"] = {"gbs": round(2 * 16383 * 16383 * 4 / sec / 1e9, 1)}
+    del x, y
+    torch.cuda.empty_cache()
+    log("suite batched probe: " + ", ".join(f"{k} {v['gbs']}" for k, v in res.items()))
+    return res
+
+
 # ---------------------------------------------------------------- segmented sums
 
 def segmented(xtr, torch, log, total=1 << 27, nseg=100000):
@@ -392,6 +429,7 @@ def run_all(xtr, torch, log, parts=("paper", "widths", "batched", "segmented", "
                                    "host", "scan", "hist", "matmul", "serving")):
     out = {}
     for name, fn in (("paper", paper_shapes), ("widths", piece_widths), ("batched", batched_tpose),
+                     ("bprobe", batched_probe),
                      ("host", host_buffers), ("scan", prefix_sums), ("hist", histograms),
                      ("matmul", matmuls),
                      ("segmented", segmented), ("precision", precision)):

@@ -444,9 +444,20 @@ typedef struct {
     int32_t _reserved[3];
 } xtr_tpose_config;
 
-/* Current / new configuration of tpose for one element size (1, 2, 4, 8).
+/* Shape classes of the launch configurations: single calls (tpose,
+ * reduce_sum and their _ws / host / no-allocation forms) and batched ones
+ * (tpose_batched and its plans, reduce_sum_batched(_scatter), sum plans,
+ * reduce_sum_segmented).  Each class has its own tuned settings. */
+enum { XTR_SHAPE_SINGLE = 0, XTR_SHAPE_BATCHED = 1 };
+
+/* Current / new configuration of tpose for one element size (1, 2, 4, 8) and
+ * shape class.  In the batched class blocks_per_cu caps the workgroups of a
+ * group's persistent launch per CU (0: as many as are resident at once).
  * Process-wide; not synchronized with launches in flight on other threads.
  * Errors: EINVAL. */
+int xtr_tpose_get_class_config(int elem_bytes, int shape_class, xtr_tpose_config *cfg);
+int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_config *cfg);
+/* The single-call class; set applies to every class. */
 int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg);
 int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg);
 
@@ -460,7 +471,11 @@ typedef struct {
     int32_t _reserved[6];
 } xtr_reduce_config;
 
-/* Current / new configuration of the sums for one dtype.  Errors: EINVAL. */
+/* Current / new configuration of the sums for one dtype and shape class
+ * (split_chunks applies to single ranges only).  Errors: EINVAL. */
+int xtr_reduce_get_class_config(int dtype, int shape_class, xtr_reduce_config *cfg);
+int xtr_reduce_set_class_config(int dtype, int shape_class, const xtr_reduce_config *cfg);
+/* The single-call class; set applies to every class. */
 int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg);
 int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg);
 

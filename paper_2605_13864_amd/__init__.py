@@ -112,6 +112,10 @@ _SIGS = {
                              C.c_void_p], C.c_int),
     "xtr_sum_plan_run": ([C.c_void_p, C.c_void_p], C.c_int),
     "xtr_sum_plan_destroy": ([C.c_void_p], C.c_int),
+    "xtr_tpose_get_class_config": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "xtr_tpose_set_class_config": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "xtr_reduce_get_class_config": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
+    "xtr_reduce_set_class_config": ([C.c_int, C.c_int, C.c_void_p], C.c_int),
     "xtr_tpose_get_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_tpose_set_config": ([C.c_int, C.c_void_p], C.c_int),
     "xtr_reduce_get_config": ([C.c_int, C.c_void_p], C.c_int),
@@ -502,16 +506,24 @@ def copy(dst, src, nbytes=None, *, stream=None):
     return dst
 
 
-def tpose_config(elem_bytes: int) -> dict:
+SHAPE_CLASSES = {"single": 0, "batched": 1}
+
+
+def tpose_config(elem_bytes: int, shape: str = "single") -> dict:
+    """Launch settings of the transposes of one element size, for single
+    calls or batched launches."""
     c = TposeConfig()
-    _check(load().xtr_tpose_get_config(elem_bytes, C.byref(c)), "xtr_tpose_get_config")
+    _check(load().xtr_tpose_get_class_config(elem_bytes, SHAPE_CLASSES[shape], C.byref(c)),
+           "xtr_tpose_get_class_config")
     return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
             "blocks_per_cu": c.blocks_per_cu, "nt_store_shared": c.nt_store_shared,
             "nt_load_shared": c.nt_load_shared, "tile": c.tile, "tile_shared": c.tile_shared}
 
 
-def set_tpose_config(elem_bytes: int, **kw):
-    cur = tpose_config(elem_bytes)
+def set_tpose_config(elem_bytes: int, shape: str | None = None, **kw):
+    """Change settings of one shape class ("single" / "batched"), or of every
+    class (shape=None, starting from the single-call settings)."""
+    cur = tpose_config(elem_bytes, shape or "single")
     bad = set(kw) - set(cur)
     if bad:
         raise TypeError(f"set_tpose_config: unknown settings {sorted(bad)}")
@@ -519,23 +531,32 @@ def set_tpose_config(elem_bytes: int, **kw):
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
                     cur["blocks_per_cu"], cur["nt_store_shared"], cur["nt_load_shared"],
                     cur["tile"], cur["tile_shared"])
-    _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
+    if shape is None:
+        _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
+    else:
+        _check(load().xtr_tpose_set_class_config(elem_bytes, SHAPE_CLASSES[shape], C.byref(c)),
+               "xtr_tpose_set_class_config")
 
 
-def reduce_config(dtype) -> dict:
+def reduce_config(dtype, shape: str = "single") -> dict:
     c = ReduceConfig()
-    _check(load().xtr_reduce_get_config(_code(dtype), C.byref(c)), "xtr_reduce_get_config")
+    _check(load().xtr_reduce_get_class_config(_code(dtype), SHAPE_CLASSES[shape], C.byref(c)),
+           "xtr_reduce_get_class_config")
     return {"nt_load": c.nt_load, "split_chunks": c.split_chunks}
 
 
-def set_reduce_config(dtype, **kw):
-    cur = reduce_config(dtype)
+def set_reduce_config(dtype, shape: str | None = None, **kw):
+    cur = reduce_config(dtype, shape or "single")
     bad = set(kw) - set(cur)
     if bad:
         raise TypeError(f"set_reduce_config: unknown settings {sorted(bad)}")
     cur.update(kw)
     c = ReduceConfig(cur["nt_load"], cur["split_chunks"])
-    _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
+    if shape is None:
+        _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
+    else:
+        _check(load().xtr_reduce_set_class_config(_code(dtype), SHAPE_CLASSES[shape], C.byref(c)),
+               "xtr_reduce_set_class_config")
 
 
 def reduce_sum_batched_scatter(srcs, outs, *, ns=None, dtype=None, stream=None):

@@ -957,12 +957,15 @@ int check_sum_args(const void *src, int64_t n, const void *out, int dtype, bool 
 
 // Tuned settings per dtype (index = dtype code).
 constexpr int SPLIT_DEFAULT = 1024;
-xtr_reduce_config g_rcfg[XTR_U16 + 1] = {};
+// g_rcfg[XTR_SHAPE_SINGLE]: single ranges (reduce_sum, its _ws / no-allocation /
+// host forms); g_rcfg[XTR_SHAPE_BATCHED]: batched and segmented launches.
+xtr_reduce_config g_rcfg[2][XTR_U16 + 1] = {};
 bool rcfg_init() {
-    for (auto &c : g_rcfg) {
-        c.nt_load = 1;
-        c.split_chunks = SPLIT_DEFAULT;
-    }
+    for (auto &cls : g_rcfg)
+        for (auto &c : cls) {
+            c.nt_load = 1;
+            c.split_chunks = SPLIT_DEFAULT;
+        }
     return true;
 }
 bool g_rcfg_ready = rcfg_init();
@@ -970,7 +973,7 @@ bool g_rcfg_ready = rcfg_init();
 // In-kernel ticket combine: one workgroup per chunk of rg.
 template <int DT, int MODE>
 void launch_one_ticket(const Range &rg, const Levels &lv, hipStream_t st) {
-    if (g_rcfg[DT].nt_load)
+    if (g_rcfg[XTR_SHAPE_SINGLE][DT].nt_load)
         hipLaunchKernelGGL((k_reduce_one<DT, MODE, true>), dim3((unsigned)rg.nchunks), dim3(NTHR), 0,
                            st, rg, lv);
     else
@@ -984,7 +987,7 @@ void launch_one_ticket(const Range &rg, const Levels &lv, hipStream_t st) {
 template <int DT, int MODE>
 void launch_parts(const Range &rg, const Levels &lv, hipStream_t st) {
     const dim3 g((unsigned)rg.nchunks);
-    if (g_rcfg[DT].nt_load)
+    if (g_rcfg[XTR_SHAPE_SINGLE][DT].nt_load)
         hipLaunchKernelGGL((k_reduce_parts<DT, MODE, true>), g, dim3(NTHR), 0, st, rg, lv);
     else
         hipLaunchKernelGGL((k_reduce_parts<DT, MODE, false>), g, dim3(NTHR), 0, st, rg, lv);
@@ -1005,7 +1008,7 @@ void launch_combine(const Levels &lv, int64_t cnt, void *dst, hipStream_t st) {
 
 template <int DT, int MODE>
 void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
-    const xtr_reduce_config &c = g_rcfg[DT];
+    const xtr_reduce_config &c = g_rcfg[XTR_SHAPE_SINGLE][DT];
     if (c.split_chunks > 0 && rg.nchunks >= c.split_chunks && rg.nchunks > 1) {
         launch_parts<DT, MODE>(rg, lv, st);
         launch_combine<MODE>(lv, rg.nchunks, rg.dst, st);
@@ -1016,7 +1019,7 @@ void launch_one(const Range &rg, const Levels &lv, hipStream_t st) {
 template <int DT, int MODE>
 void launch_table_inl(const RangePack &pk, int nr, int64_t nchunks, const Levels &lv,
                       hipStream_t st) {
-    if (g_rcfg[DT].nt_load)
+    if (g_rcfg[XTR_SHAPE_BATCHED][DT].nt_load)
         hipLaunchKernelGGL((k_reduce_table_inl<DT, MODE, true>), dim3((unsigned)nchunks),
                            dim3(NTHR), 0, st, pk, nr, lv);
     else
@@ -1025,7 +1028,7 @@ void launch_table_inl(const RangePack &pk, int nr, int64_t nchunks, const Levels
 }
 template <int DT, int MODE>
 void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, hipStream_t st) {
-    if (g_rcfg[DT].nt_load)
+    if (g_rcfg[XTR_SHAPE_BATCHED][DT].nt_load)
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, true>), dim3((unsigned)nchunks), dim3(NTHR), 0,
                            st, tab, nr, lv);
     else
@@ -1037,7 +1040,7 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const ChunkRec *cs,
                 int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
-    const bool nt = g_rcfg[DT].nt_load != 0;
+    const bool nt = g_rcfg[XTR_SHAPE_BATCHED][DT].nt_load != 0;
     const int64_t gs_n = (nseg + NW - 1) / NW;                 // workgroups, one wave per segment
     const int64_t gc_n = cap > nseg ? cap : nseg;
 #define XTR_SEG(NTV)                                                                             \
@@ -1459,20 +1462,32 @@ int xtr_sum_plan_destroy(xtr_sum_plan *p) {
     return XTR_OK;
 }
 
-int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
-    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
-        return xtr::fail(XTR_EINVAL, "xtr_reduce_get_config: bad arguments");
-    *cfg = xtr::g_rcfg[dtype];
+int xtr_reduce_get_class_config(int dtype, int shape_class, xtr_reduce_config *cfg) {
+    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)) ||
+        (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_get_class_config: bad arguments");
+    *cfg = xtr::g_rcfg[shape_class][dtype];
     return XTR_OK;
 }
 
-int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
-    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)))
-        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: bad arguments");
+int xtr_reduce_set_class_config(int dtype, int shape_class, const xtr_reduce_config *cfg) {
+    if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)) ||
+        (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: bad arguments");
     if (cfg->split_chunks < 0)
-        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_config: split_chunks must be >= 0");
-    xtr::g_rcfg[dtype] = *cfg;
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: split_chunks must be >= 0");
+    xtr::g_rcfg[shape_class][dtype] = *cfg;
     return XTR_OK;
+}
+
+int xtr_reduce_get_config(int dtype, xtr_reduce_config *cfg) {
+    return xtr_reduce_get_class_config(dtype, XTR_SHAPE_SINGLE, cfg);
+}
+
+int xtr_reduce_set_config(int dtype, const xtr_reduce_config *cfg) {
+    int rc = xtr_reduce_set_class_config(dtype, XTR_SHAPE_SINGLE, cfg);
+    if (rc == XTR_OK) rc = xtr_reduce_set_class_config(dtype, XTR_SHAPE_BATCHED, cfg);
+    return rc;
 }
 
 int xtr_reduce_sum_host(const void *src, int64_t n, void *out, int dtype) {

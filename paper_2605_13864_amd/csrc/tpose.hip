@@ -44,10 +44,13 @@
 namespace xtr {
 using namespace tpk;
 
-// Tuned launch configuration per element size (index log2(elem bytes)).
-xtr_tpose_config tpk::g_cfg[4] = {
-    {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
-    {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
+// Tuned launch configuration per shape class and element size (slot
+// cfg_slot(elem bytes)).
+xtr_tpose_config tpk::g_cfg[2][4] = {
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}},
 };
 
 namespace {
@@ -230,7 +233,7 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         j.w = piece_width(d.src, d.dst, d.ld_src, d.ld_dst, eb);
         j._pad = 0;
         const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
-        const xtr_tpose_config &c = g_cfg[cfg_slot(eb)];
+        const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(eb)];
         const bool wide = eb >= 2 && j.w >= 4 && (lines ? c.tile : c.tile_shared) == 2 &&
                           tiles_for(eb, d.rows, d.cols, nullptr) >= WIDE_MIN_TILES &&
                           off32_wide(eb, d.ld_src, d.ld_dst);
@@ -388,22 +391,34 @@ int xtr_tpose_plan_destroy(xtr_tpose_plan *plan) {
     return XTR_OK;
 }
 
-int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg) {
-    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_get_config: bad arguments");
-    *cfg = xtr::g_cfg[xtr::cfg_slot(elem_bytes)];
+int xtr_tpose_get_class_config(int elem_bytes, int shape_class, xtr_tpose_config *cfg) {
+    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
+        (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_get_class_config: bad arguments");
+    *cfg = xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)];
     return XTR_OK;
 }
 
-int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg) {
-    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8))
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: bad arguments");
+int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_config *cfg) {
+    if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
+        (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: bad arguments");
     if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         cfg->tile < 0 || cfg->tile > 2 || cfg->tile_shared < 0 || cfg->tile_shared > 2)
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_config: group in [1, 64], blocks_per_cu in "
-                                     "[0, 64], tile and tile_shared in [0, 2]");
-    xtr::g_cfg[xtr::cfg_slot(elem_bytes)] = *cfg;
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: group in [1, 64], blocks_per_cu "
+                                     "in [0, 64], tile and tile_shared in [0, 2]");
+    xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
+}
+
+int xtr_tpose_get_config(int elem_bytes, xtr_tpose_config *cfg) {
+    return xtr_tpose_get_class_config(elem_bytes, XTR_SHAPE_SINGLE, cfg);
+}
+
+int xtr_tpose_set_config(int elem_bytes, const xtr_tpose_config *cfg) {
+    int rc = xtr_tpose_set_class_config(elem_bytes, XTR_SHAPE_SINGLE, cfg);
+    if (rc == XTR_OK) rc = xtr_tpose_set_class_config(elem_bytes, XTR_SHAPE_BATCHED, cfg);
+    return rc;
 }
 
 }  // extern "C"

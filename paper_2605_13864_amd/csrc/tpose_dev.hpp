@@ -644,7 +644,9 @@ constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs lo
 
 // Tuned launch configuration per element size (slot cfg_slot(elem bytes));
 // defined in tpose.hip, set through xtr_tpose_set_config.
-extern xtr_tpose_config g_cfg[4];
+// g_cfg[XTR_SHAPE_SINGLE] serves single transposes, g_cfg[XTR_SHAPE_BATCHED]
+// the groups of batched launches.
+extern xtr_tpose_config g_cfg[2][4];
 inline int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3; }
 
 template <int EB, int W, bool NTL, bool NTS, int SC, int DC>
@@ -707,7 +709,7 @@ constexpr int64_t SINGLE_WIDE_MIN_TILES = 2048;
 template <int EB>
 int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
                int64_t ld_dst, hipStream_t stream) {
-    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
+    const xtr_tpose_config &c = g_cfg[XTR_SHAPE_SINGLE][cfg_slot(EB)];
     const bool lines = lines_ok(src, ld_src, EB) && lines_ok(dst, ld_dst, EB);
     const int64_t ntiles = ((rows + Geo<EB>::TR - 1) / Geo<EB>::TR) *
                            ((cols + Geo<EB>::TC - 1) / Geo<EB>::TC);
@@ -757,21 +759,23 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 template <int EB, int W, bool OFF32, int DC = 16>
 void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
                       const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
-    const xtr_tpose_config &c = g_cfg[cfg_slot(EB)];
+    const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(EB)];
     const bool ntl = lines ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines ? c.nt_store != 0 : c.nt_store_shared != 0;
     const int group = c.group < 1 ? 1 : c.group;
+    // persistent grid: the resident capacity, or blocks_per_cu workgroups per CU
+    const int cap = c.blocks_per_cu;
 #define XTR_KB(NL, NS)                                                                      \
     do {                                                                                    \
         if (pk) {                                                                           \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>, NT);           \
+                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>, NT, cap);      \
             hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>),             \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                *pk, nj, ntiles, c.xcd, group);                              \
         } else {                                                                            \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, DC>, NT);               \
+                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, DC>, NT, cap);          \
             hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, DC>),                 \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                jobs, bases, nj, ntiles, c.xcd, group);                      \

@@ -2,13 +2,24 @@
 
     python -m paper_2605_13864_amd.tune [--quick] [--out PATH]
 
-For every element size it times each candidate ``xtr_tpose_config`` (streaming
-loads / stores, XCD-contiguous tile ranges, band height of the tile order,
-one-tile-per-workgroup or persistent grids, tile geometry) on a representative large
-transpose, and each ``xtr_reduce_config`` on a large sum, with HIP events on
-the launching stream; the fastest wins.  Results are written as JSON keyed by
-GPU architecture and element size / dtype; ``load_tuned()`` applies a file at
-import time (the package does this for ``tuned/<arch>.json`` when present).
+Configurations are tuned per GPU architecture, element size / dtype and shape
+class (the classes of ``xtr_tpose_set_class_config``):
+
+* single: every candidate ``xtr_tpose_config`` (streaming loads / stores,
+  XCD-contiguous tile ranges, band height of the tile order,
+  one-tile-per-workgroup or persistent grids of k workgroups per CU, tile
+  geometry = row-segment width) is timed on a representative large
+  transpose, then the settings of rows that share cache lines on two shapes
+  that have them; each ``xtr_reduce_config`` on a large sum;
+* batched: the same axes on a batch of jobs with sides uniform in
+  [16, 2048] (persistent grids of k workgroups per CU, i.e. how many tiles
+  each workgroup takes in turn; streaming flags; tile order; wide dst
+  segments for jobs whose rows share lines), and the sums' streaming loads
+  on the 100k-segment sum.
+
+Every timing uses HIP events on the launching stream; the fastest wins.
+Results are written as JSON; ``load_tuned()`` applies a file at import time
+(the package does this for ``tuned/<arch>.json`` when present).
 
 Settings change only scheduling, never results, so tuning is safe to apply
 to any call.
@@ -73,19 +84,19 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
     src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(eb))
     dst = torch.empty((cols, rows), dtype=tdt, device="cuda")
     nbytes = 2 * rows * cols * eb
-    orig = xtr.tpose_config(eb)
+    orig = xtr.tpose_config(eb, "single")
     best = None
     results = []
     try:
         for cfg in tpose_candidates(quick, eb):
-            xtr.set_tpose_config(eb, **cfg)
+            xtr.set_tpose_config(eb, "single", **cfg)
             sec = _time(torch, lambda: xtr.tpose(src, dst, dtype=dt))
             gbs = nbytes / sec / 1e9
             results.append((gbs, cfg))
             if best is None or gbs > best[0]:
                 best = (gbs, cfg)
     finally:
-        xtr.set_tpose_config(eb, **orig)
+        xtr.set_tpose_config(eb, "single", **orig)
     results.sort(key=lambda r: -r[0])
     log(f"tune tpose eb={eb} {rows}x{cols}: best {best[0]:.1f} GB/s {best[1]}; "
         f"worst {results[-1][0]:.1f} GB/s")
@@ -100,13 +111,13 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
             src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(nr))
             dst = torch.empty((nc, nr), dtype=tdt, device="cuda")
             for nls, nss, ts in itertools.product((0, 1), (0, 1), (0, 2) if eb > 1 else (0,)):
-                xtr.set_tpose_config(eb, **dict(best[1], nt_load_shared=nls, nt_store_shared=nss,
-                                                tile_shared=ts))
+                xtr.set_tpose_config(eb, "single", **dict(best[1], nt_load_shared=nls,
+                                                          nt_store_shared=nss, tile_shared=ts))
                 pairs[(nls, nss, ts)] = pairs.get((nls, nss, ts), 0.0) + _time(
                     torch, lambda: xtr.tpose(src, dst, dtype=dt))
             del src, dst
     finally:
-        xtr.set_tpose_config(eb, **orig)
+        xtr.set_tpose_config(eb, "single", **orig)
     nls, nss, ts = min(pairs, key=pairs.get)
     if pairs[(nls, nss, ts)] > 0.98 * pairs[(0, 0, 0)]:
         nls, nss, ts = 0, 0, 0
@@ -140,12 +151,12 @@ def tune_reduce(xtr, torch, dt: str, log=print):
             src.bitwise_and_(0x77)    # clears the top exponent bit: no NaN codes
     out = torch.empty((), dtype=torch.float64 if dt not in ("i32", "i64") else torch.int64,
                       device="cuda")
-    orig = xtr.reduce_config(dt)
+    orig = xtr.reduce_config(dt, "single")
     ch = 256 * 8 * (16 // eb)
     best = None
     try:
         for nt, sc in itertools.product((1, 0), (0, 1)):
-            xtr.set_reduce_config(dt, nt_load=nt, split_chunks=sc)
+            xtr.set_reduce_config(dt, "single", nt_load=nt, split_chunks=sc)
             sec = _time(torch, lambda: xtr.reduce_sum(src, out, n=n, dtype=dt))
             gbs = n * eb / sec / 1e9
             if best is None or gbs > best[0]:
@@ -159,7 +170,7 @@ def tune_reduce(xtr, torch, dt: str, log=print):
             k = max(1, min(8, n // m))
             t = {}
             for sc in (0, 1):
-                xtr.set_reduce_config(dt, nt_load=nt, split_chunks=sc)
+                xtr.set_reduce_config(dt, "single", nt_load=nt, split_chunks=sc)
                 it = [0]
 
                 def fn():
@@ -177,11 +188,83 @@ def tune_reduce(xtr, torch, dt: str, log=print):
         elif split_from == 0:
             split_from = 16384
     finally:
-        xtr.set_reduce_config(dt, **orig)
+        xtr.set_reduce_config(dt, "single", **orig)
     cfg = {"nt_load": nt, "split_chunks": split_from}
     log(f"tune sum {dt} n={n}: best {best[0]:.1f} GB/s {cfg}")
     del src
     return {"gbs": round(best[0], 1), "config": cfg, "n": n}
+
+
+def tpose_batched_candidates(quick: bool, eb: int):
+    nts = [(0, 0), (1, 1)] if quick else [(0, 0), (1, 1), (1, 0), (0, 1)]
+    groups = [1, 16] if quick else [1, 4, 16, 32]
+    bpc = [0, 4] if quick else [0, 2, 4, 8]
+    wides = [0] if eb == 1 else [0, 2]
+    for (nl, ns), xcd, g, b, w in itertools.product(nts, [1, 0], groups, bpc, wides):
+        # nearly every job of a random-size batch has rows that share lines:
+        # the *_shared flags decide; the line-aligned ones follow along
+        yield {"nt_load": nl, "nt_store": ns, "nt_load_shared": nl, "nt_store_shared": ns,
+               "xcd": xcd, "group": g, "blocks_per_cu": b, "tile": 0, "tile_shared": w}
+
+
+def tune_tpose_batched(xtr, torch, eb: int, quick=False, log=print, count=1024, seed=9):
+    """Batched class: a batch of `count` jobs with rows and cols uniform in
+    [16, 2048] (the batched workload's shape distribution) as a plan (table
+    uploaded once), every candidate timed with HIP events."""
+    import workloads as W
+    tdt = {1: torch.uint8, 2: torch.int16, 4: torch.float32, 8: torch.float64}[eb]
+    gen = torch.Generator("cuda").manual_seed(seed)
+    jobs, nbytes = [], 0
+    for r, c in W.batched_shapes(count, seed):
+        s_ = torch.empty((r, c), dtype=tdt, device="cuda")
+        s_.view(torch.uint8).random_(0, 255, generator=gen)
+        jobs.append((s_, torch.empty((c, r), dtype=tdt, device="cuda")))
+        nbytes += 2 * r * c * eb
+    orig = xtr.tpose_config(eb, "batched")
+    results = []
+    try:
+        for cfg in tpose_batched_candidates(quick, eb):
+            xtr.set_tpose_config(eb, "batched", **cfg)
+            plan = xtr.TposePlan(jobs)              # the group split depends on tile_shared
+            sec = _time(torch, plan.run, reps=3, warm=1)
+            plan.close()
+            results.append((nbytes / sec / 1e9, cfg))
+    finally:
+        xtr.set_tpose_config(eb, "batched", **orig)
+    results.sort(key=lambda r: -r[0])
+    log(f"tune tpose batched eb={eb} {count} jobs: best {results[0][0]:.1f} GB/s {results[0][1]}; "
+        f"worst {results[-1][0]:.1f} GB/s")
+    del jobs
+    torch.cuda.empty_cache()
+    return {"gbs": round(results[0][0], 1), "config": results[0][1], "jobs": count,
+            "top5": [{"gbs": round(g, 1), "config": c} for g, c in results[:5]]}
+
+
+def tune_reduce_batched(xtr, torch, dt: str, log=print, nseg=100000):
+    """Batched class of the sums: streaming loads on / off for the segmented
+    sum of 2^27 fp32-sized bytes in nseg lognormal(6, 1.5) segments."""
+    import workloads as W
+    eb = xtr.ELEM_BYTES[dt]
+    total = (1 << 29) // eb
+    off = torch.from_numpy(W.segment_offsets(total, nseg, 11)).cuda()
+    src = torch.zeros(total * eb, dtype=torch.uint8, device="cuda")
+    out = torch.empty(nseg, dtype=torch.float64 if dt not in ("i32", "i64") else torch.int64,
+                      device="cuda")
+    ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, dt), dtype=torch.uint8,
+                     device="cuda")
+    orig = xtr.reduce_config(dt, "batched")
+    t = {}
+    try:
+        for nt in (1, 0):
+            xtr.set_reduce_config(dt, "batched", nt_load=nt)
+            t[nt] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out, dtype=dt))
+    finally:
+        xtr.set_reduce_config(dt, "batched", **orig)
+    nt = min(t, key=t.get)
+    log(f"tune sum batched {dt}: nt_load {nt} ({total * eb / t[nt] / 1e9:.1f} GB/s)")
+    del src, ws
+    return {"gbs": round(total * eb / t[nt] / 1e9, 1),
+            "config": {"nt_load": nt, "split_chunks": orig["split_chunks"]}, "nseg": nseg}
 
 
 def run(quick=False, out=None, log=print):
@@ -192,9 +275,11 @@ def run(quick=False, out=None, log=print):
     t0 = time.time()
     res = {"arch": arch, "torch_hip": torch.version.hip, "tpose": {}, "reduce": {}}
     for eb in (4, 2, 1, 8):
-        res["tpose"][str(eb)] = tune_tpose(xtr, torch, eb, quick, log)
+        res["tpose"][str(eb)] = {"single": tune_tpose(xtr, torch, eb, quick, log),
+                                 "batched": tune_tpose_batched(xtr, torch, eb, quick, log)}
     for dt in ("f32", "i64", "bf16", "f16", "f8e4m3", "i32"):
-        res["reduce"][dt] = tune_reduce(xtr, torch, dt, log)
+        res["reduce"][dt] = {"single": tune_reduce(xtr, torch, dt, log),
+                             "batched": tune_reduce_batched(xtr, torch, dt, log)}
     res["seconds"] = round(time.time() - t0, 1)
     out = out or os.path.join(TUNED_DIR, f"{arch}.json")
     os.makedirs(os.path.dirname(out), exist_ok=True)
@@ -211,9 +296,17 @@ def load_tuned(xtr, path: str) -> bool:
     with open(path) as f:
         d = json.load(f)
     for eb, r in d.get("tpose", {}).items():
-        xtr.set_tpose_config(int(eb), **r["config"])
+        if "config" in r:                     # one configuration for every class
+            xtr.set_tpose_config(int(eb), **r["config"])
+            continue
+        for shape, rc in r.items():
+            xtr.set_tpose_config(int(eb), shape, **rc["config"])
     for dt, r in d.get("reduce", {}).items():
-        xtr.set_reduce_config(dt, **r["config"])
+        if "config" in r:
+            xtr.set_reduce_config(dt, **r["config"])
+            continue
+        for shape, rc in r.items():
+            xtr.set_reduce_config(dt, shape, **rc["config"])
     return True
 
 

@@ -145,3 +145,27 @@ def test_full_size_sampled(xtr, orc, trans_b):
     assert (err <= n * 2.0 ** -24 * absref).all(), err.max()
     del ta, tb, c
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("trans_b", [False, True])
+def test_deep_path_every_element(xtr, orc, trans_b):
+    """4096 x 4096 x 96 bf16: 256 workgroup tiles of 256 x 256, as many as
+    the CUs, so the product runs on the large-tile kernel; every one of the
+    16.7M entries against the oracle (computed in row blocks on 16 threads)."""
+    from concurrent.futures import ThreadPoolExecutor
+    M = N = 4096
+    K = 96
+    a, b = operands(M, N, K, "bf16", 860, trans_b)
+    got = gpu_mm(xtr, a, b, "bf16", trans_b)
+    aa, ba = a & SIGN, b & SIGN
+
+    def block(i0):
+        i1 = min(M, i0 + 256)
+        ref = orc.matmul(np.ascontiguousarray(a[i0:i1]), b, "bf16", trans_b=trans_b, N=N, K=K)
+        absref = orc.matmul(np.ascontiguousarray(aa[i0:i1]), ba, "bf16", trans_b=trans_b, N=N, K=K)
+        err = np.abs(got[i0:i1].astype(np.float64) - ref)
+        return bool((err <= K * 2.0 ** -24 * absref + 1e-30).all()), float(err.max())
+
+    with ThreadPoolExecutor(16) as ex:
+        res = list(ex.map(block, range(0, M, 256)))
+    assert all(ok for ok, _ in res), max(e for _, e in res)

@@ -79,7 +79,7 @@ def test_split_combine_matches_tickets(xtr, orc, dt):
     """Plain partials + combine launches give bit-identical results to the
     in-kernel ticket combine, over one, two and three combine levels, ragged
     tails and unaligned heads."""
-    orig = xtr.reduce_config(dt)
+    orig = xtr.reduce_config(dt, "single")
     c = CH[dt]
     try:
         for k, (n, off) in enumerate([(3 * c, 0), (1000 * c + 17, 1), (2 * c - 1, 3),
@@ -87,31 +87,31 @@ def test_split_combine_matches_tickets(xtr, orc, dt):
             if n * np.dtype(data(dt, 1, 0).dtype).itemsize > (1 << 31):
                 continue
             bits = data(dt, n + off, 1100 + k)
-            xtr.set_reduce_config(dt, split_chunks=0)
+            xtr.set_reduce_config(dt, "single", split_chunks=0)
             a = gpu_sum(xtr, bits, dt, off)
             for sc in (1, 2, 3 * c):
-                xtr.set_reduce_config(dt, split_chunks=sc)
+                xtr.set_reduce_config(dt, "single", split_chunks=sc)
                 b = gpu_sum(xtr, bits, dt, off)
                 assert a == b or (math.isnan(a) and math.isnan(b)), (dt, n, off, sc, a, b)
             check(orc, a, bits[off:], dt, (dt, n, off))
     finally:
-        xtr.set_reduce_config(dt, **orig)
+        xtr.set_reduce_config(dt, "single", **orig)
 
 
 def test_split_combine_three_levels(xtr, orc):
     """More than 256^2 chunks (three combine levels): int32 against the oracle
     bit for bit, and the split and ticket combines agree."""
-    orig = xtr.reduce_config("i32")
+    orig = xtr.reduce_config("i32", "single")
     n = 65537 * CH["i32"] + 3
     bits = data("i32", n, 1200)
     d = to_dev(bits)
     try:
-        xtr.set_reduce_config("i32", split_chunks=1)
+        xtr.set_reduce_config("i32", "single", split_chunks=1)
         a = xtr.reduce_sum(d, dtype="i32").item()
-        xtr.set_reduce_config("i32", split_chunks=0)
+        xtr.set_reduce_config("i32", "single", split_chunks=0)
         b = xtr.reduce_sum(d, dtype="i32").item()
     finally:
-        xtr.set_reduce_config("i32", **orig)
+        xtr.set_reduce_config("i32", "single", **orig)
     assert a == b == orc.sum_int(bits, "i32")[0]
 
 

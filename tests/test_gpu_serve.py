@@ -91,3 +91,42 @@ def test_native_loop_validation(xtr):
     srv.drain(10000)
     assert srv.stats()["completed"] == 1 and o.item() == 0.0
     srv.close()
+
+
+def test_native_loop_configured_sizes(xtr, orc):
+    """The serving mix at its configured sizes (transposes of side 2^5 ..
+    2^13, bf16 and fp32; sums of 2^10 .. 2^26 fp32 / int32 elements), 300
+    jobs at 20k jobs/s under a 4 GiB budget, every job with its own output:
+    each result equals the job run alone, bit for bit; the small ones are
+    checked against the oracle too."""
+    import torch
+    from paper_2605_13864_amd import serve
+    jobs = W.serving_jobs(300, 23, rate=20000.0)
+    budget = 4 << 30
+    st = serve.run_native(xtr, torch, jobs, batching=True, budget=budget, keep_results=True)
+    assert st["max_inflight_bytes"] <= budget
+    pool = serve.InputPool(torch, jobs)
+    for i, j in enumerate(jobs):
+        x = pool.get(j)
+        got = st["results"][i]
+        if j.kind == "tpose":
+            alone = xtr.tpose(x)
+            a = got.view(torch.int16) if x.dtype == torch.bfloat16 else got.view(torch.int32)
+            b = alone.view(torch.int16) if x.dtype == torch.bfloat16 else alone.view(torch.int32)
+            assert torch.equal(a, b), i
+            if j.rows <= 1024 and i % 3 == 0:
+                h = x.view(torch.int16).cpu().numpy() if x.dtype == torch.bfloat16 else x.cpu().numpy()
+                g = a.cpu().numpy()
+                assert np.array_equal(g, orc.tpose(h).view(g.dtype)), i
+            del alone
+        else:
+            alone = xtr.reduce_sum(x)
+            assert got.item() == alone.item(), (i, got.item(), alone.item())
+            if j.n <= (1 << 22):
+                h = x.cpu().numpy()
+                if j.dtype == "i32":
+                    assert got.item() == orc.sum_int(h, "i32")[0], i
+                else:
+                    check_float_sum(got.item(), orc.sum_float(h, "f32"), orc.sum_abs(h, "f32"), i)
+    del st
+    torch.cuda.empty_cache()

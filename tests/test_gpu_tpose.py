@@ -116,10 +116,10 @@ def test_unaligned_rows(xtr, orc, eb):
 def test_tile_geometries(xtr, orc, eb, tile):
     """512-byte src (tile 1) or dst (tile 2) row segments: whole and ragged
     tiles, 16-byte pieces, against the oracle."""
-    orig = xtr.tpose_config(eb)
+    orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
-        xtr.set_tpose_config(eb, tile=tile)
+        xtr.set_tpose_config(eb, "single", tile=tile)
         # >= 2048 default tiles (smaller matrices keep the default geometry)
         for i, (r, c) in enumerate([(32 * T, 64 * T), (64 * T + 3, 32 * T + 5),
                                     (48 * T - 1, 48 * T + 1), (1, 1)]):
@@ -128,7 +128,7 @@ def test_tile_geometries(xtr, orc, eb, tile):
             pad_d = (-r) % v
             run_tpose(xtr, orc, r, c, eb, pad_s=pad_s, pad_d=pad_d, seed=60 + i)
     finally:
-        xtr.set_tpose_config(eb, **orig)
+        xtr.set_tpose_config(eb, "single", **orig)
 
 
 @pytest.mark.parametrize("eb,w", [(2, 4), (2, 8), (2, 16), (4, 4), (4, 8), (4, 16), (8, 8),
@@ -136,10 +136,10 @@ def test_tile_geometries(xtr, orc, eb, tile):
 def test_tile_geometry_shared_rows(xtr, orc, eb, w):
     """512-byte dst row segments (tile_shared = 2) for rows that do not start
     on cache lines, with every piece width, whole and ragged tiles."""
-    orig = xtr.tpose_config(eb)
+    orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
-        xtr.set_tpose_config(eb, tile_shared=2)
+        xtr.set_tpose_config(eb, "single", tile_shared=2)
         # >= 2048 default tiles, and a small one that keeps the default geometry
         for i, (r, c) in enumerate([(64 * T, 32 * T), (64 * T + 3, 32 * T + 5),
                                     (50 * T - 1, 48 * T + 1), (2 * T - 1, T + 1)]):
@@ -148,7 +148,7 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w):
                 ld_s += 16 // eb                     # rows must not start on lines
             run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=80 + i)
     finally:
-        xtr.set_tpose_config(eb, **orig)
+        xtr.set_tpose_config(eb, "single", **orig)
 
 
 @pytest.mark.parametrize("wide", [0, 2])
@@ -158,10 +158,10 @@ def test_batched_geometries(xtr, orc, wide):
     element size; each job against the oracle."""
     import torch
     rng = np.random.Generator(np.random.PCG64(19))
-    origs = {eb: xtr.tpose_config(eb) for eb in (1, 2, 4, 8)}
+    origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
     try:
         for eb in (2, 4, 8):
-            xtr.set_tpose_config(eb, tile_shared=wide, tile=wide)
+            xtr.set_tpose_config(eb, "batched", tile_shared=wide, tile=wide)
         jobs, hosts = [], []
         for i in range(40):
             eb = [1, 2, 4, 8][i % 4]
@@ -188,7 +188,7 @@ def test_batched_geometries(xtr, orc, wide):
                 p.close()
     finally:
         for eb, o in origs.items():
-            xtr.set_tpose_config(eb, **o)
+            xtr.set_tpose_config(eb, "batched", **o)
 
 
 def test_tiny_enumeration(xtr, orc):
@@ -258,3 +258,38 @@ def test_full_size(xtr, orc, rows, cols, dt, seed):
     del d
     want = orc.tpose(a)
     assert np.array_equal(to_host(got, a.dtype), want)
+
+
+def test_batched_config_every_job(xtr, orc):
+    """The whole batched workload: 4096 fp32 transposes with rows and cols
+    uniform in [16, 2048] (seed 9), random bit patterns (NaN payloads
+    included), one tpose_batched call; every element of every job against
+    the oracle (the oracle runs per job on 16 threads)."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    shapes = W.batched_shapes(4096, 9)
+
+    def make(i):
+        r, c = shapes[i]
+        return W.random_bits(r * c, 20000 + i, 4).reshape(r, c)
+
+    with ThreadPoolExecutor(16) as ex:
+        hosts = list(ex.map(make, range(len(shapes))))
+    jobs = []
+    for a in hosts:
+        s = to_dev(a)
+        jobs.append((s, torch.empty((a.shape[1], a.shape[0]), dtype=s.dtype, device=s.device)))
+    xtr.tpose_batched(jobs)
+    torch.cuda.synchronize()
+
+    def check(i):
+        want = orc.tpose(hosts[i])
+        got = to_host(jobs[i][1], np.uint32)
+        return bool(np.array_equal(got, want))
+
+    bad = []
+    for k0 in range(0, len(jobs), 256):          # bounded host memory for the outputs
+        with ThreadPoolExecutor(16) as ex:
+            ok = list(ex.map(check, range(k0, min(len(jobs), k0 + 256))))
+        bad += [k0 + i for i, v in enumerate(ok) if not v]
+    assert not bad, (len(bad), [shapes[i] for i in bad[:5]])
