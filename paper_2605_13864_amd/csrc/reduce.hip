@@ -394,79 +394,170 @@ template <int DT> constexpr int64_t small_max() { return (int64_t)2 * NTHR * vec
 // A set of 64 threads that holds no element (its first vector lies past the
 // body, and it does not take the head) has zero accumulators, whose butterfly
 // gives exactly zero: it is skipped, and so is a vector row no lane reaches.
-// US: vector rows loaded (1 for bodies of at most 256 * V elements, else 2).
+//
+// Every input byte of the range is loaded up front as whole aligned 16-byte
+// vectors (SmallRegs), so the value is then computed from registers alone and
+// a wave can keep the next range's loads in flight meanwhile: the head (the
+// elements before the first 16-byte boundary) from the aligned vector that
+// holds them, and a partial last vector whole.  Such a vector holds at least
+// one element of the range, and a 16-byte aligned vector never crosses a
+// page, so it lies on a page the range touches; the bytes outside the range
+// are never used.
+template <int US> struct SmallRegs {
+    uint4 v[US][NW];   // vector row u, thread set w (vector u * 256 + w * 64 + lane)
+    uint4 hv;          // the aligned vector holding the head (lane 0 only)
+};
+
+// Every load is issued unconditionally (a branch around a load would make the
+// wave wait for it where the branches join): a lane whose vector lies past the
+// body reads the body's last vector again, and a range that is not reduced
+// here (`use` false), or has no body or no head, reads the aligned vector that
+// holds `safe` (any valid device address) instead.  A wave-instruction whose
+// lanes all read one vector touches one cache line.  Such values are never
+// used.
 template <int DT, int US, bool NT>
-__device__ __forceinline__ void small_load(const Range &rg, uint4 (&v)[US][NW]) {
+__device__ __forceinline__ void small_load(const Range &rg, bool use, const void *safe,
+                                           SmallRegs<US> &r) {
     constexpr int EB = DTI<DT>::EB;
     constexpr int V = vec_elems<DT>();
     const int l = threadIdx.x & 63;
+    // (pointer arithmetic, not integer casts, so that the loads stay global loads)
+    const unsigned char *sb = static_cast<const unsigned char *>(safe);
+    const uint4 *sv = reinterpret_cast<const uint4 *>(sb - ((uintptr_t)sb & 15));
     const uint4 *body = reinterpret_cast<const uint4 *>(rg.ptr + (int64_t)rg.head * EB);
     const int64_t body_n = rg.n - rg.head;
+    const bool has_body = use && body_n > 0;
+    const uint32_t last = has_body ? (uint32_t)((body_n - 1) / V) : 0u;
+    r.hv = load16<NT>(use && rg.head > 0
+                          ? reinterpret_cast<const uint4 *>(rg.ptr - ((uintptr_t)rg.ptr & 15))
+                          : sv);
 #pragma unroll
     for (int u = 0; u < US; u++)
 #pragma unroll
         for (int w = 0; w < NW; w++) {
-            v[u][w] = make_uint4(0, 0, 0, 0);
-            if ((int64_t)(u * NTHR + w * 64) * V < body_n) {     // uniform: the row is reached
-                const uint32_t q = (uint32_t)(u * NTHR + w * 64 + l);
-                if ((int64_t)(q + 1) * V <= body_n) v[u][w] = load16<NT>(body + q);
-            }
+            const uint32_t q = (uint32_t)(u * NTHR + w * 64 + l);
+            r.v[u][w] = load16<NT>(has_body ? body + (q < last ? q : last) : sv);
         }
+}
+
+// Element i of a 16-byte vector, decoded as acc_elem decodes it, added to
+// accumulator a (the slot acc_elem uses for element i of a vector).
+template <int DT, int MODE>
+__device__ __forceinline__ void acc_from_vec(Acc<DT, MODE> &acc, const uint4 &v, int i, int a) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    if constexpr (DT == XTR_F32) {
+        acc.add(a, __uint_as_float(w[i]));
+    } else if constexpr (DT == XTR_BF16) {
+        acc.add(a, __uint_as_float(((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) << 16));
+    } else if constexpr (DT == XTR_F16) {
+        acc.add(a, f16_lo(w[i >> 1] >> (16 * (i & 1))));
+    } else if constexpr (DT == XTR_F8E4M3) {
+        auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)((w[i >> 2] >> (8 * (i & 3))) & 0xffu), false);
+        acc.add(a, f[0]);
+    } else if constexpr (DT == XTR_I32) {
+        acc.add(a, (uint64_t)(int64_t)(int32_t)w[i]);
+    } else {
+        acc.add(a, (uint64_t)w[2 * i] | ((uint64_t)w[2 * i + 1] << 32));
+    }
+}
+
+// The four wave butterflies of small_value in one pass (a reduce-scatter):
+// p[w] is this lane's value of thread l + 64 w.  The result equals, bit for
+// bit, ((B(p0) + B(p1)) + (B(p2) + B(p3))) with B the wave butterfly of
+// wave_reduce, because it performs the same additions (each addition is
+// commutative bit for bit), only spread over the lanes.  At the first two
+// levels the two lanes of a pair keep different values: after the xor-1 step
+// a lane holds two of the four values, after the xor-2 step one, so that in
+// every quad the lanes j = 0..3 hold values (0, 2, 1, 3) (even quads) or
+// (3, 1, 2, 0) (odd quads).  That layout is symmetric under the half-row and
+// row mirrors, so those two steps pair lanes that hold the same value, as in
+// wave_reduce.  Rows are then combined as (r0 + r1) + (r2 + r3) by the
+// xor-16 and xor-32 exchanges, and the four values as (v0 + v1) + (v2 + v3)
+// by the xor-2 and xor-1 steps inside each quad; every lane ends with the
+// result.
+__device__ __forceinline__ Pair vadd(Pair a, Pair b) { return pair_add(a, b); }
+__device__ __forceinline__ float vadd(float a, float b) { return a + b; }
+__device__ __forceinline__ uint64_t vadd(uint64_t a, uint64_t b) { return a + b; }
+template <int CTRL> __device__ __forceinline__ Pair vdpp(Pair p) {
+    return Pair{dppf<CTRL>(p.s), dppf<CTRL>(p.c)};
+}
+template <int CTRL> __device__ __forceinline__ float vdpp(float v) { return dppf<CTRL>(v); }
+template <int CTRL> __device__ __forceinline__ uint64_t vdpp(uint64_t v) { return dpp64<CTRL>(v); }
+__device__ __forceinline__ Pair vxor(Pair p, int m) {
+    return Pair{__shfl_xor(p.s, m, 64), __shfl_xor(p.c, m, 64)};
+}
+__device__ __forceinline__ float vxor(float v, int m) { return __shfl_xor(v, m, 64); }
+__device__ __forceinline__ uint64_t vxor(uint64_t v, int m) {
+    return (uint64_t)__shfl_xor((unsigned long long)v, m, 64);
+}
+
+template <typename T> __device__ __forceinline__ T wave_reduce4(const T (&p)[NW]) {
+    static_assert(NW == 4, "four values per lane");
+    const int l = threadIdx.x & 63, j = l & 3;
+    const bool odd = ((l >> 2) & 1) != 0;
+    // xor 1: "A" lanes keep values 0 and 1, their partners values 2 and 3
+    const bool a = ((j & 1) == 0) != odd;
+    const T q0 = vadd(a ? p[0] : p[2], vdpp<DPP_XOR1>(a ? p[2] : p[0]));
+    const T q1 = vadd(a ? p[1] : p[3], vdpp<DPP_XOR1>(a ? p[3] : p[1]));
+    // xor 2: one of the two
+    const bool f = ((j & 2) == 0) != odd;
+    T r = vadd(f ? q0 : q1, vdpp<DPP_XOR2>(f ? q1 : q0));
+    r = vadd(r, vdpp<DPP_HALF_MIRROR>(r));
+    r = vadd(r, vdpp<DPP_MIRROR>(r));
+    r = vadd(r, vxor(r, 16));
+    r = vadd(r, vxor(r, 32));
+    r = vadd(r, vdpp<DPP_XOR2>(r));
+    return vadd(r, vdpp<DPP_XOR1>(r));
 }
 
 template <int DT, int MODE, int US>
 __device__ __forceinline__ typename PartT<MODE>::T small_value(const Range &rg,
-                                                               const uint4 (&v)[US][NW]) {
+                                                               const SmallRegs<US> &r) {
     constexpr int EB = DTI<DT>::EB;
     constexpr int V = vec_elems<DT>();
     const int l = threadIdx.x & 63;
-    const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
     const int64_t body_n = rg.n - rg.head;
     Acc<DT, MODE> a0;
     a0.init();
-    using WV = decltype(wave_reduce(a0.finish()));
-    WV wv[NW];
+    using WV = decltype(a0.finish());
+    WV tv[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
         const bool any = (w == 0 && rg.head > 0) || (int64_t)(w * 64) * V < body_n;   // uniform
         if (!any) {
-            if constexpr (MODE == COMP) wv[w] = Pair{0.f, 0.f};
-            else wv[w] = WV(0);
+            if constexpr (MODE == COMP) tv[w] = Pair{0.f, 0.f};
+            else tv[w] = WV(0);
             continue;
         }
         Acc<DT, MODE> acc;
         acc.init();
-        if (w == 0 && l == 0) {
-            for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
+        if (w == 0 && l == 0 && rg.head > 0) {
+            // the head, in order, into accumulator 0 (as reduce_chunk adds it)
+            const int h0 = (int)((uintptr_t)rg.ptr & 15) / EB;
+#pragma unroll
+            for (int i = 1; i < V; i++)
+                if (i >= h0 && i < h0 + rg.head) acc_from_vec(acc, r.hv, i, 0);
         }
 #pragma unroll
         for (int u = 0; u < US; u++) {
             if ((int64_t)(u * NTHR + w * 64) * V >= body_n) continue;   // uniform
             const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
             if (e + V <= body_n) {
-                acc_vec(acc, v[u][w]);
+                acc_vec(acc, r.v[u][w]);
             } else if (e < body_n) {
                 const int m = (int)(body_n - e);
 #pragma unroll
                 for (int i = 0; i < V; i++)
-                    if (i < m) acc_elem(acc, body + (e + i) * EB, i);
+                    if (i < m) acc_from_vec(acc, r.v[u][w], i, (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3));
             }
         }
-        wv[w] = wave_reduce(acc.finish());
+        tv[w] = acc.finish();
     }
-    if constexpr (MODE == COMP) {
-        return pair_value(pair_add(pair_add(wv[0], wv[1]), pair_add(wv[2], wv[3])));
-    } else {
-        return (wv[0] + wv[1]) + (wv[2] + wv[3]);
-    }
+    const WV res = wave_reduce4(tv);
+    if constexpr (MODE == COMP) return pair_value(res);
+    else return res;
 }
 
-template <int DT, int MODE, bool NT>
-__device__ __forceinline__ typename PartT<MODE>::T small_chunk_value(const Range &rg) {
-    uint4 v[2][NW];
-    small_load<DT, 2, NT>(rg, v);
-    return small_value<DT, MODE, 2>(rg, v);
-}
 
 // ---------------------------------------------------------------- grid combine
 
@@ -787,8 +878,12 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *
                                                          int64_t cap, void *out) {
     using P = typename PartT<MODE>::T;
     if (chunk_base[nseg] > cap) return;   // invalid table: k_reduce_seg writes every output
+    // Each wave strides over the segments (indices are wave-uniform, so the
+    // offsets come through scalar loads, one segment ahead).  A segment's
+    // loads are all issued before its value is computed from registers; the
+    // other waves of the SIMD cover the wait.
     const int64_t nwaves = (int64_t)gridDim.x * NW;
-    int64_t s = (int64_t)blockIdx.x * NW + (threadIdx.x >> 6);
+    int64_t s = (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t lo = 0, hi = 0;
     if (s < nseg) lo = off[s], hi = off[s + 1];
     for (; s < nseg; s += nwaves) {
@@ -798,7 +893,9 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *
         const Range rg = seg_range_lh(src, lo, hi, s, DTI<DT>::EB, chunk_elems<DT>(),
                                       (unsigned char *)out, (int)sizeof(P));
         if (rg.n - rg.head <= small_max<DT>()) {   // else a chunked segment (pass 4b)
-            const P v = small_chunk_value<DT, MODE, NT>(rg);
+            SmallRegs<2> r;
+            small_load<DT, 2, NT>(rg, true, off, r);
+            const P v = small_value<DT, MODE, 2>(rg, r);
             if ((threadIdx.x & 63) == 0) *reinterpret_cast<P *>(rg.dst) = v;
         }
         lo = lo_n;

@@ -248,13 +248,13 @@ def test_segmented_small(xtr, orc, dt):
                                    and math.isnan(got[i])), i
 
 
-@pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i64"])
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f16", "f8e4m3", "i32", "i64"])
 def test_segmented_wave_and_chunk_paths(xtr, orc, dt):
     """Segments around the size where one wave instead of a workgroup chunk
     takes a segment (bodies of 2 * 256 * V elements, V = 16 / element size),
     starting at every alignment: every result equals reduce_sum on that
     segment alone, bit for bit, and the oracle to the usual bar."""
-    eb = {"f32": 4, "bf16": 2, "f8e4m3": 1, "i64": 8}[dt]
+    eb = {"f32": 4, "bf16": 2, "f16": 2, "f8e4m3": 1, "i32": 4, "i64": 8}[dt]
     v = 16 // eb
     sm = 2 * 256 * v
     lens = []
@@ -270,7 +270,7 @@ def test_segmented_wave_and_chunk_paths(xtr, orc, dt):
         seg = bits[off[i]:off[i + 1]]
         alone = xtr.reduce_sum(d[off[i]:off[i + 1]], dtype=dt).item()
         assert alone == got[i], (i, lens[i], alone, got[i])
-        check(orc, float(got[i]) if dt != "i64" else int(got[i]), seg, dt, (i, lens[i]))
+        check(orc, int(got[i]) if dt in ("i32", "i64") else float(got[i]), seg, dt, (i, lens[i]))
 
 
 def test_segmented_ws_and_invalid_table(xtr):
