@@ -17,8 +17,10 @@ Besides the step, the default run measures the rest of the metric:
     [16, 2048]) and the 100k-segment fp32 sum (2^27 values), each as one
     batched call against one launch per job, in GB/s of algorithmic bytes;
   * "serving": the request loop on its Poisson mix (20k jobs/s) for a few
-    seconds, continuous batching against one launch per job: p50 / p99
-    latency and aggregate GB/s;
+    seconds, continuous batching against one launch per job (and two
+    variants: graph-replayed units, a lane for large jobs): p50 / p99 latency
+    and aggregate GB/s; then with a share of the inputs in host memory, and
+    at 60k and 200k jobs/s;
   * "cpu_baseline": the CPU oracle on one thread, and the same plain loops on
     every host core (OpenMP), with the host's core count and CPU model.
 Per-kernel times are reported as medians and means of per-launch HIP events.
@@ -314,10 +316,16 @@ def batched_vs_per_job(xtr, torch, per_job=True):
     return res
 
 
-def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12):
+def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12, host_frac=0.25,
+            sweep=((60000.0, 1.5), (200000.0, 1.0))):
     """The serving workload for a few seconds: Poisson arrivals at `rate`
-    jobs/s of the configured mix, continuous batching against one launch per
-    job on the same GPU."""
+    jobs/s of the configured mix.  Continuous batching ("batched") against
+    one launch per job on the same GPU, and two variants of the batched
+    server: launch units replayed from executable graphs, and large jobs in
+    order on a lane of their own.  Then the same comparison with a share of
+    the inputs arriving in page-locked host memory (copied by the loop on its
+    copy stream, overlapping the other jobs' kernels), and at higher arrival
+    rates, where launches become the scarce resource."""
     import workloads as W
     from paper_2605_13864_amd import serve
     count = int(seconds * rate)
@@ -326,16 +334,43 @@ def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12):
     outs = serve.OutputBuffers(torch, jobs)
     warm = [j for j in W.serving_jobs(2000, seed + 1000, rate=rate)
             if serve.InputPool.key(j) in pool.t]
-    serve.run_native(xtr, torch, warm, pool=pool, outs=outs)
-    serve.run_native(xtr, torch, warm, batching=False, pool=pool, outs=outs)
+    configs = (("batched", dict(batching=True)),
+               ("per_job", dict(batching=False)),
+               ("batched_graphs", dict(batching=True, graphs=True)),
+               ("batched_large_lane", dict(batching=True, big_lane=True)))
+    for _, kw in configs:
+        serve.run_native(xtr, torch, warm, pool=pool, outs=outs, **kw)
     keys = ("jobs", "p50_ms", "p99_ms", "mean_ms", "throughput_gbs", "achieved_jobs_per_s",
-            "launches", "batches", "mean_jobs_per_batch", "max_inflight_gib")
+            "launches", "batches", "mean_jobs_per_batch", "max_inflight_gib", "graph_launches",
+            "graph_builds", "host_copies")
     res = {"rate_jobs_per_s": rate, "seconds": seconds, "loop": "native (xtr_server)",
            "offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1)}
-    for name, b in (("batched", True), ("per_job", False)):
-        st = serve.run_native(xtr, torch, jobs, batching=b, pool=pool, outs=outs)
+    for name, kw in configs:
+        st = serve.run_native(xtr, torch, jobs, pool=pool, outs=outs, **kw)
         res[name] = {k: st[k] for k in keys}
+        res[name]["config"] = kw
     res["batched_p99_below_per_job"] = res["batched"]["p99_ms"] < res["per_job"]["p99_ms"]
+    host = serve.host_resident(jobs, host_frac, seed + 1)
+    hin = serve.HostInputs(torch, pool, {serve.InputPool.key(jobs[i]) for i in host})
+    hb = sum((jobs[i].nbytes // 2 if jobs[i].kind == "tpose" else jobs[i].nbytes) for i in host)
+    ent = {"host_jobs": len(host), "host_input_gbs_offered": round(hb / seconds / 1e9, 2),
+           "rule": f"each job with an input of at most 16 MiB, with probability {host_frac}"}
+    for name, kw in configs[:2]:
+        st = serve.run_native(xtr, torch, jobs, pool=pool, outs=outs, host=host, host_inputs=hin, **kw)
+        ent[name] = {k: st[k] for k in keys}
+    res["host_inputs"] = ent
+    del hin
+    res["sweep"] = []
+    for r, secs in sweep:
+        js = [j for j in W.serving_jobs(int(r * secs), seed + int(r), rate=r)
+              if serve.InputPool.key(j) in pool.t]
+        e = {"rate_jobs_per_s": r, "offered_gbs": round(W.mean_job_bytes() * r / 1e9, 1),
+             "jobs": len(js)}
+        for name, kw in configs[:2]:
+            st = serve.run_native(xtr, torch, js, pool=pool, outs=outs, **kw)
+            e[name] = {k: st[k] for k in ("p50_ms", "p99_ms", "throughput_gbs",
+                                          "achieved_jobs_per_s", "launches", "batches")}
+        res["sweep"].append(e)
     del pool, outs
     torch.cuda.empty_cache()
     return res
@@ -352,6 +387,8 @@ def main():
     ap.add_argument("--no-serving", action="store_true", help="skip the short serving run")
     ap.add_argument("--no-per-job", action="store_true",
                     help="batched section without the one-launch-per-job loops (profiling)")
+    ap.add_argument("--no-step", action="store_true",
+                    help="profiling: skip the step (the plain copy still runs)")
     ap.add_argument("--parts", default="paper,widths,batched,segmented,precision,host,scan,hist,matmul,serving",
                     help="suite parts for --suite full (comma-separated)")
     args = ap.parse_args()
@@ -365,6 +402,14 @@ def main():
     xtr.load()
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     log(f"bench: device {torch.cuda.get_device_name(0)}")
+
+    if args.no_step:
+        # profiling runs of the other parts: the plain copy (the counters'
+        # calibration) and whatever parts are not switched off
+        out = {"metric": None, "note": "--no-step: profiling run, no step measured",
+               "copy_gbs": copy_ceiling(xtr, torch)}
+        rest(args, out, xtr, torch)
+        return
 
     step = Step(xtr, torch)
     for _ in range(args.warmup):
@@ -431,6 +476,12 @@ def main():
         "kernels": per,
         "copy_gbs": copy,
     }
+    rest(args, out, xtr, torch)
+
+
+def rest(args, out, xtr, torch):
+    """The parts after the step: batched vs per-job, serving, CPU baseline,
+    the full suite; then the JSON line."""
     if not args.no_batched:
         t0 = time.time()
         out["batched"] = batched_vs_per_job(xtr, torch, per_job=not args.no_per_job)
@@ -443,9 +494,18 @@ def main():
         t0 = time.time()
         out["serving"] = serving(xtr, torch)
         v = out["serving"]
-        log(f"bench: serving 20k jobs/s: batched p50 {v['batched']['p50_ms']} p99 "
-            f"{v['batched']['p99_ms']} ms {v['batched']['throughput_gbs']} GB/s; per-job p50 "
-            f"{v['per_job']['p50_ms']} p99 {v['per_job']['p99_ms']} ms ({time.time() - t0:.1f}s)")
+        for name in ("batched", "per_job", "batched_graphs", "batched_large_lane"):
+            log(f"bench: serving 20k jobs/s {name:16s} p50 {v[name]['p50_ms']} p99 "
+                f"{v[name]['p99_ms']} ms {v[name]['throughput_gbs']} GB/s, "
+                f"{v[name]['launches']} launches, {v[name]['graph_launches']} graph launches")
+        h = v["host_inputs"]
+        log(f"bench: serving with {h['host_jobs']} host inputs: batched p99 "
+            f"{h['batched']['p99_ms']} ms, per-job p99 {h['per_job']['p99_ms']} ms")
+        for e in v["sweep"]:
+            log(f"bench: serving {e['rate_jobs_per_s']:.0f} jobs/s: batched p99 "
+                f"{e['batched']['p99_ms']} ms {e['batched']['throughput_gbs']} GB/s; per-job p99 "
+                f"{e['per_job']['p99_ms']} ms {e['per_job']['throughput_gbs']} GB/s")
+        log(f"bench: serving done ({time.time() - t0:.1f}s)")
     if not args.no_cpu:
         log("bench: timing the CPU oracle on a bounded sample ...")
         out["cpu_baseline"] = cpu_baseline()

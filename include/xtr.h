@@ -358,31 +358,41 @@ int xtr_sum_plan_destroy(xtr_sum_plan *plan);
 
 /* ------------------------------------------------------------------------
  * Serving: a request loop with continuous batching (the serving workload;
- * the paper has no serving).  A server owns a thread and `nstreams` streams
- * of default priority on the device current at creation.  Each job names a
- * device-resident input and output the caller owns (they must stay valid and
- * the input ready until the job completes); the loop allocates nothing per
- * job.  A job becomes visible to the loop at its arrival time; the loop
- * admits arrived jobs in FIFO order while the in-flight bytes (input + output
- * of every admitted, unfinished job) stay within budget_bytes, and launches
- * the jobs admitted in one pass as units on the next stream, each unit with
- * a completion event: with batching, jobs under small_job_bytes share one
- * unit per kind (one tpose_batched / reduce_sum_batched_scatter launch per
- * element size or dtype) and larger jobs are units of their own unless jobs
- * are left waiting; without batching, one launch per job.  Results are the
- * entry points' own (tpose, reduce_sum), bit for bit whatever the mix.
+ * the paper has no serving).  A server owns a thread, `nstreams` compute
+ * streams and one copy stream, all of default priority, on the device current
+ * at creation.  Each job names a device input and output the caller owns
+ * (they must stay valid, and the input ready, until the job completes); the
+ * loop allocates nothing per job.  A job becomes visible to the loop at its
+ * arrival time; the loop admits arrived jobs in FIFO order while the
+ * in-flight bytes (input + output of every admitted, unfinished job) stay
+ * within budget_bytes, and launches the jobs admitted in one pass as units,
+ * each unit with a completion event: with batching, jobs under
+ * small_job_bytes share one unit per kind (one tpose_batched /
+ * reduce_sum_batched_scatter launch per element size or dtype; a kind with
+ * one job in the unit takes tpose / reduce_sum) and larger jobs are units of
+ * their own unless jobs are left waiting; without batching, one launch per
+ * job.  Results are the entry points' own (tpose, reduce_sum), bit for bit
+ * whatever the mix.
+ *
+ * Host-resident inputs (the host side of Listing 3.6 inside the loop): a job
+ * with host_src != NULL has its input in page-locked host memory at host_src;
+ * when the job is launched the loop copies it to `src` (a device buffer of the
+ * input's size, owned by the caller) on the copy stream, and the job's unit
+ * waits for that copy only, so copies overlap the kernels of other units.
+ * Outputs stay in device memory.
  */
 typedef struct {
     int32_t kind;        /* 0: transpose (tpose of a contiguous rows x cols matrix),
                             1: sum (reduce_sum of n elements)                       */
     int32_t dtype;
-    const void *src;     /* device input                                            */
+    const void *src;     /* device input (with host_src: where it is copied to)      */
     void *dst;           /* device output: cols x rows matrix, or the sum's result  */
     int64_t rows, cols;  /* transpose                                               */
     int64_t n;           /* sum                                                     */
     int64_t arrival_ns;  /* arrival on xtr_server_clock_ns(); < 0: at submission.
                             Arrivals are non-decreasing in submission order (a time
                             before the previous job's is raised to it).             */
+    const void *host_src;  /* NULL, or the input in page-locked host memory         */
 } xtr_job;
 
 typedef struct {
@@ -390,12 +400,26 @@ typedef struct {
     int32_t batching;         /* 1: continuous batching; 0: one launch per job     */
     int64_t budget_bytes;     /* HBM budget of the in-flight jobs                  */
     int64_t small_job_bytes;  /* jobs below this share launch units                */
-    int64_t _reserved[4];
+    int32_t graphs;           /* 1: each unit's launches are captured into a graph
+                                 and run from a cached executable graph of the same
+                                 shape (same kernels and grids, same stream), given
+                                 the unit's kernel arguments; a shared unit then
+                                 holds at most 24 jobs of a kind (job tables in the
+                                 kernel arguments, so the graph has kernel nodes
+                                 only).  A unit that cannot be captured so runs
+                                 eagerly.                                          */
+    int32_t big_lane;         /* 1 (with nstreams >= 2): every unit holding a job of
+                                 at least small_job_bytes runs on stream 0, in
+                                 admission order; the others take streams 1..K-1.  */
+    int64_t _reserved[3];
 } xtr_server_config;
 
 typedef struct {
     int64_t submitted, completed, failed, launches, units, max_inflight_bytes;
-    int64_t _reserved[4];
+    int64_t graph_launches;   /* units run from an executable graph               */
+    int64_t graph_builds;     /* executable graphs instantiated                   */
+    int64_t host_copies;      /* host-to-device input copies                      */
+    int64_t _reserved;
 } xtr_server_stats;
 
 typedef struct xtr_server xtr_server;

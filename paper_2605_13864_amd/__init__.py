@@ -49,18 +49,20 @@ class ReduceConfig(C.Structure):
 class Job(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dtype", C.c_int32), ("src", C.c_void_p),
                 ("dst", C.c_void_p), ("rows", C.c_int64), ("cols", C.c_int64), ("n", C.c_int64),
-                ("arrival_ns", C.c_int64)]
+                ("arrival_ns", C.c_int64), ("host_src", C.c_void_p)]
 
 
 class ServerConfig(C.Structure):
     _fields_ = [("nstreams", C.c_int32), ("batching", C.c_int32), ("budget_bytes", C.c_int64),
-                ("small_job_bytes", C.c_int64), ("_reserved", C.c_int64 * 4)]
+                ("small_job_bytes", C.c_int64), ("graphs", C.c_int32), ("big_lane", C.c_int32),
+                ("_reserved", C.c_int64 * 3)]
 
 
 class ServerStats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64),
                 ("launches", C.c_int64), ("units", C.c_int64), ("max_inflight_bytes", C.c_int64),
-                ("_reserved", C.c_int64 * 4)]
+                ("graph_launches", C.c_int64), ("graph_builds", C.c_int64),
+                ("host_copies", C.c_int64), ("_reserved", C.c_int64)]
 
 
 class TposeDesc(C.Structure):
@@ -421,9 +423,11 @@ class Server:
     """The native request loop (xtr_server_*): submit jobs on device-resident
     tensors, drain, read arrival / completion times (ns, server clock)."""
 
-    def __init__(self, *, nstreams=4, batching=True, budget=64 << 30, small_job_bytes=4 << 20):
+    def __init__(self, *, nstreams=4, batching=True, budget=64 << 30, small_job_bytes=4 << 20,
+                 graphs=False, big_lane=False):
         lib = load()
-        cfg = ServerConfig(nstreams, int(bool(batching)), int(budget), int(small_job_bytes))
+        cfg = ServerConfig(nstreams, int(bool(batching)), int(budget), int(small_job_bytes),
+                           int(bool(graphs)), int(bool(big_lane)))
         h = C.c_void_p()
         _check(lib.xtr_server_create(C.byref(cfg), C.byref(h)), "xtr_server_create")
         self._h = h

@@ -13,9 +13,16 @@
 //      or dtype) and every large job is a unit of its own (it is
 //      bandwidth-bound and gains nothing from sharing a launch) -- unless jobs
 //      are left waiting, when the large jobs of a kind share a unit too (then
-//      launches are the scarce resource); without batching, one unit per job;
-//   4. launch every unit at once on the next of K streams, each with its own
-//      completion event.
+//      launches are the scarce resource); a shared unit holds at most
+//      `max_per_kind` jobs of a kind (0: no limit); without batching, one unit
+//      per job;
+//   4. launch every unit at once, each with its own completion event: on the
+//      next of K streams, or -- with the large-job lane -- every unit that
+//      holds a large job on stream 0, in admission order, and the others on
+//      streams 1..K-1 in turn.  Large jobs then run one after another at the
+//      full bandwidth instead of sharing it, which shortens the tail of the
+//      latency distribution (its top percent is made of the largest jobs),
+//      while small jobs never queue behind them.
 // Jobs that arrive while others run join the next unit as soon as budget
 // frees up, and units on different streams overlap on the device.
 #pragma once
@@ -38,26 +45,48 @@ struct Pending {
 
 // Launch units of the jobs admitted in one step (order of admission kept).
 inline void make_units(const std::vector<Pending> &group, bool batching, bool backlog,
-                       int64_t small_bytes, std::vector<std::vector<Pending>> &units) {
+                       int64_t small_bytes, int max_per_kind,
+                       std::vector<std::vector<Pending>> &units) {
     units.clear();
     if (!batching) {
         for (const Pending &p : group) units.push_back({p});
         return;
     }
-    int shared[2][2] = {{-1, -1}, {-1, -1}};   // [kind][small] -> unit index
+    int shared[2][2] = {{-1, -1}, {-1, -1}};   // [kind][small] -> open unit index
+    int count[2][2] = {{0, 0}, {0, 0}};        // jobs of that kind in the open unit
     for (const Pending &p : group) {
         const bool small = p.bytes < small_bytes;
         if (small || backlog) {
-            int &u = shared[p.kind & 1][small ? 1 : 0];
-            if (u < 0) {
+            const int k = p.kind & 1, c = small ? 1 : 0;
+            int &u = shared[k][c];
+            if (u < 0 || (max_per_kind > 0 && count[k][c] >= max_per_kind)) {
                 u = (int)units.size();
+                count[k][c] = 0;
                 units.emplace_back();
             }
             units[u].push_back(p);
+            count[k][c]++;
         } else {
             units.push_back({p});
         }
     }
+}
+
+// Stream of a unit: with the large-job lane (and at least two streams), a
+// unit that holds a job of at least small_bytes goes to stream 0 and the
+// others take streams 1..K-1 in turn; else every unit takes the next stream.
+inline int pick_stream(const std::vector<Pending> &unit, bool big_lane, int nstreams,
+                       int64_t small_bytes, int &next_small, int &next_any) {
+    if (big_lane && nstreams >= 2) {
+        for (const Pending &p : unit)
+            if (p.bytes >= small_bytes) return 0;
+        const int s = 1 + next_small;
+        next_small = (next_small + 1) % (nstreams - 1);
+        return s;
+    }
+    const int s = next_any;
+    next_any = (next_any + 1) % nstreams;
+    return s;
 }
 
 // Exec: int64_t launch(const std::vector<Pending> &unit, int stream) returns a
@@ -65,9 +94,10 @@ inline void make_units(const std::vector<Pending> &group, bool batching, bool ba
 // completion time (ns) or -1 while running.
 template <class Exec> class Scheduler {
   public:
-    Scheduler(Exec &ex, int64_t budget, bool batching, int nstreams, int64_t small_bytes)
+    Scheduler(Exec &ex, int64_t budget, bool batching, int nstreams, int64_t small_bytes,
+              bool big_lane = false, int max_per_kind = 0)
         : ex_(ex), budget_(budget), batching_(batching), nstreams_(nstreams),
-          small_(small_bytes) {}
+          small_(small_bytes), big_lane_(big_lane), max_per_kind_(max_per_kind) {}
 
     void arrive(const Pending &p) { pending_.push_back(p); }
 
@@ -99,10 +129,10 @@ template <class Exec> class Scheduler {
         }
         if (used_ > max_used) max_used = used_;
         if (group_.empty()) return false;
-        make_units(group_, batching_, !pending_.empty(), small_, units_);
+        make_units(group_, batching_, !pending_.empty(), small_, max_per_kind_, units_);
         for (auto &u : units_) {
-            const int64_t h = ex_.launch(u, si_);
-            si_ = (si_ + 1) % nstreams_;
+            const int si = pick_stream(u, big_lane_, nstreams_, small_, next_small_, si_);
+            const int64_t h = ex_.launch(u, si);
             units++;
             if (h < 0) {   // nothing of the unit runs: its jobs fail now
                 for (const Pending &p : u) {
@@ -133,8 +163,10 @@ template <class Exec> class Scheduler {
     Exec &ex_;
     int64_t budget_, used_ = 0;
     bool batching_;
-    int nstreams_, si_ = 0;
+    int nstreams_, si_ = 0, next_small_ = 0;
     int64_t small_;
+    bool big_lane_;
+    int max_per_kind_;
     std::deque<Pending> pending_;
     std::vector<Unit> inflight_;
     std::vector<Pending> group_;

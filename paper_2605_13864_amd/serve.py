@@ -326,16 +326,43 @@ def run(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=No
     return stats
 
 
+class HostInputs:
+    """Page-locked host copies of the pool's inputs, for jobs whose input
+    arrives in host memory."""
+
+    def __init__(self, torch, pool, keys):
+        self.t = {k: pool.t[k].cpu().pin_memory() for k in keys}
+
+    def get(self, j):
+        return self.t[InputPool.key(j)]
+
+
+def host_resident(jobs, frac, seed, max_input_bytes=16 << 20):
+    """Indices of the jobs whose input is in host memory: each job with an
+    input of at most max_input_bytes, with probability frac (seeded)."""
+    rng = np.random.default_rng(seed)
+    pick = rng.random(len(jobs)) < frac
+    return {i for i, j in enumerate(jobs)
+            if pick[i] and (j.nbytes // 2 if j.kind == "tpose" else j.nbytes) <= max_input_bytes}
+
+
 def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=None,
-               outs=None, keep_results=False, lead_s=0.005, log=None):
+               outs=None, keep_results=False, lead_s=0.005, log=None, graphs=False,
+               big_lane=False, host=None, host_inputs=None):
     """Serve `jobs` with the native request loop (xtr_server_*, the same
     policy as Scheduler, in a server thread of the library): the whole arrival
     schedule is handed over at once and each job becomes visible to the loop
     at its arrival time, so no host-side submission cost enters the
     latencies.  With keep_results every job gets an output of its own (else
     the jobs of a class take that class's output slots in turn: the timing
-    does not depend on the values).  Returns stats like run()."""
+    does not depend on the values).  `host`: indices of the jobs whose input
+    is in page-locked host memory (host_inputs); the loop copies each to the
+    pool's device tensor of the same key, which holds the same bytes, so
+    concurrent readers see unchanged values.  Returns stats like run()."""
     pool = pool or InputPool(torch, jobs)
+    host = host or set()
+    if host and host_inputs is None:
+        host_inputs = HostInputs(torch, pool, {InputPool.key(jobs[i]) for i in host})
     arr = (xtr.Job * len(jobs))()
     keep = []
     nxt = {}
@@ -361,8 +388,10 @@ def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, 
         a.src = x.data_ptr()
         a.dst = o.data_ptr()
         a.rows, a.cols, a.n = j.rows, j.cols, j.n
+        a.host_src = host_inputs.get(j).data_ptr() if i in host else None
     torch.cuda.synchronize()                     # inputs and outputs exist before serving
-    srv = xtr.Server(nstreams=nstreams, batching=batching, budget=budget)
+    srv = xtr.Server(nstreams=nstreams, batching=batching, budget=budget, graphs=graphs,
+                     big_lane=big_lane)
     t0 = xtr.Server.clock_ns() + int(lead_s * 1e9)
     for i, j in enumerate(jobs):
         arr[i].arrival_ns = t0 + int(round(j.arrival_s * 1e9))
@@ -387,6 +416,8 @@ def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, 
         "achieved_jobs_per_s": round(len(jobs) / span, 1),
         "launches": st["launches"], "batches": st["units"],
         "mean_jobs_per_batch": round(len(jobs) / max(st["units"], 1), 2),
+        "graphs": graphs, "big_lane": big_lane, "graph_launches": st["graph_launches"],
+        "graph_builds": st["graph_builds"], "host_copies": st["host_copies"],
     }
     if log:
         log(f"serve (native) batching={batching}: p50 {stats['p50_ms']} ms p99 {stats['p99_ms']} ms, "

@@ -7,7 +7,10 @@
 //   * the batching rule: small jobs of a kind share a unit, a large job is a
 //     unit of its own unless jobs are left waiting; without batching every
 //     unit holds one job;
-//   * a launch that fails marks its jobs failed (-2) and frees their budget.
+//   * a launch that fails marks its jobs failed (-2) and frees their budget;
+//   * with a cap of jobs per kind, no unit holds more than the cap;
+//   * with the large-job lane, every unit holding a large job goes to stream
+//     0 (and only those), in admission order.
 #include "../../paper_2605_13864_amd/csrc/serve_policy.h"
 
 #include <cstdio>
@@ -35,9 +38,11 @@ struct FakeExec {
     int fail_every = 0;                         // every k-th launch fails (0: never)
     std::vector<int64_t> t_done;
     std::vector<std::vector<Pending>> launched;
+    std::vector<int> stream_of;
     int64_t calls = 0;
-    int64_t launch(const std::vector<Pending> &u, int) {
+    int64_t launch(const std::vector<Pending> &u, int si) {
         calls++;
+        stream_of.push_back(si);
         if (fail_every && calls % fail_every == 0) return -1;
         int64_t b = 0;
         for (const Pending &p : u) b += p.bytes;
@@ -67,12 +72,14 @@ static std::vector<Arrival> stream(int n, unsigned seed, double mean_gap_ns) {
     return a;
 }
 
-static void run(const char *name, bool batching, int64_t budget, double gbs, int fail_every) {
+static void run(const char *name, bool batching, int64_t budget, double gbs, int fail_every,
+                bool big_lane = false, int cap = 0, double gap_ns = 50000.0) {
     int64_t clock = 0;
     FakeExec ex{&clock, gbs, fail_every};
     const int64_t small = 4 << 20;
-    xtr::srv::Scheduler<FakeExec> sch(ex, budget, batching, 3, small);
-    auto arr = stream(20000, 7, 50000.0);
+    const int nstreams = 3;
+    xtr::srv::Scheduler<FakeExec> sch(ex, budget, batching, nstreams, small, big_lane, cap);
+    auto arr = stream(20000, 7, gap_ns);
     std::vector<int64_t> done(arr.size(), -1), fin;
     size_t next = 0;
     int64_t max_used = 0, steps = 0;
@@ -93,6 +100,12 @@ static void run(const char *name, bool batching, int64_t budget, double gbs, int
                 for (const Pending &p : unit)
                     CHECK(p.bytes < small, "%s: large job shared a unit with no backlog", name);
             for (const Pending &p : unit) CHECK(p.kind == unit[0].kind, "%s: kinds mixed in a unit", name);
+            if (cap > 0) CHECK((int)unit.size() <= cap, "%s: unit of %zu jobs > cap %d", name, unit.size(), cap);
+            bool large = false;
+            for (const Pending &p : unit) large |= p.bytes >= small;
+            const int si = ex.stream_of[u];
+            CHECK(si >= 0 && si < nstreams, "%s: stream %d", name, si);
+            if (big_lane) CHECK((si == 0) == large, "%s: unit (large %d) on stream %d", name, (int)large, si);
         }
         if (sch.used() > max_used) max_used = sch.used();
         CHECK(sch.used() <= budget, "%s: %lld bytes in flight > budget", name, (long long)sch.used());
@@ -114,8 +127,10 @@ static void run(const char *name, bool batching, int64_t budget, double gbs, int
     CHECK(failed == sch.failed, "%s: failed count", name);
     if (fail_every) CHECK(failed > 0, "%s: no failed launch", name);
     else CHECK(failed == 0, "%s: unexpected failures", name);
-    std::printf("%-34s units %7lld  launches %7lld  max in flight %6.1f MiB of %6.1f  failed %lld\n",
-                name, (long long)sch.units, (long long)ex.calls, max_used / 1048576.0,
+    int64_t maxu = 0;
+    for (const auto &u : ex.launched) maxu = (int64_t)u.size() > maxu ? (int64_t)u.size() : maxu;
+    std::printf("%-36s largest unit %3lld  units %7lld  launches %7lld  max in flight %6.1f MiB of %6.1f  failed %lld\n",
+                name, (long long)maxu, (long long)sch.units, (long long)ex.calls, max_used / 1048576.0,
                 budget / 1048576.0, (long long)failed);
 }
 
@@ -125,6 +140,9 @@ int main() {
     run("batching, slow device (backlog)", true, (int64_t)1 << 30, 20.0, 0);
     run("one launch per job", false, (int64_t)1 << 30, 20.0, 0);
     run("batching, failing launches", true, (int64_t)1 << 30, 500.0, 7);
+    run("batching, large-job lane", true, (int64_t)1 << 30, 20.0, 0, true);
+    run("batching, 24 jobs per kind (graphs)", true, (int64_t)1 << 30, 500.0, 0, false, 24, 200.0);
+    run("lane + cap, tight budget", true, (int64_t)96 << 20, 500.0, 0, true, 24, 200.0);
     std::printf("%s\n", failures ? "FAILED" : "serving policy ok");
     return failures ? 1 : 0;
 }

@@ -130,3 +130,39 @@ def test_native_loop_configured_sizes(xtr, orc):
                     check_float_sum(got.item(), orc.sum_float(h, "f32"), orc.sum_abs(h, "f32"), i)
     del st
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("graphs,big_lane,host_frac,rate",
+                         [(True, False, 0.0, 300000.0), (True, True, 0.3, 300000.0),
+                          (False, True, 0.3, 20000.0), (True, False, 0.0, 20000.0)])
+def test_native_loop_graphs_lane_host_inputs(xtr, orc, graphs, big_lane, host_frac, rate):
+    """Launch units replayed from executable graphs, the large-job lane, and
+    inputs that arrive in page-locked host memory (copied by the loop on its
+    copy stream): every result equals the job run alone, bit for bit; graph
+    mode runs units from graphs; every host input is copied once."""
+    import torch
+    from paper_2605_13864_amd import serve
+    jobs = W.serving_jobs(800, 24, rate=rate, tpose_k=(5, 10), sum_k=(10, 20))
+    host = serve.host_resident(jobs, host_frac, 25)
+    st = serve.run_native(xtr, torch, jobs, batching=True, budget=64 << 20, keep_results=True,
+                          graphs=graphs, big_lane=big_lane, host=host)
+    assert st["max_inflight_bytes"] <= 64 << 20
+    assert st["host_copies"] == len(host)
+    if graphs:
+        assert st["graph_launches"] > 0 and st["graph_builds"] <= st["graph_launches"]
+    if rate > 100000:
+        assert st["mean_jobs_per_batch"] > 1.0
+    pool = serve.InputPool(torch, jobs)
+    for i, j in enumerate(jobs):
+        x = pool.get(j)
+        got = st["results"][i]
+        if j.kind == "tpose":
+            alone = xtr.tpose(x)
+            a = got.view(torch.int16) if x.dtype == torch.bfloat16 else got.view(torch.int32)
+            b = alone.view(torch.int16) if x.dtype == torch.bfloat16 else alone.view(torch.int32)
+            assert torch.equal(a, b), (i, i in host)
+        else:
+            alone = xtr.reduce_sum(x)
+            assert got.item() == alone.item(), (i, i in host, got.item(), alone.item())
+            if i % 20 == 0 and j.dtype == "i32":
+                assert got.item() == orc.sum_int(x.cpu().numpy(), "i32")[0]
