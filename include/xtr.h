@@ -462,9 +462,10 @@ typedef struct {
     int32_t nt_load_shared; /* 1: nontemporal loads of such src rows               */
     int32_t tile;           /* tile geometry of single transposes of 2- to 8-byte   */
                             /*    elements with line-aligned rows: 0 = 256 x 256   */
-                            /*    bytes, 1 = 512-byte src row segments (16-byte    */
-                            /*    pieces only), 2 = 512-byte dst row segments       */
-    int32_t tile_shared;    /* the same for rows that do not start on lines         */
+                            /*    bytes, 1 = 512-byte src row segments, 2 = 512-   */
+                            /*    byte dst row segments                             */
+    int32_t tile_shared;    /* the same for rows that do not start on lines (in the */
+                            /*    batched class: the geometry of every batch job)   */
     int32_t _reserved[3];
 } xtr_tpose_config;
 

@@ -190,10 +190,12 @@ int tpose_host_impl(const void *src, void *dst, int64_t rows, int64_t cols, int6
 // Host-side form of a batch: jobs grouped by (element size, piece width,
 // 32-bit offsets); each group has its own slice of the device table, its own
 // concatenated tile space and one persistent launch.
-// eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows x wide
-// (512-byte dst row segments)
-constexpr int NGROUPS = 4 * 4 * 2 * 2 * 2;
-// jobs of at least this many default tiles may take the wide geometry
+// eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows x tile
+// geometry (0: 256 x 256 bytes, 1: 512-byte src row segments, 2: 512-byte dst
+// row segments)
+constexpr int NGEO = 3;
+constexpr int NGROUPS = 4 * 4 * 2 * 2 * NGEO;
+// jobs of at least this many default tiles may take a wider geometry
 constexpr int64_t WIDE_MIN_TILES = 16;
 int wclass(int w) { return w == 16 ? 0 : w == 8 ? 1 : w == 4 ? 2 : 3; }
 int wof(int wc) { return wc == 0 ? 16 : wc == 1 ? 8 : wc == 2 ? 4 : 0; }
@@ -234,17 +236,23 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         j._pad = 0;
         const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
         const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(eb)];
-        const bool wide = eb >= 2 && j.w >= 4 && (lines ? c.tile : c.tile_shared) == 2 &&
-                          tiles_for(eb, d.rows, d.cols, nullptr) >= WIDE_MIN_TILES &&
-                          off32_wide(eb, d.ld_src, d.ld_dst);
+        const int want = lines ? c.tile : c.tile_shared;
+        const int geo = eb >= 2 && j.w >= 4 && (want == 1 || want == 2) &&
+                                tiles_for(eb, d.rows, d.cols, nullptr) >= WIDE_MIN_TILES &&
+                                off32_geo(eb, want, d.ld_src, d.ld_dst)
+                            ? want
+                            : 0;
         const int g = (((cfg_slot(eb) * 4 + wclass(j.w)) * 2 +
-                        (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0)) * 2 + (lines ? 1 : 0)) * 2 +
-                      (wide ? 1 : 0);
+                        (off32_rt(eb, d.ld_src, d.ld_dst) ? 1 : 0)) * 2 + (lines ? 1 : 0)) * NGEO +
+                      geo;
         j.tile_base = bt.ntiles[g];
-        bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c, wide);
+        bt.ntiles[g] += tiles_for(eb, d.rows, d.cols, &j.tiles_c, geo);
         groups[g].push_back(j);
     }
     for (int g = 0; g < NGROUPS; g++) {
+        if (bt.ntiles[g] >= MAX_TILES)
+            return fail(XTR_EINVAL, "%s: %lld tiles in one launch group (limit 2^31)", who,
+                        (long long)bt.ntiles[g]);
         bt.at[g] = bt.all.size();
         bt.nj[g] = (int)groups[g].size();
         bt.all.insert(bt.all.end(), groups[g].begin(), groups[g].end());
@@ -287,18 +295,19 @@ int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
             }
             pk = &pack;
         }
-        const int slot = g / 32, w = wof((g / 8) % 4);
-        const bool off32 = ((g / 4) & 1) != 0, lines = ((g / 2) & 1) != 0, wide = (g & 1) != 0;
+        const int geo = g % NGEO, h = g / NGEO;
+        const int slot = h / 16, w = wof((h / 4) % 4);
+        const bool off32 = ((h / 2) & 1) != 0, lines = (h & 1) != 0;
         // at most the resident capacity of the group's kernel (clamped at launch)
         int64_t grid = bt.ntiles[g] < 0x7fffffff ? bt.ntiles[g] : 0x7fffffff;
         if (grid < 1) grid = 1;
         const Job *jobs = dev ? djobs + bt.at[g] : nullptr;
         const int64_t *bases = dev ? dbases + bt.at[g] : nullptr;
         switch (slot) {
-        case 0: launch_group_e1(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 1: launch_group_e2(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 2: launch_group_e4(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        default: launch_group_e8(w, off32, lines, wide, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 0: launch_group_e1(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 1: launch_group_e2(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 2: launch_group_e4(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        default: launch_group_e8(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
         }
         XTR_HIP(hipGetLastError());
     }

@@ -123,23 +123,28 @@ template <bool NT> __device__ __forceinline__ void st16(unsigned char *p, const 
 // XCD b % 8).  xcd_remap gives each XCD a contiguous range of the launch's
 // linear order, so neighbouring tiles -- which share the cache lines at their
 // edges when rows are not 128-byte aligned -- meet in the same L2.
-__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t G) {
-    const int64_t x = b & 7, k = b >> 3, q = G >> 3, r = G & 7;
+// Tile counts fit in 32 bits (the host checks it), so the index arithmetic
+// of a tile's position is 32-bit.
+__device__ __forceinline__ uint32_t xcd_remap(uint32_t b, uint32_t G) {
+    const uint32_t x = b & 7, k = b >> 3, q = G >> 3, r = G & 7;
     return x * q + (x < r ? x : r) + k;
 }
 
 // Tile (tr, tc) at position L of the launch order: bands of `group` tile rows,
 // column-major inside a band (group = 1 is plain row-major), so that the tiles
 // in flight together write longer runs of each dst row.
-__device__ __forceinline__ void band_order(int64_t L, int64_t tiles_r, int64_t tiles_c, int group,
-                                           int64_t &tr, int64_t &tc) {
-    const int64_t per = (int64_t)group * tiles_c;
-    const int64_t band = L / per, w = L - band * per;
-    const int64_t left = tiles_r - band * group;
-    const int64_t rib = left < group ? left : group;
-    tr = band * group + w % rib;
+__device__ __forceinline__ void band_order(uint32_t L, uint32_t tiles_r, uint32_t tiles_c,
+                                           uint32_t group, uint32_t &tr, uint32_t &tc) {
+    const uint32_t per = group * tiles_c;
+    const uint32_t band = L / per, w = L - band * per;
+    const uint32_t left = tiles_r - band * group;
+    const uint32_t rib = left < group ? left : group;
     tc = w / rib;
+    tr = band * group + (w - tc * rib);
 }
+
+// Largest tile count of one launch (single call or batch group).
+constexpr int64_t MAX_TILES = (int64_t)1 << 31;
 
 // ---------------------------------------------------------------- W-byte pieces
 
@@ -273,11 +278,13 @@ __device__ __forceinline__ void st_funnel_edge(unsigned char *pp, uint32_t piece
 
 // ---------------------------------------------------------------- one tile
 
-// Moves the TR x TC tile at (R0, C0).  Interior tiles run without any bounds
-// test; tiles on the right or bottom edge mask whole pieces and fall back to
-// single elements only for the one piece a matrix edge cuts.
-template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
-__device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
+// Moves the TR x TC tile at (R0, C0), in two phases with a block barrier
+// between them (tile_phase<1>: src -> LDS; tile_phase<2>: LDS -> dst).
+// Interior tiles run without any bounds test; tiles on the right or bottom
+// edge mask whole pieces and fall back to single elements only for the one
+// piece a matrix edge cuts.
+template <int PH, int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
+__device__ __forceinline__ void tile_phase(const unsigned char *__restrict__ src,
                                         unsigned char *__restrict__ dst, int64_t rows,
                                         int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                         int64_t C0, uint4 *lds) {
@@ -305,7 +312,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     // the first two live in scalar registers, the lane offset is computed once.
 
     // phase 1: P lanes per src row segment, rows RP apart per pass
-    {
+    if constexpr (PH == 1) {
         const int k = t % P, r0 = M::p1_row(t, 0);
         const int64_t ldsrc = ld_src * EB;
         const unsigned char *tb = src + (R0 * ld_src + C0) * EB;           // uniform
@@ -372,16 +379,27 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
                 *reinterpret_cast<PT *>(ldsb + M::lds_byte(row, M::p1_byte(t))) = v[p];
             }
         } else {
+            // Edge tile: every whole piece in range is loaded first, all in
+            // flight (a piece out of range, or the one a matrix edge cuts,
+            // loads the tile's first piece instead -- it always exists -- and
+            // that value is never used); then the LDS writes, with the cut
+            // piece read element by element.  LDS rows and columns outside
+            // the matrix are left as they are: phase 2 never stores them.
             const int64_t c = C0 + (int64_t)k * EPW;
-#pragma unroll 4
-            for (int p = 0; p < PASSES; p++) {   // edge tile: one piece at a time
+            const bool cin = c < cols, cwhole = c + EPW <= cols;
+            PT v[PASSES];
+#pragma unroll
+            for (int p = 0; p < PASSES; p++) {
+                const bool use = cwhole && R0 + M::p1_row(t, p) < rows;
+                v[p] = ldw<W, NTL>(use ? (tb + (int64_t)(RP * p) * ldsrc) + lane : tb);
+            }
+#pragma unroll
+            for (int p = 0; p < PASSES; p++) {
                 const int row = M::p1_row(t, p);
-                if (R0 + row >= rows || c >= cols) continue;   // never stored: LDS left as is
-                const unsigned char *a = (tb + (int64_t)(RP * p) * ldsrc) + lane;
-                PT pv;
-                if (c + EPW <= cols) {
-                    pv = ldw<W, NTL>(a);
-                } else {
+                if (R0 + row >= rows || !cin) continue;   // never stored: LDS left as is
+                PT pv = v[p];
+                if (!cwhole) {
+                    const unsigned char *a = (tb + (int64_t)(RP * p) * ldsrc) + lane;
                     union { PT pt; T e[EPW]; } u;
                     u.pt = PT{};
 #pragma unroll
@@ -394,7 +412,8 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
         }
     }
 
-    __syncthreads();   // ownership of the LDS tile moves from loaders to storers
+    // (between the phases: a block barrier -- ownership of the LDS tile moves
+    // from loaders to storers)
 
     // phase 2: P2 lanes per dst row segment.  Lane k stores piece k,
     // i.e. src rows k*E .. k*E+E-1 of one src column, so the lanes of a store
@@ -402,7 +421,7 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     // per instruction whatever W is).  The lane reads E 16-byte row chunks
     // from LDS and transposes them in registers into V pieces, one per dst
     // row of the chunk.  With W = 16 this is the V x V block transpose.
-    {
+    if constexpr (PH == 2) {
         constexpr int RP2 = M::RP2;                  // column chunks per pass
         constexpr int CPT = M::CPT;                  // 16-byte column chunks per lane
         const int k = M::p2_piece(t), g = M::p2_chunk(t, 0);
@@ -455,20 +474,31 @@ __device__ __forceinline__ void do_tile(const unsigned char *__restrict__ src,
     }
 }
 
-// W = 0 selects the form for rows that are not 4-byte aligned.  OFF32: every per-lane offset inside a
+// W = 0 selects the form for rows that are not 4-byte aligned (funnel-shifted
+// 4-byte pieces, default geometry).  OFF32: every per-lane offset inside a
 // tile fits in 32 bits (the host checks the pitches), so addresses are a
 // uniform 64-bit tile base plus a 32-bit lane offset.
+template <int PH, int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
+__device__ __forceinline__ void phase_any(const unsigned char *src, unsigned char *dst, int64_t rows,
+                                          int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
+                                          int64_t C0, uint4 *lds) {
+    if constexpr (W == 0) {
+        static_assert(SC == 16 && DC == 16, "unaligned rows use the default geometry");
+        tile_phase<PH, EB, 1, NTL, NTS, OFF32, 16, 16>(src, dst, rows, cols, ld_src, ld_dst, R0,
+                                                       C0, lds);
+    } else {
+        tile_phase<PH, EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0,
+                                                       C0, lds);
+    }
+}
+
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __device__ __forceinline__ void tile_any(const unsigned char *src, unsigned char *dst, int64_t rows,
                                          int64_t cols, int64_t ld_src, int64_t ld_dst, int64_t R0,
                                          int64_t C0, uint4 *lds) {
-    if constexpr (W == 0) {
-        // rows not 4-byte aligned: funnel-shifted 4-byte pieces
-        static_assert(SC == 16 && DC == 16, "unaligned rows use the default geometry");
-        do_tile<EB, 1, NTL, NTS, OFF32, 16, 16>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
-    } else {
-        do_tile<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
-    }
+    phase_any<1, EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
+    __syncthreads();   // ownership of the LDS tile moves from loaders to storers
+    phase_any<2, EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, R0, C0, lds);
 }
 
 // ---------------------------------------------------------------- kernels
@@ -481,17 +511,16 @@ __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ 
                                               int group) {
     using G = Geo<EB, SC, DC>;
     __shared__ uint4 lds[G::LDS_VECS];
-    const int64_t ntiles = tiles_r * tiles_c;
-    for (int64_t b = blockIdx.x; b < ntiles; b += gridDim.x) {
-        const int64_t G = gridDim.x;
-        // position in the launch order: XCD-contiguous within each wave of G tiles
-        const int64_t wave0 = b - blockIdx.x;
-        const int64_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
-        const int64_t L = xcd ? wave0 + xcd_remap(blockIdx.x, inwave) : b;
-        int64_t tr, tc;
-        band_order(L, tiles_r, tiles_c, group, tr, tc);
-        tile_any<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst, tr * G::TR,
-                                                 tc * G::TC, lds);
+    const uint32_t ntiles = (uint32_t)(tiles_r * tiles_c), Gd = gridDim.x, bx = blockIdx.x;
+    for (uint32_t b = bx; b < ntiles; b += Gd) {
+        // position in the launch order: XCD-contiguous within each wave of Gd tiles
+        const uint32_t wave0 = b - bx;
+        const uint32_t inwave = (ntiles - wave0) < Gd ? (ntiles - wave0) : Gd;
+        const uint32_t L = xcd ? wave0 + xcd_remap(bx, inwave) : b;
+        uint32_t tr, tc;
+        band_order(L, (uint32_t)tiles_r, (uint32_t)tiles_c, (uint32_t)group, tr, tc);
+        tile_any<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst,
+                                                 (int64_t)tr * G::TR, (int64_t)tc * G::TC, lds);
         __syncthreads();   // LDS is reused by the next tile of this workgroup
     }
 }
@@ -505,6 +534,8 @@ struct Job {
     int64_t tile_base;   // first global tile id of this job
     int32_t w, _pad;     // piece width in bytes (4, 8, 16), 0 = rows not 4-byte aligned
 };
+constexpr int JOB_DWORDS = (int)(sizeof(Job) / 4);
+static_assert(sizeof(Job) % 4 == 0 && JOB_DWORDS <= 64, "a Job is loaded one dword per lane");
 
 // Job of linear tile L within a group: the last j with bases[j] <= L
 // (bases[0] = 0, increasing; bases[j] = first tile of job j).  Every lane of
@@ -532,39 +563,92 @@ __device__ __forceinline__ int job_forward(const int64_t *bases, int nj, int j, 
     }
 }
 
+// A job's record, dword i held by lane i (one vector load per lane, so the
+// wave can wait for it together with its other vector loads), and the record
+// gathered from the lanes.
+__device__ __forceinline__ uint32_t job_dword(const Job *jobs, int j) {
+    const int l = threadIdx.x & 63;
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(jobs + j);
+    return p[l < JOB_DWORDS ? l : 0];   // lanes past the record reload dword 0
+}
+__device__ __forceinline__ Job job_gather(uint32_t v) {
+    uint32_t d[JOB_DWORDS];
+#pragma unroll
+    for (int i = 0; i < JOB_DWORDS; i++) d[i] = (uint32_t)__builtin_amdgcn_readlane((int)v, i);
+    Job jb;
+    __builtin_memcpy(&jb, d, sizeof(Job));
+    return jb;
+}
+
 // Persistent over the concatenated tile space of a group of jobs.  Round i
 // of the grid covers positions [i G, i G + G) of the launch order; within a
 // round each XCD takes a contiguous range (xcd_remap), and within a job tiles
 // follow the band order, so tiles that share cache lines at their edges (rows
 // of a job whose pitch is not a multiple of the line) meet in one L2.
-template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC>
+// The next tile's job is found while the current tile moves: its search
+// probe is loaded before the tile's loads, and its record after the tile is
+// staged in LDS, ahead of the tile's stores; neither waits on the tile's
+// memory traffic.
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC, int DC>
 __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *bases, int njobs,
-                                              int64_t ntiles, int xcd, int group, uint4 *lds) {
-    using Gm = Geo<EB, 16, DC>;
-    const int64_t G = gridDim.x;
-    int j = -1;
-    for (int64_t wave0 = 0; wave0 < ntiles; wave0 += G) {
-        const int64_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
-        if ((int64_t)blockIdx.x >= inwave) break;          // only in the last round
-        const int64_t L = wave0 + (xcd ? xcd_remap(blockIdx.x, inwave) : (int64_t)blockIdx.x);
-        j = (j < 0) ? job_search(bases, njobs, L) : job_forward(bases, njobs, j, L);
-        const Job &jb = jobs[j];
-        const int64_t tiles_r = (jb.rows + Gm::TR - 1) / Gm::TR;
-        int64_t tr, tc;
-        band_order(L - jb.tile_base, tiles_r, jb.tiles_c, group, tr, tc);
-        tile_any<EB, W, NTL, NTS, OFF32, 16, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
-                                                 jb.ld_dst, tr * Gm::TR, tc * Gm::TC, lds);
-        __syncthreads();
+                                              int64_t ntiles64, int xcd, int group, uint4 *lds) {
+    using Gm = Geo<EB, SC, DC>;
+    const uint32_t ntiles = (uint32_t)ntiles64, G = gridDim.x, bx = blockIdx.x;
+    const int l = threadIdx.x & 63;
+    auto position = [&](uint32_t wave0) {
+        const uint32_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
+        return wave0 + (xcd ? xcd_remap(bx, inwave) : bx);
+    };
+    auto runs = [&](uint32_t wave0) {   // this workgroup has a tile in the round at wave0
+        return wave0 < ntiles && bx < ntiles - wave0;
+    };
+    if (!runs(0)) return;
+    uint32_t wave0 = 0, L = position(0);
+    int j = job_search(bases, njobs, L);
+    Job jb = job_gather(job_dword(jobs, j));
+    for (;;) {
+        const uint32_t wave1 = wave0 + G;
+        const bool more = wave1 > wave0 && runs(wave1);   // uniform
+        uint32_t Ln = 0;
+        int c = 0;
+        int64_t probe = 0;
+        if (more) {
+            Ln = position(wave1);
+            c = j + 1 + l;
+            probe = bases[c < njobs ? c : njobs - 1];   // (unconditional load; c checked below)
+        }
+        const uint32_t tiles_r = (uint32_t)((jb.rows + Gm::TR - 1) / Gm::TR);
+        uint32_t tr, tc;
+        band_order(L - (uint32_t)jb.tile_base, tiles_r, (uint32_t)jb.tiles_c, (uint32_t)group, tr, tc);
+        const int64_t R0 = (int64_t)tr * Gm::TR, C0 = (int64_t)tc * Gm::TC;
+        phase_any<1, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
+                                                     jb.ld_dst, R0, C0, lds);
+        __syncthreads();   // ownership of the LDS tile moves from loaders to storers
+        uint32_t next = 0;
+        if (more) {
+            const int k = __popcll(__ballot(c < njobs && probe <= (int64_t)Ln));
+            j += k;
+            if (k == 64) j = job_forward(bases, njobs, j, Ln);   // more than 64 jobs ahead
+            next = job_dword(jobs, j);
+        }
+        phase_any<2, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
+                                                     jb.ld_dst, R0, C0, lds);
+        __syncthreads();   // LDS is reused by the next tile of this workgroup
+        if (!more) break;
+        jb = job_gather(next);
+        L = Ln;
+        wave0 = wave1;
     }
 }
 
-// DC = 32: 512-byte dst row segments (the tile_shared = 2 geometry).
-template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC = 16>
+// Tile geometry of a batch group: SC / DC 16-byte chunks per src / dst row
+// segment (SC = 32: 512-byte src row segments, DC = 32: 512-byte dst ones).
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
                                                       const int64_t *__restrict__ bases, int njobs,
                                                       int64_t ntiles, int xcd, int group) {
-    __shared__ uint4 lds[Geo<EB, 16, DC>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32, DC>(jobs, bases, njobs, ntiles, xcd, group, lds);
+    __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(jobs, bases, njobs, ntiles, xcd, group, lds);
 }
 
 // A small group passes its jobs inside the kernel arguments: no table upload
@@ -575,18 +659,18 @@ struct JobPack {
     int64_t bases[INLINE_JOBS];
 };
 
-template <int EB, int W, bool NTL, bool NTS, bool OFF32, int DC = 16>
+template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched_inl(JobPack pk, int njobs, int64_t ntiles,
                                                           int xcd, int group) {
-    __shared__ uint4 lds[Geo<EB, 16, DC>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
+    __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
+    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
 }
 
 // ---------------------------------------------------------------- host side
 
 
 // Per-lane offsets inside a tile stay below 2^31 (so the 32-bit addressing of
-// do_tile is exact): tile rows x row pitch on either side, plus one row.
+// tile_phase is exact): tile rows x row pitch on either side, plus one row.
 template <int EB, int SC = 16, int DC = 16> bool off32_ok(int64_t ld_src, int64_t ld_dst) {
     using G = Geo<EB, SC, DC>;
     const int64_t lim = (int64_t)1 << 31;
@@ -613,31 +697,46 @@ inline int piece_width(const void *src, const void *dst, int64_t ld_src, int64_t
     return 0;
 }
 
-template <int EB, int DC = 16> int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
-    using G = Geo<EB, 16, DC>;
+template <int EB, int SC = 16, int DC = 16>
+int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
+    using G = Geo<EB, SC, DC>;
     const int64_t tr = (rows + G::TR - 1) / G::TR;
     const int64_t tc = (cols + G::TC - 1) / G::TC;
     if (tiles_c) *tiles_c = tc;
     return tr * tc;
 }
 
-// wide: the DC = 32 geometry (2- to 8-byte elements)
-inline int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, bool wide = false) {
+// Tile geometries of 2- to 8-byte elements: 0 = 256 x 256 bytes, 1 = 512-byte
+// src row segments (SC = 32), 2 = 512-byte dst row segments (DC = 32).
+template <int EB, int GEO> struct GeoOf;
+template <int EB> struct GeoOf<EB, 0> { static constexpr int SC = 16, DC = 16; };
+template <int EB> struct GeoOf<EB, 1> { static constexpr int SC = 32, DC = 16; };
+template <int EB> struct GeoOf<EB, 2> { static constexpr int SC = 16, DC = 32; };
+
+inline int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, int geo = 0) {
+#define XTR_TF(E)                                                                              \
+    return geo == 1 ? tiles_of<E, 32, 16>(rows, cols, tiles_c)                                \
+         : geo == 2 ? tiles_of<E, 16, 32>(rows, cols, tiles_c) : tiles_of<E>(rows, cols, tiles_c)
     switch (eb) {
     case 1: return tiles_of<1>(rows, cols, tiles_c);
-    case 2: return wide ? tiles_of<2, 32>(rows, cols, tiles_c) : tiles_of<2>(rows, cols, tiles_c);
-    case 4: return wide ? tiles_of<4, 32>(rows, cols, tiles_c) : tiles_of<4>(rows, cols, tiles_c);
-    default: return wide ? tiles_of<8, 32>(rows, cols, tiles_c) : tiles_of<8>(rows, cols, tiles_c);
+    case 2: XTR_TF(2);
+    case 4: XTR_TF(4);
+    default: XTR_TF(8);
     }
+#undef XTR_TF
 }
 
-inline bool off32_wide(int eb, int64_t ld_src, int64_t ld_dst) {
+inline bool off32_geo(int eb, int geo, int64_t ld_src, int64_t ld_dst) {
+#define XTR_OG(E)                                                                              \
+    return geo == 1 ? off32_ok<E, 32, 16>(ld_src, ld_dst)                                     \
+         : geo == 2 ? off32_ok<E, 16, 32>(ld_src, ld_dst) : off32_ok<E>(ld_src, ld_dst)
     switch (eb) {
-    case 2: return off32_ok<2, 16, 32>(ld_src, ld_dst);
-    case 4: return off32_ok<4, 16, 32>(ld_src, ld_dst);
-    case 8: return off32_ok<8, 16, 32>(ld_src, ld_dst);
-    default: return false;
+    case 1: return off32_ok<1>(ld_src, ld_dst);
+    case 2: XTR_OG(2);
+    case 4: XTR_OG(4);
+    default: XTR_OG(8);
     }
+#undef XTR_OG
 }
 
 constexpr int64_t MAX_GRID = 1 << 20;   // workgroups per launch; larger jobs loop
@@ -698,8 +797,8 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
 }
 
 // Tile geometry of a single transpose (`tile` for line-aligned rows,
-// `tile_shared` otherwise): 1 = 512-byte src row segments (16-byte pieces
-// only), 2 = 512-byte dst row segments, else 256 x 256 bytes.  Wider segments
+// `tile_shared` otherwise): 1 = 512-byte src row segments, 2 = 512-byte dst
+// row segments, else 256 x 256 bytes.  Wider segments
 // halve the share of edge lines that neighbouring tiles split.  2- to 8-byte
 // elements only.
 // A matrix of fewer default tiles than SINGLE_WIDE_MIN_TILES (8 per CU on
@@ -713,6 +812,7 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     const bool lines = lines_ok(src, ld_src, EB) && lines_ok(dst, ld_dst, EB);
     const int64_t ntiles = ((rows + Geo<EB>::TR - 1) / Geo<EB>::TR) *
                            ((cols + Geo<EB>::TC - 1) / Geo<EB>::TC);
+    if (ntiles >= MAX_TILES) return fail(XTR_EINVAL, "tpose: %lld tiles (limit 2^31)", (long long)ntiles);
     const int tile = ntiles < SINGLE_WIDE_MIN_TILES ? 0 : lines ? c.tile : c.tile_shared;
     switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
     case 16:
@@ -730,6 +830,10 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         break;
     case 8:
         if constexpr (EB >= 2 && EB <= 8) {
+            if (tile == 1) {
+                launch_w<EB, 8, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
             if (tile == 2) {
                 launch_w<EB, 8, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
@@ -739,6 +843,10 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         break;
     case 4:
         if constexpr (EB >= 2 && EB <= 4) {
+            if (tile == 1) {
+                launch_w<EB, 4, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
             if (tile == 2) {
                 launch_w<EB, 4, 16, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
@@ -756,7 +864,7 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 
 // `lines`: every job of the group has line-aligned src and dst rows.  `pk`
 // (host) non-null: the group's jobs travel in the kernel arguments.
-template <int EB, int W, bool OFF32, int DC = 16>
+template <int EB, int W, bool OFF32, int SC = 16, int DC = 16>
 void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
                       const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
     const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(EB)];
@@ -769,14 +877,14 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
     do {                                                                                    \
         if (pk) {                                                                           \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>, NT, cap);      \
-            hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32, DC>),             \
+                (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, SC, DC>, NT, cap);  \
+            hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32, SC, DC>),         \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                *pk, nj, ntiles, c.xcd, group);                              \
         } else {                                                                            \
             const int64_t occ = resident_blocks(                                            \
-                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, DC>, NT, cap);          \
-            hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, DC>),                 \
+                (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>, NT, cap);      \
+            hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>),             \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
                                jobs, bases, nj, ntiles, c.xcd, group);                      \
         }                                                                                   \
@@ -788,14 +896,20 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
 #undef XTR_KB
 }
 
+// geo: the group's tile geometry (0, 1 or 2, as `tile`); the wider ones need
+// 32-bit lane offsets (the host groups jobs accordingly).
 template <int EB>
-void launch_batched(int w, bool off32, bool lines, bool wide, int64_t grid, hipStream_t st,
+void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStream_t st,
                     const Job *jobs, const int64_t *bases, int nj, int64_t ntiles,
                     const JobPack *pk) {
 #define XTR_BW(WW)                                                                             \
     if constexpr (EB >= 2 && WW >= 4) {                                                        \
-        if (wide) {                                                                            \
-            launch_batched_w<EB, WW, true, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk);  \
+        if (geo == 1) {                                                                        \
+            launch_batched_w<EB, WW, true, 32, 16>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+            return;                                                                            \
+        }                                                                                      \
+        if (geo == 2) {                                                                        \
+            launch_batched_w<EB, WW, true, 16, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
             return;                                                                            \
         }                                                                                      \
     }                                                                                          \
@@ -823,7 +937,7 @@ void launch_batched(int w, bool off32, bool lines, bool wide, int64_t grid, hipS
 #define XTR_TPOSE_EB_DECL(EB)                                                               \
     int launch_single_e##EB(const void *src, void *dst, int64_t rows, int64_t cols,          \
                             int64_t ld_src, int64_t ld_dst, hipStream_t stream);             \
-    void launch_group_e##EB(int w, bool off32, bool lines, bool wide, int64_t grid,          \
+    void launch_group_e##EB(int w, bool off32, bool lines, int geo, int64_t grid,            \
                             hipStream_t st, const Job *jobs, const int64_t *bases, int nj,   \
                             int64_t ntiles, const JobPack *pk);
 XTR_TPOSE_EB_DECL(1)

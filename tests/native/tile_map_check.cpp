@@ -162,6 +162,11 @@ int main() {
     check<8, 16, 32, 16>("f64 W16 src512");
     check<8, 16, 16, 32>("f64 W16 dst512");
     check<8, 8, 16, 32>("f64 W8  dst512");
+    check<2, 8, 32, 16>("b16 W8  src512");
+    check<2, 4, 32, 16>("b16 W4  src512");
+    check<4, 8, 32, 16>("f32 W8  src512");
+    check<4, 4, 32, 16>("f32 W4  src512");
+    check<8, 8, 32, 16>("f64 W8  src512");
     std::printf("%s\n", failures ? "FAILED" : "all tile maps ok");
     return failures ? 1 : 0;
 }

@@ -131,15 +131,17 @@ def test_tile_geometries(xtr, orc, eb, tile):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
+@pytest.mark.parametrize("geo", [1, 2])
 @pytest.mark.parametrize("eb,w", [(2, 4), (2, 8), (2, 16), (4, 4), (4, 8), (4, 16), (8, 8),
                                   (8, 16)])
-def test_tile_geometry_shared_rows(xtr, orc, eb, w):
-    """512-byte dst row segments (tile_shared = 2) for rows that do not start
-    on cache lines, with every piece width, whole and ragged tiles."""
+def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
+    """512-byte src (tile_shared = 1) or dst (tile_shared = 2) row segments
+    for rows that do not start on cache lines, with every piece width, whole
+    and ragged tiles."""
     orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
-        xtr.set_tpose_config(eb, "single", tile_shared=2)
+        xtr.set_tpose_config(eb, "single", tile_shared=geo)
         # >= 2048 default tiles, and a small one that keeps the default geometry
         for i, (r, c) in enumerate([(64 * T, 32 * T), (64 * T + 3, 32 * T + 5),
                                     (50 * T - 1, 48 * T + 1), (2 * T - 1, T + 1)]):
@@ -151,11 +153,12 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("wide", [0, 2])
+@pytest.mark.parametrize("wide", [0, 1, 2])
 def test_batched_geometries(xtr, orc, wide):
-    """Batched transposes with the wide (512-byte dst rows) geometry for jobs
-    whose rows share lines, mixed with small and aligned jobs and every
-    element size; each job against the oracle."""
+    """Batched transposes with each tile geometry (512-byte src rows: 1, dst
+    rows: 2) for jobs whose rows share lines, mixed with small and aligned
+    jobs, every element size and every piece width; each job against the
+    oracle."""
     import torch
     rng = np.random.Generator(np.random.PCG64(19))
     origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
