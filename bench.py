@@ -342,7 +342,7 @@ def serving(xtr, torch, seconds=3.0, rate=20000.0, seed=12, host_frac=0.25,
         serve.run_native(xtr, torch, warm, pool=pool, outs=outs, **kw)
     keys = ("jobs", "p50_ms", "p99_ms", "mean_ms", "throughput_gbs", "achieved_jobs_per_s",
             "launches", "batches", "mean_jobs_per_batch", "max_inflight_gib", "graph_launches",
-            "graph_builds", "host_copies")
+            "graph_builds", "host_copies", "by_size")
     res = {"rate_jobs_per_s": rate, "seconds": seconds, "loop": "native (xtr_server)",
            "offered_gbs": round(W.mean_job_bytes() * rate / 1e9, 1)}
     for name, kw in configs:

@@ -707,16 +707,22 @@ int64_t tiles_of(int64_t rows, int64_t cols, int64_t *tiles_c) {
 }
 
 // Tile geometries of 2- to 8-byte elements: 0 = 256 x 256 bytes, 1 = 512-byte
-// src row segments (SC = 32), 2 = 512-byte dst row segments (DC = 32).
+// src row segments (SC = 32), 2 = 512-byte dst row segments (DC = 32), 3 =
+// both (4- and 8-byte elements only: 64 KiB of LDS for fp32).  Wider row
+// segments leave fewer partial cache lines at segment ends, which neighbouring
+// tiles share when rows do not start on lines.
 template <int EB, int GEO> struct GeoOf;
 template <int EB> struct GeoOf<EB, 0> { static constexpr int SC = 16, DC = 16; };
 template <int EB> struct GeoOf<EB, 1> { static constexpr int SC = 32, DC = 16; };
 template <int EB> struct GeoOf<EB, 2> { static constexpr int SC = 16, DC = 32; };
+template <int EB> struct GeoOf<EB, 3> { static constexpr int SC = 32, DC = 32; };
 
 inline int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, int geo = 0) {
 #define XTR_TF(E)                                                                              \
     return geo == 1 ? tiles_of<E, 32, 16>(rows, cols, tiles_c)                                \
-         : geo == 2 ? tiles_of<E, 16, 32>(rows, cols, tiles_c) : tiles_of<E>(rows, cols, tiles_c)
+         : geo == 2 ? tiles_of<E, 16, 32>(rows, cols, tiles_c)                                \
+         : geo == 3 && E >= 4 ? tiles_of<E, 32, 32>(rows, cols, tiles_c)                      \
+                              : tiles_of<E>(rows, cols, tiles_c)
     switch (eb) {
     case 1: return tiles_of<1>(rows, cols, tiles_c);
     case 2: XTR_TF(2);
@@ -729,7 +735,8 @@ inline int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, i
 inline bool off32_geo(int eb, int geo, int64_t ld_src, int64_t ld_dst) {
 #define XTR_OG(E)                                                                              \
     return geo == 1 ? off32_ok<E, 32, 16>(ld_src, ld_dst)                                     \
-         : geo == 2 ? off32_ok<E, 16, 32>(ld_src, ld_dst) : off32_ok<E>(ld_src, ld_dst)
+         : geo == 2 ? off32_ok<E, 16, 32>(ld_src, ld_dst)                                     \
+         : geo == 3 && E >= 4 ? off32_ok<E, 32, 32>(ld_src, ld_dst) : off32_ok<E>(ld_src, ld_dst)
     switch (eb) {
     case 1: return off32_ok<1>(ld_src, ld_dst);
     case 2: XTR_OG(2);
@@ -798,7 +805,7 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
 
 // Tile geometry of a single transpose (`tile` for line-aligned rows,
 // `tile_shared` otherwise): 1 = 512-byte src row segments, 2 = 512-byte dst
-// row segments, else 256 x 256 bytes.  Wider segments
+// row segments, 3 = both (4- and 8-byte elements), else 256 x 256 bytes.  Wider segments
 // halve the share of edge lines that neighbouring tiles split.  2- to 8-byte
 // elements only.
 // A matrix of fewer default tiles than SINGLE_WIDE_MIN_TILES (8 per CU on
@@ -816,6 +823,12 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     const int tile = ntiles < SINGLE_WIDE_MIN_TILES ? 0 : lines ? c.tile : c.tile_shared;
     switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
     case 16:
+        if constexpr (EB >= 4) {
+            if (tile == 3) {
+                launch_w<EB, 16, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
         if constexpr (EB >= 2) {
             if (tile == 1) {
                 launch_w<EB, 16, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
@@ -829,6 +842,12 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         launch_w<EB, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     case 8:
+        if constexpr (EB >= 4 && EB <= 8) {
+            if (tile == 3) {
+                launch_w<EB, 8, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
         if constexpr (EB >= 2 && EB <= 8) {
             if (tile == 1) {
                 launch_w<EB, 8, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
@@ -842,6 +861,12 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         if constexpr (EB <= 8) launch_w<EB, 8>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
         break;
     case 4:
+        if constexpr (EB == 4) {
+            if (tile == 3) {
+                launch_w<EB, 4, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+        }
         if constexpr (EB >= 2 && EB <= 4) {
             if (tile == 1) {
                 launch_w<EB, 4, 32, 16>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
@@ -910,6 +935,12 @@ void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStr
         }                                                                                      \
         if (geo == 2) {                                                                        \
             launch_batched_w<EB, WW, true, 16, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+            return;                                                                            \
+        }                                                                                      \
+    }                                                                                          \
+    if constexpr (EB >= 4 && WW >= 4) {                                                        \
+        if (geo == 3) {                                                                        \
+            launch_batched_w<EB, WW, true, 32, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
             return;                                                                            \
         }                                                                                      \
     }                                                                                          \

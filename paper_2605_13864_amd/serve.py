@@ -346,6 +346,23 @@ def host_resident(jobs, frac, seed, max_input_bytes=16 << 20):
             if pick[i] and (j.nbytes // 2 if j.kind == "tpose" else j.nbytes) <= max_input_bytes}
 
 
+def size_classes(jobs, lat):
+    """p50 / p99 latency (ms) and job count per size class: algorithmic bytes
+    under 4 MiB, 4 to 64 MiB, 64 MiB and more."""
+    nb = np.array([j.nbytes for j in jobs], dtype=np.float64)
+    out = {}
+    for name, lo, hi in (("under_4MiB", 0, 4 << 20), ("4_to_64MiB", 4 << 20, 64 << 20),
+                         ("64MiB_up", 64 << 20, float("inf"))):
+        m = (nb >= lo) & (nb < hi)
+        if m.any():
+            out[name] = {"jobs": int(m.sum()),
+                         "p50_ms": round(float(np.percentile(lat[m], 50)) * 1e3, 4),
+                         "p99_ms": round(float(np.percentile(lat[m], 99)) * 1e3, 4)}
+    top = lat >= np.percentile(lat, 99)
+    out["top_1pct_mean_mib"] = round(float(nb[top].mean()) / 2 ** 20, 1)
+    return out
+
+
 def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, pool=None,
                outs=None, keep_results=False, lead_s=0.005, log=None, graphs=False,
                big_lane=False, host=None, host_inputs=None):
@@ -418,6 +435,7 @@ def run_native(xtr, torch, jobs, *, batching=True, budget=64 << 30, nstreams=4, 
         "mean_jobs_per_batch": round(len(jobs) / max(st["units"], 1), 2),
         "graphs": graphs, "big_lane": big_lane, "graph_launches": st["graph_launches"],
         "graph_builds": st["graph_builds"], "host_copies": st["host_copies"],
+        "by_size": size_classes(jobs, lat),
     }
     if log:
         log(f"serve (native) batching={batching}: p50 {stats['p50_ms']} ms p99 {stats['p99_ms']} ms, "

@@ -68,7 +68,7 @@ def tpose_candidates(quick: bool, eb: int = 4):
     nts = [(1, 1), (0, 0)] if quick else [(1, 1), (1, 0), (0, 1), (0, 0)]
     groups = [1, 4, 16] if quick else [1, 2, 4, 8, 16, 32]
     bpc = [0, 8] if quick else [0, 4, 8, 16]
-    tiles = [0] if eb == 1 else [0, 1, 2]
+    tiles = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
     for (nl, ns), xcd, g, b, tl in itertools.product(nts, [1, 0], groups, bpc, tiles):
         # the *_shared flags follow along here (the main shape may have rows
         # that share lines); they are refined on a shared-line shape afterwards
@@ -199,7 +199,7 @@ def tpose_batched_candidates(quick: bool, eb: int):
     nts = [(0, 0), (1, 1)] if quick else [(0, 0), (1, 1), (1, 0), (0, 1)]
     groups = [1, 16] if quick else [1, 4, 16, 32]
     bpc = [0, 4] if quick else [0, 2, 4, 8]
-    wides = [0] if eb == 1 else [0, 1, 2]
+    wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
     for (nl, ns), xcd, g, b, w in itertools.product(nts, [1, 0], groups, bpc, wides):
         # nearly every job of a random-size batch has rows that share lines:
         # the *_shared flags decide; the line-aligned ones follow along

@@ -167,6 +167,11 @@ int main() {
     check<4, 8, 32, 16>("f32 W8  src512");
     check<4, 4, 32, 16>("f32 W4  src512");
     check<8, 8, 32, 16>("f64 W8  src512");
+    check<4, 16, 32, 32>("f32 W16 512x512");
+    check<4, 8, 32, 32>("f32 W8  512x512");
+    check<4, 4, 32, 32>("f32 W4  512x512");
+    check<8, 16, 32, 32>("f64 W16 512x512");
+    check<8, 8, 32, 32>("f64 W8  512x512");
     std::printf("%s\n", failures ? "FAILED" : "all tile maps ok");
     return failures ? 1 : 0;
 }

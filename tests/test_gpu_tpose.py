@@ -112,10 +112,11 @@ def test_unaligned_rows(xtr, orc, eb):
 
 
 @pytest.mark.parametrize("eb", [2, 4, 8])
-@pytest.mark.parametrize("tile", [1, 2])
+@pytest.mark.parametrize("tile", [1, 2, 3])
 def test_tile_geometries(xtr, orc, eb, tile):
-    """512-byte src (tile 1) or dst (tile 2) row segments: whole and ragged
-    tiles, 16-byte pieces, against the oracle."""
+    """512-byte src (tile 1), dst (tile 2) or both (tile 3; 2-byte elements
+    keep the default) row segments: whole and ragged tiles, 16-byte pieces,
+    against the oracle."""
     orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
@@ -131,11 +132,11 @@ def test_tile_geometries(xtr, orc, eb, tile):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("geo", [1, 2])
+@pytest.mark.parametrize("geo", [1, 2, 3])
 @pytest.mark.parametrize("eb,w", [(2, 4), (2, 8), (2, 16), (4, 4), (4, 8), (4, 16), (8, 8),
                                   (8, 16)])
 def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
-    """512-byte src (tile_shared = 1) or dst (tile_shared = 2) row segments
+    """512-byte src (tile_shared = 1), dst (2) or both (3) row segments
     for rows that do not start on cache lines, with every piece width, whole
     and ragged tiles."""
     orig = xtr.tpose_config(eb, "single")
@@ -153,10 +154,10 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("wide", [0, 1, 2])
+@pytest.mark.parametrize("wide", [0, 1, 2, 3])
 def test_batched_geometries(xtr, orc, wide):
     """Batched transposes with each tile geometry (512-byte src rows: 1, dst
-    rows: 2) for jobs whose rows share lines, mixed with small and aligned
+    rows: 2, both: 3) for jobs whose rows share lines, mixed with small and aligned
     jobs, every element size and every piece width; each job against the
     oracle."""
     import torch
