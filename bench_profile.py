@@ -46,8 +46,9 @@ def _rows(d: str, suffix: str):
 
 def short(name: str) -> str:
     name = re.sub(r"^void ", "", name)
+    name = name.replace("(anonymous namespace)::", "")
     name = re.sub(r"\(.*$", "", name)          # drop the argument list
-    return name.replace("xtr::", "").replace("tpk::", "").replace("(anonymous namespace)::", "")
+    return name.replace("xtr::", "").replace("tpk::", "")
 
 
 def stats(d: str):

@@ -494,7 +494,11 @@ typedef struct {
                             /*    small follow-up kernels add them level by level;  */
                             /*    smaller ranges (or 0 = always) combine in-kernel  */
                             /*    through atomic tickets.  Same result either way.  */
-    int32_t _reserved[6];
+    int32_t seg_fused;      /* segmented sums: 1 = the chunked segments and the     */
+                            /*    small ones in one launch (each workgroup takes    */
+                            /*    chunks first, then its waves take small           */
+                            /*    segments); 0 = two launches.  Same result.        */
+    int32_t _reserved[5];
 } xtr_reduce_config;
 
 /* Current / new configuration of the sums for one dtype and shape class

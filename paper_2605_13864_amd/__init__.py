@@ -43,7 +43,8 @@ class TposeConfig(C.Structure):
 
 
 class ReduceConfig(C.Structure):
-    _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("_reserved", C.c_int32 * 6)]
+    _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("seg_fused", C.c_int32),
+                ("_reserved", C.c_int32 * 5)]
 
 
 class Job(C.Structure):
@@ -546,7 +547,7 @@ def reduce_config(dtype, shape: str = "single") -> dict:
     c = ReduceConfig()
     _check(load().xtr_reduce_get_class_config(_code(dtype), SHAPE_CLASSES[shape], C.byref(c)),
            "xtr_reduce_get_class_config")
-    return {"nt_load": c.nt_load, "split_chunks": c.split_chunks}
+    return {"nt_load": c.nt_load, "split_chunks": c.split_chunks, "seg_fused": c.seg_fused}
 
 
 def set_reduce_config(dtype, shape: str | None = None, **kw):
@@ -555,7 +556,7 @@ def set_reduce_config(dtype, shape: str | None = None, **kw):
     if bad:
         raise TypeError(f"set_reduce_config: unknown settings {sorted(bad)}")
     cur.update(kw)
-    c = ReduceConfig(cur["nt_load"], cur["split_chunks"])
+    c = ReduceConfig(cur["nt_load"], cur["split_chunks"], cur["seg_fused"])
     if shape is None:
         _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
     else:

@@ -871,17 +871,15 @@ __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const
 // Pass 4a: small segments, one wave each (grid-stride over segments); the
 // next segment's bounds are loaded before this one's data, so each segment
 // costs one memory round trip.
+// Small segments, one wave each: the waves of the grid stride over the
+// segments (indices are wave-uniform, so the offsets come through scalar
+// loads, one segment ahead).  A segment's loads are all issued before its
+// value is computed from registers; the other waves of the SIMD cover the
+// wait.
 template <int DT, int MODE, bool NT>
-__global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *src,
-                                                         const int64_t *off,
-                                                         const int64_t *chunk_base, int64_t nseg,
-                                                         int64_t cap, void *out) {
+__device__ __forceinline__ void small_segments(const unsigned char *src, const int64_t *off,
+                                               int64_t nseg, void *out) {
     using P = typename PartT<MODE>::T;
-    if (chunk_base[nseg] > cap) return;   // invalid table: k_reduce_seg writes every output
-    // Each wave strides over the segments (indices are wave-uniform, so the
-    // offsets come through scalar loads, one segment ahead).  A segment's
-    // loads are all issued before its value is computed from registers; the
-    // other waves of the SIMD cover the wait.
     const int64_t nwaves = (int64_t)gridDim.x * NW;
     int64_t s = (int64_t)blockIdx.x * NW + __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int64_t lo = 0, hi = 0;
@@ -901,6 +899,15 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *
         lo = lo_n;
         hi = hi_n;
     }
+}
+
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_seg_small(const unsigned char *src,
+                                                         const int64_t *off,
+                                                         const int64_t *chunk_base, int64_t nseg,
+                                                         int64_t cap, void *out) {
+    if (chunk_base[nseg] > cap) return;   // invalid table: k_reduce_seg writes every output
+    small_segments<DT, MODE, NT>(src, off, nseg, out);
 }
 
 // Pass 4b: the chunks of the other segments, workgroups striding over the
@@ -935,6 +942,43 @@ __global__ void __launch_bounds__(NTHR) k_reduce_seg(const unsigned char *src,
         if (threadIdx.x < 64) grid_combine<MODE>(rg, cr.j, v, lv);
         cr = nx;
     }
+}
+
+// Both passes in one launch: each workgroup reduces chunk records first
+// (as k_reduce_seg), then its waves take small segments (as
+// k_reduce_seg_small), so the fine-grained small segments fill the tail of
+// the chunk work.  Same arithmetic, same results.
+template <int DT, int MODE, bool NT>
+__global__ void __launch_bounds__(NTHR) k_reduce_seg_all(const unsigned char *src,
+                                                       const int64_t *off,
+                                                       const int64_t *chunk_base,
+                                                       const ChunkRec *__restrict__ recs,
+                                                       int64_t nseg, int64_t cap, Levels lv,
+                                                       void *out) {
+    using P = typename PartT<MODE>::T;
+    const int64_t total = chunk_base[nseg];
+    if (total > cap) {   // invalid offsets table: defined outputs, no reads, no tickets
+        for (int64_t s = (int64_t)blockIdx.x * NTHR + threadIdx.x; s < nseg;
+             s += (int64_t)gridDim.x * NTHR) {
+            if constexpr (MODE == INTM) reinterpret_cast<P *>(out)[s] = 0;
+            else reinterpret_cast<P *>(out)[s] = (P)__builtin_nan("");
+        }
+        return;
+    }
+    int64_t b = blockIdx.x;
+    ChunkRec cr{};
+    if (b < total) cr = recs[b];
+    for (; b < total; b += gridDim.x) {
+        ChunkRec nx{};
+        if (b + gridDim.x < total) nx = recs[b + gridDim.x];
+        Range rg = seg_range_lh(src, cr.lo, cr.hi, cr.s, DTI<DT>::EB, chunk_elems<DT>(),
+                                (unsigned char *)out, (int)sizeof(P));
+        rg.chunk_base = b - cr.j;
+        auto v = reduce_chunk<DT, MODE, NT>(rg, cr.j);
+        if (threadIdx.x < 64) grid_combine<MODE>(rg, cr.j, v, lv);
+        cr = nx;
+    }
+    small_segments<DT, MODE, NT>(src, off, nseg, out);
 }
 
 // ---------------------------------------------------------------- host side
@@ -1151,8 +1195,21 @@ void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb,
                            dim3((unsigned)(gc_n < o2 ? gc_n : o2)), dim3(NTHR), 0, st, src, cb,  \
                            cs, nseg, cap, lv, out);                                              \
     } while (0)
-    if (nt) XTR_SEG(true);
-    else XTR_SEG(false);
+#define XTR_SEG_ALL(NTV)                                                                         \
+    do {                                                                                         \
+        const int64_t o = resident_blocks((const void *)&k_reduce_seg_all<DT, MODE, NTV>, NTHR); \
+        const int64_t g = gc_n > gs_n ? gc_n : gs_n;                                             \
+        hipLaunchKernelGGL((k_reduce_seg_all<DT, MODE, NTV>), dim3((unsigned)(g < o ? g : o)),   \
+                           dim3(NTHR), 0, st, src, off, cb, cs, nseg, cap, lv, out);             \
+    } while (0)
+    if (g_rcfg[XTR_SHAPE_BATCHED][DT].seg_fused) {
+        if (nt) XTR_SEG_ALL(true);
+        else XTR_SEG_ALL(false);
+    } else {
+        if (nt) XTR_SEG(true);
+        else XTR_SEG(false);
+    }
+#undef XTR_SEG_ALL
 #undef XTR_SEG
 }
 

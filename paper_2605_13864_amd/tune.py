@@ -110,7 +110,8 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
             src = torch.empty((nr, nc), dtype=tdt, device="cuda")
             src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(nr))
             dst = torch.empty((nc, nr), dtype=tdt, device="cuda")
-            for nls, nss, ts in itertools.product((0, 1), (0, 1), (0, 2) if eb > 1 else (0,)):
+            geos = (0, 1, 2, 3) if eb >= 4 else (0, 1, 2) if eb == 2 else (0,)
+            for nls, nss, ts in itertools.product((0, 1), (0, 1), geos):
                 xtr.set_tpose_config(eb, "single", **dict(best[1], nt_load_shared=nls,
                                                           nt_store_shared=nss, tile_shared=ts))
                 pairs[(nls, nss, ts)] = pairs.get((nls, nss, ts), 0.0) + _time(
@@ -256,15 +257,20 @@ def tune_reduce_batched(xtr, torch, dt: str, log=print, nseg=100000):
     t = {}
     try:
         for nt in (1, 0):
-            xtr.set_reduce_config(dt, "batched", nt_load=nt)
-            t[nt] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out, dtype=dt))
+            for fu in (0, 1):
+                xtr.set_reduce_config(dt, "batched", nt_load=nt, seg_fused=fu)
+                t[(nt, fu)] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out,
+                                                                                dtype=dt))
     finally:
         xtr.set_reduce_config(dt, "batched", **orig)
-    nt = min(t, key=t.get)
-    log(f"tune sum batched {dt}: nt_load {nt} ({total * eb / t[nt] / 1e9:.1f} GB/s)")
+    nt, fu = min(t, key=t.get)
+    log(f"tune sum batched {dt}: nt_load {nt} seg_fused {fu} "
+        f"({total * eb / t[(nt, fu)] / 1e9:.1f} GB/s)")
     del src, ws
-    return {"gbs": round(total * eb / t[nt] / 1e9, 1),
-            "config": {"nt_load": nt, "split_chunks": orig["split_chunks"]}, "nseg": nseg}
+    return {"gbs": round(total * eb / t[(nt, fu)] / 1e9, 1),
+            "config": {"nt_load": nt, "split_chunks": orig["split_chunks"], "seg_fused": fu},
+            "nseg": nseg, "all": {f"nt_load={a} seg_fused={b}": round(total * eb / v / 1e9, 1)
+                                  for (a, b), v in t.items()}}
 
 
 def run(quick=False, out=None, log=print):

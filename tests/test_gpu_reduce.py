@@ -354,3 +354,37 @@ def test_segmented_full_config(xtr, orc):
     rel = np.abs(got[nz] - want[nz]) / np.abs(want[nz])
     assert rel.max() <= 1e-6, rel.max()
     assert np.all(got[~nz] == 0)
+
+
+@pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i32", "i64"])
+def test_segmented_fused_launch_same(xtr, orc, dt):
+    """The segmented sum's two passes in one launch (seg_fused) give the same
+    bits as two launches, for small, chunked and empty segments, and an
+    invalid table still gives NaN / 0 everywhere."""
+    import torch
+    total = 300000
+    off = W.segment_offsets(total, 2000, 95)
+    off[700] = off[699]
+    bits = data(dt, total, 96)
+    d, doff = to_dev(bits), to_dev(off)
+    orig = xtr.reduce_config(dt, "batched")
+    try:
+        res = {}
+        for fu in (0, 1):
+            xtr.set_reduce_config(dt, "batched", seg_fused=fu)
+            res[fu] = xtr.reduce_sum_segmented(d, doff, dtype=dt).cpu()
+        assert torch.equal(res[0], res[1]) or (dt not in ("i32", "i64") and torch.equal(
+            torch.nan_to_num(res[0], nan=7.0), torch.nan_to_num(res[1], nan=7.0)))
+        want = orc.sum_segmented(bits, off, dt)
+        if dt in ("i32", "i64"):
+            assert np.array_equal(res[1].numpy(), want)
+        bad = off.copy()
+        bad[10], bad[11] = bad[11], bad[10] - 1
+        xtr.set_reduce_config(dt, "batched", seg_fused=1)
+        out = xtr.reduce_sum_segmented(d, to_dev(bad), dtype=dt).cpu()
+        if dt in ("i32", "i64"):
+            assert (out == 0).all()
+        else:
+            assert torch.isnan(out).all()
+    finally:
+        xtr.set_reduce_config(dt, "batched", **orig)
