@@ -467,7 +467,11 @@ typedef struct {
                             /*    and 8-byte elements; others take 0)               */
     int32_t tile_shared;    /* the same for rows that do not start on lines (in the */
                             /*    batched class: the geometry of every batch job)   */
-    int32_t _reserved[3];
+    int32_t run;            /* batched class: tiles a workgroup takes one after     */
+                            /*    another in the launch order (0 or 1: one), so    */
+                            /*    neighbouring tiles, which share the cache lines   */
+                            /*    at their edges, meet in one CU; 0..64             */
+    int32_t _reserved[2];
 } xtr_tpose_config;
 
 /* Shape classes of the launch configurations: single calls (tpose,
@@ -498,7 +502,14 @@ typedef struct {
                             /*    small ones in one launch (each workgroup takes    */
                             /*    chunks first, then its waves take small           */
                             /*    segments); 0 = two launches.  Same result.        */
-    int32_t _reserved[5];
+    int32_t seg_streams;    /* segmented sums, two launches: 1 = the small          */
+                            /*    segments run on a library-owned second stream     */
+                            /*    while the chunks run on the caller's (the call    */
+                            /*    still completes in the caller's stream order)     */
+    int32_t seg_small_per_cu; /* workgroups per CU of the small-segment launch     */
+                            /*    (0: as many as are resident)                      */
+    int32_t seg_chunk_per_cu; /* the same for the chunk launch                     */
+    int32_t _reserved[2];
 } xtr_reduce_config;
 
 /* Current / new configuration of the sums for one dtype and shape class

@@ -39,12 +39,13 @@ class TposeConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("nt_store", C.c_int32), ("xcd", C.c_int32),
                 ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("nt_store_shared", C.c_int32),
                 ("nt_load_shared", C.c_int32), ("tile", C.c_int32), ("tile_shared", C.c_int32),
-                ("_reserved", C.c_int32 * 3)]
+                ("run", C.c_int32), ("_reserved", C.c_int32 * 2)]
 
 
 class ReduceConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("seg_fused", C.c_int32),
-                ("_reserved", C.c_int32 * 5)]
+                ("seg_streams", C.c_int32), ("seg_small_per_cu", C.c_int32),
+                ("seg_chunk_per_cu", C.c_int32), ("_reserved", C.c_int32 * 2)]
 
 
 class Job(C.Structure):
@@ -522,7 +523,8 @@ def tpose_config(elem_bytes: int, shape: str = "single") -> dict:
            "xtr_tpose_get_class_config")
     return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
             "blocks_per_cu": c.blocks_per_cu, "nt_store_shared": c.nt_store_shared,
-            "nt_load_shared": c.nt_load_shared, "tile": c.tile, "tile_shared": c.tile_shared}
+            "nt_load_shared": c.nt_load_shared, "tile": c.tile, "tile_shared": c.tile_shared,
+            "run": c.run}
 
 
 def set_tpose_config(elem_bytes: int, shape: str | None = None, **kw):
@@ -535,7 +537,7 @@ def set_tpose_config(elem_bytes: int, shape: str | None = None, **kw):
     cur.update(kw)
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
                     cur["blocks_per_cu"], cur["nt_store_shared"], cur["nt_load_shared"],
-                    cur["tile"], cur["tile_shared"])
+                    cur["tile"], cur["tile_shared"], cur["run"])
     if shape is None:
         _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
     else:
@@ -547,7 +549,9 @@ def reduce_config(dtype, shape: str = "single") -> dict:
     c = ReduceConfig()
     _check(load().xtr_reduce_get_class_config(_code(dtype), SHAPE_CLASSES[shape], C.byref(c)),
            "xtr_reduce_get_class_config")
-    return {"nt_load": c.nt_load, "split_chunks": c.split_chunks, "seg_fused": c.seg_fused}
+    return {"nt_load": c.nt_load, "split_chunks": c.split_chunks, "seg_fused": c.seg_fused,
+            "seg_streams": c.seg_streams, "seg_small_per_cu": c.seg_small_per_cu,
+            "seg_chunk_per_cu": c.seg_chunk_per_cu}
 
 
 def set_reduce_config(dtype, shape: str | None = None, **kw):
@@ -556,7 +560,8 @@ def set_reduce_config(dtype, shape: str | None = None, **kw):
     if bad:
         raise TypeError(f"set_reduce_config: unknown settings {sorted(bad)}")
     cur.update(kw)
-    c = ReduceConfig(cur["nt_load"], cur["split_chunks"], cur["seg_fused"])
+    c = ReduceConfig(cur["nt_load"], cur["split_chunks"], cur["seg_fused"], cur["seg_streams"],
+                     cur["seg_small_per_cu"], cur["seg_chunk_per_cu"])
     if shape is None:
         _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
     else:

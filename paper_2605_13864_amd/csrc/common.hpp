@@ -65,6 +65,23 @@ int zero_fill(void *p, size_t bytes, hipStream_t stream);
 // Number of compute units of the current device (cached).
 int cu_count();
 
+// A second stream of default priority on the current device, owned by the
+// library (created on first use, kept until the process ends), for work that one
+// call splits over two streams: fork(st) makes the side stream wait for
+// everything enqueued on st so far, join(st) makes st wait for everything
+// enqueued on the side stream so far.  The pattern is capturable in a graph
+// (the side stream joins the capture through the fork event).  A mutex held
+// from fork to join keeps concurrent callers' forks and joins apart.
+struct SideStream {
+    std::mutex mu;
+    int device = 0;
+    hipStream_t s = nullptr;
+    hipEvent_t fork_ev = nullptr, join_ev = nullptr;
+};
+int side_stream(SideStream **side);
+int side_fork(SideStream *side, hipStream_t st);
+int side_join(SideStream *side, hipStream_t st);
+
 // ------------------------------------------------------------------ host buffers
 // Resources of the entry points that take host buffers, one set per device
 // (created on first use, kept until xtr_release): copies in, kernels and

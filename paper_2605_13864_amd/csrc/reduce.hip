@@ -1178,18 +1178,25 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
 }
 // Both passes run as resident grids (8 workgroups per CU at most) that stride
 // over their segments / chunks: the chunk space is only known on the device.
+// side: a second stream for the small segments (their launch then overlaps
+// the chunks'), or nullptr.
 template <int DT, int MODE>
 void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb, const ChunkRec *cs,
-                int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st) {
-    const bool nt = g_rcfg[XTR_SHAPE_BATCHED][DT].nt_load != 0;
+                int64_t nseg, int64_t cap, const Levels &lv, void *out, hipStream_t st,
+                hipStream_t side) {
+    const xtr_reduce_config &c = g_rcfg[XTR_SHAPE_BATCHED][DT];
+    const bool nt = c.nt_load != 0;
     const int64_t gs_n = (nseg + NW - 1) / NW;                 // workgroups, one wave per segment
     const int64_t gc_n = cap > nseg ? cap : nseg;
+    hipStream_t ss = side ? side : st;
 #define XTR_SEG(NTV)                                                                             \
     do {                                                                                         \
-        const int64_t o1 = resident_blocks((const void *)&k_reduce_seg_small<DT, MODE, NTV>, NTHR); \
-        const int64_t o2 = resident_blocks((const void *)&k_reduce_seg<DT, MODE, NTV>, NTHR);   \
+        const int64_t o1 = resident_blocks((const void *)&k_reduce_seg_small<DT, MODE, NTV>, NTHR, \
+                                           c.seg_small_per_cu);                                  \
+        const int64_t o2 = resident_blocks((const void *)&k_reduce_seg<DT, MODE, NTV>, NTHR,    \
+                                           c.seg_chunk_per_cu);                                  \
         hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, NTV>),                                 \
-                           dim3((unsigned)(gs_n < o1 ? gs_n : o1)), dim3(NTHR), 0, st, src, off, \
+                           dim3((unsigned)(gs_n < o1 ? gs_n : o1)), dim3(NTHR), 0, ss, src, off, \
                            cb, nseg, cap, out);                                                  \
         hipLaunchKernelGGL((k_reduce_seg<DT, MODE, NTV>),                                       \
                            dim3((unsigned)(gc_n < o2 ? gc_n : o2)), dim3(NTHR), 0, st, src, cb,  \
@@ -1202,7 +1209,7 @@ void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb,
         hipLaunchKernelGGL((k_reduce_seg_all<DT, MODE, NTV>), dim3((unsigned)(g < o ? g : o)),   \
                            dim3(NTHR), 0, st, src, off, cb, cs, nseg, cap, lv, out);             \
     } while (0)
-    if (g_rcfg[XTR_SHAPE_BATCHED][DT].seg_fused) {
+    if (c.seg_fused && !side) {
         if (nt) XTR_SEG_ALL(true);
         else XTR_SEG_ALL(false);
     } else {
@@ -1476,9 +1483,25 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
                        (const int64_t *)btot, offsets, nseg, cap, cbase, cmap);
     XTR_HIP(hipGetLastError());
     Levels lv = levels_at(v, w + L.parts, cap, mode);
+    const xtr_reduce_config &c = g_rcfg[XTR_SHAPE_BATCHED][dtype];
+    if (c.seg_streams && !c.seg_fused) {
+        // the small segments on the side stream, the chunks on st: fork after
+        // the planning passes, join before returning
+        SideStream *side = nullptr;
+        rc = side_stream(&side);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lk(side->mu);
+        rc = side_fork(side, st);
+        if (rc) return rc;
+        XTR_DISPATCH_SUM(dtype, mode, launch_seg,
+                         ((const unsigned char *)src, offsets, (const int64_t *)cbase,
+                          (const ChunkRec *)cmap, nseg, cap, lv, out, st, side->s));
+        XTR_HIP(hipGetLastError());
+        return side_join(side, st);
+    }
     XTR_DISPATCH_SUM(dtype, mode, launch_seg,
                      ((const unsigned char *)src, offsets, (const int64_t *)cbase,
-                      (const ChunkRec *)cmap, nseg, cap, lv, out, st));
+                      (const ChunkRec *)cmap, nseg, cap, lv, out, st, nullptr));
     XTR_HIP(hipGetLastError());
     return XTR_OK;
 }
@@ -1628,8 +1651,10 @@ int xtr_reduce_set_class_config(int dtype, int shape_class, const xtr_reduce_con
     if (!cfg || !(xtr::is_float_sum_dtype(dtype) || xtr::is_int_sum_dtype(dtype)) ||
         (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: bad arguments");
-    if (cfg->split_chunks < 0)
-        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: split_chunks must be >= 0");
+    if (cfg->split_chunks < 0 || cfg->seg_small_per_cu < 0 || cfg->seg_small_per_cu > 64 ||
+        cfg->seg_chunk_per_cu < 0 || cfg->seg_chunk_per_cu > 64)
+        return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: split_chunks >= 0, "
+                                     "seg_*_per_cu in [0, 64]");
     xtr::g_rcfg[shape_class][dtype] = *cfg;
     return XTR_OK;
 }

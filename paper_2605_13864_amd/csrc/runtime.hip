@@ -191,6 +191,47 @@ int upload(const void *host, size_t bytes, void *dev_dst, hipStream_t stream) {
     return XTR_OK;
 }
 
+namespace {
+std::mutex g_side_mu;
+std::map<int, SideStream *> g_side;   // by device; never moved once created
+}  // namespace
+
+int side_stream(SideStream **side) {
+    int dev = 0;
+    XTR_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_side_mu);
+    SideStream *&p = g_side[dev];
+    if (!p) {
+        SideStream *q = new (std::nothrow) SideStream();
+        if (!q) return fail(XTR_ENOMEM, "side stream: out of host memory");
+        q->device = dev;
+        hipError_t e = hipStreamCreateWithFlags(&q->s, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->fork_ev, hipEventDisableTiming);
+        if (e == hipSuccess) e = hipEventCreateWithFlags(&q->join_ev, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            if (q->s) (void)hipStreamDestroy(q->s);
+            if (q->fork_ev) (void)hipEventDestroy(q->fork_ev);
+            delete q;
+            return hip_fail(e, "side stream");
+        }
+        p = q;
+    }
+    *side = p;
+    return XTR_OK;
+}
+
+int side_fork(SideStream *side, hipStream_t st) {
+    XTR_HIP(hipEventRecord(side->fork_ev, st));
+    XTR_HIP(hipStreamWaitEvent(side->s, side->fork_ev, 0));
+    return XTR_OK;
+}
+
+int side_join(SideStream *side, hipStream_t st) {
+    XTR_HIP(hipEventRecord(side->join_ev, side->s));
+    XTR_HIP(hipStreamWaitEvent(st, side->join_ev, 0));
+    return XTR_OK;
+}
+
 int cu_count() {
     static int cached[64] = {0};
     int dev = 0;

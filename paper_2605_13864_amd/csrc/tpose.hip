@@ -47,10 +47,10 @@ using namespace tpk;
 // Tuned launch configuration per shape class and element size (slot
 // cfg_slot(elem bytes)).
 xtr_tpose_config tpk::g_cfg[2][4] = {
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}},
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, {0, 0, 0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}},
 };
 
 namespace {
@@ -413,9 +413,10 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
         (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: bad arguments");
     if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
-        cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3)
+        cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
+        cfg->run < 0 || cfg->run > 64)
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: group in [1, 64], blocks_per_cu "
-                                     "in [0, 64], tile and tile_shared in [0, 3]");
+                                     "in [0, 64], tile and tile_shared in [0, 3], run in [0, 64]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

@@ -580,40 +580,55 @@ __device__ __forceinline__ Job job_gather(uint32_t v) {
     return jb;
 }
 
-// Persistent over the concatenated tile space of a group of jobs.  Round i
-// of the grid covers positions [i G, i G + G) of the launch order; within a
-// round each XCD takes a contiguous range (xcd_remap), and within a job tiles
-// follow the band order, so tiles that share cache lines at their edges (rows
-// of a job whose pitch is not a multiple of the line) meet in one L2.
+// Persistent over the concatenated tile space of a group of jobs.  Round r
+// of the grid covers positions [r G K, r G K + G K) of the launch order in G
+// slots of K consecutive positions (K = run, the tiles a workgroup takes one
+// after another); within a round each XCD takes a contiguous range of slots
+// (xcd_remap), and within a job tiles follow the band order, so tiles that
+// share cache lines at their edges (rows of a job whose pitch is not a
+// multiple of the line) meet in one L2, and with K > 1 in one CU.
 // The next tile's job is found while the current tile moves: its search
 // probe is loaded before the tile's loads, and its record after the tile is
 // staged in LDS, ahead of the tile's stores; neither waits on the tile's
 // memory traffic.
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC, int DC>
 __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *bases, int njobs,
-                                              int64_t ntiles64, int xcd, int group, uint4 *lds) {
+                                              int64_t ntiles64, int xcd, int group, int run,
+                                              uint4 *lds) {
     using Gm = Geo<EB, SC, DC>;
     const uint32_t ntiles = (uint32_t)ntiles64, G = gridDim.x, bx = blockIdx.x;
+    const uint32_t K = run > 1 ? (uint32_t)run : 1u;
     const int l = threadIdx.x & 63;
-    auto position = [&](uint32_t wave0) {
-        const uint32_t inwave = (ntiles - wave0) < G ? (ntiles - wave0) : G;
-        return wave0 + (xcd ? xcd_remap(bx, inwave) : bx);
+    // this workgroup's positions: round base R, first position, count, index
+    uint32_t R = 0, first = 0, count = 0, i = 0;
+    auto round_at = [&](uint32_t r0) {   // false: no position for this workgroup
+        if (r0 >= ntiles) return false;
+        const uint32_t rem = ntiles - r0;
+        const uint32_t slots = (rem + K - 1) / K < G ? (rem + K - 1) / K : G;
+        if (bx >= slots) return false;
+        R = r0;
+        first = r0 + (xcd ? xcd_remap(bx, slots) : bx) * K;
+        count = ntiles - first < K ? ntiles - first : K;
+        i = 0;
+        return true;
     };
-    auto runs = [&](uint32_t wave0) {   // this workgroup has a tile in the round at wave0
-        return wave0 < ntiles && bx < ntiles - wave0;
-    };
-    if (!runs(0)) return;
-    uint32_t wave0 = 0, L = position(0);
+    if (!round_at(0)) return;
+    uint32_t L = first;
     int j = job_search(bases, njobs, L);
     Job jb = job_gather(job_dword(jobs, j));
     for (;;) {
-        const uint32_t wave1 = wave0 + G;
-        const bool more = wave1 > wave0 && runs(wave1);   // uniform
-        uint32_t Ln = 0;
+        // the next position of this workgroup
+        bool more;
+        if (i + 1 < count) {
+            i++;
+            more = true;
+        } else {
+            more = round_at(R + G * K);
+        }
+        const uint32_t Ln = more ? first + i : 0;
         int c = 0;
         int64_t probe = 0;
         if (more) {
-            Ln = position(wave1);
             c = j + 1 + l;
             probe = bases[c < njobs ? c : njobs - 1];   // (unconditional load; c checked below)
         }
@@ -637,7 +652,6 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
         if (!more) break;
         jb = job_gather(next);
         L = Ln;
-        wave0 = wave1;
     }
 }
 
@@ -646,9 +660,9 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
                                                       const int64_t *__restrict__ bases, int njobs,
-                                                      int64_t ntiles, int xcd, int group) {
+                                                      int64_t ntiles, int xcd, int group, int run) {
     __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(jobs, bases, njobs, ntiles, xcd, group, lds);
+    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(jobs, bases, njobs, ntiles, xcd, group, run, lds);
 }
 
 // A small group passes its jobs inside the kernel arguments: no table upload
@@ -661,9 +675,10 @@ struct JobPack {
 
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched_inl(JobPack pk, int njobs, int64_t ntiles,
-                                                          int xcd, int group) {
+                                                          int xcd, int group, int run) {
     __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, lds);
+    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, run,
+                                                  lds);
 }
 
 // ---------------------------------------------------------------- host side
@@ -905,13 +920,13 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
                 (const void *)&k_tpose_batched_inl<EB, W, NL, NS, OFF32, SC, DC>, NT, cap);  \
             hipLaunchKernelGGL((k_tpose_batched_inl<EB, W, NL, NS, OFF32, SC, DC>),         \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
-                               *pk, nj, ntiles, c.xcd, group);                              \
+                               *pk, nj, ntiles, c.xcd, group, c.run);                       \
         } else {                                                                            \
             const int64_t occ = resident_blocks(                                            \
                 (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>, NT, cap);      \
             hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>),             \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
-                               jobs, bases, nj, ntiles, c.xcd, group);                      \
+                               jobs, bases, nj, ntiles, c.xcd, group, c.run);               \
         }                                                                                   \
     } while (0)
     if (ntl && nts) XTR_KB(true, true);

@@ -201,11 +201,13 @@ def tpose_batched_candidates(quick: bool, eb: int):
     groups = [1, 16] if quick else [1, 4, 16, 32]
     bpc = [0, 4] if quick else [0, 2, 4, 8]
     wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
-    for (nl, ns), xcd, g, b, w in itertools.product(nts, [1, 0], groups, bpc, wides):
+    runs = [0, 4] if quick else [0, 2, 4]
+    for (nl, ns), xcd, g, b, w, r in itertools.product(nts, [1, 0], groups, bpc, wides, runs):
         # nearly every job of a random-size batch has rows that share lines:
         # the *_shared flags decide; the line-aligned ones follow along
         yield {"nt_load": nl, "nt_store": ns, "nt_load_shared": nl, "nt_store_shared": ns,
-               "xcd": xcd, "group": g, "blocks_per_cu": b, "tile": 0, "tile_shared": w}
+               "xcd": xcd, "group": g, "blocks_per_cu": b, "tile": 0, "tile_shared": w,
+               "run": r}
 
 
 def tune_tpose_batched(xtr, torch, eb: int, quick=False, log=print, count=1024, seed=9):
@@ -254,23 +256,26 @@ def tune_reduce_batched(xtr, torch, dt: str, log=print, nseg=100000):
     ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, dt), dtype=torch.uint8,
                      device="cuda")
     orig = xtr.reduce_config(dt, "batched")
+    # (seg_fused, seg_streams, seg_small_per_cu, seg_chunk_per_cu)
+    modes = [(0, 0, 0, 0), (1, 0, 0, 0)] + [(0, 1, a, b) for a in (0, 2, 3) for b in (0, 3, 5)]
     t = {}
     try:
         for nt in (1, 0):
-            for fu in (0, 1):
-                xtr.set_reduce_config(dt, "batched", nt_load=nt, seg_fused=fu)
-                t[(nt, fu)] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out,
-                                                                                dtype=dt))
+            for m in modes:
+                xtr.set_reduce_config(dt, "batched", nt_load=nt, seg_fused=m[0], seg_streams=m[1],
+                                      seg_small_per_cu=m[2], seg_chunk_per_cu=m[3])
+                t[(nt,) + m] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out,
+                                                                                 dtype=dt))
     finally:
         xtr.set_reduce_config(dt, "batched", **orig)
-    nt, fu = min(t, key=t.get)
-    log(f"tune sum batched {dt}: nt_load {nt} seg_fused {fu} "
-        f"({total * eb / t[(nt, fu)] / 1e9:.1f} GB/s)")
+    best = min(t, key=t.get)
+    cfg = {"nt_load": best[0], "split_chunks": orig["split_chunks"], "seg_fused": best[1],
+           "seg_streams": best[2], "seg_small_per_cu": best[3], "seg_chunk_per_cu": best[4]}
+    log(f"tune sum batched {dt}: {cfg} ({total * eb / t[best] / 1e9:.1f} GB/s)")
     del src, ws
-    return {"gbs": round(total * eb / t[(nt, fu)] / 1e9, 1),
-            "config": {"nt_load": nt, "split_chunks": orig["split_chunks"], "seg_fused": fu},
-            "nseg": nseg, "all": {f"nt_load={a} seg_fused={b}": round(total * eb / v / 1e9, 1)
-                                  for (a, b), v in t.items()}}
+    return {"gbs": round(total * eb / t[best] / 1e9, 1), "config": cfg, "nseg": nseg,
+            "all": {"nt_load={} fused={} streams={} small/cu={} chunk/cu={}".format(*k):
+                    round(total * eb / v / 1e9, 1) for k, v in t.items()}}
 
 
 def run(quick=False, out=None, log=print):

@@ -179,3 +179,39 @@ def test_replay_after_workspace_growth(xtr, orc):
         del r, sc, hh
     want = orc.scan(xi.cpu().numpy(), "i32")
     assert np.array_equal(eager["si"].cpu().numpy(), want)
+
+
+@pytest.mark.parametrize("streams", [0, 1])
+def test_segmented_ws_replay(xtr, streams):
+    """The segmented sum with a caller workspace captured in a graph, on one
+    stream or forked to the library's second stream (the small segments) and
+    joined back: every replay equals the eager result."""
+    import torch
+    total, nseg = 400000, 3000
+    off = W.segment_offsets(total, nseg, 97)
+    d, doff = to_dev(W.normal(total, 98, "f32")), to_dev(off)
+    ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, "f32"), dtype=torch.uint8,
+                     device="cuda")
+    out = torch.empty(nseg, dtype=torch.float64, device="cuda")
+    orig = xtr.reduce_config("f32", "batched")
+    try:
+        xtr.set_reduce_config("f32", "batched", seg_fused=0, seg_streams=streams,
+                              seg_small_per_cu=2 if streams else 0,
+                              seg_chunk_per_cu=4 if streams else 0)
+        eager = xtr.reduce_sum_segmented_ws(d, doff, ws, out, total=total, dtype="f32").clone()
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                xtr.reduce_sum_segmented_ws(d, doff, ws, out, total=total, dtype="f32")
+        torch.cuda.synchronize()
+        for rep in range(4):
+            out.fill_(-1.0)
+            xtr.reduce_sum(d, dtype="f32")            # another library call in between
+            torch.cuda.synchronize()
+            g.replay()
+            torch.cuda.synchronize()
+            assert torch.equal(out, eager), rep
+    finally:
+        xtr.set_reduce_config("f32", "batched", **orig)

@@ -154,8 +154,9 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
+@pytest.mark.parametrize("run", [0, 3])
 @pytest.mark.parametrize("wide", [0, 1, 2, 3])
-def test_batched_geometries(xtr, orc, wide):
+def test_batched_geometries(xtr, orc, wide, run):
     """Batched transposes with each tile geometry (512-byte src rows: 1, dst
     rows: 2, both: 3) for jobs whose rows share lines, mixed with small and aligned
     jobs, every element size and every piece width; each job against the
@@ -165,7 +166,8 @@ def test_batched_geometries(xtr, orc, wide):
     origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
     try:
         for eb in (2, 4, 8):
-            xtr.set_tpose_config(eb, "batched", tile_shared=wide, tile=wide)
+            xtr.set_tpose_config(eb, "batched", tile_shared=wide, tile=wide, run=run)
+        xtr.set_tpose_config(1, "batched", run=run)
         jobs, hosts = [], []
         for i in range(40):
             eb = [1, 2, 4, 8][i % 4]
