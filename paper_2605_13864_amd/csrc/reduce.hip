@@ -187,6 +187,17 @@ template <int DT> struct Acc<DT, COMP> {
             p[a].c = p[a].c + e;
         }
     }
+    // add into an accumulator that is still (+0, +0): two_sum(+0, x) gives
+    // s = +0 + x and e = +0 exactly, and c = +0 + +0 = +0, so this is add()
+    // bit for bit while s is finite (once s is not, c is never used).
+    __device__ __forceinline__ void add_first(int a, float x) {
+        if constexpr (DT == XTR_F8E4M3) {
+            g[a] = g[a] + x;
+        } else {
+            p[a].s = 0.f + x;
+            p[a].c = 0.f;
+        }
+    }
     __device__ Pair finish() {
         if constexpr (DT == XTR_F8E4M3) {
 #pragma unroll
@@ -204,6 +215,7 @@ template <int DT> struct Acc<DT, PLAIN> {
         for (int a = 0; a < 4; a++) s[a] = 0.f;
     }
     __device__ __forceinline__ void add(int a, float x) { s[a] = s[a] + x; }
+    __device__ __forceinline__ void add_first(int a, float x) { add(a, x); }
     __device__ float finish() { return (s[0] + s[1]) + (s[2] + s[3]); }
 };
 
@@ -212,6 +224,7 @@ template <int DT> struct Acc<DT, INTM> {
     uint64_t s[2];
     __device__ void init() { s[0] = s[1] = 0; }
     __device__ __forceinline__ void add(int a, uint64_t x) { s[a & 1] += x; }
+    __device__ __forceinline__ void add_first(int a, uint64_t x) { add(a, x); }
     __device__ uint64_t finish() { return s[0] + s[1]; }
 };
 
@@ -224,41 +237,59 @@ __device__ __forceinline__ float f16_hi(uint32_t d) {
     return (float)__builtin_bit_cast(_Float16, (uint16_t)(d >> 16));
 }
 
+template <bool FIRST, class A, class X> __device__ __forceinline__ void acc_put(A &acc, int a, X x) {
+    if constexpr (FIRST) acc.add_first(a, x);
+    else acc.add(a, x);
+}
+
 // accumulate element i (0 <= i < V) of a decoded vector into accumulator i % 4
-template <int DT, int MODE>
+// (FIRST: every accumulator it reaches is still zero -- the thread's first
+// vector, with no head before it)
+template <int DT, int MODE, bool FIRST = false>
 __device__ __forceinline__ void acc_vec(Acc<DT, MODE> &acc, const uint4 &v) {
     const uint32_t w[4] = {v.x, v.y, v.z, v.w};
     if constexpr (DT == XTR_F32) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc.add(i, __uint_as_float(w[i]));
+        for (int i = 0; i < 4; i++) acc_put<FIRST>(acc, i, __uint_as_float(w[i]));
     } else if constexpr (DT == XTR_BF16) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            acc.add((2 * k) & 3, __uint_as_float(w[k] << 16));
-            acc.add((2 * k + 1) & 3, __uint_as_float(w[k] & 0xffff0000u));
+            // elements 4..7 reach accumulators 0..3 a second time
+            if (k < 2) {
+                acc_put<FIRST>(acc, (2 * k) & 3, __uint_as_float(w[k] << 16));
+                acc_put<FIRST>(acc, (2 * k + 1) & 3, __uint_as_float(w[k] & 0xffff0000u));
+            } else {
+                acc.add((2 * k) & 3, __uint_as_float(w[k] << 16));
+                acc.add((2 * k + 1) & 3, __uint_as_float(w[k] & 0xffff0000u));
+            }
         }
     } else if constexpr (DT == XTR_F16) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
-            acc.add((2 * k) & 3, f16_lo(w[k]));
-            acc.add((2 * k + 1) & 3, f16_hi(w[k]));
+            if (k < 2) {
+                acc_put<FIRST>(acc, (2 * k) & 3, f16_lo(w[k]));
+                acc_put<FIRST>(acc, (2 * k + 1) & 3, f16_hi(w[k]));
+            } else {
+                acc.add((2 * k) & 3, f16_lo(w[k]));
+                acc.add((2 * k + 1) & 3, f16_hi(w[k]));
+            }
         }
     } else if constexpr (DT == XTR_F8E4M3) {
 #pragma unroll
         for (int k = 0; k < 4; k++) {
             auto lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], false);   // bytes 0, 1
             auto hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)w[k], true);    // bytes 2, 3
-            acc.add(0, lo[0]);
-            acc.add(1, lo[1]);
-            acc.add(2, hi[0]);
-            acc.add(3, hi[1]);
+            acc_put<FIRST>(acc, 0, lo[0]);
+            acc_put<FIRST>(acc, 1, lo[1]);
+            acc_put<FIRST>(acc, 2, hi[0]);
+            acc_put<FIRST>(acc, 3, hi[1]);
         }
     } else if constexpr (DT == XTR_I32) {
 #pragma unroll
-        for (int i = 0; i < 4; i++) acc.add(i, (uint64_t)(int64_t)(int32_t)w[i]);
+        for (int i = 0; i < 4; i++) acc_put<FIRST>(acc, i, (uint64_t)(int64_t)(int32_t)w[i]);
     } else {  // I64
-        acc.add(0, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
-        acc.add(1, (uint64_t)w[2] | ((uint64_t)w[3] << 32));
+        acc_put<FIRST>(acc, 0, (uint64_t)w[0] | ((uint64_t)w[1] << 32));
+        acc_put<FIRST>(acc, 1, (uint64_t)w[2] | ((uint64_t)w[3] << 32));
     }
 }
 
@@ -334,13 +365,49 @@ __device__ __forceinline__ typename PartT<MODE>::T chunk_tree(Acc<DT, MODE> &acc
 
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
+// 16-byte load of device memory through a global-memory pointer (a pointer
+// that went through a struct or a select may reach here as a generic one; a
+// generic load would also count against the scalar-load counter, so waiting
+// for a scalar load would wait for it too).
+typedef __attribute__((address_space(1))) const u32x4 gu32x4;
 template <bool NT> __device__ __forceinline__ uint4 load16(const uint4 *p) {
+    gu32x4 *g = (gu32x4 *)p;
     u32x4 v;
-    if constexpr (NT) v = __builtin_nontemporal_load(reinterpret_cast<const u32x4 *>(p));
-    else v = *reinterpret_cast<const u32x4 *>(p);
+    if constexpr (NT) v = __builtin_nontemporal_load(g);
+    else v = *g;
     return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+// Element i of a 16-byte vector, decoded as acc_elem decodes it, added to
+// accumulator a (the slot acc_elem uses for element i of a vector).
+template <int DT, int MODE, bool FIRST = false>
+__device__ __forceinline__ void acc_from_vec(Acc<DT, MODE> &acc, const uint4 &v, int i, int a) {
+    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
+    if constexpr (DT == XTR_F32) {
+        acc_put<FIRST>(acc, a, __uint_as_float(w[i]));
+    } else if constexpr (DT == XTR_BF16) {
+        acc_put<FIRST>(acc, a, __uint_as_float(((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) << 16));
+    } else if constexpr (DT == XTR_F16) {
+        acc_put<FIRST>(acc, a, f16_lo(w[i >> 1] >> (16 * (i & 1))));
+    } else if constexpr (DT == XTR_F8E4M3) {
+        auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)((w[i >> 2] >> (8 * (i & 3))) & 0xffu), false);
+        acc_put<FIRST>(acc, a, f[0]);
+    } else if constexpr (DT == XTR_I32) {
+        acc_put<FIRST>(acc, a, (uint64_t)(int64_t)(int32_t)w[i]);
+    } else {
+        acc_put<FIRST>(acc, a, (uint64_t)w[2 * i] | ((uint64_t)w[2 * i + 1] << 32));
+    }
+}
+
+// Chunk j of range rg, by one workgroup.  Every load is issued before any
+// element is added (no load sits behind a branch, so none waits where
+// branches join): the head (the elements before the first 16-byte boundary,
+// added by thread 0 of chunk 0) comes from the aligned vector that holds it,
+// and in a partial chunk a lane whose vector lies past the body reloads the
+// body's last vector (a partial last vector is loaded whole); those values
+// are never used.  A 16-byte aligned vector holding a byte of the range lies
+// on a page the range touches.  A chunk with no body or head (an empty range)
+// loads the vector holding the range's output slot instead.
 template <int DT, int MODE, bool NT>
 __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg, int64_t j) {
     constexpr int EB = DTI<DT>::EB;
@@ -351,30 +418,53 @@ __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg,
     acc.init();
     const unsigned char *body = rg.ptr + (int64_t)rg.head * EB;
     const int64_t body_n = rg.n - rg.head;
-    if (j == 0 && t == 0) {
-        for (int i = 0; i < rg.head; i++) acc_elem(acc, rg.ptr + (int64_t)i * EB, 0);
-    }
     const int64_t e0 = j * CH;
+    const unsigned char *sb = rg.n > 0 ? rg.ptr : rg.dst;   // a byte that exists
+    const uint4 *safe = reinterpret_cast<const uint4 *>(sb - ((uintptr_t)sb & 15));
     if (e0 + CH <= body_n) {
         const uint4 *vp = reinterpret_cast<const uint4 *>(body + e0 * EB) + t;
         uint4 v[U];
 #pragma unroll
         for (int u = 0; u < U; u++) v[u] = load16<NT>(vp + u * NTHR);
+        uint4 hv = make_uint4(0, 0, 0, 0);
+        if (j == 0 && rg.head > 0) hv = load16<NT>(safe);   // uniform: the first chunk only
+        if (j == 0 && t == 0 && rg.head > 0) {
+            const int h0 = (int)((uintptr_t)rg.ptr & 15) / EB;
+#pragma unroll
+            for (int i = 1; i < V; i++)
+                if (i >= h0 && i < h0 + rg.head) acc_from_vec(acc, hv, i, 0);
+        }
 #pragma unroll
         for (int u = 0; u < U; u++) acc_vec(acc, v[u]);
     } else {
+        // partial chunk: clamped loads, then the elements in range
+        const uint4 *bv = reinterpret_cast<const uint4 *>(body);
+        const bool has_body = body_n > e0;
+        const int64_t last = has_body ? (body_n - 1) / V : 0;   // last vector of the body
+        uint4 v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            const int64_t q = e0 / V + (int64_t)(u * NTHR + t);
+            v[u] = load16<NT>(has_body ? bv + (q < last ? q : last) : safe);
+        }
+        const uint4 hv = load16<NT>(safe);
+        if (j == 0 && t == 0 && rg.head > 0) {
+            const int h0 = (int)((uintptr_t)rg.ptr & 15) / EB;
+#pragma unroll
+            for (int i = 1; i < V; i++)
+                if (i >= h0 && i < h0 + rg.head) acc_from_vec(acc, hv, i, 0);
+        }
 #pragma unroll
         for (int u = 0; u < U; u++) {
             const int64_t e = e0 + (int64_t)(u * NTHR + t) * V;
             if (e + V <= body_n) {
-                uint4 v = load16<NT>(reinterpret_cast<const uint4 *>(body + e * EB));
-                acc_vec(acc, v);
+                acc_vec(acc, v[u]);
             } else if (e < body_n) {
                 const int m = (int)(body_n - e);
                 // compile-time element index: the accumulators stay in registers
 #pragma unroll
                 for (int i = 0; i < V; i++)
-                    if (i < m) acc_elem(acc, body + (e + i) * EB, i);
+                    if (i < m) acc_from_vec(acc, v[u], i, (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3));
             }
         }
     }
@@ -440,26 +530,6 @@ __device__ __forceinline__ void small_load(const Range &rg, bool use, const void
         }
 }
 
-// Element i of a 16-byte vector, decoded as acc_elem decodes it, added to
-// accumulator a (the slot acc_elem uses for element i of a vector).
-template <int DT, int MODE>
-__device__ __forceinline__ void acc_from_vec(Acc<DT, MODE> &acc, const uint4 &v, int i, int a) {
-    const uint32_t w[4] = {v.x, v.y, v.z, v.w};
-    if constexpr (DT == XTR_F32) {
-        acc.add(a, __uint_as_float(w[i]));
-    } else if constexpr (DT == XTR_BF16) {
-        acc.add(a, __uint_as_float(((w[i >> 1] >> (16 * (i & 1))) & 0xffffu) << 16));
-    } else if constexpr (DT == XTR_F16) {
-        acc.add(a, f16_lo(w[i >> 1] >> (16 * (i & 1))));
-    } else if constexpr (DT == XTR_F8E4M3) {
-        auto f = __builtin_amdgcn_cvt_pk_f32_fp8((int)((w[i >> 2] >> (8 * (i & 3))) & 0xffu), false);
-        acc.add(a, f[0]);
-    } else if constexpr (DT == XTR_I32) {
-        acc.add(a, (uint64_t)(int64_t)(int32_t)w[i]);
-    } else {
-        acc.add(a, (uint64_t)w[2 * i] | ((uint64_t)w[2 * i + 1] << 32));
-    }
-}
 
 // The four wave butterflies of small_value in one pass (a reduce-scatter):
 // p[w] is this lane's value of thread l + 64 w.  The result equals, bit for
@@ -538,17 +608,26 @@ __device__ __forceinline__ typename PartT<MODE>::T small_value(const Range &rg,
             for (int i = 1; i < V; i++)
                 if (i >= h0 && i < h0 + rg.head) acc_from_vec(acc, r.hv, i, 0);
         }
+        // row 0 reaches each accumulator first (unless the head came before
+        // it, in set 0): the zero-accumulator shortcut, bit-identical
+        const bool first_ok = !(w == 0 && rg.head > 0);   // uniform
 #pragma unroll
         for (int u = 0; u < US; u++) {
             if ((int64_t)(u * NTHR + w * 64) * V >= body_n) continue;   // uniform
             const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
+            const bool first = u == 0 && first_ok;
             if (e + V <= body_n) {
-                acc_vec(acc, r.v[u][w]);
+                if (first) acc_vec<DT, MODE, true>(acc, r.v[u][w]);
+                else acc_vec(acc, r.v[u][w]);
             } else if (e < body_n) {
                 const int m = (int)(body_n - e);
 #pragma unroll
-                for (int i = 0; i < V; i++)
-                    if (i < m) acc_from_vec(acc, r.v[u][w], i, (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3));
+                for (int i = 0; i < V; i++) {
+                    if (i >= m) continue;
+                    const int a = (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3);
+                    if (first && i < 4) acc_from_vec<DT, MODE, true>(acc, r.v[u][w], i, a);
+                    else acc_from_vec(acc, r.v[u][w], i, a);
+                }
             }
         }
         tv[w] = acc.finish();
@@ -827,44 +906,79 @@ __global__ void __launch_bounds__(NTHR) k_seg_scan_blocks(int64_t *block_tot, in
     if (threadIdx.x == 0) block_tot[nblk] = carry;
 }
 
-// Pass 3: chunk_base of every segment and the chunk records.
+// Pass 3: chunk_base of every segment and the chunk records.  The block's
+// start in the chunk space is the sum of the block totals before it: read
+// from the scanned totals (prefix = true: pass 2 ran), or summed here from
+// the raw totals (a block sums at most MAX_DIRECT_BLOCKS of them, so for
+// small tables the pass-2 launch is skipped).  The records of the block's
+// chunks are written by all its threads together: slot q of the block's
+// chunk range belongs to the segment whose range holds it (found by a
+// binary search over the block's segment starts in LDS), so a segment of
+// many chunks costs no thread more than a few stores.
+constexpr int64_t MAX_DIRECT_BLOCKS = 4096;
+
 __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const int64_t *block_tot,
+                                                  bool prefix, int64_t nblk,
                                                   const int64_t *off, int64_t nseg, int64_t cap,
                                                   int64_t *chunk_base, ChunkRec *recs) {
     __shared__ int64_t sh[NTHR];
+    __shared__ int64_t start[NTHR * 4 + 1];   // chunk offset (within the block) of each segment
+    __shared__ int64_t sh_base;
+    const int t = threadIdx.x;
     const int64_t base = (int64_t)blockIdx.x * NTHR * 4;
-    const int64_t s0 = base + threadIdx.x * 4;   // this thread's 4 consecutive segments
+    const int64_t s0 = base + t * 4;   // this thread's 4 consecutive segments
+    // the block's start in the chunk space
+    if (prefix) {
+        if (t == 0) sh_base = block_tot[blockIdx.x];
+    } else {
+        int64_t part = 0;
+        for (int64_t i = t; i < (int64_t)blockIdx.x; i += NTHR) part += block_tot[i];
+        uint64_t wsum = wave_reduce((uint64_t)part);
+        if ((t & 63) == 0) sh[t >> 6] = (int64_t)wsum;
+        __syncthreads();
+        if (t == 0) sh_base = (sh[0] + sh[1]) + (sh[2] + sh[3]);
+    }
     int64_t c[4], tsum = 0;
 #pragma unroll
     for (int k = 0; k < 4; k++) {
         c[k] = (s0 + k < nseg) ? counts[s0 + k] : 0;
         tsum += c[k];
     }
-    sh[threadIdx.x] = tsum;
+    __syncthreads();
+    sh[t] = tsum;
     __syncthreads();
     for (int d = 1; d < NTHR; d <<= 1) {
-        int64_t a = threadIdx.x >= d ? sh[threadIdx.x - d] : 0;
+        int64_t a = t >= d ? sh[t - d] : 0;
         __syncthreads();
-        sh[threadIdx.x] += a;
+        sh[t] += a;
         __syncthreads();
     }
-    int64_t run = block_tot[blockIdx.x] + sh[threadIdx.x] - tsum;
+    const int64_t blk_base = sh_base;
+    const int64_t blk_total = sh[NTHR - 1];
+    int64_t run = sh[t] - tsum;   // within the block
 #pragma unroll
     for (int k = 0; k < 4; k++) {
-        const int64_t s = s0 + k;
-        if (s < nseg) {
-            chunk_base[s] = run;
-            if (c[k] > 0 && run + c[k] <= cap) {
-                const int64_t lo = off[s], hi = off[s + 1];
-                for (int64_t q = 0; q < c[k]; q++)
-                    recs[run + q] = ChunkRec{lo, hi, (int32_t)s, (int32_t)q};
-            }
-            run += c[k];
-        }
+        start[t * 4 + k] = run;
+        if (s0 + k < nseg) chunk_base[s0 + k] = blk_base + run;
+        run += c[k];
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        const int64_t nblk = (nseg + NTHR * 4 - 1) / (NTHR * 4);
-        chunk_base[nseg] = block_tot[nblk];
+    if (t == NTHR - 1) start[NTHR * 4] = run;   // = blk_total
+    if (blockIdx.x == nblk - 1 && t == 0) chunk_base[nseg] = blk_base + blk_total;
+    __syncthreads();
+    // the records, every thread taking slots q = t, t + 256, ...
+    const int nloc = (int)((nseg - base) < NTHR * 4 ? (nseg - base) : NTHR * 4);
+    if (blk_base + blk_total > cap) return;   // invalid table (or no space): no records
+    for (int64_t q = t; q < blk_total; q += NTHR) {
+        // the last segment i with start[i] <= q (segments with no chunks have
+        // start[i] == start[i + 1] and are passed over)
+        int lo = 0, hi = nloc;   // start[lo] <= q < start[hi]
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (start[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        const int64_t s = base + lo;
+        recs[blk_base + q] = ChunkRec{off[s], off[s + 1], (int32_t)s, (int32_t)(q - start[lo])};
     }
 }
 
@@ -1478,9 +1592,10 @@ int sum_segmented_impl(const void *src, const int64_t *offsets, int64_t nseg, vo
     const int64_t small = (int64_t)2 * NTHR * (16 / eb);   // small_max<DT>() of the kernels
     hipLaunchKernelGGL(k_seg_count, dim3((unsigned)nblk), dim3(NTHR), 0, st,
                        (const unsigned char *)src, offsets, nseg, eb, ch, small, counts, btot);
-    hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NTHR), 0, st, btot, nblk);
+    const bool scanned = nblk > MAX_DIRECT_BLOCKS;   // else each block sums the totals before it
+    if (scanned) hipLaunchKernelGGL(k_seg_scan_blocks, dim3(1), dim3(NTHR), 0, st, btot, nblk);
     hipLaunchKernelGGL(k_seg_place, dim3((unsigned)nblk), dim3(NTHR), 0, st, (const int64_t *)counts,
-                       (const int64_t *)btot, offsets, nseg, cap, cbase, cmap);
+                       (const int64_t *)btot, scanned, nblk, offsets, nseg, cap, cbase, cmap);
     XTR_HIP(hipGetLastError());
     Levels lv = levels_at(v, w + L.parts, cap, mode);
     const xtr_reduce_config &c = g_rcfg[XTR_SHAPE_BATCHED][dtype];

@@ -393,3 +393,17 @@ def test_segmented_fused_launch_same(xtr, orc, dt):
                 assert torch.isnan(out).all()
     finally:
         xtr.set_reduce_config(dt, "batched", **orig)
+
+
+def test_segmented_more_than_4096_blocks(xtr, orc):
+    """A table of 4.3M segments (more than 4096 planning blocks of 1024
+    segments: the block totals go through the one-workgroup scan), int32
+    (exact), lengths 0 .. 15 with a few long segments (several chunks each)."""
+    rng = np.random.default_rng(99)
+    nseg = 4_300_000
+    lens = rng.integers(0, 16, nseg)
+    lens[rng.integers(0, nseg, 40)] = rng.integers(20000, 200000, 40)
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    bits = W.integers(int(off[-1]), 100, -1000, 1000, "i32")
+    got = xtr.reduce_sum_segmented(to_dev(bits), to_dev(off), dtype="i32").cpu().numpy()
+    assert np.array_equal(got, orc.sum_segmented(bits, off, "i32"))
