@@ -399,6 +399,28 @@ __device__ __forceinline__ void acc_from_vec(Acc<DT, MODE> &acc, const uint4 &v,
     }
 }
 
+// The first m elements of a 16-byte vector (m may be <= 0 or >= V), the
+// others zeroed.  Adding a zero element is an exact no-op on every
+// accumulator: the running values are never -0 (they start at +0, and a sum
+// is -0 only when both terms are), so s + 0 = s, the two-sum error is +0 and
+// c + 0 = c; an integer sum adds 0.  A zeroed element therefore leaves the
+// same state as an element that is not added at all.
+template <int DT> __device__ __forceinline__ uint4 first_elems(uint4 v, int m) {
+    constexpr int EB = DTI<DT>::EB, V = vec_elems<DT>();
+    const int nb = (m < 0 ? 0 : (m > V ? V : m)) * EB;   // bytes kept
+    uint32_t w[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int k = 0; k < 4; k++) {
+        const int kb = nb - 4 * k;   // bytes kept in dword k
+        if constexpr (EB >= 4) {
+            w[k] = kb > 0 ? w[k] : 0u;
+        } else {
+            w[k] = kb >= 4 ? w[k] : (kb <= 0 ? 0u : w[k] & ((1u << (8 * kb)) - 1u));
+        }
+    }
+    return make_uint4(w[0], w[1], w[2], w[3]);
+}
+
 // Chunk j of range rg, by one workgroup.  Every load is issued before any
 // element is added (no load sits behind a branch, so none waits where
 // branches join): the head (the elements before the first 16-byte boundary,
@@ -514,10 +536,14 @@ __device__ __forceinline__ void small_load(const Range &rg, bool use, const void
     // (pointer arithmetic, not integer casts, so that the loads stay global loads)
     const unsigned char *sb = static_cast<const unsigned char *>(safe);
     const uint4 *sv = reinterpret_cast<const uint4 *>(sb - ((uintptr_t)sb & 15));
-    const uint4 *body = reinterpret_cast<const uint4 *>(rg.ptr + (int64_t)rg.head * EB);
-    const int64_t body_n = rg.n - rg.head;
+    // a small range's body has at most 2 * 256 * V elements: 32-bit sizes, and
+    // one wave-uniform base with a 32-bit byte offset per lane (q <= 511)
+    const int32_t body_n = __builtin_amdgcn_readfirstlane((int32_t)(rg.n - rg.head));
     const bool has_body = use && body_n > 0;
-    const uint32_t last = has_body ? (uint32_t)((body_n - 1) / V) : 0u;
+    const unsigned char *base = has_body ? rg.ptr + (int64_t)rg.head * EB
+                                         : reinterpret_cast<const unsigned char *>(sv);
+    const uint32_t last =
+        __builtin_amdgcn_readfirstlane(has_body ? (uint32_t)((body_n - 1) / V) : 0u);
     r.hv = load16<NT>(use && rg.head > 0
                           ? reinterpret_cast<const uint4 *>(rg.ptr - ((uintptr_t)rg.ptr & 15))
                           : sv);
@@ -526,7 +552,8 @@ __device__ __forceinline__ void small_load(const Range &rg, bool use, const void
 #pragma unroll
         for (int w = 0; w < NW; w++) {
             const uint32_t q = (uint32_t)(u * NTHR + w * 64 + l);
-            r.v[u][w] = load16<NT>(has_body ? body + (q < last ? q : last) : sv);
+            const uint32_t byte = (q < last ? q : last) << 4;
+            r.v[u][w] = load16<NT>(reinterpret_cast<const uint4 *>(base + (uint64_t)byte));
         }
 }
 
@@ -542,9 +569,9 @@ __device__ __forceinline__ void small_load(const Range &rg, bool use, const void
 // (3, 1, 2, 0) (odd quads).  That layout is symmetric under the half-row and
 // row mirrors, so those two steps pair lanes that hold the same value, as in
 // wave_reduce.  Rows are then combined as (r0 + r1) + (r2 + r3) by the
-// xor-16 and xor-32 exchanges, and the four values as (v0 + v1) + (v2 + v3)
-// by the xor-2 and xor-1 steps inside each quad; every lane ends with the
-// result.
+// xor-16 and xor-32 exchanges (lane swaps), and the four values as
+// (v0 + v1) + (v2 + v3) by the xor-2 and xor-1 steps inside each quad; every
+// lane ends with the result.
 __device__ __forceinline__ Pair vadd(Pair a, Pair b) { return pair_add(a, b); }
 __device__ __forceinline__ float vadd(float a, float b) { return a + b; }
 __device__ __forceinline__ uint64_t vadd(uint64_t a, uint64_t b) { return a + b; }
@@ -553,12 +580,42 @@ template <int CTRL> __device__ __forceinline__ Pair vdpp(Pair p) {
 }
 template <int CTRL> __device__ __forceinline__ float vdpp(float v) { return dppf<CTRL>(v); }
 template <int CTRL> __device__ __forceinline__ uint64_t vdpp(uint64_t v) { return dpp64<CTRL>(v); }
-__device__ __forceinline__ Pair vxor(Pair p, int m) {
-    return Pair{__shfl_xor(p.s, m, 64), __shfl_xor(p.c, m, 64)};
+// The xor-16 and xor-32 levels through gfx950's lane swaps (plain VALU
+// instructions, no LDS round trip).  With both operands a copy of v,
+// permlane16_swap leaves x = (row 0, row 0, row 2, row 2) and
+// y = (row 1, row 1, row 3, row 3), and permlane32_swap leaves x = low half,
+// y = high half in every lane: vadd(x, y) is the xor-16 (xor-32) butterfly
+// step, with the lower row (half) as the first operand in every lane, which
+// gives the same bits as either order since the additions are commutative.
+template <int M> __device__ __forceinline__ void lane_swap(uint32_t &x, uint32_t &y) {
+    static_assert(M == 16 || M == 32, "row or half-wave swap");
+    if constexpr (M == 16) {
+        const auto r = __builtin_amdgcn_permlane16_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    } else {
+        const auto r = __builtin_amdgcn_permlane32_swap(x, y, false, false);
+        x = r[0];
+        y = r[1];
+    }
 }
-__device__ __forceinline__ float vxor(float v, int m) { return __shfl_xor(v, m, 64); }
-__device__ __forceinline__ uint64_t vxor(uint64_t v, int m) {
-    return (uint64_t)__shfl_xor((unsigned long long)v, m, 64);
+template <int M> __device__ __forceinline__ float vswapadd(float v) {
+    uint32_t x = __float_as_uint(v), y = x;
+    lane_swap<M>(x, y);
+    return __uint_as_float(x) + __uint_as_float(y);
+}
+template <int M> __device__ __forceinline__ Pair vswapadd(Pair v) {
+    uint32_t xs = __float_as_uint(v.s), ys = xs, xc = __float_as_uint(v.c), yc = xc;
+    lane_swap<M>(xs, ys);
+    lane_swap<M>(xc, yc);
+    return pair_add(Pair{__uint_as_float(xs), __uint_as_float(xc)},
+                    Pair{__uint_as_float(ys), __uint_as_float(yc)});
+}
+template <int M> __device__ __forceinline__ uint64_t vswapadd(uint64_t v) {
+    uint32_t xl = (uint32_t)v, yl = xl, xh = (uint32_t)(v >> 32), yh = xh;
+    lane_swap<M>(xl, yl);
+    lane_swap<M>(xh, yh);
+    return ((uint64_t)xl | ((uint64_t)xh << 32)) + ((uint64_t)yl | ((uint64_t)yh << 32));
 }
 
 template <typename T> __device__ __forceinline__ T wave_reduce4(const T (&p)[NW]) {
@@ -574,8 +631,8 @@ template <typename T> __device__ __forceinline__ T wave_reduce4(const T (&p)[NW]
     T r = vadd(f ? q0 : q1, vdpp<DPP_XOR2>(f ? q1 : q0));
     r = vadd(r, vdpp<DPP_HALF_MIRROR>(r));
     r = vadd(r, vdpp<DPP_MIRROR>(r));
-    r = vadd(r, vxor(r, 16));
-    r = vadd(r, vxor(r, 32));
+    r = vswapadd<16>(r);
+    r = vswapadd<32>(r);
     r = vadd(r, vdpp<DPP_XOR2>(r));
     return vadd(r, vdpp<DPP_XOR1>(r));
 }
@@ -586,14 +643,15 @@ __device__ __forceinline__ typename PartT<MODE>::T small_value(const Range &rg,
     constexpr int EB = DTI<DT>::EB;
     constexpr int V = vec_elems<DT>();
     const int l = threadIdx.x & 63;
-    const int64_t body_n = rg.n - rg.head;
+    // (a small range's body has at most 2 * 256 * V elements)
+    const int32_t body_n = __builtin_amdgcn_readfirstlane((int32_t)(rg.n - rg.head));
     Acc<DT, MODE> a0;
     a0.init();
     using WV = decltype(a0.finish());
     WV tv[NW];
 #pragma unroll
     for (int w = 0; w < NW; w++) {
-        const bool any = (w == 0 && rg.head > 0) || (int64_t)(w * 64) * V < body_n;   // uniform
+        const bool any = (w == 0 && rg.head > 0) || w * 64 * V < body_n;   // uniform
         if (!any) {
             if constexpr (MODE == COMP) tv[w] = Pair{0.f, 0.f};
             else tv[w] = WV(0);
@@ -613,22 +671,15 @@ __device__ __forceinline__ typename PartT<MODE>::T small_value(const Range &rg,
         const bool first_ok = !(w == 0 && rg.head > 0);   // uniform
 #pragma unroll
         for (int u = 0; u < US; u++) {
-            if ((int64_t)(u * NTHR + w * 64) * V >= body_n) continue;   // uniform
-            const int64_t e = (int64_t)(u * NTHR + w * 64 + l) * V;
-            const bool first = u == 0 && first_ok;
-            if (e + V <= body_n) {
-                if (first) acc_vec<DT, MODE, true>(acc, r.v[u][w]);
-                else acc_vec(acc, r.v[u][w]);
-            } else if (e < body_n) {
-                const int m = (int)(body_n - e);
-#pragma unroll
-                for (int i = 0; i < V; i++) {
-                    if (i >= m) continue;
-                    const int a = (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3);
-                    if (first && i < 4) acc_from_vec<DT, MODE, true>(acc, r.v[u][w], i, a);
-                    else acc_from_vec(acc, r.v[u][w], i, a);
-                }
-            }
+            const int v0 = (u * NTHR + w * 64) * V;   // first element of the slot
+            if (v0 >= body_n) continue;                // uniform: no lane has data
+            uint4 v = r.v[u][w];
+            // the slot that holds the end of the body: each lane keeps the
+            // elements of its vector that lie in the body (a lane past the
+            // end, which loaded a copy of the last vector, keeps none)
+            if (v0 + 64 * V > body_n) v = first_elems<DT>(v, body_n - (v0 + l * V));   // uniform
+            if (u == 0 && first_ok) acc_vec<DT, MODE, true>(acc, v);
+            else acc_vec(acc, v);
         }
         tv[w] = acc.finish();
     }
@@ -982,10 +1033,7 @@ __global__ void __launch_bounds__(NTHR) k_seg_place(const int64_t *counts, const
     }
 }
 
-// Pass 4a: small segments, one wave each (grid-stride over segments); the
-// next segment's bounds are loaded before this one's data, so each segment
-// costs one memory round trip.
-// Small segments, one wave each: the waves of the grid stride over the
+// Pass 4a: small segments, one wave each: the waves of the grid stride over the
 // segments (indices are wave-uniform, so the offsets come through scalar
 // loads, one segment ahead).  A segment's loads are all issued before its
 // value is computed from registers; the other waves of the SIMD cover the
