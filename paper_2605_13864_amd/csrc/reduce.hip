@@ -426,10 +426,11 @@ template <int DT> __device__ __forceinline__ uint4 first_elems(uint4 v, int m) {
 // branches join): the head (the elements before the first 16-byte boundary,
 // added by thread 0 of chunk 0) comes from the aligned vector that holds it,
 // and in a partial chunk a lane whose vector lies past the body reloads the
-// body's last vector (a partial last vector is loaded whole); those values
-// are never used.  A 16-byte aligned vector holding a byte of the range lies
-// on a page the range touches.  A chunk with no body or head (an empty range)
-// loads the vector holding the range's output slot instead.
+// body's last vector (a partial last vector is loaded whole); the elements
+// outside the body are zeroed before they are added, which leaves the
+// accumulators as they are.  A 16-byte aligned vector holding a byte of the
+// range lies on a page the range touches.  A chunk with no body or head (an
+// empty range) loads the vector holding the range's output slot instead.
 template <int DT, int MODE, bool NT>
 __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg, int64_t j) {
     constexpr int EB = DTI<DT>::EB;
@@ -476,17 +477,21 @@ __device__ __forceinline__ typename PartT<MODE>::T reduce_chunk(const Range &rg,
             for (int i = 1; i < V; i++)
                 if (i >= h0 && i < h0 + rg.head) acc_from_vec(acc, hv, i, 0);
         }
+        // per wave and vector row (uniform): all of the wave's vectors in the
+        // body, none, or the row holding the body's end, where each lane keeps
+        // the elements of its vector that lie in the body (zeroed elements
+        // leave the accumulators exactly as they are)
+        const int wv = __builtin_amdgcn_readfirstlane(t >> 6);
+        const int64_t ew = e0 + (int64_t)(wv * 64) * V;   // the wave's first element
 #pragma unroll
         for (int u = 0; u < U; u++) {
-            const int64_t e = e0 + (int64_t)(u * NTHR + t) * V;
-            if (e + V <= body_n) {
+            const int64_t eu = ew + (int64_t)(u * NTHR) * V;
+            if (eu >= body_n) continue;
+            if (eu + 64 * V <= body_n) {
                 acc_vec(acc, v[u]);
-            } else if (e < body_n) {
-                const int m = (int)(body_n - e);
-                // compile-time element index: the accumulators stay in registers
-#pragma unroll
-                for (int i = 0; i < V; i++)
-                    if (i < m) acc_from_vec(acc, v[u], i, (DT == XTR_I32 || DT == XTR_I64) ? i : (i & 3));
+            } else {
+                const int64_t m = body_n - (eu + (int64_t)(t & 63) * V);
+                acc_vec(acc, first_elems<DT>(v[u], m < 0 ? 0 : (m > V ? V : (int)m)));
             }
         }
     }
