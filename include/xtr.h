@@ -454,7 +454,11 @@ typedef struct {
     int32_t nt_load;        /* 1: nontemporal (streaming) loads of src rows that   */
                             /*    start on 128-byte lines (base and pitch)         */
     int32_t nt_store;       /* 1: nontemporal stores of such dst rows              */
-    int32_t xcd;            /* 1: each XCD takes a contiguous range of tiles       */
+    int32_t xcd;            /* 1: each XCD takes a contiguous range of tiles (per  */
+                            /*    round of a persistent launch); 2: a persistent   */
+                            /*    launch of at least 8 workgroups gives each XCD a */
+                            /*    contiguous eighth of the whole launch order      */
+                            /*    (0..2; single launches take 2 as 1)              */
     int32_t group;          /* tile rows per band of the launch order, 1..64       */
     int32_t blocks_per_cu;  /* 0: one workgroup per tile; k in 1..64: persistent   */
     int32_t nt_store_shared;/* 1: nontemporal stores of dst rows that do not start */

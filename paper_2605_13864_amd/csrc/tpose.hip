@@ -412,11 +412,13 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
     if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
         (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: bad arguments");
-    if (cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
+    if (cfg->xcd < 0 || cfg->xcd > 2 ||
+        cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
         cfg->run < 0 || cfg->run > 64)
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: group in [1, 64], blocks_per_cu "
-                                     "in [0, 64], tile and tile_shared in [0, 3], run in [0, 64]");
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 2], group in "
+                                     "[1, 64], blocks_per_cu in [0, 64], tile and tile_shared in "
+                                     "[0, 3], run in [0, 64]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

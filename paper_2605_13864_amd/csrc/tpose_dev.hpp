@@ -580,13 +580,15 @@ __device__ __forceinline__ Job job_gather(uint32_t v) {
     return jb;
 }
 
-// Persistent over the concatenated tile space of a group of jobs.  Round r
-// of the grid covers positions [r G K, r G K + G K) of the launch order in G
-// slots of K consecutive positions (K = run, the tiles a workgroup takes one
-// after another); within a round each XCD takes a contiguous range of slots
-// (xcd_remap), and within a job tiles follow the band order, so tiles that
-// share cache lines at their edges (rows of a job whose pitch is not a
-// multiple of the line) meet in one L2, and with K > 1 in one CU.
+// Persistent over the concatenated tile space of a group of jobs, in slots
+// of K consecutive positions of the launch order (K = run, the tiles a
+// workgroup takes one after another).  xcd 0 / 1: round r of the grid covers
+// positions [r G K, r G K + G K) in G slots; with xcd = 1 each XCD takes a
+// contiguous range of the round's slots (xcd_remap).  xcd = 2: each XCD
+// sweeps a contiguous eighth of the whole order.  Within a job tiles follow
+// the band order, so tiles that share cache lines at their edges (rows of a
+// job whose pitch is not a multiple of the line) meet in one L2, and with
+// K > 1 in one CU.
 // The next tile's job is found while the current tile moves: its search
 // probe is loaded before the tile's loads, and its record after the tile is
 // staged in LDS, ahead of the tile's stores; neither waits on the tile's
@@ -599,20 +601,43 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
     const uint32_t ntiles = (uint32_t)ntiles64, G = gridDim.x, bx = blockIdx.x;
     const uint32_t K = run > 1 ? (uint32_t)run : 1u;
     const int l = threadIdx.x & 63;
-    // this workgroup's positions: round base R, first position, count, index
+    // xcd == 2 (with at least 8 workgroups): XCD x = bx % 8 sweeps its own
+    // eighth [lo_x, hi_x) of the launch order, its Gx workgroups taking slots
+    // of K positions round-robin, as a launch of one workgroup per tile
+    // places them; so the tiles that share edge lines meet in one L2 close
+    // together in time.  Slot s of region x goes to workgroup 8 (s % Gx) + x,
+    // and 8 (Gx - 1) + x < G, so every position is taken exactly once.
+    const bool reg = xcd == 2 && G >= 8;
+    const uint32_t xr = bx & 7, kx = bx >> 3;
+    const uint32_t Gx = (G >> 3) + (xr < (G & 7) ? 1u : 0u);
+    const uint32_t share = (ntiles + 7) >> 3;
+    const uint32_t lo_x = xr * share < ntiles ? xr * share : ntiles;
+    const uint32_t hi_x = ntiles - lo_x < share ? ntiles : lo_x + share;
+    // this workgroup's positions: visit R, its first position, count, index
     uint32_t R = 0, first = 0, count = 0, i = 0;
-    auto round_at = [&](uint32_t r0) {   // false: no position for this workgroup
-        if (r0 >= ntiles) return false;
-        const uint32_t rem = ntiles - r0;
-        const uint32_t slots = (rem + K - 1) / K < G ? (rem + K - 1) / K : G;
-        if (bx >= slots) return false;
-        R = r0;
-        first = r0 + (xcd ? xcd_remap(bx, slots) : bx) * K;
-        count = ntiles - first < K ? ntiles - first : K;
+    auto visit = [&](uint32_t r) {   // this workgroup's r-th slot; false: none left
+        uint64_t f;
+        uint32_t end;
+        if (reg) {
+            f = (uint64_t)lo_x + ((uint64_t)kx + (uint64_t)r * Gx) * K;
+            end = hi_x;
+        } else {
+            const uint64_t r0 = (uint64_t)r * G * K;   // rounds of G slots
+            if (r0 >= ntiles) return false;
+            const uint32_t rem = ntiles - (uint32_t)r0;
+            const uint32_t slots = (rem + K - 1) / K < G ? (rem + K - 1) / K : G;
+            if (bx >= slots) return false;
+            f = r0 + (uint64_t)(xcd ? xcd_remap(bx, slots) : bx) * K;
+            end = ntiles;
+        }
+        if (f >= end) return false;
+        R = r;
+        first = (uint32_t)f;
+        count = end - first < K ? end - first : K;
         i = 0;
         return true;
     };
-    if (!round_at(0)) return;
+    if (!visit(0)) return;
     uint32_t L = first;
     int j = job_search(bases, njobs, L);
     Job jb = job_gather(job_dword(jobs, j));
@@ -623,7 +648,7 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
             i++;
             more = true;
         } else {
-            more = round_at(R + G * K);
+            more = visit(R + 1);
         }
         const uint32_t Ln = more ? first + i : 0;
         int c = 0;

@@ -204,3 +204,21 @@ def test_matmul_rejects(lib, args, code):
 def test_matmul_empty_is_noop(lib):
     assert lib.matmul(None, None, C.c_void_p(FAKE), 0, 4, 4, 4, 4, 4, 0, 2, None) == 0
     assert lib.matmul(None, None, C.c_void_p(FAKE), 4, 0, 4, 4, 4, 4, 0, 2, None) == 0
+
+
+def test_launch_config_validation(lib):
+    """The launch settings are range-checked (they change scheduling only);
+    a rejected setting leaves the class's settings as they were."""
+    orig = X.tpose_config(4, "batched")
+    try:
+        X.set_tpose_config(4, "batched", xcd=2)
+        assert X.tpose_config(4, "batched")["xcd"] == 2
+        for bad in ({"xcd": 3}, {"xcd": -1}, {"group": 0}, {"run": 65}, {"tile": 4},
+                    {"blocks_per_cu": 65}):
+            with pytest.raises(X.XtrError) as e:
+                X.set_tpose_config(4, "batched", **bad)
+            assert e.value.code == -1, bad
+        assert X.tpose_config(4, "batched")["xcd"] == 2
+    finally:
+        X.set_tpose_config(4, "batched", **orig)
+    assert X.tpose_config(4, "batched") == orig
