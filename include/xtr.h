@@ -330,10 +330,12 @@ int xtr_reduce_sum_host(const void *src, int64_t n, void *out, int dtype);
  * Batch plans: a batch whose buffers and shapes repeat (a serving slot, a
  * training step) is validated and uploaded once; each run then only launches
  * kernels, with no host allocation, copy or memset, so a run can be captured
- * in a hipGraph and replayed.  The plan owns its device job table (and, for
- * sums, a zeroed workspace that every run leaves reusable); the caller owns
- * the data buffers, which must stay valid for the plan's lifetime.  Runs of
- * one plan must not overlap in time (they share its workspace).
+ * in a hipGraph and replayed.  The plan owns its device job table (with the
+ * slot counters of the transposes' dynamic order, which every run leaves at
+ * zero, and, for sums, a zeroed workspace that every run leaves reusable);
+ * the caller owns the data buffers, which must stay valid for the plan's
+ * lifetime.  Runs of one plan must not overlap in time (they share its
+ * counters and workspace).
  */
 typedef struct xtr_tpose_plan xtr_tpose_plan;
 
@@ -457,8 +459,12 @@ typedef struct {
     int32_t xcd;            /* 1: each XCD takes a contiguous range of tiles (per  */
                             /*    round of a persistent launch); 2: a persistent   */
                             /*    launch of at least 8 workgroups gives each XCD a */
-                            /*    contiguous eighth of the whole launch order      */
-                            /*    (0..2; single launches take 2 as 1)              */
+                            /*    contiguous eighth of the whole launch order; 3:  */
+                            /*    chunks of the order dealt to the XCDs in turn, a */
+                            /*    workgroup taking the next free slot of its XCD's */
+                            /*    chunks from a counter in the batch table         */
+                            /*    (batches with a table; others take 3 as 1);      */
+                            /*    0..3, single launches take 2 and 3 as 1          */
     int32_t group;          /* tile rows per band of the launch order, 1..64       */
     int32_t blocks_per_cu;  /* 0: one workgroup per tile; k in 1..64: persistent   */
     int32_t nt_store_shared;/* 1: nontemporal stores of dst rows that do not start */

@@ -200,15 +200,23 @@ constexpr int64_t WIDE_MIN_TILES = 16;
 int wclass(int w) { return w == 16 ? 0 : w == 8 ? 1 : w == 4 ? 2 : 3; }
 int wof(int wc) { return wc == 0 ? 16 : wc == 1 ? 8 : wc == 2 ? 4 : 0; }
 
+// Slot counters of a group launch (order xcd = 3): one per XCD and an exit
+// count, zero before every launch (uploaded as zeros; the last
+// workgroup of a launch sets them back to zero).
+constexpr int CTR_WORDS = 16;
+
 struct BatchTable {
     std::vector<Job> all;                // groups concatenated
     std::vector<int64_t> bases;          // tile_base of every job of `all` (same order)
     size_t at[NGROUPS] = {};             // first job of each group in `all` / `bases`
     int nj[NGROUPS] = {};
     int64_t ntiles[NGROUPS] = {};
-    // device image: the Job array, then (at a 256-byte boundary) the bases
+    // device image: the Job array, then (at a 256-byte boundary) `tail`: for
+    // each non-empty group its bases, then its CTR_WORDS zero counter words
+    std::vector<int64_t> tail;
+    size_t tail_at[NGROUPS] = {};        // a group's bases in `tail`; counters follow
     size_t jobs_bytes() const { return (all.size() * sizeof(Job) + 255) / 256 * 256; }
-    size_t bytes() const { return jobs_bytes() + bases.size() * sizeof(int64_t); }
+    size_t bytes() const { return jobs_bytes() + tail.size() * sizeof(int64_t); }
 };
 
 int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, BatchTable &bt) {
@@ -259,14 +267,22 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
     }
     bt.bases.resize(bt.all.size());
     for (size_t i = 0; i < bt.all.size(); i++) bt.bases[i] = bt.all[i].tile_base;
+    for (int g = 0; g < NGROUPS; g++) {
+        if (!bt.nj[g]) continue;
+        bt.tail_at[g] = bt.tail.size();
+        bt.tail.insert(bt.tail.end(), bt.bases.begin() + bt.at[g],
+                       bt.bases.begin() + bt.at[g] + bt.nj[g]);
+        bt.tail.insert(bt.tail.end(), CTR_WORDS / 2, 0);   // counters, 8-byte aligned
+    }
     return XTR_OK;
 }
 
-// Copies the device image of bt (jobs, then bases) to dev with upload().
+// Copies the device image of bt (jobs, then bases and zero counters) to dev
+// with upload().
 int upload_batch(const BatchTable &bt, void *dev, hipStream_t stream) {
     int rc = upload(bt.all.data(), bt.all.size() * sizeof(Job), dev, stream);
     if (rc) return rc;
-    return upload(bt.bases.data(), bt.bases.size() * sizeof(int64_t),
+    return upload(bt.tail.data(), bt.tail.size() * sizeof(int64_t),
                   static_cast<unsigned char *>(dev) + bt.jobs_bytes(), stream);
 }
 
@@ -281,9 +297,10 @@ bool batch_inline(const BatchTable &bt) {
 // or nullptr when batch_inline(bt) (jobs in the kernel arguments).
 int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
     const Job *djobs = static_cast<const Job *>(dev);
-    const int64_t *dbases = dev ? reinterpret_cast<const int64_t *>(
-                                      static_cast<const unsigned char *>(dev) + bt.jobs_bytes())
-                                : nullptr;
+    int64_t *dtail = dev ? reinterpret_cast<int64_t *>(
+                               static_cast<unsigned char *>(const_cast<void *>(dev)) +
+                               bt.jobs_bytes())
+                         : nullptr;
     JobPack pack;
     for (int g = 0; g < NGROUPS; g++) {
         if (!bt.nj[g]) continue;
@@ -302,12 +319,16 @@ int launch_batch(const BatchTable &bt, const void *dev, hipStream_t stream) {
         int64_t grid = bt.ntiles[g] < 0x7fffffff ? bt.ntiles[g] : 0x7fffffff;
         if (grid < 1) grid = 1;
         const Job *jobs = dev ? djobs + bt.at[g] : nullptr;
-        const int64_t *bases = dev ? dbases + bt.at[g] : nullptr;
+        const int64_t *bases = dev ? dtail + bt.tail_at[g] : nullptr;
+        uint32_t *ctr = dev ? reinterpret_cast<uint32_t *>(dtail + bt.tail_at[g] + bt.nj[g])
+                            : nullptr;
+        const int64_t nt = bt.ntiles[g];
+        const int nj = bt.nj[g];
         switch (slot) {
-        case 0: launch_group_e1(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 1: launch_group_e2(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        case 2: launch_group_e4(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
-        default: launch_group_e8(w, off32, lines, geo, grid, stream, jobs, bases, bt.nj[g], bt.ntiles[g], pk); break;
+        case 0: launch_group_e1(w, off32, lines, geo, grid, stream, jobs, bases, nj, nt, pk, ctr); break;
+        case 1: launch_group_e2(w, off32, lines, geo, grid, stream, jobs, bases, nj, nt, pk, ctr); break;
+        case 2: launch_group_e4(w, off32, lines, geo, grid, stream, jobs, bases, nj, nt, pk, ctr); break;
+        default: launch_group_e8(w, off32, lines, geo, grid, stream, jobs, bases, nj, nt, pk, ctr); break;
         }
         XTR_HIP(hipGetLastError());
     }
@@ -372,7 +393,7 @@ int xtr_tpose_plan_create(const xtr_tpose_desc *descs, int64_t count, void *stre
                                hipMemcpyHostToDevice, st);
             if (e == hipSuccess)
                 e = hipMemcpyAsync(static_cast<unsigned char *>(p->dev) + p->bt.jobs_bytes(),
-                                   p->bt.bases.data(), p->bt.bases.size() * sizeof(int64_t),
+                                   p->bt.tail.data(), p->bt.tail.size() * sizeof(int64_t),
                                    hipMemcpyHostToDevice, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) rc = xtr::hip_fail(e, "xtr_tpose_plan_create: table upload");
@@ -412,11 +433,11 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
     if (!cfg || (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8) ||
         (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: bad arguments");
-    if (cfg->xcd < 0 || cfg->xcd > 2 ||
+    if (cfg->xcd < 0 || cfg->xcd > 3 ||
         cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
         cfg->run < 0 || cfg->run > 64)
-        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 2], group in "
+        return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 3], group in "
                                      "[1, 64], blocks_per_cu in [0, 64], tile and tile_shared in "
                                      "[0, 3], run in [0, 64]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;

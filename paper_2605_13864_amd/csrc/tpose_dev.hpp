@@ -596,7 +596,7 @@ __device__ __forceinline__ Job job_gather(uint32_t v) {
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC, int DC>
 __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *bases, int njobs,
                                               int64_t ntiles64, int xcd, int group, int run,
-                                              uint4 *lds) {
+                                              uint32_t *ctr, uint4 *lds, uint32_t *slot) {
     using Gm = Geo<EB, SC, DC>;
     const uint32_t ntiles = (uint32_t)ntiles64, G = gridDim.x, bx = blockIdx.x;
     const uint32_t K = run > 1 ? (uint32_t)run : 1u;
@@ -607,6 +607,19 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
     // places them; so the tiles that share edge lines meet in one L2 close
     // together in time.  Slot s of region x goes to workgroup 8 (s % Gx) + x,
     // and 8 (Gx - 1) + x < G, so every position is taken exactly once.
+    // xcd == 3 (with a counter block): the order is cut into chunks of
+    // CS slots, chunk k belonging to "XCD" k % 8, and a workgroup takes the
+    // next free slot of its XCD's chunks from that XCD's counter, as the
+    // dispatcher hands out the workgroups of a launch of one workgroup per
+    // tile: the tiles in flight stay a window of the order however the
+    // workgroups' speeds drift apart, and the eight XCDs work on adjacent
+    // chunks (far-apart windows that advance in step can meet the same HBM
+    // channels).  Each counter value is taken once, and the values of XCD x
+    // map to increasing positions, so its workgroups, which take values in
+    // increasing order until one lies past the end, take every position of
+    // x's chunks; every class bx % 8 has a workgroup (G >= 8).
+    constexpr uint32_t CS = 128;
+    const bool dyn = xcd == 3 && ctr != nullptr && G >= 8;
     const bool reg = xcd == 2 && G >= 8;
     const uint32_t xr = bx & 7, kx = bx >> 3;
     const uint32_t Gx = (G >> 3) + (xr < (G & 7) ? 1u : 0u);
@@ -637,46 +650,98 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
         i = 0;
         return true;
     };
-    if (!visit(0)) return;
-    uint32_t L = first;
-    int j = job_search(bases, njobs, L);
-    Job jb = job_gather(job_dword(jobs, j));
-    for (;;) {
-        // the next position of this workgroup
-        bool more;
-        if (i + 1 < count) {
-            i++;
-            more = true;
-        } else {
-            more = visit(R + 1);
+    // dynamic slots: value s of XCD x is slot s % CS of x's chunk s / CS,
+    // i.e. chunk 8 (s / CS) + x of the order (CS K positions per chunk)
+    auto take = [&](uint32_t s) {
+        const uint64_t chunk = (uint64_t)(s / CS) * 8 + xr;
+        const uint64_t f = (chunk * CS + s % CS) * K;
+        if (f >= ntiles) return false;
+        first = (uint32_t)f;
+        count = ntiles - first < K ? ntiles - first : K;
+        i = 0;
+        return true;
+    };
+    bool live;
+    if (dyn) {
+        if (threadIdx.x == 0)
+            slot[0] = __hip_atomic_fetch_add(&ctr[xr], 1u, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        live = take(slot[0]);
+    } else {
+        live = visit(0);
+    }
+    if (live) {
+        uint32_t L = first;
+        int j = job_search(bases, njobs, L);
+        Job jb = job_gather(job_dword(jobs, j));
+        for (;;) {
+            // the next position of this workgroup: the next one of its slot, or
+            // the first of its next slot (a dynamic slot is known after the
+            // barrier below: its counter is read while the tile loads fly)
+            bool more = false, ask = false;
+            uint32_t got = 0;
+            if (i + 1 < count) {
+                i++;
+                more = true;
+            } else if (dyn) {
+                ask = true;
+                if (threadIdx.x == 0)
+                    got = __hip_atomic_fetch_add(&ctr[xr], 1u, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT);
+            } else {
+                more = visit(R + 1);
+            }
+            uint32_t Ln = more ? first + i : 0;
+            int c = 0;
+            int64_t probe = 0;
+            if (more) {
+                c = j + 1 + l;
+                probe = bases[c < njobs ? c : njobs - 1];   // (unconditional load; c checked below)
+            }
+            const uint32_t tiles_r = (uint32_t)((jb.rows + Gm::TR - 1) / Gm::TR);
+            uint32_t tr, tc;
+            band_order(L - (uint32_t)jb.tile_base, tiles_r, (uint32_t)jb.tiles_c, (uint32_t)group,
+                       tr, tc);
+            const int64_t R0 = (int64_t)tr * Gm::TR, C0 = (int64_t)tc * Gm::TC;
+            phase_any<1, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols,
+                                                         jb.ld_src, jb.ld_dst, R0, C0, lds);
+            if (ask && threadIdx.x == 0) slot[1] = got;
+            __syncthreads();   // ownership of the LDS tile moves from loaders to storers
+            if (ask) {
+                more = take(slot[1]);
+                Ln = more ? first : 0;
+                if (more) {
+                    c = j + 1 + l;
+                    probe = bases[c < njobs ? c : njobs - 1];
+                }
+            }
+            uint32_t next = 0;
+            if (more) {
+                const int k = __popcll(__ballot(c < njobs && probe <= (int64_t)Ln));
+                j += k;
+                if (k == 64) j = job_forward(bases, njobs, j, Ln);   // more than 64 jobs ahead
+                next = job_dword(jobs, j);
+            }
+            phase_any<2, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols,
+                                                         jb.ld_src, jb.ld_dst, R0, C0, lds);
+            __syncthreads();   // LDS is reused by the next tile of this workgroup
+            if (!more) break;
+            jb = job_gather(next);
+            L = Ln;
         }
-        const uint32_t Ln = more ? first + i : 0;
-        int c = 0;
-        int64_t probe = 0;
-        if (more) {
-            c = j + 1 + l;
-            probe = bases[c < njobs ? c : njobs - 1];   // (unconditional load; c checked below)
+    }
+    if (dyn && threadIdx.x == 0) {
+        // the last workgroup to leave sets the counters back to zero for the
+        // next launch: every workgroup takes its last slot before it counts
+        // itself out (release), and the last one sees all of them (acquire)
+        const uint32_t done = __hip_atomic_fetch_add(&ctr[8], 1u, __ATOMIC_ACQ_REL,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+        if (done == G - 1) {
+#pragma unroll
+            for (int k = 0; k < 9; k++)
+                __hip_atomic_store(&ctr[k], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
-        const uint32_t tiles_r = (uint32_t)((jb.rows + Gm::TR - 1) / Gm::TR);
-        uint32_t tr, tc;
-        band_order(L - (uint32_t)jb.tile_base, tiles_r, (uint32_t)jb.tiles_c, (uint32_t)group, tr, tc);
-        const int64_t R0 = (int64_t)tr * Gm::TR, C0 = (int64_t)tc * Gm::TC;
-        phase_any<1, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
-                                                     jb.ld_dst, R0, C0, lds);
-        __syncthreads();   // ownership of the LDS tile moves from loaders to storers
-        uint32_t next = 0;
-        if (more) {
-            const int k = __popcll(__ballot(c < njobs && probe <= (int64_t)Ln));
-            j += k;
-            if (k == 64) j = job_forward(bases, njobs, j, Ln);   // more than 64 jobs ahead
-            next = job_dword(jobs, j);
-        }
-        phase_any<2, EB, W, NTL, NTS, OFF32, SC, DC>(jb.src, jb.dst, jb.rows, jb.cols, jb.ld_src,
-                                                     jb.ld_dst, R0, C0, lds);
-        __syncthreads();   // LDS is reused by the next tile of this workgroup
-        if (!more) break;
-        jb = job_gather(next);
-        L = Ln;
     }
 }
 
@@ -685,9 +750,12 @@ __device__ __forceinline__ void batched_tiles(const Job *jobs, const int64_t *ba
 template <int EB, int W, bool NTL, bool NTS, bool OFF32, int SC = 16, int DC = 16>
 __global__ void __launch_bounds__(NT) k_tpose_batched(const Job *__restrict__ jobs,
                                                       const int64_t *__restrict__ bases, int njobs,
-                                                      int64_t ntiles, int xcd, int group, int run) {
+                                                      int64_t ntiles, int xcd, int group, int run,
+                                                      uint32_t *ctr) {
     __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
-    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(jobs, bases, njobs, ntiles, xcd, group, run, lds);
+    __shared__ uint32_t slot[2];
+    batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(jobs, bases, njobs, ntiles, xcd, group, run, ctr,
+                                                  lds, slot);
 }
 
 // A small group passes its jobs inside the kernel arguments: no table upload
@@ -703,7 +771,7 @@ __global__ void __launch_bounds__(NT) k_tpose_batched_inl(JobPack pk, int njobs,
                                                           int xcd, int group, int run) {
     __shared__ uint4 lds[Geo<EB, SC, DC>::LDS_VECS];
     batched_tiles<EB, W, NTL, NTS, OFF32, SC, DC>(pk.jobs, pk.bases, njobs, ntiles, xcd, group, run,
-                                                  lds);
+                                                  nullptr, lds, nullptr);
 }
 
 // ---------------------------------------------------------------- host side
@@ -931,7 +999,8 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
 // (host) non-null: the group's jobs travel in the kernel arguments.
 template <int EB, int W, bool OFF32, int SC = 16, int DC = 16>
 void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
-                      const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk) {
+                      const int64_t *bases, int nj, int64_t ntiles, const JobPack *pk,
+                      uint32_t *ctr) {
     const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(EB)];
     const bool ntl = lines ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines ? c.nt_store != 0 : c.nt_store_shared != 0;
@@ -951,7 +1020,7 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
                 (const void *)&k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>, NT, cap);      \
             hipLaunchKernelGGL((k_tpose_batched<EB, W, NL, NS, OFF32, SC, DC>),             \
                                dim3((unsigned)(grid < occ ? grid : occ)), dim3(NT), 0, st,   \
-                               jobs, bases, nj, ntiles, c.xcd, group, c.run);               \
+                               jobs, bases, nj, ntiles, c.xcd, group, c.run, ctr);          \
         }                                                                                   \
     } while (0)
     if (ntl && nts) XTR_KB(true, true);
@@ -966,26 +1035,26 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
 template <int EB>
 void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStream_t st,
                     const Job *jobs, const int64_t *bases, int nj, int64_t ntiles,
-                    const JobPack *pk) {
+                    const JobPack *pk, uint32_t *ctr) {
 #define XTR_BW(WW)                                                                             \
     if constexpr (EB >= 2 && WW >= 4) {                                                        \
         if (geo == 1) {                                                                        \
-            launch_batched_w<EB, WW, true, 32, 16>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+            launch_batched_w<EB, WW, true, 32, 16>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr); \
             return;                                                                            \
         }                                                                                      \
         if (geo == 2) {                                                                        \
-            launch_batched_w<EB, WW, true, 16, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+            launch_batched_w<EB, WW, true, 16, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr); \
             return;                                                                            \
         }                                                                                      \
     }                                                                                          \
     if constexpr (EB >= 4 && WW >= 4) {                                                        \
         if (geo == 3) {                                                                        \
-            launch_batched_w<EB, WW, true, 32, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk); \
+            launch_batched_w<EB, WW, true, 32, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr); \
             return;                                                                            \
         }                                                                                      \
     }                                                                                          \
-    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles, pk);   \
-    else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles, pk);
+    if (off32) launch_batched_w<EB, WW, true>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr);   \
+    else launch_batched_w<EB, WW, false>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr);
     switch (w) {
     case 16: XTR_BW(16) break;
     case 8:
@@ -1010,7 +1079,7 @@ void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStr
                             int64_t ld_src, int64_t ld_dst, hipStream_t stream);             \
     void launch_group_e##EB(int w, bool off32, bool lines, int geo, int64_t grid,            \
                             hipStream_t st, const Job *jobs, const int64_t *bases, int nj,   \
-                            int64_t ntiles, const JobPack *pk);
+                            int64_t ntiles, const JobPack *pk, uint32_t *ctr);
 XTR_TPOSE_EB_DECL(1)
 XTR_TPOSE_EB_DECL(2)
 XTR_TPOSE_EB_DECL(4)

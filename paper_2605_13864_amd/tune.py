@@ -202,7 +202,7 @@ def tpose_batched_candidates(quick: bool, eb: int):
     bpc = [0, 4] if quick else [0, 2, 4, 8]
     wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
     runs = [0, 4] if quick else [0, 2, 4]
-    xcds = [2, 1] if quick else [2, 1, 0]
+    xcds = [3, 2] if quick else [3, 2, 1, 0]
     for (nl, ns), xcd, g, b, w, r in itertools.product(nts, xcds, groups, bpc, wides, runs):
         # nearly every job of a random-size batch has rows that share lines:
         # the *_shared flags decide; the line-aligned ones follow along

@@ -25,11 +25,34 @@ def _tpose_jobs(torch, n, seed, dtypes=("f32", "bf16", "u8", "f64")):
     return jobs, hosts
 
 
-def test_tpose_plan_runs_and_replays(xtr, orc):
+@pytest.mark.parametrize("xcd", [1, 3])
+def test_tpose_plan_runs_and_replays(xtr, orc, xcd):
+    """A transpose plan run eagerly, then captured and replayed; with xcd = 3
+    the launches take their slots from counters in the plan's table, which
+    every run must leave at zero for the next one."""
     import torch
+    origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
+    for eb in origs:
+        xtr.set_tpose_config(eb, "batched", xcd=xcd, blocks_per_cu=2)
+    try:
+        _plan_replays(xtr, orc, torch)
+    finally:
+        for eb, o in origs.items():
+            xtr.set_tpose_config(eb, "batched", **o)
+
+
+def _plan_replays(xtr, orc, torch):
     jobs, hosts = _tpose_jobs(torch, 40, 3)
+    for k in range(8, 40):                            # a group of more than 24 jobs: a table
+        r, c = (int(x) for x in np.random.Generator(np.random.PCG64(k)).integers(200, 900, 2))
+        a = W.random_bits(r * c, 900 + k, 4).reshape(r, c)
+        s = to_dev(a)
+        jobs.append({"src": s, "dst": torch.empty((c, r), dtype=s.dtype, device=s.device),
+                     "rows": r, "cols": c, "dtype": "f32"})
+        hosts.append(a)
     plan = xtr.TposePlan(jobs)
     plan.run()
+    plan.run()                                        # eager runs back to back
     torch.cuda.synchronize()
     for j, a in zip(jobs, hosts):
         assert np.array_equal(to_host(j["dst"], a.dtype), orc.tpose(a))

@@ -154,14 +154,14 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("run,xcd", [(0, 1), (3, 1), (0, 2), (3, 2)])
+@pytest.mark.parametrize("run,xcd", [(0, 1), (3, 1), (0, 2), (3, 2), (0, 3), (3, 3)])
 @pytest.mark.parametrize("wide", [0, 1, 2, 3])
 def test_batched_geometries(xtr, orc, wide, run, xcd):
     """Batched transposes with each tile geometry (512-byte src rows: 1, dst
     rows: 2, both: 3) for jobs whose rows share lines, mixed with small and aligned
-    jobs, every element size and every piece width, in both XCD orders (per
-    round, or one contiguous eighth of the launch order per XCD); each job
-    against the oracle."""
+    jobs, every element size and every piece width, in each XCD order (per round;
+    one contiguous eighth of the launch order per XCD, with static slots or
+    slots taken from counters); each job against the oracle."""
     import torch
     rng = np.random.Generator(np.random.PCG64(19))
     origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
