@@ -481,7 +481,11 @@ typedef struct {
                             /*    another in the launch order (0 or 1: one), so    */
                             /*    neighbouring tiles, which share the cache lines   */
                             /*    at their edges, meet in one CU; 0..64             */
-    int32_t _reserved[2];
+    int32_t narrow;         /* batched class: 1 = every job whose pieces could be  */
+                            /*    wider takes the narrowest piece of its element  */
+                            /*    size (4 bytes; 8 for 8-byte elements), so the   */
+                            /*    jobs of one element size share one launch; 0..1  */
+    int32_t _reserved[1];
 } xtr_tpose_config;
 
 /* Shape classes of the launch configurations: single calls (tpose,

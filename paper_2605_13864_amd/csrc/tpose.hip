@@ -47,10 +47,10 @@ using namespace tpk;
 // Tuned launch configuration per shape class and element size (slot
 // cfg_slot(elem bytes)).
 xtr_tpose_config tpk::g_cfg[2][4] = {
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}},
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, {0, 0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}},
 };
 
 namespace {
@@ -241,6 +241,8 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         j.dst = (unsigned char *)d.dst;
         j.rows = d.rows; j.cols = d.cols; j.ld_src = d.ld_src; j.ld_dst = d.ld_dst;
         j.w = piece_width(d.src, d.dst, d.ld_src, d.ld_dst, eb);
+        const xtr_tpose_config &cb = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(eb)];
+        if (cb.narrow && j.w > 4) j.w = eb >= 8 ? 8 : 4;   // one launch per element size
         j._pad = 0;
         const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
         const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(eb)];
@@ -436,10 +438,10 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
     if (cfg->xcd < 0 || cfg->xcd > 3 ||
         cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
-        cfg->run < 0 || cfg->run > 64)
+        cfg->run < 0 || cfg->run > 64 || cfg->narrow < 0 || cfg->narrow > 1)
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 3], group in "
                                      "[1, 64], blocks_per_cu in [0, 64], tile and tile_shared in "
-                                     "[0, 3], run in [0, 64]");
+                                     "[0, 3], run in [0, 64], narrow in [0, 1]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

@@ -204,13 +204,14 @@ def tpose_batched_candidates(quick: bool, eb: int):
     groups = [16, 32] if quick else [8, 16, 32]
     bpc = [2, 4] if quick else [0, 2, 3, 4]
     wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
-    runs = [0] if quick else [0, 2]
-    for (nl, ns), xcd, g, b, w, r in itertools.product(nts, xcds, groups, bpc, wides, runs):
+    narrows = [1, 0]
+    for (nl, ns), xcd, g, b, w, nw in itertools.product(nts, xcds, groups, bpc, wides, narrows):
         # nearly every job of a random-size batch has rows that share lines:
         # the *_shared flags decide; the line-aligned ones follow along
+        # (runs of consecutive tiles per workgroup never led: run 0)
         yield {"nt_load": nl, "nt_store": ns, "nt_load_shared": nl, "nt_store_shared": ns,
                "xcd": xcd, "group": g, "blocks_per_cu": b, "tile": 0, "tile_shared": w,
-               "run": r}
+               "run": 0, "narrow": nw}
 
 
 def tune_tpose_batched(xtr, torch, eb: int, quick=False, log=print, count=4096, seed=9):

@@ -154,21 +154,24 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("run,xcd", [(0, 1), (3, 1), (0, 2), (3, 2), (0, 3), (3, 3)])
+@pytest.mark.parametrize("run,xcd,narrow", [(0, 1, 0), (3, 1, 0), (0, 2, 0), (3, 2, 1), (0, 3, 1),
+                                            (3, 3, 0)])
 @pytest.mark.parametrize("wide", [0, 1, 2, 3])
-def test_batched_geometries(xtr, orc, wide, run, xcd):
+def test_batched_geometries(xtr, orc, wide, run, xcd, narrow):
     """Batched transposes with each tile geometry (512-byte src rows: 1, dst
     rows: 2, both: 3) for jobs whose rows share lines, mixed with small and aligned
     jobs, every element size and every piece width, in each XCD order (per round;
     one contiguous eighth of the launch order per XCD, with static slots or
-    slots taken from counters); each job against the oracle."""
+    slots taken from counters), with or without one piece width per element
+    size; each job against the oracle."""
     import torch
     rng = np.random.Generator(np.random.PCG64(19))
     origs = {eb: xtr.tpose_config(eb, "batched") for eb in (1, 2, 4, 8)}
     try:
         for eb in (2, 4, 8):
-            xtr.set_tpose_config(eb, "batched", tile_shared=wide, tile=wide, run=run, xcd=xcd)
-        xtr.set_tpose_config(1, "batched", run=run, xcd=xcd)
+            xtr.set_tpose_config(eb, "batched", tile_shared=wide, tile=wide, run=run, xcd=xcd,
+                                 narrow=narrow)
+        xtr.set_tpose_config(1, "batched", run=run, xcd=xcd, narrow=narrow)
         jobs, hosts = [], []
         for i in range(40):
             eb = [1, 2, 4, 8][i % 4]
