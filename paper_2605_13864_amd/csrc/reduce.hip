@@ -113,9 +113,6 @@ template <int CTRL> __device__ __forceinline__ float dppf(float v) {
 template <int CTRL> __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
     return (uint64_t)dpp<CTRL>((uint32_t)v) | ((uint64_t)dpp<CTRL>((uint32_t)(v >> 32)) << 32);
 }
-__device__ __forceinline__ float readlane_f(float v, int lane) {
-    return __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)__float_as_uint(v), lane));
-}
 __device__ __forceinline__ uint64_t readlane_u64(uint64_t v, int lane) {
     return (uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane) |
            ((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane) << 32);
@@ -126,31 +123,10 @@ constexpr int DPP_XOR2 = 0x4E;        // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7-i within each 8 lanes
 constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15-i within each row of 16
 
-// Symmetric butterfly: after xor1/xor2 the four lanes of a quad hold identical
-// values, so the half-row mirror exchanges whole quads (xor 4); after it the
-// half-rows are uniform and the row mirror exchanges them (xor 8).  Pair
-// addition is commutative bit for bit, so every lane of a row ends with the
-// same row total; the rows are then combined as ((r0 + r1) + (r2 + r3)).
-template <int CTRL> __device__ __forceinline__ Pair dpp_step(Pair p) {
-    Pair o{dppf<CTRL>(p.s), dppf<CTRL>(p.c)};
-    return pair_add(p, o);
-}
-__device__ __forceinline__ Pair wave_reduce(Pair p) {
-    p = dpp_step<DPP_XOR1>(p);
-    p = dpp_step<DPP_XOR2>(p);
-    p = dpp_step<DPP_HALF_MIRROR>(p);
-    p = dpp_step<DPP_MIRROR>(p);
-    Pair r0{readlane_f(p.s, 0), readlane_f(p.c, 0)}, r1{readlane_f(p.s, 16), readlane_f(p.c, 16)};
-    Pair r2{readlane_f(p.s, 32), readlane_f(p.c, 32)}, r3{readlane_f(p.s, 48), readlane_f(p.c, 48)};
-    return pair_add(pair_add(r0, r1), pair_add(r2, r3));
-}
-__device__ __forceinline__ float wave_reduce(float v) {
-    v = v + dppf<DPP_XOR1>(v);
-    v = v + dppf<DPP_XOR2>(v);
-    v = v + dppf<DPP_HALF_MIRROR>(v);
-    v = v + dppf<DPP_MIRROR>(v);
-    return (readlane_f(v, 0) + readlane_f(v, 16)) + (readlane_f(v, 32) + readlane_f(v, 48));
-}
+// Integer wave sum (the planning kernels' counts): symmetric DPP butterfly
+// (after xor1/xor2 the four lanes of a quad hold identical values, so the
+// half-row mirror exchanges whole quads and the row mirror the half-rows),
+// then the four row totals.
 __device__ __forceinline__ uint64_t wave_reduce(uint64_t v) {
     v = v + dpp64<DPP_XOR1>(v);
     v = v + dpp64<DPP_XOR2>(v);
@@ -340,26 +316,35 @@ template <> struct PartT<INTM> { using T = uint64_t; };
 
 // ---------------------------------------------------------------- one chunk
 
-// Thread accumulators -> wave butterfly -> LDS tree over the 4 waves: the
-// chunk's value (fp64 for compensated pairs, fp32 plain, int64).
+// wave_reduce4 (defined below): the four 64-lane butterflies of a workgroup
+// and their ((w0 + w1) + (w2 + w3)) combination, by one wave.
+template <typename T> __device__ __forceinline__ T wave_reduce4(const T (&p)[NW]);
+
+// Thread accumulators -> the chunk's value (fp64 for compensated pairs, fp32
+// plain, int64): each thread's accumulators combined, then the wave butterfly
+// over each wave's 64 threads and ((w0 + w1) + (w2 + w3)) over the 4 waves.
+// The threads' values go through LDS to wave 0, which performs exactly those
+// additions in one reduce-scatter pass (wave_reduce4) instead of four waves
+// running a butterfly each; the value is returned to the threads of wave 0
+// (the callers use it there only).
 template <int DT, int MODE>
 __device__ __forceinline__ typename PartT<MODE>::T chunk_tree(Acc<DT, MODE> &acc) {
     auto tv = acc.finish();
-    auto wv = wave_reduce(tv);
-    using W = decltype(wv);
-    __shared__ W slot[NW];
+    using W = decltype(tv);
+    __shared__ W vals[NTHR];
     const int t = threadIdx.x;
-    const int wave = t >> 6, lane = t & 63;
-    if (lane == 0) slot[wave] = wv;
+    vals[t] = tv;
     __syncthreads();
-    typename PartT<MODE>::T res;
-    if constexpr (MODE == COMP) {
-        Pair b = pair_add(pair_add(slot[0], slot[1]), pair_add(slot[2], slot[3]));
-        res = pair_value(b);
-    } else {
-        res = (slot[0] + slot[1]) + (slot[2] + slot[3]);
+    typename PartT<MODE>::T res{};
+    if (t < 64) {
+        W p[NW];
+#pragma unroll
+        for (int w = 0; w < NW; w++) p[w] = vals[t + 64 * w];
+        const W r = wave_reduce4(p);
+        if constexpr (MODE == COMP) res = pair_value(r);
+        else res = r;
     }
-    __syncthreads();   // slot[] is reused by the next chunk
+    __syncthreads();   // vals[] is reused by the next chunk
     return res;
 }
 
@@ -563,17 +548,20 @@ __device__ __forceinline__ void small_load(const Range &rg, bool use, const void
 }
 
 
-// The four wave butterflies of small_value in one pass (a reduce-scatter):
-// p[w] is this lane's value of thread l + 64 w.  The result equals, bit for
-// bit, ((B(p0) + B(p1)) + (B(p2) + B(p3))) with B the wave butterfly of
-// wave_reduce, because it performs the same additions (each addition is
-// commutative bit for bit), only spread over the lanes.  At the first two
+// The canonical combination of a workgroup's 256 thread values: each set of
+// 64 (threads 64 w .. 64 w + 63) reduced by the symmetric wave butterfly B
+// (xor 1, xor 2, half-row mirror, row mirror -- every lane of a row then holds
+// the row total -- and the rows as (r0 + r1) + (r2 + r3)), and the four set
+// values as ((B(p0) + B(p1)) + (B(p2) + B(p3))).  One wave performs all of it
+// in one pass (a reduce-scatter): p[w] is this lane's value of thread
+// l + 64 w; it makes the same additions as the four butterflies (each
+// addition is commutative bit for bit), only spread over the lanes.  At the first two
 // levels the two lanes of a pair keep different values: after the xor-1 step
 // a lane holds two of the four values, after the xor-2 step one, so that in
 // every quad the lanes j = 0..3 hold values (0, 2, 1, 3) (even quads) or
 // (3, 1, 2, 0) (odd quads).  That layout is symmetric under the half-row and
 // row mirrors, so those two steps pair lanes that hold the same value, as in
-// wave_reduce.  Rows are then combined as (r0 + r1) + (r2 + r3) by the
+// B.  Rows are then combined as (r0 + r1) + (r2 + r3) by the
 // xor-16 and xor-32 exchanges (lane swaps), and the four values as
 // (v0 + v1) + (v2 + v3) by the xor-2 and xor-1 steps inside each quad; every
 // lane ends with the result.
