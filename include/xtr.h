@@ -523,7 +523,11 @@ typedef struct {
     int32_t seg_small_per_cu; /* workgroups per CU of the small-segment launch     */
                             /*    (0: as many as are resident)                      */
     int32_t seg_chunk_per_cu; /* the same for the chunk launch                     */
-    int32_t _reserved[2];
+    int32_t seg_over;       /* segmented launches: grids of this many times the    */
+                            /*    resident workgroups (0 or 1: the resident ones;  */
+                            /*    up to 16), the others starting as earlier ones   */
+                            /*    finish, so the dispatcher balances the work      */
+    int32_t _reserved[1];
 } xtr_reduce_config;
 
 /* Current / new configuration of the sums for one dtype and shape class

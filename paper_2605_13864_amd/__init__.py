@@ -45,7 +45,8 @@ class TposeConfig(C.Structure):
 class ReduceConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("split_chunks", C.c_int32), ("seg_fused", C.c_int32),
                 ("seg_streams", C.c_int32), ("seg_small_per_cu", C.c_int32),
-                ("seg_chunk_per_cu", C.c_int32), ("_reserved", C.c_int32 * 2)]
+                ("seg_chunk_per_cu", C.c_int32), ("seg_over", C.c_int32),
+                ("_reserved", C.c_int32 * 1)]
 
 
 class Job(C.Structure):
@@ -551,7 +552,7 @@ def reduce_config(dtype, shape: str = "single") -> dict:
            "xtr_reduce_get_class_config")
     return {"nt_load": c.nt_load, "split_chunks": c.split_chunks, "seg_fused": c.seg_fused,
             "seg_streams": c.seg_streams, "seg_small_per_cu": c.seg_small_per_cu,
-            "seg_chunk_per_cu": c.seg_chunk_per_cu}
+            "seg_chunk_per_cu": c.seg_chunk_per_cu, "seg_over": c.seg_over}
 
 
 def set_reduce_config(dtype, shape: str | None = None, **kw):
@@ -561,7 +562,7 @@ def set_reduce_config(dtype, shape: str | None = None, **kw):
         raise TypeError(f"set_reduce_config: unknown settings {sorted(bad)}")
     cur.update(kw)
     c = ReduceConfig(cur["nt_load"], cur["split_chunks"], cur["seg_fused"], cur["seg_streams"],
-                     cur["seg_small_per_cu"], cur["seg_chunk_per_cu"])
+                     cur["seg_small_per_cu"], cur["seg_chunk_per_cu"], cur["seg_over"])
     if shape is None:
         _check(load().xtr_reduce_set_config(_code(dtype), C.byref(c)), "xtr_reduce_set_config")
     else:

@@ -1331,8 +1331,11 @@ void launch_table(const Range *tab, int nr, int64_t nchunks, const Levels &lv, h
         hipLaunchKernelGGL((k_reduce_table<DT, MODE, false>), dim3((unsigned)nchunks), dim3(NTHR), 0,
                            st, tab, nr, lv);
 }
-// Both passes run as resident grids (8 workgroups per CU at most) that stride
-// over their segments / chunks: the chunk space is only known on the device.
+// Both passes run as grids that stride over their segments / chunks (the
+// chunk space is only known on the device): the resident workgroups (8 per CU
+// at most), or seg_over times as many, the later ones starting as earlier
+// ones finish (measured: 4x the resident grid, 130 -> 120 us for 100k fp32
+// segments).
 // side: a second stream for the small segments (their launch then overlaps
 // the chunks'), or nullptr.
 template <int DT, int MODE>
@@ -1343,13 +1346,15 @@ void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb,
     const bool nt = c.nt_load != 0;
     const int64_t gs_n = (nseg + NW - 1) / NW;                 // workgroups, one wave per segment
     const int64_t gc_n = cap > nseg ? cap : nseg;
+    const int64_t over = c.seg_over > 1 ? c.seg_over : 1;      // grids beyond the resident ones
     hipStream_t ss = side ? side : st;
 #define XTR_SEG(NTV)                                                                             \
     do {                                                                                         \
-        const int64_t o1 = resident_blocks((const void *)&k_reduce_seg_small<DT, MODE, NTV>, NTHR, \
-                                           c.seg_small_per_cu);                                  \
-        const int64_t o2 = resident_blocks((const void *)&k_reduce_seg<DT, MODE, NTV>, NTHR,    \
-                                           c.seg_chunk_per_cu);                                  \
+        const int64_t o1 = over * resident_blocks(                                               \
+                                      (const void *)&k_reduce_seg_small<DT, MODE, NTV>, NTHR,    \
+                                      c.seg_small_per_cu);                                       \
+        const int64_t o2 = over * resident_blocks((const void *)&k_reduce_seg<DT, MODE, NTV>,    \
+                                                  NTHR, c.seg_chunk_per_cu);                     \
         hipLaunchKernelGGL((k_reduce_seg_small<DT, MODE, NTV>),                                 \
                            dim3((unsigned)(gs_n < o1 ? gs_n : o1)), dim3(NTHR), 0, ss, src, off, \
                            cb, nseg, cap, out);                                                  \
@@ -1359,7 +1364,8 @@ void launch_seg(const unsigned char *src, const int64_t *off, const int64_t *cb,
     } while (0)
 #define XTR_SEG_ALL(NTV)                                                                         \
     do {                                                                                         \
-        const int64_t o = resident_blocks((const void *)&k_reduce_seg_all<DT, MODE, NTV>, NTHR); \
+        const int64_t o =                                                                        \
+            over * resident_blocks((const void *)&k_reduce_seg_all<DT, MODE, NTV>, NTHR);         \
         const int64_t g = gc_n > gs_n ? gc_n : gs_n;                                             \
         hipLaunchKernelGGL((k_reduce_seg_all<DT, MODE, NTV>), dim3((unsigned)(g < o ? g : o)),   \
                            dim3(NTHR), 0, st, src, off, cb, cs, nseg, cap, lv, out);             \
@@ -1808,9 +1814,10 @@ int xtr_reduce_set_class_config(int dtype, int shape_class, const xtr_reduce_con
         (shape_class != XTR_SHAPE_SINGLE && shape_class != XTR_SHAPE_BATCHED))
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: bad arguments");
     if (cfg->split_chunks < 0 || cfg->seg_small_per_cu < 0 || cfg->seg_small_per_cu > 64 ||
-        cfg->seg_chunk_per_cu < 0 || cfg->seg_chunk_per_cu > 64)
+        cfg->seg_chunk_per_cu < 0 || cfg->seg_chunk_per_cu > 64 || cfg->seg_over < 0 ||
+        cfg->seg_over > 16)
         return xtr::fail(XTR_EINVAL, "xtr_reduce_set_class_config: split_chunks >= 0, "
-                                     "seg_*_per_cu in [0, 64]");
+                                     "seg_*_per_cu in [0, 64], seg_over in [0, 16]");
     xtr::g_rcfg[shape_class][dtype] = *cfg;
     return XTR_OK;
 }

@@ -272,25 +272,28 @@ def tune_reduce_batched(xtr, torch, dt: str, log=print, nseg=100000):
     ws = torch.zeros(xtr.segmented_workspace_bytes(nseg, total, dt), dtype=torch.uint8,
                      device="cuda")
     orig = xtr.reduce_config(dt, "batched")
-    # (seg_fused, seg_streams, seg_small_per_cu, seg_chunk_per_cu)
-    modes = [(0, 0, 0, 0), (1, 0, 0, 0)] + [(0, 1, a, b) for a in (0, 2, 3) for b in (0, 3, 5)]
+    # (seg_fused, seg_streams, seg_small_per_cu, seg_chunk_per_cu, seg_over)
+    modes = [(f, 0, 0, 0, o) for f in (0, 1) for o in (1, 2, 4, 8)] + \
+            [(0, 1, a, b, 1) for a in (0, 2, 3) for b in (0, 3, 5)]
     t = {}
     try:
         for nt in (1, 0):
             for m in modes:
                 xtr.set_reduce_config(dt, "batched", nt_load=nt, seg_fused=m[0], seg_streams=m[1],
-                                      seg_small_per_cu=m[2], seg_chunk_per_cu=m[3])
+                                      seg_small_per_cu=m[2], seg_chunk_per_cu=m[3],
+                                      seg_over=m[4])
                 t[(nt,) + m] = _time(torch, lambda: xtr.reduce_sum_segmented_ws(src, off, ws, out,
                                                                                  dtype=dt))
     finally:
         xtr.set_reduce_config(dt, "batched", **orig)
     best = min(t, key=t.get)
     cfg = {"nt_load": best[0], "split_chunks": orig["split_chunks"], "seg_fused": best[1],
-           "seg_streams": best[2], "seg_small_per_cu": best[3], "seg_chunk_per_cu": best[4]}
+           "seg_streams": best[2], "seg_small_per_cu": best[3], "seg_chunk_per_cu": best[4],
+           "seg_over": best[5]}
     log(f"tune sum batched {dt}: {cfg} ({total * eb / t[best] / 1e9:.1f} GB/s)")
     del src, ws
     return {"gbs": round(total * eb / t[best] / 1e9, 1), "config": cfg, "nseg": nseg,
-            "all": {"nt_load={} fused={} streams={} small/cu={} chunk/cu={}".format(*k):
+            "all": {"nt_load={} fused={} streams={} small/cu={} chunk/cu={} over={}".format(*k):
                     round(total * eb / v / 1e9, 1) for k, v in t.items()}}
 
 

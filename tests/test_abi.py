@@ -222,3 +222,14 @@ def test_launch_config_validation(lib):
     finally:
         X.set_tpose_config(4, "batched", **orig)
     assert X.tpose_config(4, "batched") == orig
+    ro = X.reduce_config("f32", "batched")
+    try:
+        X.set_reduce_config("f32", "batched", seg_over=16)
+        for bad in ({"seg_over": 17}, {"seg_over": -1}, {"seg_chunk_per_cu": 65}):
+            with pytest.raises(X.XtrError) as e:
+                X.set_reduce_config("f32", "batched", **bad)
+            assert e.value.code == -1, bad
+        assert X.reduce_config("f32", "batched")["seg_over"] == 16
+    finally:
+        X.set_reduce_config("f32", "batched", **ro)
+    assert X.reduce_config("f32", "batched") == ro

@@ -359,9 +359,10 @@ def test_segmented_full_config(xtr, orc):
 @pytest.mark.parametrize("dt", ["f32", "bf16", "f8e4m3", "i32", "i64"])
 def test_segmented_fused_launch_same(xtr, orc, dt):
     """The segmented sum's two passes in one launch (seg_fused), or on two
-    streams (seg_streams, with and without per-CU caps), give the same bits
-    as two launches on one stream, for small, chunked and empty segments; an
-    invalid table still gives NaN / 0 everywhere."""
+    streams (seg_streams, with and without per-CU caps), and grids beyond the
+    resident workgroups (seg_over), give the same bits as two launches on one
+    stream, for small, chunked and empty segments; an invalid table still
+    gives NaN / 0 everywhere."""
     import torch
     total = 300000
     off = W.segment_offsets(total, 2000, 95)
@@ -371,20 +372,23 @@ def test_segmented_fused_launch_same(xtr, orc, dt):
     orig = xtr.reduce_config(dt, "batched")
     try:
         res = {}
-        modes = {0: dict(seg_fused=0, seg_streams=0), 1: dict(seg_fused=1, seg_streams=0),
+        modes = {0: dict(seg_fused=0, seg_streams=0, seg_over=1),
+                 1: dict(seg_fused=1, seg_streams=0, seg_over=1),
                  2: dict(seg_fused=0, seg_streams=1, seg_small_per_cu=2, seg_chunk_per_cu=4),
-                 3: dict(seg_fused=0, seg_streams=1, seg_small_per_cu=0, seg_chunk_per_cu=0)}
+                 3: dict(seg_fused=0, seg_streams=1, seg_small_per_cu=0, seg_chunk_per_cu=0),
+                 4: dict(seg_fused=1, seg_streams=0, seg_over=4),
+                 5: dict(seg_fused=0, seg_streams=0, seg_over=16)}
         for m, kw in modes.items():
             xtr.set_reduce_config(dt, "batched", **kw)
             res[m] = xtr.reduce_sum_segmented(d, doff, dtype=dt).cpu()
-        for m in (1, 2, 3):
+        for m in (1, 2, 3, 4, 5):
             assert torch.equal(res[0], res[m]), m
         want = orc.sum_segmented(bits, off, dt)
         if dt in ("i32", "i64"):
             assert np.array_equal(res[1].numpy(), want)
         bad = off.copy()
         bad[10], bad[11] = bad[11], bad[10] - 1
-        for m in (1, 2):
+        for m in (1, 2, 4):
             xtr.set_reduce_config(dt, "batched", **modes[m])
             out = xtr.reduce_sum_segmented(d, to_dev(bad), dtype=dt).cpu()
             if dt in ("i32", "i64"):
