@@ -173,8 +173,8 @@ def test_batched_geometries(xtr, orc, wide, run, xcd, narrow):
                                  narrow=narrow)
         xtr.set_tpose_config(1, "batched", run=run, xcd=xcd, narrow=narrow)
         jobs, hosts = [], []
-        for i in range(40):
-            eb = [1, 2, 4, 8][i % 4]
+        for i in range(112):                 # 28 jobs per element size: with one piece
+            eb = [1, 2, 4, 8][i % 4]         # width per size, groups above 24 jobs (a table)
             r, c = (int(x) for x in rng.integers(1, 1500, 2))
             if i % 5 == 0:
                 r, c = 8 * TILE[eb] + 3, 6 * TILE[eb] + 1      # many tiles: takes the geometry
@@ -189,6 +189,7 @@ def test_batched_geometries(xtr, orc, wide, run, xcd, narrow):
             if use_plan:
                 p = xtr.TposePlan(jobs)
                 p.run()
+                p.run()                      # a second run (counters left at zero)
             else:
                 xtr.tpose_batched(jobs)
             torch.cuda.synchronize()
