@@ -77,7 +77,6 @@ template <int DT> struct HistT;
 template <> struct HistT<XTR_F32> { static constexpr int EB = 4; };
 template <> struct HistT<XTR_F16> { static constexpr int EB = 2; };
 template <> struct HistT<XTR_BF16> { static constexpr int EB = 2; };
-template <> struct HistT<XTR_F8E4M3> { static constexpr int EB = 1; };
 template <> struct HistT<XTR_I32> { static constexpr int EB = 4; };
 template <> struct HistT<XTR_I64> { static constexpr int EB = 8; };
 template <> struct HistT<XTR_U8> { static constexpr int EB = 1; };
