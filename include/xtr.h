@@ -485,7 +485,10 @@ typedef struct {
                             /*    wider takes the narrowest piece of its element  */
                             /*    size (4 bytes; 8 for 8-byte elements), so the   */
                             /*    jobs of one element size share one launch; 0..1  */
-    int32_t _reserved[1];
+    int32_t wide_min;       /* single class: a matrix of fewer than wide_min       */
+                            /*    256 x 256-byte tiles per CU takes 256 x 256      */
+                            /*    bytes whatever tile / tile_shared say (wider     */
+                            /*    tiles leave CUs idle there); 0..1024             */
 } xtr_tpose_config;
 
 /* Shape classes of the launch configurations: single calls (tpose,

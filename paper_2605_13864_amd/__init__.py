@@ -39,7 +39,7 @@ class TposeConfig(C.Structure):
     _fields_ = [("nt_load", C.c_int32), ("nt_store", C.c_int32), ("xcd", C.c_int32),
                 ("group", C.c_int32), ("blocks_per_cu", C.c_int32), ("nt_store_shared", C.c_int32),
                 ("nt_load_shared", C.c_int32), ("tile", C.c_int32), ("tile_shared", C.c_int32),
-                ("run", C.c_int32), ("narrow", C.c_int32), ("_reserved", C.c_int32 * 1)]
+                ("run", C.c_int32), ("narrow", C.c_int32), ("wide_min", C.c_int32)]
 
 
 class ReduceConfig(C.Structure):
@@ -525,7 +525,7 @@ def tpose_config(elem_bytes: int, shape: str = "single") -> dict:
     return {"nt_load": c.nt_load, "nt_store": c.nt_store, "xcd": c.xcd, "group": c.group,
             "blocks_per_cu": c.blocks_per_cu, "nt_store_shared": c.nt_store_shared,
             "nt_load_shared": c.nt_load_shared, "tile": c.tile, "tile_shared": c.tile_shared,
-            "run": c.run, "narrow": c.narrow}
+            "run": c.run, "narrow": c.narrow, "wide_min": c.wide_min}
 
 
 def set_tpose_config(elem_bytes: int, shape: str | None = None, **kw):
@@ -538,7 +538,8 @@ def set_tpose_config(elem_bytes: int, shape: str | None = None, **kw):
     cur.update(kw)
     c = TposeConfig(cur["nt_load"], cur["nt_store"], cur["xcd"], cur["group"],
                     cur["blocks_per_cu"], cur["nt_store_shared"], cur["nt_load_shared"],
-                    cur["tile"], cur["tile_shared"], cur["run"], cur["narrow"])
+                    cur["tile"], cur["tile_shared"], cur["run"], cur["narrow"],
+                    cur["wide_min"])
     if shape is None:
         _check(load().xtr_tpose_set_config(elem_bytes, C.byref(c)), "xtr_tpose_set_config")
     else:

@@ -45,12 +45,15 @@ namespace xtr {
 using namespace tpk;
 
 // Tuned launch configuration per shape class and element size (slot
-// cfg_slot(elem bytes)).
+// cfg_slot(elem bytes)).  wide_min as measured on rotating buffers: 2-byte
+// elements keep wide tiles from 8 default tiles per CU (bf16 8192 x 8192 runs
+// 2% faster in them), 4- and 8-byte ones from 32 (fp32 4096 x 4096: 15% faster
+// in default tiles).
 xtr_tpose_config tpk::g_cfg[2][4] = {
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}},
-    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}},
-     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, {0}}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 8},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}},
+    {{1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 8},
+     {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}, {1, 1, 1, 1, 0, 0, 0, 0, 0, 0, 0, 32}},
 };
 
 namespace {
@@ -438,10 +441,12 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
     if (cfg->xcd < 0 || cfg->xcd > 3 ||
         cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
         cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
-        cfg->run < 0 || cfg->run > 64 || cfg->narrow < 0 || cfg->narrow > 1)
+        cfg->run < 0 || cfg->run > 64 || cfg->narrow < 0 || cfg->narrow > 1 ||
+        cfg->wide_min < 0 || cfg->wide_min > 1024)
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 3], group in "
                                      "[1, 64], blocks_per_cu in [0, 64], tile and tile_shared in "
-                                     "[0, 3], run in [0, 64], narrow in [0, 1]");
+                                     "[0, 3], run in [0, 64], narrow in [0, 1], wide_min in "
+                                     "[0, 1024]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;
 }

@@ -916,10 +916,10 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
 // row segments, 3 = both (4- and 8-byte elements), else 256 x 256 bytes.  Wider segments
 // halve the share of edge lines that neighbouring tiles split.  2- to 8-byte
 // elements only.
-// A matrix of fewer default tiles than SINGLE_WIDE_MIN_TILES (8 per CU on
-// MI355X) keeps the default geometry: wider tiles would leave CUs idle.
-constexpr int64_t SINGLE_WIDE_MIN_TILES = 2048;
-
+// A matrix of fewer default tiles than c.wide_min per CU keeps the default
+// geometry: there wide tiles leave CUs idle and tie or lose; from fp32 8192 x
+// 8192 up they win, halving the edge lines that tiles of power-of-two strides
+// split.
 template <int EB>
 int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t ld_src,
                int64_t ld_dst, hipStream_t stream) {
@@ -928,7 +928,8 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
     const int64_t ntiles = ((rows + Geo<EB>::TR - 1) / Geo<EB>::TR) *
                            ((cols + Geo<EB>::TC - 1) / Geo<EB>::TC);
     if (ntiles >= MAX_TILES) return fail(XTR_EINVAL, "tpose: %lld tiles (limit 2^31)", (long long)ntiles);
-    const int tile = ntiles < SINGLE_WIDE_MIN_TILES ? 0 : lines ? c.tile : c.tile_shared;
+    const int tile = ntiles < (int64_t)c.wide_min * cu_count() ? 0
+                   : lines ? c.tile : c.tile_shared;
     switch (piece_width(src, dst, ld_src, ld_dst, EB)) {
     case 16:
         if constexpr (EB >= 4) {

@@ -116,14 +116,17 @@ def test_unaligned_rows(xtr, orc, eb):
 def test_tile_geometries(xtr, orc, eb, tile):
     """512-byte src (tile 1), dst (tile 2) or both (tile 3; 2-byte elements
     keep the default) row segments: whole and ragged tiles, 16-byte pieces,
-    against the oracle."""
+    against the oracle; wide_min 0 lets every size take the wide geometry, the
+    tuned threshold one large matrix."""
     orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
-        xtr.set_tpose_config(eb, "single", tile=tile)
-        # >= 2048 default tiles (smaller matrices keep the default geometry)
-        for i, (r, c) in enumerate([(32 * T, 64 * T), (64 * T + 3, 32 * T + 5),
-                                    (48 * T - 1, 48 * T + 1), (1, 1)]):
+        xtr.set_tpose_config(eb, "single", tile=tile, wide_min=0)
+        for i, (r, c) in enumerate([(8 * T, 16 * T), (16 * T + 3, 8 * T + 5),
+                                    (12 * T - 1, 12 * T + 1), (T + 1, 2 * T - 1), (1, 1),
+                                    (32 * T, 64 * T)]):
+            if i == 5:
+                xtr.set_tpose_config(eb, "single", wide_min=8)   # 2048 tiles: wide
             v = 16 // eb
             pad_s = (-c) % v + v * (i % 2)          # keep 16-byte pitches: 16-byte pieces
             pad_d = (-r) % v
@@ -142,10 +145,10 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
     orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
     try:
-        xtr.set_tpose_config(eb, "single", tile_shared=geo)
-        # >= 2048 default tiles, and a small one that keeps the default geometry
-        for i, (r, c) in enumerate([(64 * T, 32 * T), (64 * T + 3, 32 * T + 5),
-                                    (50 * T - 1, 48 * T + 1), (2 * T - 1, T + 1)]):
+        xtr.set_tpose_config(eb, "single", tile_shared=geo, wide_min=0)
+        # every size in the wide geometry (one ragged tile included)
+        for i, (r, c) in enumerate([(16 * T, 8 * T), (16 * T + 3, 8 * T + 5),
+                                    (10 * T - 1, 12 * T + 1), (2 * T - 1, T + 1)]):
             ld_s, ld_d = _ld_with_piece(c, eb, w), _ld_with_piece(r, eb, w)
             if (ld_s * eb) % 128 == 0:
                 ld_s += 16 // eb                     # rows must not start on lines
