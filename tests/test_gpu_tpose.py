@@ -157,6 +157,27 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
+@pytest.mark.parametrize("bpc,tile", [(1, 0), (2, 3), (1, 1), (3, 2)])
+@pytest.mark.parametrize("eb,w", [(1, 16), (1, 4), (2, 16), (2, 8), (4, 16), (4, 8), (4, 4), (8, 16),
+                                  (8, 8)])
+def test_persistent_single(xtr, orc, eb, w, bpc, tile):
+    """Persistent single launches (blocks_per_cu > 0, fewer workgroups than
+    tiles): each workgroup takes several tiles in turn, interior and edge
+    tiles, each tile geometry (wide_min 0), against the oracle, twice in a
+    row."""
+    orig = xtr.tpose_config(eb, "single")
+    T = TILE[eb]
+    try:
+        xtr.set_tpose_config(eb, "single", blocks_per_cu=bpc, tile=tile, tile_shared=tile,
+                             wide_min=0)
+        for i, (r, c) in enumerate([(40 * T + 3, 36 * T + 5), (48 * T, 40 * T)]):
+            ld_s, ld_d = _ld_with_piece(c, eb, w), _ld_with_piece(r, eb, w)
+            for rep in range(2):
+                run_tpose(xtr, orc, r, c, eb, pad_s=ld_s - c, pad_d=ld_d - r, seed=300 + 2 * i + rep)
+    finally:
+        xtr.set_tpose_config(eb, "single", **orig)
+
+
 @pytest.mark.parametrize("run,xcd,narrow", [(0, 1, 0), (3, 1, 0), (0, 2, 0), (3, 2, 1), (0, 3, 1),
                                             (3, 3, 0)])
 @pytest.mark.parametrize("wide", [0, 1, 2, 3])
