@@ -127,7 +127,7 @@ def test_segmented_and_batched_validation(lib):
     assert lib.reduce_sum_segmented_ws_total(C.c_void_p(FAKE), C.c_void_p(FAKE + 4096), 5, 100,
                                              C.c_void_p(FAKE + 8192), 0,
                                              C.c_void_p(FAKE + 16384), 8, None) == -7
-    # the survey signature sizes its chunk space from the workspace: 8 bytes hold none
+    # the workspace-only form sizes its chunk space from the workspace: 8 bytes hold none
     assert lib.reduce_sum_segmented_ws(C.c_void_p(FAKE), C.c_void_p(FAKE + 4096), 5,
                                        C.c_void_p(FAKE + 8192), 0, C.c_void_p(FAKE + 16384), 8,
                                        None) == -7
