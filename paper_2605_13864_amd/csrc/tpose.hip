@@ -440,12 +440,12 @@ int xtr_tpose_set_class_config(int elem_bytes, int shape_class, const xtr_tpose_
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: bad arguments");
     if (cfg->xcd < 0 || cfg->xcd > 3 ||
         cfg->group < 1 || cfg->group > 64 || cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 64 ||
-        cfg->tile < 0 || cfg->tile > 3 || cfg->tile_shared < 0 || cfg->tile_shared > 3 ||
+        cfg->tile < 0 || cfg->tile > 4 || cfg->tile_shared < 0 || cfg->tile_shared > 4 ||
         cfg->run < 0 || cfg->run > 64 || cfg->narrow < 0 || cfg->narrow > 1 ||
         cfg->wide_min < 0 || cfg->wide_min > 1024)
         return xtr::fail(XTR_EINVAL, "xtr_tpose_set_class_config: xcd in [0, 3], group in "
                                      "[1, 64], blocks_per_cu in [0, 64], tile and tile_shared in "
-                                     "[0, 3], run in [0, 64], narrow in [0, 1], wide_min in "
+                                     "[0, 4], run in [0, 64], narrow in [0, 1], wide_min in "
                                      "[0, 1024]");
     xtr::g_cfg[shape_class][xtr::cfg_slot(elem_bytes)] = *cfg;
     return XTR_OK;

@@ -824,12 +824,14 @@ template <int EB> struct GeoOf<EB, 0> { static constexpr int SC = 16, DC = 16; }
 template <int EB> struct GeoOf<EB, 1> { static constexpr int SC = 32, DC = 16; };
 template <int EB> struct GeoOf<EB, 2> { static constexpr int SC = 16, DC = 32; };
 template <int EB> struct GeoOf<EB, 3> { static constexpr int SC = 32, DC = 32; };
+template <int EB> struct GeoOf<EB, 4> { static constexpr int SC = 16, DC = 64; };
 
 inline int64_t tiles_for(int eb, int64_t rows, int64_t cols, int64_t *tiles_c, int geo = 0) {
 #define XTR_TF(E)                                                                              \
     return geo == 1 ? tiles_of<E, 32, 16>(rows, cols, tiles_c)                                \
          : geo == 2 ? tiles_of<E, 16, 32>(rows, cols, tiles_c)                                \
          : geo == 3 && E >= 4 ? tiles_of<E, 32, 32>(rows, cols, tiles_c)                      \
+         : geo == 4 && E >= 4 ? tiles_of<E, 16, 64>(rows, cols, tiles_c)                      \
                               : tiles_of<E>(rows, cols, tiles_c)
     switch (eb) {
     case 1: return tiles_of<1>(rows, cols, tiles_c);
@@ -844,7 +846,8 @@ inline bool off32_geo(int eb, int geo, int64_t ld_src, int64_t ld_dst) {
 #define XTR_OG(E)                                                                              \
     return geo == 1 ? off32_ok<E, 32, 16>(ld_src, ld_dst)                                     \
          : geo == 2 ? off32_ok<E, 16, 32>(ld_src, ld_dst)                                     \
-         : geo == 3 && E >= 4 ? off32_ok<E, 32, 32>(ld_src, ld_dst) : off32_ok<E>(ld_src, ld_dst)
+         : geo == 3 && E >= 4 ? off32_ok<E, 32, 32>(ld_src, ld_dst)                           \
+         : geo == 4 && E >= 4 ? off32_ok<E, 16, 64>(ld_src, ld_dst) : off32_ok<E>(ld_src, ld_dst)
     switch (eb) {
     case 1: return off32_ok<1>(ld_src, ld_dst);
     case 2: XTR_OG(2);
@@ -913,8 +916,9 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
 
 // Tile geometry of a single transpose (`tile` for line-aligned rows,
 // `tile_shared` otherwise): 1 = 512-byte src row segments, 2 = 512-byte dst
-// row segments, 3 = both (4- and 8-byte elements), else 256 x 256 bytes.  Wider segments
-// halve the share of edge lines that neighbouring tiles split.  2- to 8-byte
+// row segments, 3 = both, 4 = 1 KiB dst row segments of 256-byte src ones (3
+// and 4: 4- and 8-byte elements), else 256 x 256 bytes.  Wider segments halve
+// the share of edge lines that neighbouring tiles split.  2- to 8-byte
 // elements only.
 // A matrix of fewer default tiles than c.wide_min per CU keeps the default
 // geometry: there wide tiles leave CUs idle and tie or lose; from fp32 8192 x
@@ -937,6 +941,10 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
                 launch_w<EB, 16, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
             }
+            if (tile == 4) {
+                launch_w<EB, 16, 16, 64>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
         }
         if constexpr (EB >= 2) {
             if (tile == 1) {
@@ -956,6 +964,10 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
                 launch_w<EB, 8, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
             }
+            if (tile == 4) {
+                launch_w<EB, 8, 16, 64>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
         }
         if constexpr (EB >= 2 && EB <= 8) {
             if (tile == 1) {
@@ -973,6 +985,10 @@ int launch_one(const void *src, void *dst, int64_t rows, int64_t cols, int64_t l
         if constexpr (EB == 4) {
             if (tile == 3) {
                 launch_w<EB, 4, 32, 32>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
+                break;
+            }
+            if (tile == 4) {
+                launch_w<EB, 4, 16, 64>(c, stream, src, dst, rows, cols, ld_src, ld_dst);
                 break;
             }
         }

@@ -68,7 +68,7 @@ def tpose_candidates(quick: bool, eb: int = 4):
     nts = [(1, 1), (0, 0)] if quick else [(1, 1), (1, 0), (0, 1), (0, 0)]
     groups = [1, 4, 16] if quick else [1, 2, 4, 8, 16, 32]
     bpc = [0, 8] if quick else [0, 4, 8, 16]
-    tiles = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
+    tiles = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3, 4]
     for (nl, ns), xcd, g, b, tl in itertools.product(nts, [1, 0], groups, bpc, tiles):
         # the *_shared flags follow along here (the main shape may have rows
         # that share lines); they are refined on a shared-line shape afterwards
@@ -110,7 +110,7 @@ def tune_tpose(xtr, torch, eb: int, quick=False, log=print):
             src = torch.empty((nr, nc), dtype=tdt, device="cuda")
             src.view(torch.uint8).random_(0, 255, generator=torch.Generator("cuda").manual_seed(nr))
             dst = torch.empty((nc, nr), dtype=tdt, device="cuda")
-            geos = (0, 1, 2, 3) if eb >= 4 else (0, 1, 2) if eb == 2 else (0,)
+            geos = (0, 1, 2, 3, 4) if eb >= 4 else (0, 1, 2) if eb == 2 else (0,)
             for nls, nss, ts in itertools.product((0, 1), (0, 1), geos):
                 xtr.set_tpose_config(eb, "single", **dict(best[1], nt_load_shared=nls,
                                                           nt_store_shared=nss, tile_shared=ts))

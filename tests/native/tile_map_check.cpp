@@ -172,6 +172,11 @@ int main() {
     check<4, 4, 32, 32>("f32 W4  512x512");
     check<8, 16, 32, 32>("f64 W16 512x512");
     check<8, 8, 32, 32>("f64 W8  512x512");
+    check<4, 16, 16, 64>("f32 W16 dst1024");
+    check<4, 8, 16, 64>("f32 W8  dst1024");
+    check<4, 4, 16, 64>("f32 W4  dst1024");
+    check<8, 16, 16, 64>("f64 W16 dst1024");
+    check<8, 8, 16, 64>("f64 W8  dst1024");
     std::printf("%s\n", failures ? "FAILED" : "all tile maps ok");
     return failures ? 1 : 0;
 }

@@ -213,7 +213,7 @@ def test_launch_config_validation(lib):
     try:
         X.set_tpose_config(4, "batched", xcd=2)
         assert X.tpose_config(4, "batched")["xcd"] == 2
-        for bad in ({"xcd": 4}, {"xcd": -1}, {"group": 0}, {"run": 65}, {"tile": 4},
+        for bad in ({"xcd": 4}, {"xcd": -1}, {"group": 0}, {"run": 65}, {"tile": 5},
                     {"blocks_per_cu": 65}, {"narrow": 2}, {"wide_min": 1025},
                     {"wide_min": -1}):
             with pytest.raises(X.XtrError) as e:

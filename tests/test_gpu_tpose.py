@@ -112,10 +112,10 @@ def test_unaligned_rows(xtr, orc, eb):
 
 
 @pytest.mark.parametrize("eb", [2, 4, 8])
-@pytest.mark.parametrize("tile", [1, 2, 3])
+@pytest.mark.parametrize("tile", [1, 2, 3, 4])
 def test_tile_geometries(xtr, orc, eb, tile):
-    """512-byte src (tile 1), dst (tile 2) or both (tile 3; 2-byte elements
-    keep the default) row segments: whole and ragged tiles, 16-byte pieces,
+    """512-byte src (tile 1), dst (tile 2) or both (tile 3), or 1 KiB dst row
+    segments (tile 4; 2-byte elements keep the default for 3 and 4): whole and ragged tiles, 16-byte pieces,
     against the oracle; wide_min 0 lets every size take the wide geometry, the
     tuned threshold one large matrix."""
     orig = xtr.tpose_config(eb, "single")
@@ -135,12 +135,12 @@ def test_tile_geometries(xtr, orc, eb, tile):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("geo", [1, 2, 3])
+@pytest.mark.parametrize("geo", [1, 2, 3, 4])
 @pytest.mark.parametrize("eb,w", [(2, 4), (2, 8), (2, 16), (4, 4), (4, 8), (4, 16), (8, 8),
                                   (8, 16)])
 def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
-    """512-byte src (tile_shared = 1), dst (2) or both (3) row segments
-    for rows that do not start on cache lines, with every piece width, whole
+    """512-byte src (tile_shared = 1), dst (2) or both (3) row segments, or
+    1 KiB dst ones (4), for rows that do not start on cache lines, with every piece width, whole
     and ragged tiles."""
     orig = xtr.tpose_config(eb, "single")
     T = TILE[eb]
@@ -157,7 +157,7 @@ def test_tile_geometry_shared_rows(xtr, orc, eb, w, geo):
         xtr.set_tpose_config(eb, "single", **orig)
 
 
-@pytest.mark.parametrize("bpc,tile", [(1, 0), (2, 3), (1, 1), (3, 2)])
+@pytest.mark.parametrize("bpc,tile", [(1, 0), (2, 3), (1, 1), (3, 2), (2, 4)])
 @pytest.mark.parametrize("eb,w", [(1, 16), (1, 4), (2, 16), (2, 8), (4, 16), (4, 8), (4, 4), (8, 16),
                                   (8, 8)])
 def test_persistent_single(xtr, orc, eb, w, bpc, tile):

@@ -28,7 +28,7 @@ def run_check(tmp_path, header=HEADER):
 def test_tile_maps(tmp_path):
     r = run_check(tmp_path)
     assert r.returncode == 0 and "all tile maps ok" in r.stdout, r.stdout[-3000:]
-    assert r.stdout.count("ok=1") == 32
+    assert r.stdout.count("ok=1") == 37
 
 
 MUTANTS = [
