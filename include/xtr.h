@@ -475,8 +475,7 @@ typedef struct {
                             /*    bytes, 1 = 512-byte src row segments, 2 = 512-   */
                             /*    byte dst row segments, 3 = 512 x 512 bytes, 4 =   */
                             /*    1 KiB dst row segments of 256-byte src ones (3   */
-                            /*    and 4: 4- and 8-byte elements, single calls;     */
-                            /*    others take 0)                                   */
+                            /*    and 4: 4- and 8-byte elements; others take 0)    */
     int32_t tile_shared;    /* the same for rows that do not start on lines (in the */
                             /*    batched class: the geometry of every batch job)   */
     int32_t run;            /* batched class: tiles a workgroup takes one after     */

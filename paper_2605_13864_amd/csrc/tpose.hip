@@ -195,8 +195,8 @@ int tpose_host_impl(const void *src, void *dst, int64_t rows, int64_t cols, int6
 // concatenated tile space and one persistent launch.
 // eb slot x piece class (16, 8, 4, elem) x off32 x line-aligned rows x tile
 // geometry (0: 256 x 256 bytes, 1: 512-byte src row segments, 2: 512-byte dst
-// row segments, 3: both)
-constexpr int NGEO = 4;
+// row segments, 3: both, 4: 1 KiB dst row segments)
+constexpr int NGEO = 5;
 constexpr int NGROUPS = 4 * 4 * 2 * 2 * NGEO;
 // jobs of at least this many default tiles may take a wider geometry
 constexpr int64_t WIDE_MIN_TILES = 16;
@@ -250,7 +250,8 @@ int build_batch(const xtr_tpose_desc *descs, int64_t count, const char *who, Bat
         const bool lines = lines_ok(d.src, d.ld_src, eb) && lines_ok(d.dst, d.ld_dst, eb);
         const xtr_tpose_config &c = g_cfg[XTR_SHAPE_BATCHED][cfg_slot(eb)];
         const int want = lines ? c.tile : c.tile_shared;
-        const int geo = eb >= 2 && j.w >= 4 && (want == 1 || want == 2 || (want == 3 && eb >= 4)) &&
+        const int geo = eb >= 2 && j.w >= 4 &&
+                                (want == 1 || want == 2 || (want >= 3 && eb >= 4)) &&
                                 tiles_for(eb, d.rows, d.cols, nullptr) >= WIDE_MIN_TILES &&
                                 off32_geo(eb, want, d.ld_src, d.ld_dst)
                             ? want

@@ -1047,7 +1047,7 @@ void launch_batched_w(bool lines, int64_t grid, hipStream_t st, const Job *jobs,
 #undef XTR_KB
 }
 
-// geo: the group's tile geometry (0, 1 or 2, as `tile`); the wider ones need
+// geo: the group's tile geometry (0 to 4, as `tile`); the wider ones need
 // 32-bit lane offsets (the host groups jobs accordingly).
 template <int EB>
 void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStream_t st,
@@ -1067,6 +1067,10 @@ void launch_batched(int w, bool off32, bool lines, int geo, int64_t grid, hipStr
     if constexpr (EB >= 4 && WW >= 4) {                                                        \
         if (geo == 3) {                                                                        \
             launch_batched_w<EB, WW, true, 32, 32>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr); \
+            return;                                                                            \
+        }                                                                                      \
+        if (geo == 4) {                                                                        \
+            launch_batched_w<EB, WW, true, 16, 64>(lines, grid, st, jobs, bases, nj, ntiles, pk, ctr); \
             return;                                                                            \
         }                                                                                      \
     }                                                                                          \

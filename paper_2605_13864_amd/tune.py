@@ -203,7 +203,7 @@ def tpose_batched_candidates(quick: bool, eb: int):
     xcds = [3, 1] if quick else [3, 2, 1, 0]
     groups = [16, 32] if quick else [8, 16, 32]
     bpc = [2, 4] if quick else [0, 2, 3, 4]
-    wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3]
+    wides = [0] if eb == 1 else [0, 1, 2] if eb == 2 else [0, 1, 2, 3, 4]
     narrows = [1, 0]
     for (nl, ns), xcd, g, b, w, nw in itertools.product(nts, xcds, groups, bpc, wides, narrows):
         # nearly every job of a random-size batch has rows that share lines:

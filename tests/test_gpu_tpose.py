@@ -180,10 +180,10 @@ def test_persistent_single(xtr, orc, eb, w, bpc, tile):
 
 @pytest.mark.parametrize("run,xcd,narrow", [(0, 1, 0), (3, 1, 0), (0, 2, 0), (3, 2, 1), (0, 3, 1),
                                             (3, 3, 0)])
-@pytest.mark.parametrize("wide", [0, 1, 2, 3])
+@pytest.mark.parametrize("wide", [0, 1, 2, 3, 4])
 def test_batched_geometries(xtr, orc, wide, run, xcd, narrow):
     """Batched transposes with each tile geometry (512-byte src rows: 1, dst
-    rows: 2, both: 3) for jobs whose rows share lines, mixed with small and aligned
+    rows: 2, both: 3, 1 KiB dst rows: 4) for jobs whose rows share lines, mixed with small and aligned
     jobs, every element size and every piece width, in each XCD order (per round;
     one contiguous eighth of the launch order per XCD, with static slots or
     slots taken from counters), with or without one piece width per element
