@@ -508,7 +508,7 @@ __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ 
                                               unsigned char *__restrict__ dst, int64_t rows,
                                               int64_t cols, int64_t ld_src, int64_t ld_dst,
                                               int64_t tiles_r, int64_t tiles_c, int xcd,
-                                              int group) {
+                                              int group, int skew) {
     using G = Geo<EB, SC, DC>;
     __shared__ uint4 lds[G::LDS_VECS];
     const uint32_t ntiles = (uint32_t)(tiles_r * tiles_c), Gd = gridDim.x, bx = blockIdx.x;
@@ -519,6 +519,11 @@ __global__ void __launch_bounds__(NT) k_tpose(const unsigned char *__restrict__ 
         const uint32_t L = xcd ? wave0 + xcd_remap(bx, inwave) : b;
         uint32_t tr, tc;
         band_order(L, (uint32_t)tiles_r, (uint32_t)tiles_c, (uint32_t)group, tr, tc);
+        // skewed band: tile row i of a band starts i tile columns further on
+        // (a permutation of each tile row), so that tiles dispatched together
+        // differ in both coordinates and, with power-of-two pitches, read and
+        // write rows that fall on different memory channels
+        if (skew) tc = (tc + tr % (uint32_t)group) % (uint32_t)tiles_c;
         tile_any<EB, W, NTL, NTS, OFF32, SC, DC>(src, dst, rows, cols, ld_src, ld_dst,
                                                  (int64_t)tr * G::TR, (int64_t)tc * G::TC, lds);
         __syncthreads();   // LDS is reused by the next tile of this workgroup
@@ -869,15 +874,15 @@ inline int cfg_slot(int eb) { return eb == 1 ? 0 : eb == 2 ? 1 : eb == 4 ? 2 : 3
 template <int EB, int W, bool NTL, bool NTS, int SC, int DC>
 void launch_k(dim3 grid, hipStream_t st, const void *src, void *dst, int64_t rows, int64_t cols,
               int64_t ld_src, int64_t ld_dst, int64_t tiles_r, int64_t tiles_c, int xcd,
-              int group) {
+              int group, int skew) {
     if (off32_ok<EB, SC, DC>(ld_src, ld_dst))
         hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, true, SC, DC>), grid, dim3(NT), 0, st,
                            (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
-                           ld_dst, tiles_r, tiles_c, xcd, group);
+                           ld_dst, tiles_r, tiles_c, xcd, group, skew);
     else
         hipLaunchKernelGGL((k_tpose<EB, W, NTL, NTS, false, SC, DC>), grid, dim3(NT), 0, st,
                            (const unsigned char *)src, (unsigned char *)dst, rows, cols, ld_src,
-                           ld_dst, tiles_r, tiles_c, xcd, group);
+                           ld_dst, tiles_r, tiles_c, xcd, group, skew);
 }
 
 // Rows of a matrix start on 128-byte cache lines (base and pitch), so no
@@ -901,12 +906,17 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
         if (g < grid) grid = g;
     }
     const int group = c.group < 1 ? 1 : c.group;
+    // both byte pitches powers of two: tiles of one tile column share memory
+    // channels, so the band is skewed (fp32 16384 x 16384 +2%, 8192 x 8192 +4%;
+    // other pitches gain nothing)
+    const uint64_t ps = (uint64_t)(ld_src * EB), pd = (uint64_t)(ld_dst * EB);
+    const int skew = ((ps & (ps - 1)) == 0 && (pd & (pd - 1)) == 0) ? 1 : 0;
     const dim3 gd((unsigned)grid);
     const bool ntl = lines_ok(src, ld_src, EB) ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines_ok(dst, ld_dst, EB) ? c.nt_store != 0 : c.nt_store_shared != 0;
 #define XTR_K(NL, NS)                                                                        \
     launch_k<EB, W, NL, NS, SC, DC>(gd, st, src, dst, rows, cols, ld_src, ld_dst, tiles_r,    \
-                                    tiles_c, c.xcd, group)
+                                    tiles_c, c.xcd, group, skew)
     if (ntl && nts) XTR_K(true, true);
     else if (ntl) XTR_K(true, false);
     else if (nts) XTR_K(false, true);
