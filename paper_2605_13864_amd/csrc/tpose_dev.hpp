@@ -906,11 +906,12 @@ void launch_w(const xtr_tpose_config &c, hipStream_t st, const void *src, void *
         if (g < grid) grid = g;
     }
     const int group = c.group < 1 ? 1 : c.group;
-    // both byte pitches powers of two: tiles of one tile column share memory
-    // channels, so the band is skewed (fp32 16384 x 16384 +2%, 8192 x 8192 +4%;
-    // other pitches gain nothing)
+    // 512 x 512-byte tiles and both byte pitches powers of two: tiles of one
+    // tile column share memory channels, so the band is skewed (fp32 16384 x
+    // 16384 +2%, 8192 x 8192 +4%; other pitches gain nothing, and other
+    // geometries lose: fp64 16384 x 8192 in 512-byte src segments -3%)
     const uint64_t ps = (uint64_t)(ld_src * EB), pd = (uint64_t)(ld_dst * EB);
-    const int skew = ((ps & (ps - 1)) == 0 && (pd & (pd - 1)) == 0) ? 1 : 0;
+    const int skew = (SC == 32 && DC == 32 && (ps & (ps - 1)) == 0 && (pd & (pd - 1)) == 0) ? 1 : 0;
     const dim3 gd((unsigned)grid);
     const bool ntl = lines_ok(src, ld_src, EB) ? c.nt_load != 0 : c.nt_load_shared != 0;
     const bool nts = lines_ok(dst, ld_dst, EB) ? c.nt_store != 0 : c.nt_store_shared != 0;
